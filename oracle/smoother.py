@@ -1,0 +1,99 @@
+"""Gauss-Seidel sweeps (oracle).
+
+Test infrastructure only (see the package header).
+
+Point Gauss-Seidel of Section 2.1, Algorithm 1: each unknown i is replaced by
+(f_i - sum_{j != i} a_ij u_j) / a_ii using the newest values of the unknowns
+already visited. A V-cycle sweeps once forward before the coarse correction and
+once in exactly the reverse order after it (Section 3, Step 2.5). Algorithm 1's
+error-based exit is not used inside a V-cycle (a fixed number of sweeps).
+
+Two visiting orders:
+  * ``colored`` (the order the GPU uses): colours ascending, vertices of a
+    colour in canonical order, components ascending; the backward sweep is the
+    exact reverse. Vertices of one colour are not coupled, so all of them can be
+    updated at once for each component.
+  * ``lex`` (the paper's order): all first components, then all second
+    components, ... (the component-major unknown vector [U1; U2; ...] of
+    Section 2), in vertex order; realised with triangular solves, since one
+    forward sweep is x_new = (D - L)^{-1} (b + S x_old).
+
+Pins (tests/test_oracle_smoother.py): a sweep equals a literal element-by-element
+Algorithm 1 loop on small dense matrices; the coloured sweep equals the
+lexicographic sweep of the colour-permuted matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
+
+
+class ColoredGS:
+    """Point GS over (colour, vertex, component) on a vertex-major scalar CSR matrix."""
+
+    def __init__(self, A: sp.csr_matrix, d: int, color: np.ndarray, dtype=np.float64):
+        self.d = d
+        self.dtype = dtype
+        A = A.astype(dtype).tocsr()
+        diag = A.diagonal()
+        ncol = int(color.max()) + 1 if color.size else 0
+        self.parts = []          # per colour: per component (rows, A[rows], a_ii)
+        for c in range(ncol):
+            verts = np.flatnonzero(color == c)
+            comps = []
+            for a in range(d):
+                rows = verts * d + a
+                comps.append((rows, A[rows].tocsr(), diag[rows]))
+            self.parts.append(comps)
+
+    def _update(self, part, b, x):
+        rows, Ar, aii = part
+        sigma = Ar @ x - aii * x[rows]            # sum over j != i of a_ij x_j
+        x[rows] = (b[rows] - sigma) / aii
+
+    def forward(self, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        x = x.astype(self.dtype, copy=True)
+        for comps in self.parts:
+            for part in comps:
+                self._update(part, b, x)
+        return x
+
+    def backward(self, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        x = x.astype(self.dtype, copy=True)
+        for comps in reversed(self.parts):
+            for part in reversed(comps):
+                self._update(part, b, x)
+        return x
+
+
+class LexGS:
+    """Point GS in the paper's component-major order via triangular solves."""
+
+    def __init__(self, A: sp.csr_matrix, d: int, dtype=np.float64):
+        n = A.shape[0]
+        nv = n // d
+        v = np.arange(nv)
+        self.perm = (v[None, :] * d + np.arange(d)[:, None]).ravel()   # cm position -> vm DOF
+        Acm = A[self.perm][:, self.perm].astype(dtype).tocsr()
+        self.low = sp.tril(Acm, format="csr")
+        self.up = sp.triu(Acm, format="csr")
+        self.strict_up = sp.triu(Acm, k=1, format="csr")
+        self.strict_low = sp.tril(Acm, k=-1, format="csr")
+        self.dtype = dtype
+
+    def forward(self, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        xc = x[self.perm].astype(self.dtype)
+        rhs = b[self.perm] - self.strict_up @ xc
+        xn = spsolve_triangular(self.low, rhs, lower=True)
+        out = np.empty_like(xc)
+        out[self.perm] = xn
+        return out.astype(self.dtype)
+
+    def backward(self, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        xc = x[self.perm].astype(self.dtype)
+        rhs = b[self.perm] - self.strict_low @ xc
+        xn = spsolve_triangular(self.up, rhs, lower=False)
+        out = np.empty_like(xc)
+        out[self.perm] = xn
+        return out.astype(self.dtype)

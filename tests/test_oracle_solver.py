@@ -1,0 +1,270 @@
+"""Pins of the oracle's hierarchy, Gauss-Seidel, V-cycle and PCG.
+
+  * Galerkin operators (Section 3, equations (R), (Ac)): symmetric positive
+    definite after the boundary conditions, positive diagonal, and for the
+    unconstrained operator they annihilate the interpolated rigid-body modes.
+  * Colouring: valid, and each colour is the first fit over lower neighbours.
+  * Gauss-Seidel (Section 2.1, Algorithm 1): equals a literal element-by-element
+    loop in the same unknown order; one forward sweep from zero equals a
+    lower-triangular solve; backward is the exact reverse order.
+  * V-cycle (Algorithm 3, recursive): its dense operator equals the closed-form
+    symmetric multigrid recursion, is symmetric positive definite; with the
+    fine level as the coarsest, B = A^{-1}.
+  * PCG (Algorithm 2): error within kappa * rtol of a dense solve; unpreconditioned
+    CG within n iterations; iteration counts stay flat under refinement
+    (Theorem 3: kappa(B A) bounded).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import Oracle, OracleOptions, fem, hierarchy
+from oracle.pcg import pcg
+from oracle.smoother import ColoredGS, LexGS
+from oracle.vcycle import dense_operator
+from workloads import manufactured_mesh, small2d, small3d
+
+
+def _tiny(dim, **kw):
+    if dim == 2:
+        return small2d(7, seed=1, **kw)
+    return small3d(4, seed=2, **kw)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_galerkin_spd_and_rigid_modes(dim):
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    for A in o.A:
+        Ad = A.toarray()
+        assert np.abs(Ad - Ad.T).max() <= 1e-13 * np.abs(Ad).max()
+        assert np.all(np.diag(Ad) > 0)
+        assert np.linalg.eigvalsh(Ad)[0] > 0
+    # unconstrained operator: coarse operators annihilate interpolated rigid modes
+    from oracle import tree
+    K = fem.assemble(m.coords, m.elems, 1.0, 0.3)
+    allv = np.arange(m.n_vertices)
+    lv = tree.build_levels(m.coords, m.coords, allv, 4 if dim == 2 else 8)
+    Kl = K
+    for l, P in enumerate(lv.prolong):
+        Kl = hierarchy.galerkin(Kl, P, dim)
+        X = lv.level_coords(l + 1)
+        n = X.shape[0]
+        modes = []
+        for a in range(dim):
+            u = np.zeros((n, dim)); u[:, a] = 1
+            modes.append(u.ravel())
+        for (a, b) in ([(0, 1)] if dim == 2 else [(0, 1), (0, 2), (1, 2)]):
+            u = np.zeros((n, dim)); u[:, a] = -X[:, b]; u[:, b] = X[:, a]
+            modes.append(u.ravel())
+        R = np.array(modes).T
+        assert np.abs(Kl @ R).max() < 1e-10 * abs(Kl).max() * max(1.0, np.abs(R).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coloring_valid_and_first_fit(dim):
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    for l in range(o.L):
+        S = o.S[l].tocsr()
+        col = o.colors[l]
+        assert hierarchy.coloring_is_valid(S, col)
+        for i in range(S.shape[0]):
+            nb = S.indices[S.indptr[i]:S.indptr[i + 1]]
+            lower = set(col[nb[nb < i]].tolist())
+            first = 0
+            while first in lower:
+                first += 1
+            assert col[i] == first
+
+
+def _literal_gs(A, b, x, order):
+    """Algorithm 1, one sweep, element by element, in the given unknown order."""
+    x = x.copy()
+    for i in order:
+        sigma = 0.0
+        for j in range(A.shape[0]):
+            if j != i:
+                sigma += A[i, j] * x[j]
+        x[i] = (b[i] - sigma) / A[i, i]
+    return x
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gauss_seidel_orders(dim):
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    rng = np.random.default_rng(4)
+    for l in range(min(o.L, 2)):
+        A = o.A[l]
+        Ad = A.toarray()
+        n = A.shape[0]
+        nv = n // dim
+        b = rng.normal(size=n)
+        x0 = rng.normal(size=n)
+        col = o.colors[l]
+        # coloured order: colours ascending, vertices ascending, components ascending
+        order = [v * dim + a for c in range(col.max() + 1) for v in np.flatnonzero(col == c)
+                 for a in range(dim)]
+        S = ColoredGS(A, dim, col)
+        assert np.allclose(S.forward(b, x0), _literal_gs(Ad, b, x0, order), rtol=1e-12, atol=1e-12)
+        assert np.allclose(S.backward(b, x0), _literal_gs(Ad, b, x0, order[::-1]),
+                           rtol=1e-12, atol=1e-12)
+        # the paper's component-major order
+        lex = [v * dim + a for a in range(dim) for v in range(nv)]
+        G = LexGS(A, dim)
+        assert np.allclose(G.forward(b, x0), _literal_gs(Ad, b, x0, lex), rtol=1e-12, atol=1e-12)
+        assert np.allclose(G.backward(b, x0), _literal_gs(Ad, b, x0, lex[::-1]),
+                           rtol=1e-12, atol=1e-12)
+        # one forward sweep from zero = lower-triangular solve of the permuted matrix
+        p = np.array(order)
+        Ap = Ad[np.ix_(p, p)]
+        y = np.linalg.solve(np.tril(Ap), b[p])
+        z = np.empty(n); z[p] = y
+        assert np.allclose(S.forward(b, np.zeros(n)), z, rtol=1e-12, atol=1e-12)
+
+
+def _closed_form_B(o, l, order_fn):
+    """B_l = Mbar^{-1} + (I - M^{-T} A) P B_{l+1} P^T (I - A M^{-1}), M = lower
+    triangle of A in the sweep order, Mbar^{-1} = M^{-1} + M^{-T} - M^{-T} A M^{-1}."""
+    A = o.A[l].toarray()
+    n = A.shape[0]
+    if l == o.L:
+        return np.linalg.inv(A)
+    p = order_fn(l)
+    Pm = np.zeros((n, n)); Pm[np.arange(n), p] = 1.0      # (Pm x)[k] = x[p[k]]
+    M = Pm.T @ np.tril(Pm @ A @ Pm.T) @ Pm
+    Mi = np.linalg.inv(M)
+    Mbar = Mi + Mi.T - Mi.T @ A @ Mi
+    Pb = hierarchy.block_prolongation(o.P[l], o.d).toarray()
+    Bc = _closed_form_B(o, l + 1, order_fn)
+    I = np.eye(n)
+    return Mbar + (I - Mi.T @ A) @ Pb @ Bc @ Pb.T @ (I - A @ Mi)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vcycle_closed_form_spd(dim):
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    n = o.A[0].shape[0]
+    B = dense_operator(lambda r: o.apply_precond(r), n)
+
+    def order(l):
+        col = o.colors[l]
+        return np.array([v * dim + a for c in range(col.max() + 1) for v in np.flatnonzero(col == c)
+                         for a in range(dim)])
+    Bc = _closed_form_B(o, 0, order)
+    assert np.abs(B - Bc).max() <= 1e-10 * np.abs(Bc).max()
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+    # lexicographic smoother: same identities with the component-major order
+    B2 = dense_operator(lambda r: o.apply_precond(r, smoother="lex"), n)
+
+    def order_lex(l):
+        nv = o.A[l].shape[0] // dim
+        return np.array([v * dim + a for a in range(dim) for v in range(nv)])
+    assert np.abs(B2 - _closed_form_B(o, 0, order_lex)).max() <= 1e-10 * np.abs(B2).max()
+    ev = np.linalg.eigvals(B @ o.A[0].toarray()).real
+    assert ev.min() > 0 and ev.max() <= 1.0 + 1e-10        # V(1,1) with exact coarse solve
+
+
+def test_coarsest_is_fine_level_gives_exact_inverse():
+    m = _tiny(2)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed,
+               OracleOptions(coarsest_max_dofs=10 ** 6))
+    assert o.L == 0
+    x, info = o.solve(m.rhs[0], 1e-10)
+    assert info["iterations"] == 1
+    assert info["rel_res_true"] < 1e-12
+
+
+def test_truncated_hierarchy_matches_prefix():
+    m = small2d(13, seed=2)
+    full = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    cut = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(coarsest_max_dofs=200))
+    assert cut.L < full.L
+    for l in range(cut.L + 1):
+        assert abs(cut.A[l] - full.A[l]).max() == 0
+    assert cut.A[cut.L].shape[0] <= 200 < cut.A[cut.L - 1].shape[0]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pcg_error_bound(dim):
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    A = o.A[0].toarray()
+    b = o.to_free(m.rhs[0])
+    xs = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A)
+    for rtol in (1e-4, 1e-8):
+        x, info = o.solve(m.rhs[0], rtol)
+        assert info["converged"]
+        assert info["rel_res_true"] < rtol * 1.0001
+        err = np.linalg.norm(o.to_free(x) - xs) / np.linalg.norm(xs)
+        assert err <= kappa * rtol
+
+
+def test_plain_cg_within_n_iterations():
+    m = small2d(5, seed=1)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    n = o.A[0].shape[0]
+    x, info = o.solve(m.rhs[0], 1e-10, precond="none")
+    assert info["converged"] and info["iterations"] <= n
+
+
+def test_pcg_zero_rhs_and_x0():
+    m = small2d(7, seed=2)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    x, info = o.solve(np.zeros_like(m.rhs[0]), 1e-6)
+    assert info["iterations"] == 0 and np.all(x == 0)
+    x1, i1 = o.solve(m.rhs[0], 1e-3)
+    x2, i2 = o.solve(m.rhs[0], 1e-8, x0=x1)
+    assert i2["converged"] and i2["rel_res_true"] < 1e-8
+
+
+def test_iterations_flat_under_refinement():
+    """Theorem 3: kappa(B A) is bounded, so PCG iteration counts stay flat."""
+    its = []
+    for n in (17, 33, 65, 129):
+        m = manufactured_mesh(n, seed=0)
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        _, info = o.solve(m.rhs[0], 1e-6)
+        its.append(info["iterations"])
+    assert max(its) - min(its) <= 4, its
+    assert max(its) <= 20, its
+
+
+def test_fp32_vcycle_reaches_rtol():
+    m = manufactured_mesh(33, seed=0)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    x64, i64 = o.solve(m.rhs[0], 1e-6)
+    x32, i32 = o.solve(m.rhs[0], 1e-6, precision="fp32")
+    assert i32["converged"] and i32["rel_res_true"] < 1e-6
+    assert abs(i32["iterations"] - i64["iterations"]) <= 1
+    assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) < 1e-5
+
+
+def test_jacobi_preconditioner():
+    m = manufactured_mesh(17, seed=0)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    _, info = o.solve(m.rhs[0], 1e-6, precond="jacobi")
+    assert info["converged"]
+
+
+def test_no_boundary_conditions_is_degenerate():
+    m = small2d(6, seed=1, fix="none")
+    with pytest.raises(np.linalg.LinAlgError):
+        Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+
+
+def test_tree_over_free_vertices_option():
+    m = small2d(9, seed=3)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(tree_vertices="free"))
+    x, info = o.solve(m.rhs[0], 1e-6)
+    assert info["converged"]
+
+
+def test_sparse_helpers():
+    S = sp.csr_matrix(np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]]))
+    col = hierarchy.greedy_coloring(S)
+    assert list(col) == [0, 1, 0]
