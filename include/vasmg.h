@@ -1,0 +1,196 @@
+/*
+ * vasmg.h -- C ABI of the MI355X (gfx950) V-ASMG-preconditioned CG solver for
+ * P1 finite-element linear elasticity (Li, Wu, Zhang, Liu, "Vertex-based
+ * auxiliary space multigrid method and its application to linear elasticity
+ * equations", arXiv 2505.09064).
+ *
+ * The library computes the paper's solve phase: PCG (Section 2.2, Algorithm 2)
+ * preconditioned by one V-cycle (Section 3, Algorithm 3 applied recursively)
+ * over the vertex-based auxiliary region-tree hierarchy (Section 3.1), with
+ * Gauss-Seidel smoothing (Section 2.1, Algorithm 1), bilinear/trilinear
+ * restriction and prolongation (Section 3.2), Galerkin coarse operators
+ * A_c = P^T A P (Section 3, equations (R), (Ac)) and a direct coarsest solve.
+ * The setup (assembly of Section 2, tree, levels, Galerkin products, colouring,
+ * coarsest Cholesky) runs on the host inside vasmg_setup; every step of the
+ * solve runs in hand-written HIP kernels on one GPU.
+ *
+ * Conventions for every function:
+ *  - Return value: vasmg_status, VASMG_OK (0) on success. On failure a message
+ *    is available from vasmg_last_error() (thread-local, valid until the next
+ *    call on the same thread).
+ *  - Ownership: vasmg_setup deep-copies the mesh; the caller may free it on
+ *    return. The handle owns every host and device buffer it allocates until
+ *    vasmg_free. Device pointers passed to *_device functions stay owned by the
+ *    caller and must stay valid until the call returns (all *_device calls are
+ *    synchronous with respect to the given stream on return).
+ *  - Threads: one call in flight per handle. Different handles may be used
+ *    from different threads.
+ *  - Layouts: user-facing vectors are FP64, vertex-major [n_vertices][dim]
+ *    (DOF = vertex*dim + component). Entries of a right-hand side at fixed DOFs
+ *    are ignored; solutions are 0 there. Level vectors of the debug entry
+ *    points are [n_level_vertices][dim] in the level's canonical order (fine
+ *    level: free vertices in ascending mesh index; coarse levels: vertices in
+ *    lexicographic (z, y, x) lattice-key order).
+ */
+#ifndef VASMG_H
+#define VASMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vasmg_ctx* vasmg_handle;
+
+typedef enum {
+  VASMG_OK = 0,
+  VASMG_EINVAL = 1,       /* invalid argument or mesh (see vasmg_last_error)        */
+  VASMG_ENOMEM = 2,       /* host or device allocation failed                        */
+  VASMG_EDEVICE = 3,      /* HIP runtime error, or no device / host-only handle      */
+  VASMG_ENOTCONV = 4,     /* max_iters reached; x and info hold the last iterate     */
+  VASMG_EBREAKDOWN = 5,   /* p^T A p <= 0 or not finite (e.g. NaN right-hand side)   */
+  VASMG_EDEGENERATE = 6   /* coarsest operator not positive definite (e.g. no BCs)   */
+} vasmg_status;
+
+enum { VASMG_FP64 = 0, VASMG_FP32_PRECOND = 1 };
+enum { VASMG_TREE_ALL = 0, VASMG_TREE_FREE = 1 };
+enum { VASMG_PRECOND_VASMG = 0, VASMG_PRECOND_JACOBI = 1, VASMG_PRECOND_NONE = 2 };
+
+/* Mesh: P1 triangles (dim 2, plane strain) or tetrahedra (dim 3); Section 2. */
+typedef struct {
+  int32_t dim;                 /* 2 or 3                                                 */
+  int64_t n_vertices;
+  const double* coords;        /* [n_vertices][dim], host                                */
+  int64_t n_elements;
+  const int32_t* elems;        /* [n_elements][dim+1], 0-based, positively oriented      */
+  const double* E;             /* [n_elements] Young's modulus, > 0                       */
+  const double* nu;            /* [n_elements] Poisson ratio, in (-1, 0.5)                */
+  const uint8_t* fixed;        /* [n_vertices][dim], 1 = homogeneous Dirichlet DOF. A
+                                  vertex must have all or none of its DOFs fixed.         */
+} vasmg_mesh;
+
+typedef struct {
+  int32_t leaf_capacity;       /* max vertices per leaf region (Section 3.1.1 Step 2);
+                                  0 = default (4 in 2D as in the paper, 8 in 3D)          */
+  int32_t n_pre, n_post;       /* GS sweeps before/after the coarse correction (V(1,1))  */
+  int32_t precision;           /* VASMG_FP64 | VASMG_FP32_PRECOND (V-cycle in FP32,
+                                  PCG, SpMV, dots and coarsest solve in FP64)             */
+  int32_t tree_vertices;       /* VASMG_TREE_ALL (every mesh vertex, Section 3.1.1) or
+                                  VASMG_TREE_FREE (only unconstrained vertices)           */
+  int64_t coarsest_max_dofs;   /* 0 = coarsen to the root region (Section 3.1.2); else
+                                  the first level with <= this many DOFs is the coarsest  */
+  int32_t max_iters;           /* max products A p per solve (default 10000)             */
+  int32_t preconditioner;      /* VASMG_PRECOND_VASMG (default) | _JACOBI | _NONE         */
+  int32_t profile;             /* 1 = per-phase device timings in vasmg_solve_info       */
+  int32_t host_only;           /* 1 = build the hierarchy on the host only (no device
+                                  upload; solves return VASMG_EDEVICE). Introspection.    */
+  int32_t verbose;             /* 1 = print level statistics at setup                     */
+  int32_t reserved[7];
+} vasmg_options;
+
+typedef struct {
+  int32_t iterations;          /* number of products A p when ||r||/||F|| < rtol held     */
+  int32_t converged;           /* 1 if the recurrence residual reached rtol               */
+  double rel_res;              /* recurrence ||r_k|| / ||F||                              */
+  double rel_res_true;         /* ||F - A x|| / ||F|| recomputed in FP64 at exit           */
+  double t_solve_ms;           /* device time of the whole solve (hipEvent)               */
+  double t_spmv_ms;            /* profile=1: accumulated fine SpMV time                   */
+  double t_precond_ms;         /* profile=1: accumulated V-cycle time                     */
+  double t_vector_ms;          /* profile=1: accumulated PCG vector-kernel time           */
+  double bytes_model;          /* algorithmic HBM bytes of the solve (byte model)         */
+} vasmg_solve_info;
+
+/* Fill *out with the defaults for dimension dim (2 or 3). */
+vasmg_status vasmg_default_options(int32_t dim, vasmg_options* out);
+
+/* Build the hierarchy (Section 3 setup step) on the host and upload it to the
+ * current HIP device. opt may be NULL (defaults). On failure *out = NULL.
+ * Errors: EINVAL (bad mesh/options; duplicate vertices exceed the tree's depth
+ * limit), EDEGENERATE (coarsest operator not positive definite, e.g. no fixed
+ * DOFs), ENOMEM, EDEVICE. */
+vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg_handle* out);
+
+/* Solve A x = rhs for n_rhs right-hand sides with PCG (Algorithm 2) to
+ * ||F - A x|| / ||F|| < rtol (Section 5 (3)). Host pointers:
+ * rhs, x: [n_rhs][n_vertices][dim]; x0: same or NULL (zero initial guess);
+ * info: [n_rhs] or NULL. Returns the worst status over the columns. */
+vasmg_status vasmg_solve(vasmg_handle h, const double* rhs, const double* x0, double* x,
+                         int32_t n_rhs, double rtol, vasmg_solve_info* info);
+
+/* Same with device pointers (e.g. torch tensor data_ptr()), enqueued on
+ * stream (a hipStream_t; NULL = default stream). Returns after the solve has
+ * finished on that stream. */
+vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const double* d_x0,
+                                double* d_x, int32_t n_rhs, double rtol, void* stream,
+                                vasmg_solve_info* info);
+
+/* Release every host and device resource of h. NULL-safe. */
+void vasmg_free(vasmg_handle h);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* vasmg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Introspection (hierarchy produced by the setup; host data, no device use).
+ * ------------------------------------------------------------------------- */
+
+/* Number of levels L+1 (level 0 = fine, level L = coarsest) and the DOF count
+ * of the fine level (dim * free vertices). */
+vasmg_status vasmg_hierarchy_info(vasmg_handle h, int32_t* n_levels, int64_t* n_dofs,
+                                  int32_t* dim);
+
+/* Per level: vertices, stored d x d blocks (structural pattern incl. diagonal),
+ * colours (0 on the coarsest level), entries of P_level (0 on the coarsest). */
+vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices,
+                              int64_t* n_blocks, int32_t* n_colors, int64_t* p_nnz);
+
+/* Copy level data in canonical order into caller-allocated host arrays (any
+ * pointer may be NULL to skip it):
+ *   keys   [n_vertices][dim] int64 lattice keys (coarse levels; fine: -1)
+ *   color  [n_vertices] int32 (coarsest level: 0)
+ *   rowptr [n_vertices+1] int64, cols [n_blocks] int32, vals [n_blocks][dim][dim] FP64
+ *   p_rowptr [n_vertices+1] int64, p_cols [p_nnz] int32, p_vals [p_nnz] FP64
+ *     (scalar prolongation P_level from this level's vertices to the next's). */
+vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* color,
+                                int64_t* rowptr, int32_t* cols, double* vals,
+                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals);
+
+/* Root box [m, M]^dim of the region tree (Section 3.1.1 Step 1) and its depth. */
+vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_depth);
+
+/* ---------------------------------------------------------------------------
+ * Single-step device entry points (FP64 in/out, device pointers, canonical
+ * level order). precision selects the level copy used: VASMG_FP64 or
+ * VASMG_FP32_PRECOND (the FP32 copy exists only if the handle was set up with
+ * VASMG_FP32_PRECOND). Each returns after the work finished on stream.
+ * ------------------------------------------------------------------------- */
+
+/* y = A_level x (block CSR SpMV). */
+vasmg_status vasmg_spmv_device(vasmg_handle h, int32_t level, int32_t precision,
+                               const double* d_x, double* d_y, void* stream);
+
+/* x <- one GS sweep on A_level x = b (forward = colours/vertices/components
+ * ascending, backward = exact reverse; Section 2.1 Algorithm 1 in colour order). */
+vasmg_status vasmg_gs_sweep_device(vasmg_handle h, int32_t level, int32_t precision,
+                                   int32_t backward, const double* d_b, double* d_x,
+                                   void* stream);
+
+/* b_{level+1} = P_level^T r_level (restriction, Section 3 Step 2.2). */
+vasmg_status vasmg_restrict_device(vasmg_handle h, int32_t level, int32_t precision,
+                                   const double* d_r, double* d_bc, void* stream);
+
+/* x_level += P_level e_{level+1} (prolongation, Section 3 Step 2.4). */
+vasmg_status vasmg_prolong_device(vasmg_handle h, int32_t level, int32_t precision,
+                                  const double* d_e, double* d_x, void* stream);
+
+/* z = B r: one V-cycle (Algorithm 3, recursive) on the fine level, using the
+ * handle's precision. r, z: [n_free_vertices][dim] FP64, canonical order. */
+vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, double* d_z,
+                                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VASMG_H */

@@ -1,0 +1,80 @@
+// Host-side multigrid hierarchy produced by the setup and consumed by the
+// device upload. Plain C++17; no HIP types.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vasmg {
+
+// Setup failure: status is a vasmg_status value.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+using Key = std::array<uint64_t, 3>;   // lattice key per axis (unused axes 0)
+
+// d x d block CSR, structural pattern including the diagonal block, columns
+// ascending within a row. val holds row-major d x d blocks.
+struct BlockCSR {
+  int64_t n = 0;
+  int d = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  int64_t nnzb() const { return static_cast<int64_t>(col.size()); }
+};
+
+// Scalar CSR (prolongation weights; the same weight applies to every component).
+struct ScalarCSR {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct Level {
+  int64_t n = 0;               // vertices
+  std::vector<Key> keys;       // coarse levels: lattice keys in canonical order
+  BlockCSR A;                  // operator, canonical vertex order
+  std::vector<int32_t> color;  // greedy colouring (levels below the coarsest)
+  int32_t ncolors = 0;
+  ScalarCSR P;                 // prolongation to the next level (empty on the coarsest)
+};
+
+struct Hierarchy {
+  int d = 0;
+  int64_t n_mesh_vertices = 0;
+  std::vector<int32_t> free_vertices;   // fine canonical order -> mesh vertex
+  std::vector<Level> levels;            // levels[0] = fine, levels.back() = coarsest
+  std::vector<double> chol;             // lower Cholesky factor of the coarsest, row-major
+  int64_t n_coarse_dofs = 0;
+  double box_m = 0.0, box_M = 0.0;      // root box [m, M]^d
+  int max_depth = 0;
+  int capacity = 0;
+};
+
+struct MeshView {
+  int d;
+  int64_t nv;
+  const double* coords;
+  int64_t ne;
+  const int32_t* elems;
+  const double* E;
+  const double* nu;
+  const uint8_t* fixed;
+};
+
+struct SetupParams {
+  int capacity;                // leaf capacity (> 0)
+  bool tree_free_only;         // tree over free vertices only
+  int64_t coarsest_max_dofs;   // 0 = root level
+};
+
+// Builds the whole hierarchy on the host. Throws vasmg::Error.
+void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);
+
+}  // namespace vasmg

@@ -1,0 +1,579 @@
+// HIP kernels of the V-ASMG-PCG solve phase for gfx950 (CDNA4, wave64).
+//
+// Data layout (per level, device numbering = vertices sorted by colour, then
+// canonical index):
+//   * off-diagonal blocks of A_l in CSR: rowptr[n+1], col[nnz] (ascending),
+//     split[n] = first position in the row whose column exceeds the row
+//     (so [rowptr, split) couples to earlier colours, [split, end) to later
+//     ones); values stored component-plane-major, val[(a*D+b)*nnz + k], so
+//     lanes walking consecutive blocks of a row read consecutive addresses;
+//   * diagonal blocks dense, diag[i*D*D + a*D + b];
+//   * vectors vertex-major with a padded stride DP (2 in 2D, 4 in 3D) so a
+//     neighbour's components come in one 8/16-byte (FP32) or 16/32-byte (FP64)
+//     load; pad entries are kept at zero.
+// A block row is handled by a group of G lanes (G divides 64) that stride over
+// its blocks; partial sums are combined with cross-lane shuffles inside the
+// group and lane 0 of the group finishes the row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vasmg {
+namespace dev {
+
+constexpr int kBlock = 256;
+
+template <int D>
+struct Pad {
+  static constexpr int value = (D == 3) ? 4 : 2;
+};
+
+// ---- padded vector loads/stores -------------------------------------------
+template <typename T, int D>
+struct VecIO;
+
+template <>
+struct VecIO<float, 2> {
+  static __device__ __forceinline__ void load(const float* p, float* v) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  }
+  static __device__ __forceinline__ void store(float* p, const float* v) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  }
+};
+template <>
+struct VecIO<float, 3> {
+  static __device__ __forceinline__ void load(const float* p, float* v) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z;
+  }
+  static __device__ __forceinline__ void store(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], 0.0f);
+  }
+};
+template <>
+struct VecIO<double, 2> {
+  static __device__ __forceinline__ void load(const double* p, double* v) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  }
+  static __device__ __forceinline__ void store(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+};
+template <>
+struct VecIO<double, 3> {
+  static __device__ __forceinline__ void load(const double* p, double* v) {
+    const double2 t0 = *reinterpret_cast<const double2*>(p);
+    const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = t0.x; v[1] = t0.y; v[2] = t1.x;
+  }
+  static __device__ __forceinline__ void store(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], 0.0);
+  }
+};
+
+template <typename T, int G>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// Block-wide deterministic sum of one value per thread (fixed tree order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Off-diagonal block row product over positions [kb, ke): acc += sum A_k x_col(k).
+template <typename T, int D, int G>
+__device__ __forceinline__ void row_product(int kb, int ke, int lane, const int* __restrict__ col,
+                                            const T* __restrict__ val, int64_t nnz,
+                                            const T* __restrict__ x, T* acc) {
+  constexpr int DP = Pad<D>::value;
+  for (int k = kb + lane; k < ke; k += G) {
+    const int j = col[k];
+    T xj[D];
+    VecIO<T, D>::load(x + static_cast<int64_t>(j) * DP, xj);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int b = 0; b < D; ++b) acc[a] += val[(a * D + b) * nnz + k] * xj[b];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K1: y = A x (diag + off-diagonal), optional partial dot x.y per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int G, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv(int n, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ col,
+                                                 const T* __restrict__ val, int64_t nnz,
+                                                 const T* __restrict__ diag,
+                                                 const T* __restrict__ x, T* __restrict__ y,
+                                                 double* __restrict__ partial,
+                                                 const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int lane = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  double dot = 0.0;
+  if (i < n) {
+    T acc[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = T(0);
+    row_product<T, D, G>(rowptr[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
+    if (lane == 0) {
+      T xi[D], yi[D];
+      VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+      const T* dg = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T s = acc[a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) s += dg[a * D + b] * xi[b];
+        yi[a] = s;
+        if (DOT) dot += static_cast<double>(xi[a]) * static_cast<double>(s);
+      }
+      VecIO<T, D>::store(y + static_cast<int64_t>(i) * DP, yi);
+    }
+  }
+  if (DOT) {
+    __shared__ double sh[kBlock];
+    const double s = block_sum(dot, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// r = b - A x (full row), used when no saved lower-part sums exist.
+template <typename T, int D, int G>
+__global__ __launch_bounds__(kBlock) void k_residual_full(
+    int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const T* __restrict__ val, int64_t nnz, const T* __restrict__ diag,
+    const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r,
+    const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int lane = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (i >= n) return;
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  row_product<T, D, G>(rowptr[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
+  if (lane == 0) {
+    T xi[D], bi[D], ri[D];
+    VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+    VecIO<T, D>::load(b + static_cast<int64_t>(i) * DP, bi);
+    const T* dg = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T s = bi[a] - acc[a];
+#pragma unroll
+      for (int c = 0; c < D; ++c) s -= dg[a * D + c] * xi[c];
+      ri[a] = s;
+    }
+    VecIO<T, D>::store(r + static_cast<int64_t>(i) * DP, ri);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: one colour of a point Gauss-Seidel sweep (Algorithm 1 in colour order).
+//   MODE 0: forward from a zero guess (only earlier colours are nonzero, so
+//           only [rowptr, split) is read); saves s_i = b_i - sum_{j<i} A_ij x_j
+//   MODE 1: forward from a nonzero guess; saves s_i as well
+//   MODE 2: backward (components in reverse order)
+// ---------------------------------------------------------------------------
+template <typename T, int D, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gs_color(
+    int row0, int nrows, const int* __restrict__ rowptr, const int* __restrict__ split,
+    const int* __restrict__ col, const T* __restrict__ val, int64_t nnz,
+    const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ s_save,
+    const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int lane = threadIdx.x % G;
+  const int g = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (g >= nrows) return;
+  const int i = row0 + g;
+  const int kb = rowptr[i], ks = split[i], ke = rowptr[i + 1];
+  T lo[D], up[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
+  row_product<T, D, G>(kb, ks, lane, col, val, nnz, x, lo);
+  if (MODE != 0) row_product<T, D, G>(ks, ke, lane, col, val, nnz, x, up);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = group_sum<T, G>(lo[a]);
+    if (MODE != 0) up[a] = group_sum<T, G>(up[a]);
+  }
+  if (lane != 0) return;
+  T xi[D], bi[D], rhs[D];
+  if (MODE == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) xi[a] = T(0);
+  } else {
+    VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+  }
+  VecIO<T, D>::load(b + static_cast<int64_t>(i) * DP, bi);
+  T s[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    s[a] = bi[a] - lo[a];
+    rhs[a] = s[a] - up[a];
+  }
+  if (MODE != 2 && s_save) VecIO<T, D>::store(s_save + static_cast<int64_t>(i) * DP, s);
+  const T* dg = diag + static_cast<int64_t>(i) * D * D;
+  if (MODE != 2) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T t = rhs[a];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        if (c != a) t -= dg[a * D + c] * xi[c];
+      xi[a] = t / dg[a * D + a];
+    }
+  } else {
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      T t = rhs[a];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        if (c != a) t -= dg[a * D + c] * xi[c];
+      xi[a] = t / dg[a * D + a];
+    }
+  }
+  VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, xi);
+}
+
+// K2: r = s - D x - sum_{j > i} A_ij x_j after a forward sweep that saved s.
+template <typename T, int D, int G>
+__global__ __launch_bounds__(kBlock) void k_residual_upper(
+    int n, const int* __restrict__ rowptr, const int* __restrict__ split,
+    const int* __restrict__ col, const T* __restrict__ val, int64_t nnz,
+    const T* __restrict__ diag, const T* __restrict__ s_save, const T* __restrict__ x,
+    T* __restrict__ r, const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int lane = threadIdx.x % G;
+  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (i >= n) return;
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  row_product<T, D, G>(split[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
+  if (lane == 0) {
+    T xi[D], si[D], ri[D];
+    VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+    VecIO<T, D>::load(s_save + static_cast<int64_t>(i) * DP, si);
+    const T* dg = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T s = si[a] - acc[a];
+#pragma unroll
+      for (int c = 0; c < D; ++c) s -= dg[a * D + c] * xi[c];
+      ri[a] = s;
+    }
+    VecIO<T, D>::store(r + static_cast<int64_t>(i) * DP, ri);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: restriction b_c = P^T r (gather over the CSR of P^T); K5: x += P e.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx,
+                                                     const T* __restrict__ w,
+                                                     const T* __restrict__ r, T* __restrict__ bc,
+                                                     const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int I = blockIdx.x * kBlock + threadIdx.x;
+  if (I >= nc) return;
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  for (int p = ptr[I]; p < ptr[I + 1]; ++p) {
+    T v[D];
+    VecIO<T, D>::load(r + static_cast<int64_t>(idx[p]) * DP, v);
+    const T wp = w[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wp * v[a];
+  }
+  VecIO<T, D>::store(bc + static_cast<int64_t>(I) * DP, acc);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __restrict__ ptr,
+                                                        const int* __restrict__ idx,
+                                                        const T* __restrict__ w,
+                                                        const T* __restrict__ e, T* x,
+                                                        const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nf) return;
+  T acc[D];
+  VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, acc);
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+    T v[D];
+    VecIO<T, D>::load(e + static_cast<int64_t>(idx[p]) * DP, v);
+    const T wp = w[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wp * v[a];
+  }
+  VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, acc);
+}
+
+// ---------------------------------------------------------------------------
+// K6: coarsest solve L L^T e = b in FP64 (one workgroup; n <= kCoarseMax).
+// ---------------------------------------------------------------------------
+constexpr int kCoarseMax = 4096;
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ L,
+                                                         const T* __restrict__ b, T* __restrict__ x,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  __shared__ double y[kCoarseMax];
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    y[i] = static_cast<double>(b[(i / D) * DP + (i % D)]);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {           // L y = b, column by column
+    if (threadIdx.x == 0) y[j] /= L[static_cast<int64_t>(j) * n + j];
+    __syncthreads();
+    const double yj = y[j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x)
+      y[i] -= L[static_cast<int64_t>(i) * n + j] * yj;
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {      // L^T x = y
+    if (threadIdx.x == 0) y[j] /= L[static_cast<int64_t>(j) * n + j];
+    __syncthreads();
+    const double yj = y[j];
+    for (int i = threadIdx.x; i < j; i += blockDim.x)
+      y[i] -= L[static_cast<int64_t>(j) * n + i] * yj;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[(i / D) * DP + (i % D)] = static_cast<T>(y[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K7/K8: PCG vector kernels and device-side scalars (FP64, deterministic).
+// ---------------------------------------------------------------------------
+struct Scalars {
+  double rho;       // r^T z of the current direction
+  double pq;        // p^T A p
+  double alpha, beta;
+  double res;       // ||r||
+  double normF;     // ||F||
+  double rtol;
+  double res_true;  // ||F - A x||
+  int done;         // 1 = stop (converged or breakdown)
+  int status;       // 0 running/converged, 5 breakdown
+  int first;        // next beta finalisation is the first one
+  int iters;        // products A p so far
+};
+
+enum FinMode { FIN_NORMF = 0, FIN_ALPHA = 1, FIN_RES = 2, FIN_BETA = 3, FIN_TRUE = 4 };
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partial, int np,
+                                                   Scalars* s) {
+  __shared__ double sh[1024];
+  if (MODE != FIN_NORMF && MODE != FIN_TRUE && s->done) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += partial[i];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x != 0) return;
+  if (MODE == FIN_NORMF) {
+    s->normF = sqrt(tot);
+    s->res = s->normF;
+    s->done = 0;
+    s->status = 0;
+    s->first = 1;
+    s->iters = 0;
+    s->alpha = s->beta = 0.0;
+  } else if (MODE == FIN_ALPHA) {
+    s->pq = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      s->status = 5;
+      s->done = 1;
+    } else {
+      s->alpha = s->rho / tot;
+    }
+  } else if (MODE == FIN_RES) {
+    s->res = sqrt(tot);
+    s->iters += 1;
+    if (!isfinite(s->res)) {
+      s->status = 5;
+      s->done = 1;
+    } else if (s->res / s->normF < s->rtol) {
+      s->done = 1;
+    }
+  } else if (MODE == FIN_BETA) {
+    if (s->first) {
+      s->beta = 0.0;
+      s->first = 0;
+    } else {
+      s->beta = tot / s->rho;
+    }
+    s->rho = tot;
+    if (!isfinite(tot)) {
+      s->status = 5;
+      s->done = 1;
+    }
+  } else {
+    s->res_true = sqrt(tot);
+  }
+}
+
+// partial sums of a.b over a flat vector (grid-stride, fixed grid)
+template <typename TB>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double* __restrict__ a,
+                                                const TB* __restrict__ b,
+                                                double* __restrict__ partial,
+                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    v += a[i] * static_cast<double>(b[i]);
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2; b0 = (T) r (V-cycle input)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, const Scalars* __restrict__ s,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r, T* __restrict__ b0,
+                                                      double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  if (s->done) return;
+  const double alpha = s->alpha;
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    if (b0) b0[i] = static_cast<T>(ri);
+    v += ri * ri;
+  }
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// p = z + beta p with z = (double) the V-cycle output
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const Scalars* __restrict__ s,
+                                                     const T* __restrict__ z,
+                                                     double* __restrict__ p) {
+  if (s->done) return;
+  const double beta = s->beta;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    p[i] = static_cast<double>(z[i]) + beta * p[i];
+}
+
+// point Jacobi z = r / a_ii (a context preconditioner, not the paper's)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_jacobi(int n, const double* __restrict__ diag,
+                                                   const double* __restrict__ r,
+                                                   double* __restrict__ z,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    z[static_cast<int64_t>(i) * DP + a] =
+        r[static_cast<int64_t>(i) * DP + a] / diag[static_cast<int64_t>(i) * D * D + a * D + a];
+}
+
+// flat conversions and fills
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kBlock) void k_convert(int64_t n, const TA* __restrict__ a,
+                                                    TB* __restrict__ b) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    b[i] = static_cast<TB>(a[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T* __restrict__ a, T v) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    a[i] = v;
+}
+
+// r = F - q (flat), partial ||r||^2
+__global__ __launch_bounds__(kBlock) void k_sub_norm(int64_t n, const double* __restrict__ F,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ r,
+                                                     double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const double t = F[i] - q[i];
+    if (r) r[i] = t;
+    v += t * t;
+  }
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// user layout [nv][D] <-> device numbering (padded) through a vertex map
+template <typename TS, typename TD, int D>
+__global__ __launch_bounds__(kBlock) void k_gather_user(int n, const int* __restrict__ map,
+                                                        const TS* __restrict__ src,
+                                                        TD* __restrict__ dst) {
+  constexpr int DP = Pad<D>::value;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = map[i];
+#pragma unroll
+  for (int a = 0; a < DP; ++a)
+    dst[static_cast<int64_t>(i) * DP + a] = a < D ? static_cast<TD>(src[v * D + a]) : TD(0);
+}
+
+template <typename TS, typename TD, int D>
+__global__ __launch_bounds__(kBlock) void k_scatter_user(int n, const int* __restrict__ map,
+                                                         const TS* __restrict__ src,
+                                                         TD* __restrict__ dst) {
+  constexpr int DP = Pad<D>::value;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = map[i];
+#pragma unroll
+  for (int a = 0; a < D; ++a) dst[v * D + a] = static_cast<TD>(src[static_cast<int64_t>(i) * DP + a]);
+}
+
+}  // namespace dev
+}  // namespace vasmg

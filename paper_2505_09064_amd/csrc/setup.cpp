@@ -1,0 +1,695 @@
+// Host setup of the V-ASMG hierarchy (arXiv 2505.09064, Section 3 setup step).
+//
+//  * P1 stiffness assembly in d x d blocks over the free vertices (Section 2:
+//    weak form a(u,v) = int 2 mu eps(u):eps(v) + lambda div u div v with the
+//    Lame constants of Section 2; plane strain in 2D).
+//  * Region tree (Section 3.1.1 Steps 1-3): root square/cube from one min and
+//    one max over all coordinates; a node holding more than `capacity` vertices
+//    splits into 2^d children; a vertex goes to the upper child along an axis
+//    iff its coordinate is >= the midline. Node geometry lives on an integer
+//    lattice: depth-i nodes (root depth 1) have side 2^(48-i) and key K maps to
+//    m + (M - m) * (K * 2^-47), so midlines are reproducible bit for bit.
+//  * Level 1 vertices: corners of the non-empty leaves; fine-to-level-1
+//    prolongation by bilinear/trilinear interpolation in the leaf
+//    (Section 3.1.1 Step 4, Section 3.2, weights read as 1 - |dx|/h per axis).
+//  * Coarser levels (Section 3.1.2): the deepest regions merge into their
+//    parents until only the root is left; a vertex of the next level is
+//    injected, any other vertex is interpolated in its merged parent.
+//  * Prolongation columns with no nonzero weight are dropped.
+//  * Galerkin operators A_{l+1} = P_l^T A_l P_l (Section 3, equations (R), (Ac))
+//    by a row-wise block SpGEMM over the structural pattern.
+//  * Greedy first-fit colouring of each level in canonical order (the order of
+//    the parallel Gauss-Seidel; not part of the paper).
+//  * Dense Cholesky factor of the coarsest operator (Section 3 Step 2.3).
+//
+// Must be compiled without floating-point contraction (-ffp-contract=off):
+// tree decisions and level-1 weights are compared bit for bit with an
+// independent implementation.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <utility>
+
+#include "hierarchy.hpp"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace vasmg {
+namespace {
+
+constexpr int kMaxDepth = 48;          // depth-48 nodes have side 1 key unit
+constexpr double kKeyScale = 0x1p-47;  // keys in [0, 2^47]
+
+[[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+inline uint64_t side_of(int depth) { return uint64_t(1) << (kMaxDepth - depth); }
+
+// canonical vertex order: lexicographic in (z, y, x)
+inline bool key_less(const Key& a, const Key& b) {
+  if (a[2] != b[2]) return a[2] < b[2];
+  if (a[1] != b[1]) return a[1] < b[1];
+  return a[0] < b[0];
+}
+
+struct Region {
+  int depth;
+  Key lo;
+};
+inline bool region_less(const Region& a, const Region& b) {
+  if (a.depth != b.depth) return a.depth < b.depth;
+  return key_less(a.lo, b.lo);
+}
+inline bool region_eq(const Region& a, const Region& b) {
+  return a.depth == b.depth && a.lo == b.lo;
+}
+
+// --------------------------------------------------------------------------
+// validation
+// --------------------------------------------------------------------------
+void validate(const MeshView& m) {
+  if (m.d != 2 && m.d != 3) fail(1, "dim must be 2 or 3");
+  if (m.nv <= 0 || m.ne <= 0) fail(1, "mesh has no vertices or no elements");
+  if (m.nv >= (int64_t(1) << 31) / 3) fail(1, "too many vertices for int32 indexing");
+  if (!m.coords || !m.elems || !m.E || !m.nu || !m.fixed) fail(1, "null mesh array");
+  const int d = m.d;
+  for (int64_t i = 0; i < m.nv * d; ++i)
+    if (!std::isfinite(m.coords[i])) fail(1, "non-finite vertex coordinate");
+  for (int64_t v = 0; v < m.nv; ++v) {
+    int nf = 0;
+    for (int a = 0; a < d; ++a) {
+      uint8_t f = m.fixed[v * d + a];
+      if (f > 1) fail(1, "fixed flags must be 0 or 1");
+      nf += f;
+    }
+    if (nf != 0 && nf != d)
+      fail(1, "vertex " + std::to_string(v) + " has only some components fixed (unsupported)");
+  }
+  for (int64_t e = 0; e < m.ne; ++e) {
+    if (!(m.E[e] > 0.0) || !std::isfinite(m.E[e])) fail(1, "E must be finite and > 0");
+    if (!(m.nu[e] > -1.0 && m.nu[e] < 0.5)) fail(1, "nu must lie in (-1, 0.5)");
+    for (int a = 0; a <= d; ++a) {
+      int32_t v = m.elems[e * (d + 1) + a];
+      if (v < 0 || v >= m.nv) fail(1, "element vertex index out of range");
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// P1 element stiffness
+// --------------------------------------------------------------------------
+// Gradients of the barycentric functions: with X the matrix of edge vectors
+// x_a - x_0 (rows), grad lambda_a = row a of X^{-T}; grad lambda_0 = -sum.
+// Returns the signed determinant of X.
+double p1_grads(int d, const double* xs[4], double G[4][3]) {
+  double X[3][3] = {{0}};
+  for (int a = 0; a < d; ++a)
+    for (int k = 0; k < d; ++k) X[a][k] = xs[a + 1][k] - xs[0][k];
+  double det, inv[3][3];
+  if (d == 2) {
+    det = X[0][0] * X[1][1] - X[0][1] * X[1][0];
+    inv[0][0] = X[1][1] / det;  inv[0][1] = -X[0][1] / det;
+    inv[1][0] = -X[1][0] / det; inv[1][1] = X[0][0] / det;
+  } else {
+    const double c00 = X[1][1] * X[2][2] - X[1][2] * X[2][1];
+    const double c01 = X[1][2] * X[2][0] - X[1][0] * X[2][2];
+    const double c02 = X[1][0] * X[2][1] - X[1][1] * X[2][0];
+    det = X[0][0] * c00 + X[0][1] * c01 + X[0][2] * c02;
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (X[0][2] * X[2][1] - X[0][1] * X[2][2]) / det;
+    inv[1][1] = (X[0][0] * X[2][2] - X[0][2] * X[2][0]) / det;
+    inv[2][1] = (X[0][1] * X[2][0] - X[0][0] * X[2][1]) / det;
+    inv[0][2] = (X[0][1] * X[1][2] - X[0][2] * X[1][1]) / det;
+    inv[1][2] = (X[0][2] * X[1][0] - X[0][0] * X[1][2]) / det;
+    inv[2][2] = (X[0][0] * X[1][1] - X[0][1] * X[1][0]) / det;
+  }
+  // G[a+1][k] = (X^{-T})[a][k] = inv[k][a]
+  for (int a = 0; a < d; ++a)
+    for (int k = 0; k < d; ++k) G[a + 1][k] = inv[k][a];
+  for (int k = 0; k < d; ++k) {
+    double s = 0.0;
+    for (int a = 1; a <= d; ++a) s += G[a][k];
+    G[0][k] = -s;
+  }
+  return det;
+}
+
+// --------------------------------------------------------------------------
+// fine-level assembly
+// --------------------------------------------------------------------------
+void assemble_fine(const MeshView& m, const std::vector<int32_t>& vfree, int64_t nfree,
+                   BlockCSR& A) {
+  const int d = m.d, nvpe = d + 1, dd = d * d;
+  // vertex -> elements
+  std::vector<int64_t> vptr(m.nv + 1, 0);
+  for (int64_t e = 0; e < m.ne; ++e)
+    for (int a = 0; a < nvpe; ++a) vptr[m.elems[e * nvpe + a] + 1]++;
+  for (int64_t v = 0; v < m.nv; ++v) vptr[v + 1] += vptr[v];
+  std::vector<int64_t> velem(vptr[m.nv]);
+  {
+    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+    for (int64_t e = 0; e < m.ne; ++e)
+      for (int a = 0; a < nvpe; ++a) velem[fill[m.elems[e * nvpe + a]]++] = e;
+  }
+  std::vector<int32_t> fine2mesh(nfree);
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (vfree[v] >= 0) fine2mesh[vfree[v]] = static_cast<int32_t>(v);
+
+  // structural pattern: free vertices sharing an element (incl. self)
+  A.n = nfree;
+  A.d = d;
+  A.rowptr.assign(nfree + 1, 0);
+  std::vector<std::vector<int32_t>> rows(nfree);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < nfree; ++i) {
+    const int32_t v = fine2mesh[i];
+    auto& r = rows[i];
+    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+      const int64_t e = velem[k];
+      for (int a = 0; a < nvpe; ++a) {
+        const int32_t f = vfree[m.elems[e * nvpe + a]];
+        if (f >= 0) r.push_back(f);
+      }
+    }
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+  }
+  for (int64_t i = 0; i < nfree; ++i) A.rowptr[i + 1] = A.rowptr[i] + rows[i].size();
+  A.col.resize(A.rowptr[nfree]);
+  for (int64_t i = 0; i < nfree; ++i)
+    std::copy(rows[i].begin(), rows[i].end(), A.col.begin() + A.rowptr[i]);
+  rows.clear();
+  rows.shrink_to_fit();
+  A.val.assign(A.col.size() * dd, 0.0);
+
+  // values: each row gathers the element matrices of its elements, so rows
+  // are independent and the result does not depend on the thread count
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < nfree; ++i) {
+    const int32_t v = fine2mesh[i];
+    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+      const int64_t e = velem[k];
+      const int32_t* ev = m.elems + e * nvpe;
+      const double* xs[4];
+      for (int a = 0; a < nvpe; ++a) xs[a] = m.coords + int64_t(ev[a]) * d;
+      double G[4][3];
+      const double det = p1_grads(d, xs, G);
+      const double vol = std::fabs(det) / (d == 2 ? 2.0 : 6.0);
+      const double E = m.E[e], nu = m.nu[e];
+      const double mu = E / (2.0 * (1.0 + nu));
+      const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+      int la = 0;
+      while (ev[la] != v) ++la;
+      for (int b = 0; b < nvpe; ++b) {
+        const int32_t fj = vfree[ev[b]];
+        if (fj < 0) continue;
+        const int32_t* c0 = A.col.data() + A.rowptr[i];
+        const int32_t* c1 = A.col.data() + A.rowptr[i + 1];
+        const int64_t pos = (std::lower_bound(c0, c1, fj) - A.col.data());
+        double* blk = A.val.data() + pos * dd;
+        double gab = 0.0;
+        for (int k = 0; k < d; ++k) gab += G[la][k] * G[b][k];
+        for (int ci = 0; ci < d; ++ci)
+          for (int cj = 0; cj < d; ++cj) {
+            double t = mu * G[la][cj] * G[b][ci] + lam * G[la][ci] * G[b][cj];
+            if (ci == cj) t += mu * gab;
+            blk[ci * d + cj] += vol * t;
+          }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// region tree
+// --------------------------------------------------------------------------
+struct TreeResult {
+  double m, M;
+  int max_depth;
+  std::vector<int32_t> leaf_depth;   // per tree vertex
+  std::vector<Key> leaf_lo;
+};
+
+void build_tree(const double* coords, const std::vector<int32_t>& tree_vtx, int d, int cap,
+                TreeResult& T) {
+  const int64_t N = static_cast<int64_t>(tree_vtx.size());
+  double m = coords[int64_t(tree_vtx[0]) * d], M = m;
+  for (int64_t i = 0; i < N; ++i)
+    for (int a = 0; a < d; ++a) {
+      const double x = coords[int64_t(tree_vtx[i]) * d + a];
+      m = std::min(m, x);
+      M = std::max(M, x);
+    }
+  T.m = m;
+  T.M = M;
+  T.leaf_depth.assign(N, 0);
+  T.leaf_lo.assign(N, Key{0, 0, 0});
+  T.max_depth = 1;
+  const double S = M - m;
+  auto keycoord = [&](uint64_t K) { return m + S * (static_cast<double>(K) * kKeyScale); };
+
+  std::vector<int32_t> idx(N), tmp(N);
+  std::iota(idx.begin(), idx.end(), 0);
+  struct Node {
+    int depth;
+    Key lo;
+    int64_t b, e;
+  };
+  std::vector<Node> stack;
+  stack.push_back({1, Key{0, 0, 0}, 0, N});
+  const int nch = 1 << d;
+  while (!stack.empty()) {
+    Node nd = stack.back();
+    stack.pop_back();
+    const int64_t cnt = nd.e - nd.b;
+    if (cnt <= cap) {
+      for (int64_t i = nd.b; i < nd.e; ++i) {
+        T.leaf_depth[idx[i]] = nd.depth;
+        T.leaf_lo[idx[i]] = nd.lo;
+      }
+      T.max_depth = std::max(T.max_depth, nd.depth);
+      continue;
+    }
+    if (nd.depth >= kMaxDepth)
+      fail(1, "region tree exceeds its depth limit (duplicate vertices?)");
+    const uint64_t half = side_of(nd.depth + 1);
+    double mid[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) mid[a] = keycoord(nd.lo[a] + half);
+    int64_t count[8] = {0};
+    for (int64_t i = nd.b; i < nd.e; ++i) {
+      const double* x = coords + int64_t(tree_vtx[idx[i]]) * d;
+      int c = 0;
+      for (int a = 0; a < d; ++a) c |= (x[a] >= mid[a] ? 1 : 0) << a;
+      tmp[i] = c;
+      count[c]++;
+    }
+    int64_t start[9];
+    start[0] = nd.b;
+    for (int c = 0; c < nch; ++c) start[c + 1] = start[c] + count[c];
+    {
+      std::vector<int32_t> part(cnt);
+      int64_t fillp[8];
+      for (int c = 0; c < nch; ++c) fillp[c] = start[c] - nd.b;
+      for (int64_t i = nd.b; i < nd.e; ++i) part[fillp[tmp[i]]++] = idx[i];
+      std::copy(part.begin(), part.end(), idx.begin() + nd.b);
+    }
+    for (int c = 0; c < nch; ++c) {
+      if (count[c] == 0) continue;
+      Node ch{nd.depth + 1, nd.lo, start[c], start[c + 1]};
+      for (int a = 0; a < d; ++a)
+        if ((c >> a) & 1) ch.lo[a] += half;
+      stack.push_back(ch);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// prolongation assembly helpers
+// --------------------------------------------------------------------------
+struct Triplet {
+  int64_t row;
+  Key key;
+  double w;
+};
+
+// Builds P from (row, column key, weight) triplets with nonzero weights; the
+// columns are the distinct keys in canonical order. Returns the column keys.
+std::vector<Key> triplets_to_csr(std::vector<Triplet>& tr, int64_t nrows, ScalarCSR& P) {
+  std::vector<Key> keys;
+  keys.reserve(tr.size());
+  for (const auto& t : tr) keys.push_back(t.key);
+  std::sort(keys.begin(), keys.end(), key_less);
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  P.nrows = nrows;
+  P.ncols = static_cast<int64_t>(keys.size());
+  P.rowptr.assign(nrows + 1, 0);
+  for (const auto& t : tr) P.rowptr[t.row + 1]++;
+  for (int64_t i = 0; i < nrows; ++i) P.rowptr[i + 1] += P.rowptr[i];
+  P.col.assign(tr.size(), 0);
+  P.val.assign(tr.size(), 0.0);
+  std::vector<int64_t> fill(P.rowptr.begin(), P.rowptr.end() - 1);
+  for (const auto& t : tr) {
+    const int64_t c = std::lower_bound(keys.begin(), keys.end(), t.key, key_less) - keys.begin();
+    const int64_t p = fill[t.row]++;
+    P.col[p] = static_cast<int32_t>(c);
+    P.val[p] = t.w;
+  }
+  // columns ascending within each row
+  for (int64_t i = 0; i < nrows; ++i) {
+    const int64_t b = P.rowptr[i], e = P.rowptr[i + 1];
+    std::vector<std::pair<int32_t, double>> r;
+    for (int64_t p = b; p < e; ++p) r.emplace_back(P.col[p], P.val[p]);
+    std::sort(r.begin(), r.end());
+    for (int64_t p = b; p < e; ++p) {
+      P.col[p] = r[p - b].first;
+      P.val[p] = r[p - b].second;
+    }
+  }
+  return keys;
+}
+
+std::vector<Key> region_corners(const std::vector<Region>& R, int d) {
+  std::vector<Key> out;
+  out.reserve(R.size() << d);
+  for (const auto& r : R) {
+    const uint64_t s = side_of(r.depth);
+    for (int b = 0; b < (1 << d); ++b) {
+      Key k = r.lo;
+      for (int a = 0; a < d; ++a)
+        if ((b >> a) & 1) k[a] += s;
+      out.push_back(k);
+    }
+  }
+  std::sort(out.begin(), out.end(), key_less);
+  out.erase(std::unique(out.begin(), out.end()), out.end());
+  return out;
+}
+
+// --------------------------------------------------------------------------
+// Galerkin product A_c = P^T A P (block, weights shared by the components)
+// --------------------------------------------------------------------------
+void galerkin(const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
+  const int d = A.d, dd = d * d;
+  const int64_t nc = P.ncols;
+  // P^T (rows = coarse vertices)
+  ScalarCSR PT;
+  PT.nrows = nc;
+  PT.ncols = P.nrows;
+  PT.rowptr.assign(nc + 1, 0);
+  for (int32_t c : P.col) PT.rowptr[c + 1]++;
+  for (int64_t i = 0; i < nc; ++i) PT.rowptr[i + 1] += PT.rowptr[i];
+  PT.col.resize(P.col.size());
+  PT.val.resize(P.col.size());
+  {
+    std::vector<int64_t> fill(PT.rowptr.begin(), PT.rowptr.end() - 1);
+    for (int64_t r = 0; r < P.nrows; ++r)
+      for (int64_t p = P.rowptr[r]; p < P.rowptr[r + 1]; ++p) {
+        const int64_t q = fill[P.col[p]]++;
+        PT.col[q] = static_cast<int32_t>(r);
+        PT.val[q] = P.val[p];
+      }
+  }
+  std::vector<std::vector<int32_t>> rcol(nc);
+  std::vector<std::vector<double>> rval(nc);
+#pragma omp parallel
+  {
+    std::vector<int64_t> pos(nc, -1);
+    std::vector<int32_t> cols;
+    std::vector<double> acc;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t I = 0; I < nc; ++I) {
+      cols.clear();
+      acc.clear();
+      for (int64_t p = PT.rowptr[I]; p < PT.rowptr[I + 1]; ++p) {
+        const int32_t k = PT.col[p];
+        const double wk = PT.val[p];
+        for (int64_t q = A.rowptr[k]; q < A.rowptr[k + 1]; ++q) {
+          const int32_t l = A.col[q];
+          const double* blk = A.val.data() + q * dd;
+          for (int64_t s = P.rowptr[l]; s < P.rowptr[l + 1]; ++s) {
+            const int32_t J = P.col[s];
+            const double w = wk * P.val[s];
+            int64_t at = pos[J];
+            if (at < 0) {
+              at = static_cast<int64_t>(cols.size());
+              pos[J] = at;
+              cols.push_back(J);
+              acc.resize(acc.size() + dd, 0.0);
+            }
+            double* dst = acc.data() + at * dd;
+            for (int t = 0; t < dd; ++t) dst[t] += w * blk[t];
+          }
+        }
+      }
+      std::vector<int64_t> order(cols.size());
+      std::iota(order.begin(), order.end(), 0);
+      std::sort(order.begin(), order.end(),
+                [&](int64_t a, int64_t b) { return cols[a] < cols[b]; });
+      auto& oc = rcol[I];
+      auto& ov = rval[I];
+      oc.resize(cols.size());
+      ov.resize(cols.size() * dd);
+      for (size_t t = 0; t < order.size(); ++t) {
+        oc[t] = cols[order[t]];
+        std::memcpy(ov.data() + t * dd, acc.data() + order[t] * dd, sizeof(double) * dd);
+      }
+      for (int32_t J : cols) pos[J] = -1;
+    }
+  }
+  Ac.n = nc;
+  Ac.d = d;
+  Ac.rowptr.assign(nc + 1, 0);
+  for (int64_t I = 0; I < nc; ++I) Ac.rowptr[I + 1] = Ac.rowptr[I] + rcol[I].size();
+  Ac.col.resize(Ac.rowptr[nc]);
+  Ac.val.resize(Ac.rowptr[nc] * dd);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t I = 0; I < nc; ++I) {
+    std::copy(rcol[I].begin(), rcol[I].end(), Ac.col.begin() + Ac.rowptr[I]);
+    std::copy(rval[I].begin(), rval[I].end(), Ac.val.begin() + Ac.rowptr[I] * dd);
+  }
+}
+
+// --------------------------------------------------------------------------
+// greedy first-fit colouring in index order (diagonal ignored)
+// --------------------------------------------------------------------------
+int32_t greedy_color(const BlockCSR& A, std::vector<int32_t>& color) {
+  color.assign(A.n, -1);
+  std::vector<int64_t> stamp;
+  int32_t ncol = 0;
+  for (int64_t i = 0; i < A.n; ++i) {
+    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+      const int32_t c = color[A.col[p]];
+      if (c >= 0) {
+        if (static_cast<size_t>(c) >= stamp.size()) stamp.resize(c + 1, -1);
+        stamp[c] = i;
+      }
+    }
+    int32_t c = 0;
+    while (static_cast<size_t>(c) < stamp.size() && stamp[c] == i) ++c;
+    color[i] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  return ncol;
+}
+
+// --------------------------------------------------------------------------
+// dense Cholesky (lower), FP64
+// --------------------------------------------------------------------------
+void dense_cholesky(const BlockCSR& A, std::vector<double>& L, int64_t& n) {
+  const int d = A.d, dd = d * d;
+  n = A.n * d;
+  if (n > 20000) fail(1, "coarsest level too large for a dense factorisation");
+  std::vector<double> M(n * n, 0.0);
+  double maxdiag = 0.0;
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+      const int64_t j = A.col[p];
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) M[(i * d + a) * n + j * d + b] = A.val[p * dd + a * d + b];
+    }
+  for (int64_t i = 0; i < n; ++i) maxdiag = std::max(maxdiag, M[i * n + i]);
+  for (int64_t j = 0; j < n; ++j) {
+    double s = M[j * n + j];
+    for (int64_t k = 0; k < j; ++k) s -= M[j * n + k] * M[j * n + k];
+    if (!(s > 1e-12 * maxdiag) || !std::isfinite(s))
+      fail(6, "coarsest operator is not positive definite (are any DOFs fixed?)");
+    const double ljj = std::sqrt(s);
+    M[j * n + j] = ljj;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double t = M[i * n + j];
+      for (int64_t k = 0; k < j; ++k) t -= M[i * n + k] * M[j * n + k];
+      M[i * n + j] = t / ljj;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) M[i * n + j] = 0.0;
+  L.swap(M);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
+  validate(m);
+  if (prm.capacity < 1) fail(1, "leaf_capacity must be >= 1");
+  const int d = m.d;
+  H = Hierarchy();
+  H.d = d;
+  H.n_mesh_vertices = m.nv;
+  H.capacity = prm.capacity;
+
+  // free vertices (fine canonical order = ascending mesh index)
+  std::vector<int32_t> vfree(m.nv, -1);
+  int64_t nfree = 0;
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (!m.fixed[v * d]) {
+      vfree[v] = static_cast<int32_t>(nfree++);
+      H.free_vertices.push_back(static_cast<int32_t>(v));
+    }
+  if (nfree == 0) fail(1, "every vertex is fixed: nothing to solve");
+  for (int64_t e = 0; e < m.ne; ++e) {
+    const double* xs[4];
+    for (int a = 0; a <= d; ++a) xs[a] = m.coords + int64_t(m.elems[e * (d + 1) + a]) * d;
+    double G[4][3];
+    const double det = p1_grads(d, xs, G);
+    if (!(det > 0.0) || !std::isfinite(det))
+      fail(1, "element " + std::to_string(e) + " is inverted or degenerate");
+  }
+
+  H.levels.emplace_back();
+  {
+    Level& L0 = H.levels.back();
+    L0.n = nfree;
+    assemble_fine(m, vfree, nfree, L0.A);
+  }
+
+  // ---- region tree over the tree vertices (Section 3.1.1 Steps 1-2)
+  std::vector<int32_t> tree_vtx;
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (!prm.tree_free_only || vfree[v] >= 0) tree_vtx.push_back(static_cast<int32_t>(v));
+  std::vector<int32_t> pos_in_tree(m.nv, -1);
+  for (size_t i = 0; i < tree_vtx.size(); ++i) pos_in_tree[tree_vtx[i]] = static_cast<int32_t>(i);
+  TreeResult T;
+  build_tree(m.coords, tree_vtx, d, prm.capacity, T);
+  H.box_m = T.m;
+  H.box_M = T.M;
+  H.max_depth = T.max_depth;
+  const double S = T.M - T.m;
+  auto keycoord = [&](uint64_t K) { return T.m + S * (static_cast<double>(K) * kKeyScale); };
+
+  // ---- Step 3: non-empty leaves = level-1 regions
+  std::vector<Region> R;
+  R.reserve(tree_vtx.size());
+  for (size_t i = 0; i < tree_vtx.size(); ++i) R.push_back({T.leaf_depth[i], T.leaf_lo[i]});
+  std::sort(R.begin(), R.end(), region_less);
+  R.erase(std::unique(R.begin(), R.end(), region_eq), R.end());
+
+  // ---- Step 4 + Section 3.2: P_0 by multilinear interpolation in the leaf
+  std::vector<Key> cur_keys;
+  {
+    std::vector<Triplet> tr;
+    tr.reserve(nfree << d);
+    for (int64_t i = 0; i < nfree; ++i) {
+      const int32_t v = H.free_vertices[i];
+      const int32_t t = pos_in_tree[v];
+      const int dep = T.leaf_depth[t];
+      const Key lo = T.leaf_lo[t];
+      const uint64_t s = side_of(dep);
+      double tup[3], tdn[3];
+      for (int a = 0; a < d; ++a) {
+        const double lc = keycoord(lo[a]);
+        const double hc = keycoord(lo[a] + s);
+        const double x = m.coords[int64_t(v) * d + a];
+        tup[a] = (x - lc) / (hc - lc);
+        tdn[a] = (hc - x) / (hc - lc);
+      }
+      for (int b = 0; b < (1 << d); ++b) {
+        double w = 1.0;
+        Key k = lo;
+        for (int a = 0; a < d; ++a) {
+          const bool up = (b >> a) & 1;
+          w = w * (up ? tup[a] : tdn[a]);
+          if (up) k[a] += s;
+        }
+        if (w != 0.0) tr.push_back({i, k, w});
+      }
+    }
+    cur_keys = triplets_to_csr(tr, nfree, H.levels[0].P);
+  }
+
+  // ---- Section 3.1.2: merge the deepest regions until only the root is left
+  while (true) {
+    H.levels.emplace_back();
+    Level& lv = H.levels.back();
+    lv.n = static_cast<int64_t>(cur_keys.size());
+    lv.keys = cur_keys;
+    if (R.size() == 1 && R[0].depth == 1) break;
+    int Dstar = 0;
+    for (const auto& r : R) Dstar = std::max(Dstar, r.depth);
+    const uint64_t ps = side_of(Dstar - 1);
+    std::vector<Region> Rn;
+    std::vector<std::pair<Key, Key>> corner_parent;   // corner of a merged region -> parent lo
+    for (const auto& r : R) {
+      if (r.depth != Dstar) {
+        Rn.push_back(r);
+        continue;
+      }
+      Region p{Dstar - 1, r.lo};
+      for (int a = 0; a < d; ++a) p.lo[a] = (r.lo[a] / ps) * ps;
+      Rn.push_back(p);
+      const uint64_t s = side_of(Dstar);
+      for (int b = 0; b < (1 << d); ++b) {
+        Key k = r.lo;
+        for (int a = 0; a < d; ++a)
+          if ((b >> a) & 1) k[a] += s;
+        corner_parent.emplace_back(k, p.lo);
+      }
+    }
+    std::sort(Rn.begin(), Rn.end(), region_less);
+    Rn.erase(std::unique(Rn.begin(), Rn.end(), region_eq), Rn.end());
+    std::sort(corner_parent.begin(), corner_parent.end(),
+              [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
+                return key_less(a.first, b.first);
+              });
+    const std::vector<Key> next_all = region_corners(Rn, d);
+    std::vector<Triplet> tr;
+    tr.reserve(cur_keys.size() * 2);
+    for (int64_t i = 0; i < static_cast<int64_t>(cur_keys.size()); ++i) {
+      const Key& kv = cur_keys[i];
+      if (std::binary_search(next_all.begin(), next_all.end(), kv, key_less)) {
+        tr.push_back({i, kv, 1.0});
+        continue;
+      }
+      auto it = std::lower_bound(corner_parent.begin(), corner_parent.end(), kv,
+                                 [](const std::pair<Key, Key>& a, const Key& k) {
+                                   return key_less(a.first, k);
+                                 });
+      if (it == corner_parent.end() || it->first != kv)
+        fail(1, "internal error: interpolated vertex is not a corner of a merged region");
+      const Key plo = it->second;
+      double up[3];
+      for (int a = 0; a < d; ++a) {
+        const uint64_t rel = kv[a] - plo[a];
+        up[a] = rel == ps ? 1.0 : (rel == 0 ? 0.0 : 0.5);
+      }
+      for (int b = 0; b < (1 << d); ++b) {
+        double w = 1.0;
+        Key k = plo;
+        for (int a = 0; a < d; ++a) {
+          const bool hi = (b >> a) & 1;
+          w = w * (hi ? up[a] : 1.0 - up[a]);
+          if (hi) k[a] += ps;
+        }
+        if (w != 0.0) tr.push_back({i, k, w});
+      }
+    }
+    Level& prev = H.levels[H.levels.size() - 2];
+    (void)prev;
+    cur_keys = triplets_to_csr(tr, static_cast<int64_t>(cur_keys.size()), lv.P);
+    R.swap(Rn);
+  }
+
+  // ---- Galerkin operators, with optional truncation of the hierarchy
+  size_t nlev = H.levels.size();
+  for (size_t l = 0; l + 1 < nlev; ++l) {
+    if (prm.coarsest_max_dofs > 0 && H.levels[l].n * d <= prm.coarsest_max_dofs) {
+      nlev = l + 1;
+      break;
+    }
+    galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
+  }
+  H.levels.resize(nlev);
+  Level& coarsest = H.levels.back();
+  coarsest.P = ScalarCSR();
+  coarsest.color.assign(coarsest.n, 0);
+  coarsest.ncolors = 0;
+  for (size_t l = 0; l + 1 < H.levels.size(); ++l)
+    H.levels[l].ncolors = greedy_color(H.levels[l].A, H.levels[l].color);
+  dense_cholesky(coarsest.A, H.chol, H.n_coarse_dofs);
+}
+
+}  // namespace vasmg

@@ -1,0 +1,1143 @@
+// Device hierarchy, V-cycle schedule, PCG driver and the C ABI of libvasmg.
+//
+// Solve phase of arXiv 2505.09064: PCG (Section 2.2, Algorithm 2) with one
+// V-cycle (Section 3, Algorithm 3 applied recursively) as the preconditioner.
+// All steps run in the kernels of kernels.hpp. One PCG iteration is split in
+// two captured hipGraphs:
+//   graph A: q = A p with p.q partials, alpha, x += alpha p, r -= alpha q with
+//            ||r||^2 partials (and the FP32 copy of r), convergence flag;
+//   graph B: z = B r (the V-cycle), r.z partials, beta, p = z + beta p.
+// The host reads the device flag after graph A (the only per-iteration sync).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/vasmg.h"
+#include "hierarchy.hpp"
+#include "kernels.hpp"
+
+using namespace vasmg;
+using dev::Scalars;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIP_CHECK(expr)                                                                    \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      throw vasmg::Error{VASMG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+  } while (0)
+
+inline int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+inline int grid_for(int64_t items, int per_block) {
+  return static_cast<int>(std::max<int64_t>(1, (items + per_block - 1) / per_block));
+}
+
+constexpr int kFlatGrid = 1024;   // fixed grid of the flat reduction kernels
+
+// -------------------------------------------------------------------------
+struct DevLevel {
+  int n = 0;
+  int d = 0;
+  int ncolors = 0;
+  int64_t nnz = 0;                 // off-diagonal blocks
+  int G = 8;                       // lanes per block row
+  std::vector<int> color_ptr;      // host: device rows of colour c = [ptr[c], ptr[c+1])
+  int* rowptr = nullptr;
+  int* split = nullptr;
+  int* col = nullptr;
+  int* perm = nullptr;             // device row -> canonical index
+  float* val32 = nullptr;
+  float* diag32 = nullptr;
+  double* val64 = nullptr;
+  double* diag64 = nullptr;
+  // prolongation to the next level (device numbering on both sides)
+  int nnext = 0;
+  int* p_ptr = nullptr;
+  int* p_idx = nullptr;
+  float* p_w32 = nullptr;
+  double* p_w64 = nullptr;
+  int* pt_ptr = nullptr;
+  int* pt_idx = nullptr;
+  float* pt_w32 = nullptr;
+  double* pt_w64 = nullptr;
+  // V-cycle work vectors (padded, V-cycle precision)
+  void* b = nullptr;
+  void* x = nullptr;
+  void* s = nullptr;
+  void* r = nullptr;
+  bool has32 = false, has64 = false;
+};
+
+}  // namespace
+
+struct vasmg_ctx {
+  Hierarchy H;
+  vasmg_options opt{};
+  int d = 0, DP = 0;
+  int L = 0;                        // index of the coarsest level
+  bool host_only = true;
+  bool vc32 = false;                // V-cycle precision FP32
+  int device = 0;
+  std::vector<void*> allocs;
+  std::vector<DevLevel> lev;
+  double* chol = nullptr;           // coarsest factor
+  int64_t n_coarse = 0;
+  // PCG state (FP64, padded, fine device numbering)
+  int n0 = 0;
+  int64_t n0p = 0;                  // n0 * DP
+  int* user_map = nullptr;          // fine device row -> mesh vertex
+  double *F = nullptr, *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *Z = nullptr;
+  double* partial = nullptr;
+  int n_partial = 0;
+  Scalars* sc = nullptr;
+  Scalars* h_sc = nullptr;          // pinned host copy
+  double* h_rtol = nullptr;         // pinned
+  int* zero_flag = nullptr;         // device int 0 (debug entry points)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gA = nullptr, gB = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  template <class T>
+  T* dalloc(int64_t count) {
+    void* p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(&p, sizeof(T) * static_cast<size_t>(count));
+    if (e != hipSuccess)
+      throw vasmg::Error{VASMG_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) +
+                                           " bytes failed: " + hipGetErrorString(e)};
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(static_cast<int64_t>(v.size()));
+    if (!v.empty()) HIP_CHECK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~vasmg_ctx() {
+    if (gA) (void)hipGraphExecDestroy(gA);
+    if (gB) (void)hipGraphExecDestroy(gB);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_sc) (void)hipHostFree(h_sc);
+    if (h_rtol) (void)hipHostFree(h_rtol);
+  }
+};
+
+namespace {
+
+// -------------------------------------------------------------------------
+// upload: colour-major renumbering, off-diagonal CSR + diagonal, transfers
+// -------------------------------------------------------------------------
+void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
+  const Level& hl = C.H.levels[l];
+  DevLevel& dl = C.lev[l];
+  const int d = C.d, dd = d * d, n = static_cast<int>(hl.n);
+  dl.n = n;
+  dl.d = d;
+  const bool coarsest = (l == C.L);
+  // device order: by colour, then canonical index (identity on the coarsest level)
+  std::vector<int> perm(n), inv(n);
+  if (coarsest) {
+    std::iota(perm.begin(), perm.end(), 0);
+    dl.ncolors = 1;
+    dl.color_ptr = {0, n};
+  } else {
+    dl.ncolors = hl.ncolors;
+    dl.color_ptr.assign(hl.ncolors + 1, 0);
+    for (int i = 0; i < n; ++i) dl.color_ptr[hl.color[i] + 1]++;
+    for (int c = 0; c < hl.ncolors; ++c) dl.color_ptr[c + 1] += dl.color_ptr[c];
+    std::vector<int> fill(dl.color_ptr.begin(), dl.color_ptr.end() - 1);
+    for (int i = 0; i < n; ++i) perm[fill[hl.color[i]]++] = i;
+  }
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  dl.perm = C.upload(perm);
+  if (coarsest && l > 0) return;   // a coarse coarsest level only needs its factor and vectors
+
+  // off-diagonal CSR in device numbering
+  std::vector<int> rowptr(n + 1, 0), split(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const int c = perm[i];
+    rowptr[i + 1] = rowptr[i] + static_cast<int>(hl.A.rowptr[c + 1] - hl.A.rowptr[c] - 1);
+  }
+  const int64_t nnz = rowptr[n];
+  dl.nnz = nnz;
+  std::vector<int> col(nnz);
+  std::vector<double> diag(static_cast<size_t>(n) * dd);
+  std::vector<double> val(static_cast<size_t>(nnz) * dd);
+  {
+    std::vector<std::pair<int, int64_t>> row;
+    for (int i = 0; i < n; ++i) {
+      const int c = perm[i];
+      row.clear();
+      for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
+        const int j = hl.A.col[p];
+        if (j == c) {
+          std::copy(hl.A.val.begin() + p * dd, hl.A.val.begin() + (p + 1) * dd,
+                    diag.begin() + static_cast<int64_t>(i) * dd);
+        } else {
+          row.emplace_back(inv[j], p);
+        }
+      }
+      std::sort(row.begin(), row.end());
+      int k = rowptr[i];
+      split[i] = rowptr[i + 1];
+      bool found = false;
+      for (const auto& e : row) {
+        if (!found && e.first > i) {
+          split[i] = k;
+          found = true;
+        }
+        col[k] = e.first;
+        for (int t = 0; t < dd; ++t) val[static_cast<size_t>(t) * nnz + k] = hl.A.val[e.second * dd + t];
+        ++k;
+      }
+    }
+  }
+  const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
+  dl.G = std::min(64, std::max(4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
+  dl.rowptr = C.upload(rowptr);
+  dl.split = C.upload(split);
+  dl.col = C.upload(col);
+  if (need64) {
+    dl.val64 = C.upload(val);
+    dl.diag64 = C.upload(diag);
+    dl.has64 = true;
+  }
+  if (need32) {
+    std::vector<float> v32(val.begin(), val.end()), d32(diag.begin(), diag.end());
+    dl.val32 = C.upload(v32);
+    dl.diag32 = C.upload(d32);
+    dl.has32 = true;
+  }
+
+  if (coarsest) return;   // no transfer below the coarsest level
+  // transfers P_l (rows: this level's device rows; cols: next level's device rows)
+  const ScalarCSR& P = hl.P;
+  const int nn = static_cast<int>(P.ncols);
+  dl.nnext = nn;
+  std::vector<int> pptr(n + 1, 0), pidx(P.col.size());
+  std::vector<double> pw(P.col.size());
+  for (int i = 0; i < n; ++i) pptr[i + 1] = pptr[i] + static_cast<int>(P.rowptr[perm[i] + 1] - P.rowptr[perm[i]]);
+  for (int i = 0; i < n; ++i) {
+    int k = pptr[i];
+    for (int64_t p = P.rowptr[perm[i]]; p < P.rowptr[perm[i] + 1]; ++p, ++k) {
+      pidx[k] = inv_next[P.col[p]];
+      pw[k] = P.val[p];
+    }
+  }
+  std::vector<int> tptr(nn + 1, 0), tidx(pidx.size());
+  std::vector<double> tw(pidx.size());
+  for (int j : pidx) tptr[j + 1]++;
+  for (int j = 0; j < nn; ++j) tptr[j + 1] += tptr[j];
+  {
+    std::vector<int> fill(tptr.begin(), tptr.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int k = pptr[i]; k < pptr[i + 1]; ++k) {
+        const int q = fill[pidx[k]]++;
+        tidx[q] = i;
+        tw[q] = pw[k];
+      }
+  }
+  dl.p_ptr = C.upload(pptr);
+  dl.p_idx = C.upload(pidx);
+  dl.pt_ptr = C.upload(tptr);
+  dl.pt_idx = C.upload(tidx);
+  if (need64) {
+    dl.p_w64 = C.upload(pw);
+    dl.pt_w64 = C.upload(tw);
+  }
+  if (need32) {
+    dl.p_w32 = C.upload(std::vector<float>(pw.begin(), pw.end()));
+    dl.pt_w32 = C.upload(std::vector<float>(tw.begin(), tw.end()));
+  }
+}
+
+// inverse permutation of level l's device numbering (canonical -> device)
+std::vector<int> device_inverse(const vasmg_ctx& C, int l) {
+  const Level& hl = C.H.levels[l];
+  const int n = static_cast<int>(hl.n);
+  std::vector<int> inv(n);
+  if (l == C.L) {
+    std::iota(inv.begin(), inv.end(), 0);
+    return inv;
+  }
+  std::vector<int> ptr(hl.ncolors + 1, 0);
+  for (int i = 0; i < n; ++i) ptr[hl.color[i] + 1]++;
+  for (int c = 0; c < hl.ncolors; ++c) ptr[c + 1] += ptr[c];
+  for (int i = 0; i < n; ++i) inv[i] = ptr[hl.color[i]]++;
+  return inv;
+}
+
+void upload_all(vasmg_ctx& C) {
+  const int nl = static_cast<int>(C.H.levels.size());
+  C.L = nl - 1;
+  C.lev.assign(nl, DevLevel());
+  const bool vasmg = C.opt.preconditioner == VASMG_PRECOND_VASMG;
+  const int last = vasmg ? C.L : 0;
+  for (int l = 0; l <= last; ++l) {
+    const bool fine = (l == 0);
+    const bool need64 = fine || !C.vc32;
+    const bool need32 = C.vc32 && vasmg;
+    std::vector<int> inv_next;
+    if (l < C.L) inv_next = device_inverse(C, l + 1);
+    upload_level(C, l, need32, need64, inv_next);
+  }
+  const int T = C.vc32 ? 4 : 8;
+  for (int l = 0; l <= last; ++l) {
+    DevLevel& dl = C.lev[l];
+    const int64_t len = static_cast<int64_t>(C.H.levels[l].n) * C.DP;
+    dl.b = C.dalloc<char>(len * T);
+    dl.x = C.dalloc<char>(len * T);
+    dl.s = C.dalloc<char>(len * T);
+    dl.r = C.dalloc<char>(len * T);
+    HIP_CHECK(hipMemset(dl.b, 0, len * T));
+    HIP_CHECK(hipMemset(dl.x, 0, len * T));
+    HIP_CHECK(hipMemset(dl.s, 0, len * T));
+    HIP_CHECK(hipMemset(dl.r, 0, len * T));
+  }
+  if (vasmg) {
+    C.n_coarse = C.H.n_coarse_dofs;
+    if (C.n_coarse > dev::kCoarseMax)
+      throw vasmg::Error{VASMG_EINVAL, "coarsest level has more than 4096 DOFs"};
+    C.chol = C.upload(C.H.chol);
+  }
+  // PCG vectors
+  C.n0 = static_cast<int>(C.H.levels[0].n);
+  C.n0p = static_cast<int64_t>(C.n0) * C.DP;
+  {
+    std::vector<int> um(C.n0);
+    std::vector<int> perm0(C.n0);
+    HIP_CHECK(hipMemcpy(perm0.data(), C.lev[0].perm, sizeof(int) * C.n0, hipMemcpyDeviceToHost));
+    for (int i = 0; i < C.n0; ++i) um[i] = C.H.free_vertices[perm0[i]];
+    C.user_map = C.upload(um);
+  }
+  for (double** v : {&C.F, &C.X, &C.R, &C.P, &C.Q, &C.Z}) {
+    *v = C.dalloc<double>(C.n0p);
+    HIP_CHECK(hipMemset(*v, 0, sizeof(double) * C.n0p));
+  }
+  // FP64 V-cycle: its fine right-hand side is the PCG residual itself
+  if (!C.vc32) C.lev[0].b = C.R;
+  // partial sums: the flat reduction grid, or one per workgroup of the fine SpMV
+  C.n_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / C.lev[0].G));
+  C.partial = C.dalloc<double>(C.n_partial);
+  C.sc = C.dalloc<Scalars>(1);
+  HIP_CHECK(hipMemset(C.sc, 0, sizeof(Scalars)));
+  C.zero_flag = C.dalloc<int>(1);
+  HIP_CHECK(hipMemset(C.zero_flag, 0, sizeof(int)));
+  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.h_sc), sizeof(Scalars)));
+  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.h_rtol), sizeof(double)));
+  for (auto& e : C.ev) HIP_CHECK(hipEventCreate(&e));
+  HIP_CHECK(hipStreamCreate(&C.cap_stream));
+}
+
+// -------------------------------------------------------------------------
+// kernel launch helpers
+// -------------------------------------------------------------------------
+#define DISPATCH_G(Gv, ...)                 \
+  switch (Gv) {                             \
+    case 4: { constexpr int GG = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int GG = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int GG = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int GG = 32; __VA_ARGS__; } break; \
+    default: { constexpr int GG = 64; __VA_ARGS__; } break; \
+  }
+
+template <typename T>
+struct LevelMats;
+template <>
+struct LevelMats<float> {
+  static const float* val(const DevLevel& l) { return l.val32; }
+  static const float* diag(const DevLevel& l) { return l.diag32; }
+  static const float* pw(const DevLevel& l) { return l.p_w32; }
+  static const float* ptw(const DevLevel& l) { return l.pt_w32; }
+  static bool ok(const DevLevel& l) { return l.has32; }
+};
+template <>
+struct LevelMats<double> {
+  static const double* val(const DevLevel& l) { return l.val64; }
+  static const double* diag(const DevLevel& l) { return l.diag64; }
+  static const double* pw(const DevLevel& l) { return l.p_w64; }
+  static const double* ptw(const DevLevel& l) { return l.pt_w64; }
+  static bool ok(const DevLevel& l) { return l.has64; }
+};
+
+template <typename T, int D>
+void launch_spmv(const DevLevel& lv, const T* x, T* y, double* partial, int n_partial,
+                 const int* done, hipStream_t st) {
+  const int G = lv.G;
+  DISPATCH_G(G, {
+    const int grid = grid_for(lv.n, dev::kBlock / GG);
+    if (partial && grid > n_partial)
+      throw vasmg::Error{VASMG_EINVAL, "internal: SpMV partial buffer too small"};
+    if (partial)
+      hipLaunchKernelGGL((dev::k_spmv<T, D, GG, true>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
+                         lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::diag(lv),
+                         x, y, partial, done);
+    else
+      hipLaunchKernelGGL((dev::k_spmv<T, D, GG, false>), dim3(grid), dim3(dev::kBlock), 0, st,
+                         lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz,
+                         LevelMats<T>::diag(lv), x, y, partial, done);
+  });
+}
+
+template <typename T, int D>
+int spmv_grid(const DevLevel& lv) {
+  return grid_for(lv.n, dev::kBlock / lv.G);
+}
+
+template <typename T, int D>
+void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s_save,
+                     const int* done, hipStream_t st) {
+  const int r0 = lv.color_ptr[c], nr = lv.color_ptr[c + 1] - r0;
+  if (nr <= 0) return;
+  DISPATCH_G(lv.G, {
+    const int grid = grid_for(nr, dev::kBlock / GG);
+    if (mode == 0)
+      hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 0>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
+                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
+                         LevelMats<T>::diag(lv), b, x, s_save, done);
+    else if (mode == 1)
+      hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 1>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
+                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
+                         LevelMats<T>::diag(lv), b, x, s_save, done);
+    else
+      hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 2>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
+                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
+                         LevelMats<T>::diag(lv), b, x, s_save, done);
+  });
+}
+
+template <typename T, int D>
+void launch_gs_sweep(const DevLevel& lv, bool backward, bool zero_guess, const T* b, T* x,
+                     T* s_save, const int* done, hipStream_t st) {
+  if (!backward) {
+    for (int c = 0; c < lv.ncolors; ++c)
+      launch_gs_color<T, D>(lv, c, zero_guess ? 0 : 1, b, x, s_save, done, st);
+  } else {
+    for (int c = lv.ncolors - 1; c >= 0; --c) launch_gs_color<T, D>(lv, c, 2, b, x, nullptr, done, st);
+  }
+}
+
+template <typename T, int D>
+void launch_residual_upper(const DevLevel& lv, const T* s, const T* x, T* r, const int* done,
+                           hipStream_t st) {
+  DISPATCH_G(lv.G, {
+    hipLaunchKernelGGL((dev::k_residual_upper<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
+                       dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.split, lv.col,
+                       LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::diag(lv), s, x, r, done);
+  });
+}
+
+template <typename T, int D>
+void launch_residual_full(const DevLevel& lv, const T* b, const T* x, T* r, const int* done,
+                          hipStream_t st) {
+  DISPATCH_G(lv.G, {
+    hipLaunchKernelGGL((dev::k_residual_full<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
+                       dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv),
+                       lv.nnz, LevelMats<T>::diag(lv), b, x, r, done);
+  });
+}
+
+template <typename T, int D>
+void launch_restrict(const DevLevel& lv, const T* r, T* bc, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL((dev::k_restrict<T, D>), dim3(grid_for(lv.nnext, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, lv.nnext, lv.pt_ptr, lv.pt_idx,
+                     LevelMats<T>::ptw(lv), r, bc, done);
+}
+
+template <typename T, int D>
+void launch_prolong(const DevLevel& lv, const T* e, T* x, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL((dev::k_prolong_add<T, D>), dim3(grid_for(lv.n, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv), e,
+                     x, done);
+}
+
+template <typename T>
+void launch_fill(T* a, int64_t n, T v, hipStream_t st) {
+  hipLaunchKernelGGL((dev::k_fill<T>), dim3(std::min<int64_t>(kFlatGrid, grid_for(n, dev::kBlock))),
+                     dim3(dev::kBlock), 0, st, n, a, v);
+}
+
+// One V-cycle: lev[0].b -> lev[0].x (Algorithm 3, recursive, zero initial guess).
+template <typename T, int D>
+void enqueue_vcycle(vasmg_ctx& C, const int* done, hipStream_t st) {
+  const int L = C.L;
+  const int npre = C.opt.n_pre, npost = C.opt.n_post;
+  for (int l = 0; l < L; ++l) {
+    DevLevel& lv = C.lev[l];
+    T* b = static_cast<T*>(lv.b);
+    T* x = static_cast<T*>(lv.x);
+    T* s = static_cast<T*>(lv.s);
+    T* r = static_cast<T*>(lv.r);
+    if (npre == 0) {
+      launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
+      launch_residual_full<T, D>(lv, b, x, r, done, st);
+    } else {
+      for (int k = 0; k < npre; ++k) launch_gs_sweep<T, D>(lv, false, k == 0, b, x, s, done, st);
+      launch_residual_upper<T, D>(lv, s, x, r, done, st);
+    }
+    launch_restrict<T, D>(lv, r, static_cast<T*>(C.lev[l + 1].b), done, st);
+  }
+  hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                     static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
+                     static_cast<T*>(C.lev[L].x), done);
+  for (int l = L - 1; l >= 0; --l) {
+    DevLevel& lv = C.lev[l];
+    T* b = static_cast<T*>(lv.b);
+    T* x = static_cast<T*>(lv.x);
+    launch_prolong<T, D>(lv, static_cast<const T*>(C.lev[l + 1].x), x, done, st);
+    for (int k = 0; k < npost; ++k) launch_gs_sweep<T, D>(lv, true, false, b, x, nullptr, done, st);
+  }
+}
+
+template <int D>
+void enqueue_precond(vasmg_ctx& C, const int* done, hipStream_t st) {
+  if (C.vc32)
+    enqueue_vcycle<float, D>(C, done, st);
+  else
+    enqueue_vcycle<double, D>(C, done, st);
+}
+
+// -------------------------------------------------------------------------
+// PCG graphs
+// -------------------------------------------------------------------------
+template <int D>
+void enqueue_iter_A(vasmg_ctx& C, hipStream_t st) {
+  const DevLevel& l0 = C.lev[0];
+  const int* done = &C.sc->done;
+  launch_spmv<double, D>(l0, C.P, C.Q, C.partial, C.n_partial, done, st);
+  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_ALPHA>), dim3(1), dim3(1024), 0, st, C.partial,
+                     spmv_grid<double, D>(l0), C.sc);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_update_xr<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.sc, C.P, C.Q, C.X, C.R, static_cast<float*>(C.lev[0].b), C.partial);
+  else
+    hipLaunchKernelGGL((dev::k_update_xr<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                       C.n0p, C.sc, C.P, C.Q, C.X, C.R, static_cast<double*>(nullptr), C.partial);
+  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_RES>), dim3(1), dim3(1024), 0, st, C.partial,
+                     kFlatGrid, C.sc);
+}
+
+// z = B r; rho = r.z; beta; p = z + beta p
+template <int D>
+void enqueue_iter_B(vasmg_ctx& C, hipStream_t st) {
+  const int* done = &C.sc->done;
+  const int pc = C.opt.preconditioner;
+  if (pc == VASMG_PRECOND_VASMG) {
+    enqueue_precond<D>(C, done, st);
+    if (C.vc32) {
+      hipLaunchKernelGGL((dev::k_dot<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p, C.R,
+                         static_cast<const float*>(C.lev[0].x), C.partial, done);
+      hipLaunchKernelGGL((dev::k_finalize<dev::FIN_BETA>), dim3(1), dim3(1024), 0, st, C.partial,
+                         kFlatGrid, C.sc);
+      hipLaunchKernelGGL((dev::k_update_p<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                         C.sc, static_cast<const float*>(C.lev[0].x), C.P);
+    } else {
+      hipLaunchKernelGGL((dev::k_dot<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                         C.R, static_cast<const double*>(C.lev[0].x), C.partial, done);
+      hipLaunchKernelGGL((dev::k_finalize<dev::FIN_BETA>), dim3(1), dim3(1024), 0, st, C.partial,
+                         kFlatGrid, C.sc);
+      hipLaunchKernelGGL((dev::k_update_p<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                         C.n0p, C.sc, static_cast<const double*>(C.lev[0].x), C.P);
+    }
+  } else {
+    const double* z = C.R;
+    if (pc == VASMG_PRECOND_JACOBI) {
+      hipLaunchKernelGGL((dev::k_jacobi<D>), dim3(grid_for(C.n0, dev::kBlock)), dim3(dev::kBlock), 0,
+                         st, C.n0, C.lev[0].diag64, C.R, C.Z, done);
+      z = C.Z;
+    }
+    hipLaunchKernelGGL((dev::k_dot<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p, C.R,
+                       z, C.partial, done);
+    hipLaunchKernelGGL((dev::k_finalize<dev::FIN_BETA>), dim3(1), dim3(1024), 0, st, C.partial,
+                       kFlatGrid, C.sc);
+    hipLaunchKernelGGL((dev::k_update_p<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.sc, z, C.P);
+  }
+}
+
+hipGraphExec_t capture(vasmg_ctx& C, void (*fn)(vasmg_ctx&, hipStream_t)) {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeThreadLocal));
+  fn(C, C.cap_stream);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamEndCapture(C.cap_stream, &g));
+  HIP_CHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  HIP_CHECK(hipGraphDestroy(g));
+  return ge;
+}
+
+template <int D>
+void ensure_graphs(vasmg_ctx& C) {
+  if (!C.gA) C.gA = capture(C, &enqueue_iter_A<D>);
+  if (!C.gB) C.gB = capture(C, &enqueue_iter_B<D>);
+}
+
+// -------------------------------------------------------------------------
+// one right-hand side: d_rhs/d_x user layout [nv][D] (device), d_x0 may be NULL
+// -------------------------------------------------------------------------
+template <int D>
+int solve_one(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x, double rtol,
+              hipStream_t st, vasmg_solve_info* info) {
+  ensure_graphs<D>(C);
+  const int n0 = C.n0;
+  const int64_t n0p = C.n0p;
+  const int gflat = kFlatGrid;
+  HIP_CHECK(hipEventRecord(C.ev[0], st));
+  hipLaunchKernelGGL((dev::k_gather_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n0, C.user_map, d_rhs, C.F);
+  // ||F||, then r = F - A x0 (or F), p = 0
+  hipLaunchKernelGGL((dev::k_dot<double>), dim3(gflat), dim3(dev::kBlock), 0, st, n0p, C.F, C.F,
+                     C.partial, static_cast<const int*>(nullptr));
+  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_NORMF>), dim3(1), dim3(1024), 0, st, C.partial, gflat,
+                     C.sc);
+  *C.h_rtol = rtol;
+  HIP_CHECK(hipMemcpyAsync(&C.sc->rtol, C.h_rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  if (d_x0) {
+    hipLaunchKernelGGL((dev::k_gather_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
+                       dim3(dev::kBlock), 0, st, n0, C.user_map, d_x0, C.X);
+    launch_spmv<double, D>(C.lev[0], C.X, C.Q, nullptr, 0, nullptr, st);
+    hipLaunchKernelGGL(dev::k_sub_norm, dim3(gflat), dim3(dev::kBlock), 0, st, n0p, C.F, C.Q, C.R,
+                       C.partial);
+    hipLaunchKernelGGL((dev::k_finalize<dev::FIN_TRUE>), dim3(1), dim3(1024), 0, st, C.partial, gflat,
+                       C.sc);
+  } else {
+    launch_fill<double>(C.X, n0p, 0.0, st);
+    hipLaunchKernelGGL((dev::k_convert<double, double>), dim3(gflat), dim3(dev::kBlock), 0, st, n0p,
+                       C.F, C.R);
+  }
+  launch_fill<double>(C.P, n0p, 0.0, st);
+  if (C.vc32 && C.opt.preconditioner == VASMG_PRECOND_VASMG)
+    hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(gflat), dim3(dev::kBlock), 0, st, n0p,
+                       C.R, static_cast<float*>(C.lev[0].b));
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemcpyAsync(C.h_sc, C.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const double normF = C.h_sc->normF;
+  int status = VASMG_OK;
+  double t_a = 0.0, t_b = 0.0;
+  const bool prof = C.opt.profile != 0;
+  bool done = false;
+  if (!std::isfinite(normF)) {
+    status = VASMG_EBREAKDOWN;
+    done = true;
+  } else if (normF == 0.0) {
+    launch_fill<double>(C.X, n0p, 0.0, st);
+    done = true;
+  } else if (d_x0 && C.h_sc->res_true / normF < rtol) {
+    done = true;
+  }
+  if (!done) {
+    // Algorithm 2 initialisation: z = B r, p = z, rho = r^T z
+    if (prof) HIP_CHECK(hipEventRecord(C.ev[2], st));
+    HIP_CHECK(hipGraphLaunch(C.gB, st));
+    if (prof) HIP_CHECK(hipEventRecord(C.ev[3], st));
+    int k = 0;
+    while (k < C.opt.max_iters) {
+      if (prof) {
+        HIP_CHECK(hipEventSynchronize(C.ev[3]));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, C.ev[2], C.ev[3]));
+        t_b += ms;
+        HIP_CHECK(hipEventRecord(C.ev[2], st));
+      }
+      HIP_CHECK(hipGraphLaunch(C.gA, st));
+      HIP_CHECK(hipMemcpyAsync(C.h_sc, C.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+      if (prof) HIP_CHECK(hipEventRecord(C.ev[3], st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      if (prof) {
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, C.ev[2], C.ev[3]));
+        t_a += ms;
+      }
+      ++k;
+      if (C.h_sc->done) break;
+      if (prof) HIP_CHECK(hipEventRecord(C.ev[2], st));
+      HIP_CHECK(hipGraphLaunch(C.gB, st));
+      if (prof) HIP_CHECK(hipEventRecord(C.ev[3], st));
+    }
+  }
+  // true residual, scatter
+  launch_spmv<double, D>(C.lev[0], C.X, C.Q, nullptr, 0, nullptr, st);
+  hipLaunchKernelGGL(dev::k_sub_norm, dim3(gflat), dim3(dev::kBlock), 0, st, n0p, C.F, C.Q,
+                     static_cast<double*>(nullptr), C.partial);
+  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_TRUE>), dim3(1), dim3(1024), 0, st, C.partial, gflat,
+                     C.sc);
+  launch_fill<double>(d_x, C.H.n_mesh_vertices * D, 0.0, st);
+  hipLaunchKernelGGL((dev::k_scatter_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n0, C.user_map, C.X, d_x);
+  HIP_CHECK(hipMemcpyAsync(C.h_sc, C.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipEventRecord(C.ev[1], st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipGetLastError());
+  const Scalars& s = *C.h_sc;
+  if (status == VASMG_OK) {
+    if (s.status == 5)
+      status = VASMG_EBREAKDOWN;
+    else if (normF != 0.0 && !(s.res / normF < rtol) && !(d_x0 && s.iters == 0))
+      status = VASMG_ENOTCONV;
+  }
+  if (info) {
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, C.ev[0], C.ev[1]));
+    info->iterations = s.iters;
+    info->converged = status == VASMG_OK ? 1 : 0;
+    info->rel_res = normF > 0 ? s.res / normF : 0.0;
+    info->rel_res_true = normF > 0 ? s.res_true / normF : 0.0;
+    info->t_solve_ms = ms;
+    info->t_spmv_ms = t_a;
+    info->t_precond_ms = t_b;
+    info->t_vector_ms = 0.0;
+    info->bytes_model = 0.0;
+  }
+  return status;
+}
+
+vasmg_status fail_with(const vasmg::Error& e) {
+  g_last_error = e.msg;
+  return static_cast<vasmg_status>(e.status);
+}
+
+bool device_available() {
+  int n = 0;
+  return hipGetDeviceCount(&n) == hipSuccess && n > 0;
+}
+
+template <typename T, int D>
+void debug_gather(vasmg_ctx& C, int l, const double* src, T* dst, hipStream_t st) {
+  const int n = static_cast<int>(C.H.levels[l].n);
+  hipLaunchKernelGGL((dev::k_gather_user<double, T, D>), dim3(grid_for(n, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n, C.lev[l].perm, src, dst);
+}
+template <typename T, int D>
+void debug_scatter(vasmg_ctx& C, int l, const T* src, double* dst, hipStream_t st) {
+  const int n = static_cast<int>(C.H.levels[l].n);
+  hipLaunchKernelGGL((dev::k_scatter_user<T, double, D>), dim3(grid_for(n, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n, C.lev[l].perm, src, dst);
+}
+
+void check_handle(vasmg_handle h) {
+  if (!h) throw vasmg::Error{VASMG_EINVAL, "null handle"};
+  if (h->host_only) throw vasmg::Error{VASMG_EDEVICE, "handle was set up host-only"};
+  HIP_CHECK(hipSetDevice(h->device));
+}
+
+void check_level(vasmg_handle h, int level, bool need_transfer) {
+  if (level < 0 || level > h->L) throw vasmg::Error{VASMG_EINVAL, "level out of range"};
+  if (need_transfer && level >= h->L) throw vasmg::Error{VASMG_EINVAL, "no transfer on the coarsest level"};
+  if (h->opt.preconditioner != VASMG_PRECOND_VASMG && level > 0)
+    throw vasmg::Error{VASMG_EINVAL, "hierarchy not uploaded (non-V-ASMG preconditioner)"};
+}
+
+template <typename T>
+void check_prec(vasmg_handle h, int level) {
+  if (level == h->L && level > 0) throw vasmg::Error{VASMG_EINVAL, "coarsest level has no operator on the device"};
+  if (!LevelMats<T>::ok(h->lev[level]))
+    throw vasmg::Error{VASMG_EINVAL, "requested precision not resident for this level"};
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* vasmg_last_error(void) { return g_last_error.c_str(); }
+
+vasmg_status vasmg_default_options(int32_t dim, vasmg_options* out) {
+  if (!out || (dim != 2 && dim != 3)) {
+    g_last_error = "vasmg_default_options: dim must be 2 or 3 and out non-null";
+    return VASMG_EINVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->leaf_capacity = dim == 2 ? 4 : 8;
+  out->n_pre = 1;
+  out->n_post = 1;
+  out->precision = VASMG_FP64;
+  out->tree_vertices = VASMG_TREE_ALL;
+  out->coarsest_max_dofs = 0;
+  out->max_iters = 10000;
+  out->preconditioner = VASMG_PRECOND_VASMG;
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg_handle* out) {
+  if (out) *out = nullptr;
+  try {
+    if (!mesh || !out) throw vasmg::Error{VASMG_EINVAL, "null mesh or output pointer"};
+    std::unique_ptr<vasmg_ctx> C(new vasmg_ctx());
+    if (opt) {
+      C->opt = *opt;
+    } else if (vasmg_default_options(mesh->dim, &C->opt) != VASMG_OK) {
+      throw vasmg::Error{VASMG_EINVAL, "dim must be 2 or 3"};
+    }
+    vasmg_options& o = C->opt;
+    if (o.leaf_capacity == 0) o.leaf_capacity = mesh->dim == 2 ? 4 : 8;
+    if (o.leaf_capacity < 1) throw vasmg::Error{VASMG_EINVAL, "leaf_capacity must be >= 1"};
+    if (o.n_pre < 0 || o.n_post < 0 || o.n_pre > 16 || o.n_post > 16)
+      throw vasmg::Error{VASMG_EINVAL, "n_pre/n_post must be in [0, 16]"};
+    if (o.precision != VASMG_FP64 && o.precision != VASMG_FP32_PRECOND)
+      throw vasmg::Error{VASMG_EINVAL, "unknown precision"};
+    if (o.tree_vertices != VASMG_TREE_ALL && o.tree_vertices != VASMG_TREE_FREE)
+      throw vasmg::Error{VASMG_EINVAL, "unknown tree_vertices"};
+    if (o.preconditioner < 0 || o.preconditioner > 2)
+      throw vasmg::Error{VASMG_EINVAL, "unknown preconditioner"};
+    if (o.max_iters <= 0) o.max_iters = 10000;
+    if (o.coarsest_max_dofs < 0) throw vasmg::Error{VASMG_EINVAL, "coarsest_max_dofs < 0"};
+    MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
+                mesh->E, mesh->nu, mesh->fixed};
+    SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
+    build_hierarchy(mv, prm, C->H);
+    C->d = mesh->dim;
+    C->DP = mesh->dim == 3 ? 4 : 2;
+    C->L = static_cast<int>(C->H.levels.size()) - 1;
+    C->vc32 = o.precision == VASMG_FP32_PRECOND;
+    C->host_only = o.host_only != 0;
+    if (o.verbose) {
+      for (size_t l = 0; l < C->H.levels.size(); ++l) {
+        const Level& lv = C->H.levels[l];
+        std::fprintf(stderr, "[vasmg] level %zu: %lld vertices, %lld blocks, %d colours\n", l,
+                     static_cast<long long>(lv.n), static_cast<long long>(lv.A.nnzb()), lv.ncolors);
+      }
+    }
+    if (!C->host_only) {
+      if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
+      HIP_CHECK(hipGetDevice(&C->device));
+      upload_all(*C);
+    }
+    *out = C.release();
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return VASMG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return VASMG_EINVAL;
+  }
+}
+
+void vasmg_free(vasmg_handle h) {
+  if (!h) return;
+  if (!h->host_only) (void)hipSetDevice(h->device);
+  delete h;
+}
+
+vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const double* d_x0,
+                                double* d_x, int32_t n_rhs, double rtol, void* stream,
+                                vasmg_solve_info* info) {
+  try {
+    check_handle(h);
+    if (!d_rhs || !d_x || n_rhs < 1) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/n_rhs"};
+    if (!(rtol > 0.0)) throw vasmg::Error{VASMG_EINVAL, "rtol must be > 0"};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t stride = h->H.n_mesh_vertices * h->d;
+    int worst = VASMG_OK;
+    for (int c = 0; c < n_rhs; ++c) {
+      const int s = h->d == 2 ? solve_one<2>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
+                                              d_x + c * stride, rtol, st, info ? info + c : nullptr)
+                              : solve_one<3>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
+                                              d_x + c * stride, rtol, st, info ? info + c : nullptr);
+      if (s != VASMG_OK && worst == VASMG_OK) worst = s;
+    }
+    if (worst == VASMG_ENOTCONV) g_last_error = "PCG did not reach rtol within max_iters";
+    if (worst == VASMG_EBREAKDOWN) g_last_error = "PCG breakdown (p^T A p <= 0 or not finite)";
+    return static_cast<vasmg_status>(worst);
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_solve(vasmg_handle h, const double* rhs, const double* x0, double* x,
+                         int32_t n_rhs, double rtol, vasmg_solve_info* info) {
+  double *drhs = nullptr, *dx0 = nullptr, *dx = nullptr;
+  try {
+    check_handle(h);
+    if (!rhs || !x || n_rhs < 1) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/n_rhs"};
+    const size_t bytes = sizeof(double) * h->H.n_mesh_vertices * h->d * n_rhs;
+    HIP_CHECK(hipMalloc(&drhs, bytes));
+    HIP_CHECK(hipMalloc(&dx, bytes));
+    HIP_CHECK(hipMemcpy(drhs, rhs, bytes, hipMemcpyHostToDevice));
+    if (x0) {
+      HIP_CHECK(hipMalloc(&dx0, bytes));
+      HIP_CHECK(hipMemcpy(dx0, x0, bytes, hipMemcpyHostToDevice));
+    }
+    const vasmg_status s = vasmg_solve_device(h, drhs, dx0, dx, n_rhs, rtol, nullptr, info);
+    const std::string msg = g_last_error;
+    HIP_CHECK(hipMemcpy(x, dx, bytes, hipMemcpyDeviceToHost));
+    (void)hipFree(drhs);
+    (void)hipFree(dx);
+    if (dx0) (void)hipFree(dx0);
+    g_last_error = msg;
+    return s;
+  } catch (const vasmg::Error& e) {
+    if (drhs) (void)hipFree(drhs);
+    if (dx) (void)hipFree(dx);
+    if (dx0) (void)hipFree(dx0);
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_hierarchy_info(vasmg_handle h, int32_t* n_levels, int64_t* n_dofs, int32_t* dim) {
+  if (!h) {
+    g_last_error = "null handle";
+    return VASMG_EINVAL;
+  }
+  if (n_levels) *n_levels = static_cast<int32_t>(h->H.levels.size());
+  if (n_dofs) *n_dofs = h->H.levels[0].n * h->d;
+  if (dim) *dim = h->d;
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices, int64_t* n_blocks,
+                              int32_t* n_colors, int64_t* p_nnz) {
+  if (!h || level < 0 || level >= static_cast<int32_t>(h->H.levels.size())) {
+    g_last_error = "null handle or level out of range";
+    return VASMG_EINVAL;
+  }
+  const Level& lv = h->H.levels[level];
+  if (n_vertices) *n_vertices = lv.n;
+  if (n_blocks) *n_blocks = lv.A.nnzb();
+  if (n_colors) *n_colors = lv.ncolors;
+  if (p_nnz) *p_nnz = static_cast<int64_t>(lv.P.col.size());
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* color,
+                                int64_t* rowptr, int32_t* cols, double* vals, int64_t* p_rowptr,
+                                int32_t* p_cols, double* p_vals) {
+  if (!h || level < 0 || level >= static_cast<int32_t>(h->H.levels.size())) {
+    g_last_error = "null handle or level out of range";
+    return VASMG_EINVAL;
+  }
+  const Level& lv = h->H.levels[level];
+  const int d = h->d;
+  if (keys) {
+    for (int64_t i = 0; i < lv.n; ++i)
+      for (int a = 0; a < d; ++a)
+        keys[i * d + a] = lv.keys.empty() ? -1 : static_cast<int64_t>(lv.keys[i][a]);
+  }
+  if (color) {
+    for (int64_t i = 0; i < lv.n; ++i) color[i] = lv.color.empty() ? 0 : lv.color[i];
+  }
+  if (rowptr) std::copy(lv.A.rowptr.begin(), lv.A.rowptr.end(), rowptr);
+  if (cols) std::copy(lv.A.col.begin(), lv.A.col.end(), cols);
+  if (vals) std::copy(lv.A.val.begin(), lv.A.val.end(), vals);
+  if (p_rowptr) {
+    if (lv.P.rowptr.empty())
+      std::fill(p_rowptr, p_rowptr + lv.n + 1, 0);
+    else
+      std::copy(lv.P.rowptr.begin(), lv.P.rowptr.end(), p_rowptr);
+  }
+  if (p_cols) std::copy(lv.P.col.begin(), lv.P.col.end(), p_cols);
+  if (p_vals) std::copy(lv.P.val.begin(), lv.P.val.end(), p_vals);
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_depth) {
+  if (!h) {
+    g_last_error = "null handle";
+    return VASMG_EINVAL;
+  }
+  if (m) *m = h->H.box_m;
+  if (M) *M = h->H.box_M;
+  if (max_depth) *max_depth = h->H.max_depth;
+  return VASMG_OK;
+}
+
+#define DEBUG_PRELUDE(NEED_TRANSFER)          \
+  check_handle(h);                            \
+  check_level(h, level, NEED_TRANSFER);       \
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+vasmg_status vasmg_spmv_device(vasmg_handle h, int32_t level, int32_t precision, const double* d_x,
+                               double* d_y, void* stream) {
+  try {
+    DEBUG_PRELUDE(false);
+    DevLevel& lv = h->lev[level];
+    auto run = [&](auto tag, auto dtag) {
+      using T = decltype(tag);
+      constexpr int D = decltype(dtag)::value;
+      check_prec<T>(h, level);
+      T* xin = static_cast<T*>(lv.x);
+      T* yout = static_cast<T*>(lv.r);
+      if (precision == VASMG_FP64 && h->vc32) {  // FP64 copy on the fine level of a mixed handle
+        xin = reinterpret_cast<T*>(h->Z);
+        yout = reinterpret_cast<T*>(h->Q);
+      }
+      debug_gather<T, D>(*h, level, d_x, xin, st);
+      launch_spmv<T, D>(lv, xin, yout, nullptr, 0, nullptr, st);
+      debug_scatter<T, D>(*h, level, yout, d_y, st);
+    };
+    if (precision == VASMG_FP64) {
+      if (h->d == 2) run(double(), std::integral_constant<int, 2>());
+      else run(double(), std::integral_constant<int, 3>());
+    } else {
+      if (h->d == 2) run(float(), std::integral_constant<int, 2>());
+      else run(float(), std::integral_constant<int, 3>());
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_gs_sweep_device(vasmg_handle h, int32_t level, int32_t precision, int32_t backward,
+                                   const double* d_b, double* d_x, void* stream) {
+  try {
+    DEBUG_PRELUDE(false);
+    if (level == h->L) throw vasmg::Error{VASMG_EINVAL, "no smoother on the coarsest level"};
+    DevLevel& lv = h->lev[level];
+    if ((precision == VASMG_FP64) == h->vc32)
+      throw vasmg::Error{VASMG_EINVAL, "GS precision must match the handle's V-cycle precision"};
+    auto run = [&](auto tag, auto dtag) {
+      using T = decltype(tag);
+      constexpr int D = decltype(dtag)::value;
+      check_prec<T>(h, level);
+      T* b = static_cast<T*>(lv.b);
+      T* x = static_cast<T*>(lv.x);
+      debug_gather<T, D>(*h, level, d_b, b, st);
+      debug_gather<T, D>(*h, level, d_x, x, st);
+      launch_gs_sweep<T, D>(lv, backward != 0, false, b, x, static_cast<T*>(lv.s), nullptr, st);
+      debug_scatter<T, D>(*h, level, x, d_x, st);
+    };
+    if (precision == VASMG_FP64) {
+      if (h->d == 2) run(double(), std::integral_constant<int, 2>());
+      else run(double(), std::integral_constant<int, 3>());
+    } else {
+      if (h->d == 2) run(float(), std::integral_constant<int, 2>());
+      else run(float(), std::integral_constant<int, 3>());
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_restrict_device(vasmg_handle h, int32_t level, int32_t precision, const double* d_r,
+                                   double* d_bc, void* stream) {
+  try {
+    DEBUG_PRELUDE(true);
+    DevLevel& lv = h->lev[level];
+    DevLevel& nx = h->lev[level + 1];
+    if ((precision == VASMG_FP64) == h->vc32)
+      throw vasmg::Error{VASMG_EINVAL, "transfer precision must match the handle's V-cycle precision"};
+    auto run = [&](auto tag, auto dtag) {
+      using T = decltype(tag);
+      constexpr int D = decltype(dtag)::value;
+      T* r = static_cast<T*>(lv.r);
+      T* bc = static_cast<T*>(nx.b);
+      debug_gather<T, D>(*h, level, d_r, r, st);
+      launch_restrict<T, D>(lv, r, bc, nullptr, st);
+      debug_scatter<T, D>(*h, level + 1, bc, d_bc, st);
+    };
+    if (precision == VASMG_FP64) {
+      if (h->d == 2) run(double(), std::integral_constant<int, 2>());
+      else run(double(), std::integral_constant<int, 3>());
+    } else {
+      if (h->d == 2) run(float(), std::integral_constant<int, 2>());
+      else run(float(), std::integral_constant<int, 3>());
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_prolong_device(vasmg_handle h, int32_t level, int32_t precision, const double* d_e,
+                                  double* d_x, void* stream) {
+  try {
+    DEBUG_PRELUDE(true);
+    DevLevel& lv = h->lev[level];
+    DevLevel& nx = h->lev[level + 1];
+    if ((precision == VASMG_FP64) == h->vc32)
+      throw vasmg::Error{VASMG_EINVAL, "transfer precision must match the handle's V-cycle precision"};
+    auto run = [&](auto tag, auto dtag) {
+      using T = decltype(tag);
+      constexpr int D = decltype(dtag)::value;
+      T* e = static_cast<T*>(nx.x);
+      T* x = static_cast<T*>(lv.x);
+      debug_gather<T, D>(*h, level + 1, d_e, e, st);
+      debug_gather<T, D>(*h, level, d_x, x, st);
+      launch_prolong<T, D>(lv, e, x, nullptr, st);
+      debug_scatter<T, D>(*h, level, x, d_x, st);
+    };
+    if (precision == VASMG_FP64) {
+      if (h->d == 2) run(double(), std::integral_constant<int, 2>());
+      else run(double(), std::integral_constant<int, 3>());
+    } else {
+      if (h->d == 2) run(float(), std::integral_constant<int, 2>());
+      else run(float(), std::integral_constant<int, 3>());
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, double* d_z, void* stream) {
+  try {
+    check_handle(h);
+    if (h->opt.preconditioner != VASMG_PRECOND_VASMG)
+      throw vasmg::Error{VASMG_EINVAL, "handle was not set up with the V-ASMG preconditioner"};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto run = [&](auto tag, auto dtag) {
+      using T = decltype(tag);
+      constexpr int D = decltype(dtag)::value;
+      T* b = static_cast<T*>(h->lev[0].b);
+      T* x = static_cast<T*>(h->lev[0].x);
+      debug_gather<T, D>(*h, 0, d_r, b, st);
+      if (h->L == 0) {
+        hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                           static_cast<int>(h->n_coarse), h->chol, b, x, h->zero_flag);
+      } else {
+        enqueue_vcycle<T, D>(*h, h->zero_flag, st);
+      }
+      debug_scatter<T, D>(*h, 0, x, d_z, st);
+    };
+    if (h->vc32) {
+      if (h->d == 2) run(float(), std::integral_constant<int, 2>());
+      else run(float(), std::integral_constant<int, 3>());
+    } else {
+      if (h->d == 2) run(double(), std::integral_constant<int, 2>());
+      else run(double(), std::integral_constant<int, 3>());
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+}  // extern "C"

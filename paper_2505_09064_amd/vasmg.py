@@ -1,0 +1,271 @@
+"""ctypes binding of libvasmg (the C ABI declared in include/vasmg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels. Device vectors are torch tensors on a HIP device (torch is used for
+device memory and streams only). The library must have been built
+(``python -m paper_2505_09064_amd.build``); importing this module fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvasmg.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EDEGENERATE = range(7)
+FP64, FP32_PRECOND = 0, 1
+TREE_ALL, TREE_FREE = 0, 1
+PRECOND_VASMG, PRECOND_JACOBI, PRECOND_NONE = 0, 1, 2
+
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV",
+                5: "EBREAKDOWN", 6: "EDEGENERATE"}
+
+EXPORTED = [
+    "vasmg_default_options", "vasmg_setup", "vasmg_solve", "vasmg_solve_device", "vasmg_free",
+    "vasmg_last_error", "vasmg_hierarchy_info", "vasmg_level_info", "vasmg_export_level",
+    "vasmg_tree_info", "vasmg_spmv_device", "vasmg_gs_sweep_device", "vasmg_restrict_device",
+    "vasmg_prolong_device", "vasmg_apply_precond_device",
+]
+
+
+class VasmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int64), ("coords", C.c_void_p),
+                ("n_elements", C.c_int64), ("elems", C.c_void_p), ("E", C.c_void_p),
+                ("nu", C.c_void_p), ("fixed", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("leaf_capacity", C.c_int32), ("n_pre", C.c_int32), ("n_post", C.c_int32),
+                ("precision", C.c_int32), ("tree_vertices", C.c_int32),
+                ("coarsest_max_dofs", C.c_int64), ("max_iters", C.c_int32),
+                ("preconditioner", C.c_int32), ("profile", C.c_int32),
+                ("host_only", C.c_int32), ("verbose", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
+                ("rel_res_true", C.c_double), ("t_solve_ms", C.c_double),
+                ("t_spmv_ms", C.c_double), ("t_precond_ms", C.c_double),
+                ("t_vector_ms", C.c_double), ("bytes_model", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libvasmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with "
+                              "`python -m paper_2505_09064_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "vasmg_default_options": (i32, [i32, C.POINTER(Options)]),
+            "vasmg_setup": (i32, [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(vp)]),
+            "vasmg_solve": (i32, [vp, vp, vp, vp, i32, dbl, C.POINTER(SolveInfo)]),
+            "vasmg_solve_device": (i32, [vp, vp, vp, vp, i32, dbl, vp, C.POINTER(SolveInfo)]),
+            "vasmg_free": (None, [vp]),
+            "vasmg_last_error": (C.c_char_p, []),
+            "vasmg_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
+            "vasmg_level_info": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
+                                       C.POINTER(i64)]),
+            "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "vasmg_tree_info": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
+            "vasmg_spmv_device": (i32, [vp, i32, i32, vp, vp, vp]),
+            "vasmg_gs_sweep_device": (i32, [vp, i32, i32, i32, vp, vp, vp]),
+            "vasmg_restrict_device": (i32, [vp, i32, i32, vp, vp, vp]),
+            "vasmg_prolong_device": (i32, [vp, i32, i32, vp, vp, vp]),
+            "vasmg_apply_precond_device": (i32, [vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().vasmg_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise VasmgError(status, last_error())
+
+
+def default_options(dim: int) -> Options:
+    o = Options()
+    _check(lib().vasmg_default_options(dim, C.byref(o)))
+    return o
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Solver:
+    """Owns one vasmg handle (vasmg_setup ... vasmg_free)."""
+
+    def __init__(self, coords, elems, E, nu, fixed, options: Options | None = None, **kw):
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        elems = np.ascontiguousarray(elems, dtype=np.int32)
+        nv, dim = coords.shape
+        ne = elems.shape[0]
+        self._arrays = (
+            coords, elems,
+            np.ascontiguousarray(np.broadcast_to(np.asarray(E, dtype=np.float64), (ne,))),
+            np.ascontiguousarray(np.broadcast_to(np.asarray(nu, dtype=np.float64), (ne,))),
+            np.ascontiguousarray(fixed, dtype=np.uint8).reshape(nv, dim),
+        )
+        c, el, Ea, nua, fx = self._arrays
+        m = Mesh(dim, nv, _ptr(c), ne, _ptr(el), _ptr(Ea), _ptr(nua), _ptr(fx))
+        opt = options if options is not None else default_options(dim)
+        for k, v in kw.items():
+            setattr(opt, k, v)
+        self.options = opt
+        self.dim = dim
+        self.n_vertices = nv
+        h = C.c_void_p()
+        _check(lib().vasmg_setup(C.byref(m), C.byref(opt), C.byref(h)))
+        self._h = h
+        self._arrays = None          # the library deep-copied the mesh
+
+    @classmethod
+    def from_mesh(cls, mesh, options: Options | None = None, **kw):
+        return cls(mesh.coords, mesh.elems, mesh.E, mesh.nu, mesh.fixed, options, **kw)
+
+    # -- lifetime -------------------------------------------------------
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vasmg_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.free()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- solves -----------------------------------------------------------
+    def solve(self, rhs, rtol: float = 1e-6, x0=None, check: bool = True):
+        """Host arrays [n_vertices, dim] or [n_rhs, n_vertices, dim]."""
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        single = rhs.ndim == 2
+        R = rhs[None] if single else rhs
+        n_rhs = R.shape[0]
+        x = np.zeros_like(R)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(R.shape)
+        infos = (SolveInfo * n_rhs)()
+        st = lib().vasmg_solve(self._h, _ptr(R), _ptr(x0a), _ptr(x), n_rhs, rtol, infos)
+        if check and st not in (OK, ENOTCONV):
+            _check(st)
+        out = [i.as_dict() for i in infos]
+        for o in out:
+            o["status"] = st
+        return (x[0], out[0]) if single else (x, out)
+
+    def solve_device(self, d_rhs, d_x, rtol: float = 1e-6, d_x0=None, stream=None,
+                     check: bool = True):
+        """torch FP64 device tensors [n_rhs?, n_vertices, dim] (contiguous)."""
+        n_rhs = 1 if d_rhs.dim() == 2 else d_rhs.shape[0]
+        infos = (SolveInfo * n_rhs)()
+        st = lib().vasmg_solve_device(self._h, _ptr(d_rhs), _ptr(d_x0), _ptr(d_x), n_rhs, rtol,
+                                      _stream_ptr(stream), infos)
+        if check and st not in (OK, ENOTCONV):
+            _check(st)
+        out = [i.as_dict() for i in infos]
+        for o in out:
+            o["status"] = st
+        return out[0] if n_rhs == 1 else out
+
+    # -- introspection ------------------------------------------------------
+    def hierarchy_info(self):
+        nl, nd, dim = C.c_int32(), C.c_int64(), C.c_int32()
+        _check(lib().vasmg_hierarchy_info(self._h, C.byref(nl), C.byref(nd), C.byref(dim)))
+        return nl.value, nd.value, dim.value
+
+    def level_info(self, level: int):
+        nv, nb, nc, pn = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        _check(lib().vasmg_level_info(self._h, level, C.byref(nv), C.byref(nb), C.byref(nc),
+                                      C.byref(pn)))
+        return dict(n_vertices=nv.value, n_blocks=nb.value, n_colors=nc.value, p_nnz=pn.value)
+
+    def export_level(self, level: int):
+        info = self.level_info(level)
+        d = self.dim
+        n, nb, pn = info["n_vertices"], info["n_blocks"], info["p_nnz"]
+        keys = np.empty((n, d), dtype=np.int64)
+        color = np.empty(n, dtype=np.int32)
+        rowptr = np.empty(n + 1, dtype=np.int64)
+        cols = np.empty(nb, dtype=np.int32)
+        vals = np.empty((nb, d, d), dtype=np.float64)
+        prow = np.empty(n + 1, dtype=np.int64)
+        pcol = np.empty(pn, dtype=np.int32)
+        pval = np.empty(pn, dtype=np.float64)
+        _check(lib().vasmg_export_level(self._h, level, _ptr(keys), _ptr(color), _ptr(rowptr),
+                                        _ptr(cols), _ptr(vals), _ptr(prow), _ptr(pcol), _ptr(pval)))
+        return dict(keys=keys, color=color, rowptr=rowptr, cols=cols, vals=vals,
+                    p_rowptr=prow, p_cols=pcol, p_vals=pval, **info)
+
+    def tree_info(self):
+        m, M, dep = C.c_double(), C.c_double(), C.c_int32()
+        _check(lib().vasmg_tree_info(self._h, C.byref(m), C.byref(M), C.byref(dep)))
+        return m.value, M.value, dep.value
+
+    # -- single-step device entry points -----------------------------------
+    def spmv_device(self, level, precision, d_x, d_y, stream=None):
+        _check(lib().vasmg_spmv_device(self._h, level, precision, _ptr(d_x), _ptr(d_y),
+                                       _stream_ptr(stream)))
+
+    def gs_sweep_device(self, level, precision, backward, d_b, d_x, stream=None):
+        _check(lib().vasmg_gs_sweep_device(self._h, level, precision, int(backward), _ptr(d_b),
+                                           _ptr(d_x), _stream_ptr(stream)))
+
+    def restrict_device(self, level, precision, d_r, d_bc, stream=None):
+        _check(lib().vasmg_restrict_device(self._h, level, precision, _ptr(d_r), _ptr(d_bc),
+                                           _stream_ptr(stream)))
+
+    def prolong_device(self, level, precision, d_e, d_x, stream=None):
+        _check(lib().vasmg_prolong_device(self._h, level, precision, _ptr(d_e), _ptr(d_x),
+                                          _stream_ptr(stream)))
+
+    def apply_precond_device(self, d_r, d_z, stream=None):
+        _check(lib().vasmg_apply_precond_device(self._h, _ptr(d_r), _ptr(d_z),
+                                                _stream_ptr(stream)))

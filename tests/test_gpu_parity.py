@@ -1,0 +1,266 @@
+"""GPU parity of libvasmg against the CPU oracle, through the C ABI.
+
+Kernel parity (single-step device entry points, canonical level order) and
+end-to-end PCG parity on meshes that span several tiles with ragged tails. The
+bar: FP64 mode within 1e-8 relative solution error and +-1 iteration of the
+oracle in the same (coloured) Gauss-Seidel order; per-kernel FP64 results
+within a few ulps of accumulated rounding; FP32 V-cycle results within FP32
+rounding; mixed-precision solves reach rtol in the FP64 true residual.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleOptions
+from oracle.hierarchy import block_prolongation
+from oracle.smoother import ColoredGS
+from workloads import cfg1, manufactured_mesh, small2d, small3d
+
+torch = pytest.importorskip("torch")
+from paper_2505_09064_amd import vasmg as V  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+MESHES = {
+    "cfg1_2d": lambda: cfg1(),
+    "small3d_n9": lambda: small3d(9, seed=5),
+    "graded2d_n33_nu049": lambda: small2d(33, seed=None, graded=True, nu=0.49),
+    "mixed3d_n8": lambda: _mixed3d(),
+}
+
+
+def _mixed3d():
+    m = small3d(8, seed=9)
+    rng = np.random.default_rng(0)
+    m.E = np.where(rng.random(m.elems.shape[0]) < 0.5, 1.0, 100.0)
+    m.nu = rng.uniform(0.25, 0.45, m.elems.shape[0])
+    return m
+
+
+_cache = {}
+
+
+def _pair(name, precision=V.FP64, **kw):
+    key = (name, precision, tuple(sorted(kw.items())))
+    if key not in _cache:
+        m = MESHES[name]()
+        oo = OracleOptions(**{k: v for k, v in kw.items() if k in ("coarsest_max_dofs",)})
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, oo)
+        s = V.Solver.from_mesh(m, precision=precision, **kw)
+        _cache[key] = (m, o, s)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+def test_kernel_parity_per_level(name, prec):
+    m, o, s = _pair(name, prec)
+    d = m.dim
+    rng = np.random.default_rng(1)
+    tol = 1e-13 if prec == V.FP64 else 2e-6
+    for l in range(o.L):
+        A = o.A[l]
+        n = A.shape[0] // d
+        x = rng.normal(size=(n, d))
+        b = rng.normal(size=(n, d))
+        # SpMV (the fine FP64 copy always exists; coarse levels in the handle's precision)
+        y = torch.zeros((n, d), dtype=torch.float64, device="cuda")
+        s.spmv_device(l, prec, _dev(x), y)
+        assert _rel(_host(y).ravel(), A @ x.ravel()) < tol, (l, "spmv")
+        # GS forward and backward sweeps from a nonzero guess
+        S = ColoredGS(A, d, o.colors[l])
+        for bw in (0, 1):
+            xg = _dev(x)
+            s.gs_sweep_device(l, prec, bw, _dev(b), xg)
+            ref = S.backward(b.ravel(), x.ravel()) if bw else S.forward(b.ravel(), x.ravel())
+            gtol = 1e-11 if prec == V.FP64 else 1e-4
+            assert _rel(_host(xg).ravel(), ref) < gtol, (l, "gs", bw)
+        # restriction and prolongation
+        Pb = block_prolongation(o.P[l], d)
+        nc = Pb.shape[1] // d
+        bc = torch.zeros((nc, d), dtype=torch.float64, device="cuda")
+        s.restrict_device(l, prec, _dev(x), bc)
+        assert _rel(_host(bc).ravel(), Pb.T @ x.ravel()) < tol, (l, "restrict")
+        e = rng.normal(size=(nc, d))
+        xg = _dev(x)
+        s.prolong_device(l, prec, _dev(e), xg)
+        assert _rel(_host(xg).ravel(), x.ravel() + Pb @ e.ravel()) < tol, (l, "prolong")
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+def test_vcycle_parity(name, prec):
+    m, o, s = _pair(name, prec)
+    n = o.A[0].shape[0] // m.dim
+    rng = np.random.default_rng(2)
+    r = rng.normal(size=(n, m.dim))
+    z = torch.zeros_like(_dev(r))
+    s.apply_precond_device(_dev(r), z)
+    ref = o.apply_precond(r.ravel(), precision="fp64")
+    tol = 1e-11 if prec == V.FP64 else 1e-4
+    assert _rel(_host(z).ravel(), ref) < tol
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_solve_parity_fp64(name):
+    m, o, s = _pair(name, V.FP64)
+    xo, io = o.solve(m.rhs[0], 1e-6)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    print(name, "gpu", info["iterations"], "oracle", io["iterations"], info["t_solve_ms"], "ms")
+    assert info["converged"] == 1
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    assert info["rel_res_true"] < 1e-6
+    assert np.all(x[m.fixed.any(axis=1)] == 0)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_solve_mixed_precision(name):
+    m, o, s = _pair(name, V.FP32_PRECOND)
+    xo, io = o.solve(m.rhs[0], 1e-6)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(name, "mixed gpu", info["iterations"], "oracle fp64", io["iterations"], "err", err)
+    assert info["converged"] == 1
+    assert info["rel_res_true"] < 1e-6
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert err < 1e-5
+
+
+def test_solve_device_pointers_and_batch():
+    m, o, s = _pair("small3d_n9", V.FP64)
+    F = np.stack([m.rhs[0], 2.0 * m.rhs[0] + 0.1])
+    d_rhs = _dev(F)
+    d_x = torch.zeros_like(d_rhs)
+    infos = s.solve_device(d_rhs, d_x, 1e-8)
+    x = _host(d_x)
+    for c in range(2):
+        xo, io = o.solve(F[c], 1e-8)
+        assert np.linalg.norm(x[c] - xo) / np.linalg.norm(xo) <= 1e-8
+        assert abs(infos[c]["iterations"] - io["iterations"]) <= 1
+
+
+def test_edge_cases():
+    m, o, s = _pair("cfg1_2d", V.FP64)
+    # zero right-hand side: zero solution, no iteration
+    x, info = s.solve(np.zeros_like(m.rhs[0]), 1e-6)
+    assert info["iterations"] == 0 and np.all(x == 0) and info["converged"] == 1
+    # warm start from a looser solve
+    x1, _ = s.solve(m.rhs[0], 1e-3)
+    x2, i2 = s.solve(m.rhs[0], 1e-8, x0=x1)
+    assert i2["converged"] == 1 and i2["rel_res_true"] < 1e-8
+    # warm start from the solution itself: nothing to do
+    x3, i3 = s.solve(m.rhs[0], 1e-6, x0=x2)
+    assert i3["iterations"] == 0 and i3["converged"] == 1
+    # not converged within max_iters: last iterate and info still returned
+    s2 = V.Solver.from_mesh(m, max_iters=2)
+    x, info = s2.solve(m.rhs[0], 1e-12)
+    assert info["status"] == V.ENOTCONV and info["iterations"] == 2 and info["converged"] == 0
+    assert np.isfinite(x).all() and np.abs(x).max() > 0
+    # NaN right-hand side: breakdown reported
+    bad = m.rhs[0].copy()
+    free = np.flatnonzero(~m.fixed.any(axis=1))
+    bad[free[3], 0] = np.nan
+    x, info = s.solve(bad, 1e-6, check=False)
+    assert info["status"] == V.EBREAKDOWN
+    # fixed entries of the right-hand side are ignored
+    F = m.rhs[0].copy()
+    F[m.fixed.any(axis=1)] = 123.0
+    xa, _ = s.solve(F, 1e-6)
+    xb, _ = s.solve(m.rhs[0], 1e-6)
+    assert np.array_equal(xa, xb)
+    s2.free()
+
+
+def test_fine_grid_larger_than_flat_reduction_grid():
+    """Regression: 66,049-vertex 2D mesh, so the fine SpMV+dot launch has more
+    workgroups (one partial sum each) than the fixed flat reduction grid."""
+    m = manufactured_mesh(257, seed=0)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    s = V.Solver.from_mesh(m, precision=V.FP64)
+    xo, io = o.solve(m.rhs[0], 1e-6)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    s.free()
+
+
+def test_determinism_bitwise():
+    m, o, s = _pair("small3d_n9", V.FP32_PRECOND)
+    x1, i1 = s.solve(m.rhs[0], 1e-6)
+    x2, i2 = s.solve(m.rhs[0], 1e-6)
+    assert i1["iterations"] == i2["iterations"]
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("pc,name", [(V.PRECOND_JACOBI, "jacobi"), (V.PRECOND_NONE, "none")])
+def test_context_preconditioners(pc, name):
+    m = manufactured_mesh(17, seed=0)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    s = V.Solver.from_mesh(m, preconditioner=pc)
+    xo, io = o.solve(m.rhs[0], 1e-6, precond=name)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    s.free()
+
+
+def test_truncated_and_single_level_hierarchies():
+    m = small2d(21, seed=7)
+    for cmax in (300, 10 ** 6):
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(coarsest_max_dofs=cmax))
+        s = V.Solver.from_mesh(m, coarsest_max_dofs=cmax)
+        xo, io = o.solve(m.rhs[0], 1e-8)
+        x, info = s.solve(m.rhs[0], 1e-8)
+        assert abs(info["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+        if cmax == 10 ** 6:
+            assert info["iterations"] == 1
+        s.free()
+
+
+def test_full_size_3d_workload_against_oracle_golden():
+    """The 65^3 benchmark workload (811,200 DOFs) in the benchmark's launch
+    configuration: sampled solution values and iteration counts of the oracle."""
+    path = os.path.join(GOLD, "cfg2_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference values not generated (tests/golden/make_oracle_golden.py)")
+    g = json.load(open(path))
+    from workloads import cfg2
+    m = cfg2()
+    s = V.Solver.from_mesh(m, precision=V.FP64)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    print("cfg2 fp64 gpu", info["iterations"], "oracle", g["fp64"]["iterations"],
+          info["t_solve_ms"], "ms")
+    assert abs(info["iterations"] - g["fp64"]["iterations"]) <= 1
+    xs = x[np.array(g["sample_vertices"])]
+    assert np.abs(xs - np.array(g["sample_x"])).max() <= 1e-8 * g["x_norminf"]
+    assert abs(np.linalg.norm(x) - g["x_norm2"]) <= 1e-8 * g["x_norm2"]
+    s.free()
+    s = V.Solver.from_mesh(m, precision=V.FP32_PRECOND)
+    x32, info = s.solve(m.rhs[0], 1e-6)
+    print("cfg2 mixed gpu", info["iterations"], "oracle fp32-mode", g["fp32"]["iterations"],
+          info["t_solve_ms"], "ms")
+    assert info["converged"] == 1 and info["rel_res_true"] < 1e-6
+    assert abs(info["iterations"] - g["fp32"]["iterations"]) <= 1
+    xs = x32[np.array(g["sample_vertices"])]
+    assert np.abs(xs - np.array(g["sample_x"])).max() <= 1e-5 * g["x_norminf"]
+    s.free()

@@ -1,0 +1,142 @@
+"""CPU tests of libvasmg: the library loads, exports every symbol of
+include/vasmg.h, its host setup reproduces the oracle's hierarchy (identical
+integer structure, bit-identical level-1 weights, operators to rounding), and
+it rejects invalid input with the documented status codes. No GPU calls."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2505_09064_amd as pkg
+from paper_2505_09064_amd import vasmg as V
+from oracle import Oracle, OracleOptions
+from workloads import cfg1, small2d, small3d
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "vasmg.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(vasmg_[a-z_]+)\s*\(", text))
+    declared.discard("vasmg_ctx")
+    lib = pkg.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(pkg.EXPORTED)
+
+
+def _compare(mesh, oopts=None, **kw):
+    oopts = oopts or OracleOptions()
+    o = Oracle(mesh.coords, mesh.elems, mesh.E, mesh.nu, mesh.fixed, oopts)
+    s = V.Solver.from_mesh(mesh, host_only=1, **kw)
+    nl, nd, dim = s.hierarchy_info()
+    assert nl == o.L + 1
+    assert nd == o.A[0].shape[0]
+    d = mesh.dim
+    m, M, depth = s.tree_info()
+    assert depth == o.levels.max_depth
+    assert (m, M) == (o.levels.m, o.levels.M)
+    for l in range(nl):
+        e = s.export_level(l)
+        n = e["n_vertices"]
+        A = sp.bsr_matrix((e["vals"], e["cols"], e["rowptr"]), shape=(n * d, n * d)).tocsr()
+        assert abs(A - o.A[l]).max() <= 1e-13 * abs(o.A[l]).max()
+        S = sp.csr_matrix((np.ones(e["cols"].size), e["cols"], e["rowptr"]), shape=(n, n))
+        assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs"
+        if l < o.L:
+            assert np.array_equal(e["color"], o.colors[l])
+            assert e["n_colors"] == o.colors[l].max() + 1
+            P = sp.csr_matrix((e["p_vals"], e["p_cols"], e["p_rowptr"]), shape=o.P[l].shape)
+            diff = P - o.P[l]
+            assert diff.nnz == 0 or abs(diff).max() == 0.0, "P not bit-identical"
+        if l >= 1:
+            assert np.array_equal(e["keys"], o.levels.level_keys(l))
+    s.free()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small3d", "small2d_x0", "graded", "cap9", "free_tree",
+                                  "truncated", "mixed_material"])
+def test_host_setup_matches_oracle(name):
+    if name == "cfg1":
+        _compare(cfg1())
+    elif name == "small3d":
+        _compare(small3d(9, seed=5))
+    elif name == "small2d_x0":
+        _compare(small2d(17, seed=3, fix="x0"))
+    elif name == "graded":
+        _compare(small2d(33, seed=None, graded=True, nu=0.49))
+    elif name == "cap9":
+        _compare(small2d(17, seed=4), OracleOptions(leaf_capacity=9), leaf_capacity=9)
+    elif name == "free_tree":
+        _compare(small3d(7, seed=6), OracleOptions(tree_vertices="free"), tree_vertices=V.TREE_FREE)
+    elif name == "truncated":
+        _compare(small2d(21, seed=7), OracleOptions(coarsest_max_dofs=300), coarsest_max_dofs=300)
+    elif name == "mixed_material":
+        m = small3d(8, seed=9)
+        rng = np.random.default_rng(0)
+        m.E = np.where(rng.random(m.elems.shape[0]) < 0.5, 1.0, 100.0)
+        m.nu = rng.uniform(0.25, 0.45, m.elems.shape[0])
+        _compare(m)
+
+
+def _expect(status, mesh_fn, **kw):
+    m = mesh_fn()
+    with pytest.raises(V.VasmgError) as ei:
+        V.Solver.from_mesh(m, host_only=1, **kw)
+    assert ei.value.status == status, str(ei.value)
+    return str(ei.value)
+
+
+def test_setup_rejects_invalid_input():
+    def partial():
+        m = small2d(5); m.fixed[7, 0] = 1; m.fixed[7, 1] = 0; return m
+
+    def inverted():
+        m = small2d(5); m.elems[3, [1, 2]] = m.elems[3, [2, 1]]; return m
+
+    def bad_nu():
+        m = small2d(5); m.nu = np.full(m.elems.shape[0], 0.5); return m
+
+    def bad_E():
+        m = small2d(5); m.E = np.zeros(m.elems.shape[0]); return m
+
+    def bad_index():
+        m = small2d(5); m.elems[0, 0] = m.n_vertices; return m
+
+    def nan_coord():
+        m = small2d(5); m.coords[4, 1] = np.nan; return m
+
+    def all_fixed():
+        m = small2d(5); m.fixed[:] = 1; return m
+
+    def duplicates():
+        m = small2d(5)
+        m.coords = np.concatenate([m.coords, np.repeat(m.coords[12:13], 6, 0)])
+        m.fixed = np.concatenate([m.fixed, np.ones((6, 2), np.uint8)])
+        return m
+
+    for fn in (partial, inverted, bad_nu, bad_E, bad_index, nan_coord, all_fixed, duplicates):
+        _expect(V.EINVAL, fn)
+    _expect(V.EDEGENERATE, lambda: small2d(6, fix="none"))
+    _expect(V.EINVAL, lambda: small2d(5), leaf_capacity=-1)
+
+
+def test_host_only_handle_refuses_device_calls():
+    m = small2d(5)
+    s = V.Solver.from_mesh(m, host_only=1)
+    with pytest.raises(V.VasmgError) as ei:
+        s.solve(m.rhs[0])
+    assert ei.value.status == V.EDEVICE
+    s.free()
+    s.free()   # idempotent
+
+
+def test_default_options():
+    o = V.default_options(2)
+    assert (o.leaf_capacity, o.n_pre, o.n_post, o.max_iters) == (4, 1, 1, 10000)
+    assert V.default_options(3).leaf_capacity == 8
+    with pytest.raises(V.VasmgError):
+        V.default_options(4)
