@@ -9,9 +9,13 @@ solved directly (Section 3, solving step; Section 4 takes B_0 = A_0^{-1}); here
 by a dense FP64 Cholesky factorisation.
 
 The multicolouring is not in the paper (its Gauss-Seidel is sequential); it
-fixes the order in which the GPU's parallel Gauss-Seidel visits the vertices:
-greedy first-fit over the vertices in canonical order on the structural
-block-sparsity graph of each level (self excluded).
+fixes the order in which the GPU's parallel Gauss-Seidel visits the vertices.
+On the fine level every vertex is its own cell; on coarse levels vertices are
+grouped into lattice cells of twice the level's finest spacing (at most 2^d
+vertices). Cells are coloured greedily (first fit) on the cell adjacency graph
+derived from the structural block pattern; the sweep visits colours in order,
+the cells of a colour in any order (they are uncoupled) and the vertices of a
+cell one after the other in canonical order.
 
 Pins (tests/test_oracle_hierarchy.py): A_l symmetric positive definite, positive
 diagonal, coarse operators annihilate the interpolated rigid-body modes of the
@@ -62,6 +66,66 @@ def greedy_coloring(S: sp.csr_matrix) -> np.ndarray:
         mark[used] = True
         color[i] = int(np.argmin(mark))
     return color
+
+
+def greedy_coloring_in_order(S: sp.csr_matrix, order: np.ndarray) -> np.ndarray:
+    """First-fit colouring visiting the vertices in ``order``."""
+    S = S.tocsr()
+    n = S.shape[0]
+    color = np.full(n, -1, dtype=np.int64)
+    indptr, indices = S.indptr, S.indices
+    for i in order:
+        nb = indices[indptr[i]:indptr[i + 1]]
+        used = color[nb]
+        used = used[used >= 0]
+        if used.size == 0:
+            color[i] = 0
+            continue
+        mark = np.zeros(used.max() + 2, dtype=bool)
+        mark[used] = True
+        color[i] = int(np.argmin(mark))
+    return color
+
+
+def cell_partition(keys: np.ndarray, cell_side: int):
+    """Groups lattice vertices into cells of side ``cell_side`` (key // cell_side).
+
+    Returns (cell_of_vertex, cell_keys) with cells numbered in canonical (z, y, x)
+    order of their cell keys. Vertices keep their canonical order inside a cell.
+    """
+    ck = keys // cell_side
+    d = keys.shape[1]
+    uniq, inv = np.unique(ck[:, ::-1], axis=0, return_inverse=True)
+    return inv.ravel().astype(np.int64), uniq[:, ::-1].copy()
+
+
+def cell_graph(S: sp.csr_matrix, cell_of: np.ndarray, n_cells: int) -> sp.csr_matrix:
+    """Cells are adjacent when any of their vertices are (structural pattern)."""
+    C = S.tocoo()
+    G = sp.csr_matrix((np.ones(C.nnz), (cell_of[C.row], cell_of[C.col])), shape=(n_cells, n_cells))
+    G.sum_duplicates()
+    return G
+
+
+def choose_cell_coloring(G: sp.csr_matrix, cell_keys: np.ndarray | None) -> np.ndarray:
+    """Greedy first-fit colouring of the cell graph with the fewest colours among
+    three visiting orders: canonical, then lattice classes (cell key mod 2) and
+    (cell key mod 3) in class order (canonical inside a class). Ties keep the
+    earlier order. Without lattice keys only the canonical order is used."""
+    n = G.shape[0]
+    best = greedy_coloring_in_order(G, np.arange(n))
+    if cell_keys is None:
+        return best
+    d = cell_keys.shape[1]
+    for q in (2, 3):
+        cls = np.zeros(n, dtype=np.int64)
+        for a in range(d):
+            cls += (cell_keys[:, a] % q) * q ** a
+        order = np.lexsort((np.arange(n), cls))
+        cand = greedy_coloring_in_order(G, order)
+        if cand.max() < best.max():
+            best = cand
+    return best
 
 
 def coloring_is_valid(S: sp.csr_matrix, color: np.ndarray) -> bool:

@@ -9,10 +9,10 @@ once in exactly the reverse order after it (Section 3, Step 2.5). Algorithm 1's
 error-based exit is not used inside a V-cycle (a fixed number of sweeps).
 
 Two visiting orders:
-  * ``colored`` (the order the GPU uses): colours ascending, vertices of a
-    colour in canonical order, components ascending; the backward sweep is the
-    exact reverse. Vertices of one colour are not coupled, so all of them can be
-    updated at once for each component.
+  * ``colored`` (the order the GPU uses): colours ascending, the cells of a
+    colour, the vertices of a cell in canonical order, components ascending; the
+    backward sweep is the exact reverse. Cells of one colour are not coupled, so
+    the same position of all of them can be updated at once for each component.
   * ``lex`` (the paper's order): all first components, then all second
     components, ... (the component-major unknown vector [U1; U2; ...] of
     Section 2), in vertex order; realised with triangular solves, since one
@@ -30,22 +30,42 @@ from scipy.sparse.linalg import spsolve_triangular
 
 
 class ColoredGS:
-    """Point GS over (colour, vertex, component) on a vertex-major scalar CSR matrix."""
+    """Point GS over (colour, cell, vertex, component) on a vertex-major scalar CSR matrix.
 
-    def __init__(self, A: sp.csr_matrix, d: int, color: np.ndarray, dtype=np.float64):
+    cell_of[v] is the cell of vertex v, cell_color[c] the colour of cell c. The
+    forward sweep visits colours ascending; cells of one colour are uncoupled,
+    so for each position p inside a cell (vertices in ascending order) and each
+    component, the p-th vertices of all cells of the colour are updated at once.
+    The backward sweep is the exact reverse.
+    """
+
+    def __init__(self, A: sp.csr_matrix, d: int, cell_of: np.ndarray, cell_color: np.ndarray,
+                 dtype=np.float64):
         self.d = d
         self.dtype = dtype
         A = A.astype(dtype).tocsr()
         diag = A.diagonal()
-        ncol = int(color.max()) + 1 if color.size else 0
-        self.parts = []          # per colour: per component (rows, A[rows], a_ii)
+        n = A.shape[0] // d
+        color = cell_color[cell_of]
+        order = np.lexsort((np.arange(n), cell_of, color))      # colour, cell, vertex
+        pos = np.zeros(n, dtype=np.int64)
+        prev_cell, k = -1, 0
+        for v in order:
+            k = k + 1 if cell_of[v] == prev_cell else 0
+            pos[v] = k
+            prev_cell = cell_of[v]
+        ncol = int(color.max()) + 1 if n else 0
+        self.parts = []          # per (colour, position): per component (rows, A[rows], a_ii)
         for c in range(ncol):
-            verts = np.flatnonzero(color == c)
-            comps = []
-            for a in range(d):
-                rows = verts * d + a
-                comps.append((rows, A[rows].tocsr(), diag[rows]))
-            self.parts.append(comps)
+            for p in range(int(pos.max()) + 1):
+                verts = np.flatnonzero((color == c) & (pos == p))
+                if verts.size == 0:
+                    continue
+                comps = []
+                for a in range(d):
+                    rows = verts * d + a
+                    comps.append((rows, A[rows].tocsr(), diag[rows]))
+                self.parts.append(comps)
 
     def _update(self, part, b, x):
         rows, Ar, aii = part

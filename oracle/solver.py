@@ -92,7 +92,23 @@ class Oracle:
         self.S = S
         self.P = P_list
         self.L = len(A) - 1
-        self.colors = [hierarchy.greedy_coloring(S[l]) for l in range(self.L)]
+        # Gauss-Seidel visiting order: cells (single vertices on the fine level,
+        # lattice cells of twice the finest spacing on coarse levels), coloured
+        self.cells, self.cell_colors, self.colors = [], [], []
+        for l in range(self.L):
+            n = A[l].shape[0] // d
+            if l == 0:
+                cell_of, ckeys, ncell = np.arange(n), None, n
+            else:
+                keys = self.levels.level_keys(l)
+                dstar = int(self.levels.regions[l - 1][0].max())
+                cell_of, ckeys = hierarchy.cell_partition(keys, 2 * int(tree.side_of(dstar)))
+                ncell = ckeys.shape[0]
+            G = hierarchy.cell_graph(S[l], cell_of, ncell)
+            cc = hierarchy.choose_cell_coloring(G, ckeys)
+            self.cells.append(cell_of)
+            self.cell_colors.append(cc)
+            self.colors.append(cc[cell_of])
         self.coarsest = hierarchy.CoarsestSolver(A[self.L])
         self.setup_seconds = time.perf_counter() - t0
         self._vcycles = {}
@@ -105,7 +121,8 @@ class Oracle:
         if key not in self._vcycles:
             dt = np.float32 if precision == "fp32" else np.float64
             if smoother == "colored":
-                sm = [ColoredGS(self.A[l], self.d, self.colors[l], dt) for l in range(self.L)]
+                sm = [ColoredGS(self.A[l], self.d, self.cells[l], self.cell_colors[l], dt)
+                      for l in range(self.L)]
             elif smoother == "lex":
                 sm = [LexGS(self.A[l], self.d, dt) for l in range(self.L)]
             else:
@@ -160,5 +177,6 @@ class Oracle:
             nv = A.shape[0] // self.d
             nb = self.S[l].nnz
             out.append(dict(level=l, n_vertices=nv, n_dofs=A.shape[0], n_blocks=int(nb),
-                            n_colors=int(self.colors[l].max() + 1) if l < self.L else 0))
+                            n_colors=int(self.colors[l].max() + 1) if l < self.L else 0,
+                            n_cells=int(self.cell_colors[l].size) if l < self.L else 0))
         return out

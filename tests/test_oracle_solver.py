@@ -3,7 +3,8 @@
   * Galerkin operators (Section 3, equations (R), (Ac)): symmetric positive
     definite after the boundary conditions, positive diagonal, and for the
     unconstrained operator they annihilate the interpolated rigid-body modes.
-  * Colouring: valid, and each colour is the first fit over lower neighbours.
+  * Gauss-Seidel cells and colouring: coupled vertices of different cells never
+    share a colour, cells are lattice blocks of at most 2^d vertices.
   * Gauss-Seidel (Section 2.1, Algorithm 1): equals a literal element-by-element
     loop in the same unknown order; one forward sweep from zero equals a
     lower-triangular solve; backward is the exact reverse order.
@@ -18,7 +19,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import Oracle, OracleOptions, fem, hierarchy
+from oracle import Oracle, OracleOptions, fem, hierarchy, tree
 from oracle.pcg import pcg
 from oracle.smoother import ColoredGS, LexGS
 from oracle.vcycle import dense_operator
@@ -61,21 +62,42 @@ def test_galerkin_spd_and_rigid_modes(dim):
         assert np.abs(Kl @ R).max() < 1e-10 * abs(Kl).max() * max(1.0, np.abs(R).max())
 
 
+def _sweep_order(o, l):
+    """Unknown order of the coloured sweep: colours, cells, vertices, components."""
+    d = o.d
+    cell, cc = o.cells[l], o.cell_colors[l]
+    n = cell.size
+    verts = np.lexsort((np.arange(n), cell, cc[cell]))
+    return np.array([v * d + a for v in verts for a in range(d)])
+
+
 @pytest.mark.parametrize("dim", [2, 3])
-def test_coloring_valid_and_first_fit(dim):
-    m = _tiny(dim)
+def test_cells_and_coloring(dim):
+    m = small2d(17, seed=1) if dim == 2 else small3d(9, seed=2)
     o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
     for l in range(o.L):
-        S = o.S[l].tocsr()
-        col = o.colors[l]
-        assert hierarchy.coloring_is_valid(S, col)
-        for i in range(S.shape[0]):
-            nb = S.indices[S.indptr[i]:S.indptr[i + 1]]
-            lower = set(col[nb[nb < i]].tolist())
-            first = 0
-            while first in lower:
-                first += 1
-            assert col[i] == first
+        S = o.S[l].tocoo()
+        cell, col = o.cells[l], o.colors[l]
+        # vertices of different cells that are coupled never share a colour
+        off = cell[S.row] != cell[S.col]
+        assert np.all(col[S.row[off]] != col[S.col[off]])
+        sizes = np.bincount(cell)
+        assert sizes.max() <= (1 if l == 0 else 2 ** dim)
+        if l == 0:
+            assert np.array_equal(cell, np.arange(cell.size))
+        else:
+            # cells are lattice blocks: all members share key // cell_side
+            keys = o.levels.level_keys(l)
+            side = 2 * int(tree.side_of(int(o.levels.regions[l - 1][0].max())))
+            ck = keys // side
+            for c in np.unique(cell):
+                assert np.all(ck[cell == c] == ck[cell == c][0])
+        # the chosen colouring is the best of the greedy visiting orders
+        G = hierarchy.cell_graph(o.S[l], cell, sizes.size)
+        canon = hierarchy.greedy_coloring_in_order(G, np.arange(sizes.size))
+        assert o.cell_colors[l].max() <= canon.max()
+    # coarse lattice levels of a near-uniform mesh reach 2^d colours
+    assert o.cell_colors[o.L - 1].max() + 1 <= 2 ** dim
 
 
 def _literal_gs(A, b, x, order):
@@ -102,11 +124,8 @@ def test_gauss_seidel_orders(dim):
         nv = n // dim
         b = rng.normal(size=n)
         x0 = rng.normal(size=n)
-        col = o.colors[l]
-        # coloured order: colours ascending, vertices ascending, components ascending
-        order = [v * dim + a for c in range(col.max() + 1) for v in np.flatnonzero(col == c)
-                 for a in range(dim)]
-        S = ColoredGS(A, dim, col)
+        order = list(_sweep_order(o, l))
+        S = ColoredGS(A, dim, o.cells[l], o.cell_colors[l])
         assert np.allclose(S.forward(b, x0), _literal_gs(Ad, b, x0, order), rtol=1e-12, atol=1e-12)
         assert np.allclose(S.backward(b, x0), _literal_gs(Ad, b, x0, order[::-1]),
                            rtol=1e-12, atol=1e-12)
@@ -149,11 +168,7 @@ def test_vcycle_closed_form_spd(dim):
     n = o.A[0].shape[0]
     B = dense_operator(lambda r: o.apply_precond(r), n)
 
-    def order(l):
-        col = o.colors[l]
-        return np.array([v * dim + a for c in range(col.max() + 1) for v in np.flatnonzero(col == c)
-                         for a in range(dim)])
-    Bc = _closed_form_B(o, 0, order)
+    Bc = _closed_form_B(o, 0, lambda l: _sweep_order(o, l))
     assert np.abs(B - Bc).max() <= 1e-10 * np.abs(Bc).max()
     assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
     assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
