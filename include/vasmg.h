@@ -141,19 +141,25 @@ vasmg_status vasmg_hierarchy_info(vasmg_handle h, int32_t* n_levels, int64_t* n_
                                   int32_t* dim);
 
 /* Per level: vertices, stored d x d blocks (structural pattern incl. diagonal),
- * colours (0 on the coarsest level), entries of P_level (0 on the coarsest). */
+ * colours of the Gauss-Seidel order (0 on the coarsest level), entries of
+ * P_level (0 on the coarsest). */
 vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices,
                               int64_t* n_blocks, int32_t* n_colors, int64_t* p_nnz);
 
 /* Copy level data in canonical order into caller-allocated host arrays (any
  * pointer may be NULL to skip it):
  *   keys   [n_vertices][dim] int64 lattice keys (coarse levels; fine: -1)
- *   color  [n_vertices] int32 (coarsest level: 0)
+ *   cell   [n_vertices] int32 Gauss-Seidel cell of each vertex (cells numbered in
+ *          canonical order of their lattice keys; fine level: the vertex itself;
+ *          coarsest level: 0)
+ *   color  [n_vertices] int32 colour of the vertex's cell (coarsest level: 0).
+ *          A sweep visits colours ascending, then cells, then the vertices of a
+ *          cell in canonical order, then components (Algorithm 1 in that order).
  *   rowptr [n_vertices+1] int64, cols [n_blocks] int32, vals [n_blocks][dim][dim] FP64
  *   p_rowptr [n_vertices+1] int64, p_cols [p_nnz] int32, p_vals [p_nnz] FP64
  *     (scalar prolongation P_level from this level's vertices to the next's). */
-vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* color,
-                                int64_t* rowptr, int32_t* cols, double* vals,
+vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* cell,
+                                int32_t* color, int64_t* rowptr, int32_t* cols, double* vals,
                                 int64_t* p_rowptr, int32_t* p_cols, double* p_vals);
 
 /* Root box [m, M]^dim of the region tree (Section 3.1.1 Step 1) and its depth. */

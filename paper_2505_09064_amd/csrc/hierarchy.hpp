@@ -40,7 +40,12 @@ struct Level {
   int64_t n = 0;               // vertices
   std::vector<Key> keys;       // coarse levels: lattice keys in canonical order
   BlockCSR A;                  // operator, canonical vertex order
-  std::vector<int32_t> color;  // greedy colouring (levels below the coarsest)
+  int max_region_depth = 0;    // coarse levels: deepest region of the level
+  // Gauss-Seidel order (levels below the coarsest): vertex -> cell, cell -> colour
+  std::vector<int32_t> cell;
+  std::vector<int32_t> cell_color;
+  int64_t ncells = 0;
+  std::vector<int32_t> color;  // colour of each vertex's cell
   int32_t ncolors = 0;
   ScalarCSR P;                 // prolongation to the next level (empty on the coarsest)
 };

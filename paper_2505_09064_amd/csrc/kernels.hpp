@@ -297,6 +297,166 @@ __global__ __launch_bounds__(kBlock) void k_residual_upper(
 }
 
 // ---------------------------------------------------------------------------
+// Coarse lattice levels: Gauss-Seidel over cells of at most NV = 2^D vertices.
+// Device rows of a cell are contiguous ([cell_ptr[c], cell_ptr[c+1])); the CSR
+// holds only blocks coupling to other cells, split per row into [rowptr,
+// lo_end) (earlier colours) and [up_beg, rowptr+1) (later colours); the blocks
+// inside a cell, diagonal included, are a dense NU x NU matrix per cell
+// (NU = NV * D, column-major: cellM[c*NU*NU + u*NU + t] = M[t][u]).
+// One workgroup handles one cell: lane group g sums the off-cell part of the
+// cell's g-th row, then lane t of wavefront 0 owns unknown t (vertex t / D,
+// component t % D) for the sequential sweep inside the cell, which broadcasts
+// each new value with a shuffle.
+// ---------------------------------------------------------------------------
+template <int D>
+struct CellShape {
+  static constexpr int NV = 1 << D;
+  static constexpr int NU = NV * D;
+};
+
+// Per-cell block of NV * GR threads: lane group g (GR lanes, inside one
+// wavefront) sums the off-cell part of the cell's g-th row; the sums meet in
+// LDS; wavefront 0 then runs the sequential sweep over the cell's unknowns.
+template <typename T, int D, int GR>
+__device__ __forceinline__ void cell_offcell_sums(int v0, int m, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ lo_end,
+                                                  const int* __restrict__ up_beg,
+                                                  const int* __restrict__ col,
+                                                  const T* __restrict__ val, int64_t nnz,
+                                                  const T* __restrict__ x, bool want_lo,
+                                                  bool want_up, T (*sh_lo)[D], T (*sh_up)[D]) {
+  const int g = threadIdx.x / GR, gl = threadIdx.x % GR;
+  T lo[D], up[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
+  if (g < m) {
+    const int i = v0 + g;
+    if (want_lo) row_product<T, D, GR>(rowptr[i], lo_end[i], gl, col, val, nnz, x, lo);
+    if (want_up) row_product<T, D, GR>(up_beg[i], rowptr[i + 1], gl, col, val, nnz, x, up);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (want_lo) lo[a] = group_sum<T, GR>(lo[a]);
+    if (want_up) up[a] = group_sum<T, GR>(up[a]);
+  }
+  if (gl == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      sh_lo[g][a] = lo[a];
+      sh_up[g][a] = up[a];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int D, int GR, int MODE>
+__global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
+    int cell0, const int* __restrict__ cell_ptr, const int* __restrict__ rowptr,
+    const int* __restrict__ lo_end, const int* __restrict__ up_beg, const int* __restrict__ col,
+    const T* __restrict__ val, int64_t nnz, const T* __restrict__ cellM,
+    const T* __restrict__ b, T* x, T* __restrict__ s_save, const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
+  __shared__ T sh_lo[NV][D], sh_up[NV][D];
+  const int c = cell0 + blockIdx.x;
+  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
+  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, true, MODE != 0,
+                              sh_lo, sh_up);
+  if (threadIdx.x >= 64) return;          // wavefront 0 finishes the cell
+  const int t = threadIdx.x;
+  const bool own = t < n;
+  const int k = own ? t / D : 0, a = own ? t % D : 0;
+  const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
+  const T s_t = own ? b[xi] - sh_lo[k][a] : T(0);
+  const T sup = (own && MODE != 0) ? sh_up[k][a] : T(0);
+  if (MODE != 2 && s_save && own) s_save[xi] = s_t;
+  T Mrow[NU];
+  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
+  T xc = (MODE == 0 || !own) ? T(0) : x[xi];
+  T acc = s_t - sup;
+  if (MODE != 0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const T xu = __shfl(xc, u);
+      if (u != t) acc -= Mrow[u] * xu;
+    }
+  }
+  if (MODE != 2) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u < n) {
+        T delta = T(0);
+        if (t == u) {
+          const T xn = acc / Mrow[u];
+          delta = xn - xc;
+          xc = xn;
+        }
+        delta = __shfl(delta, u);
+        if (t != u) acc -= Mrow[u] * delta;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = NU - 1; u >= 0; --u) {
+      if (u < n) {
+        T delta = T(0);
+        if (t == u) {
+          const T xn = acc / Mrow[u];
+          delta = xn - xc;
+          xc = xn;
+        }
+        delta = __shfl(delta, u);
+        if (t != u) acc -= Mrow[u] * delta;
+      }
+    }
+  }
+  if (own) x[xi] = xc;
+}
+
+// out_t = base_t - (off-cell part)_t - (M x)_t on cell levels.
+//   KIND 0: residual after a forward sweep: base = saved s, upper range only
+//   KIND 1: full residual: base = b, both ranges
+//   KIND 2: SpMV: base = 0, both ranges, result negated (y = A x)
+template <typename T, int D, int GR, int KIND>
+__global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
+    const int* __restrict__ cell_ptr, const int* __restrict__ rowptr,
+    const int* __restrict__ lo_end, const int* __restrict__ up_beg, const int* __restrict__ col,
+    const T* __restrict__ val, int64_t nnz, const T* __restrict__ cellM,
+    const T* __restrict__ base, const T* __restrict__ x, T* __restrict__ out,
+    const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
+  __shared__ T sh_lo[NV][D], sh_up[NV][D];
+  const int c = blockIdx.x;
+  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
+  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, KIND != 0, true,
+                              sh_lo, sh_up);
+  if (threadIdx.x >= 64) return;
+  const int t = threadIdx.x;
+  const bool own = t < n;
+  const int k = own ? t / D : 0, a = own ? t % D : 0;
+  const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
+  const T off = own ? (KIND != 0 ? sh_lo[k][a] : T(0)) + sh_up[k][a] : T(0);
+  const T xt = own ? x[xi] : T(0);
+  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+  T mx = T(0);
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const T xu = __shfl(xt, u);
+    if (own && u < n) mx += Mc[u * NU + t] * xu;
+  }
+  if (!own) return;
+  if (KIND == 2)
+    out[xi] = off + mx;
+  else
+    out[xi] = base[xi] - off - mx;
+}
+
+// ---------------------------------------------------------------------------
 // K4: restriction b_c = P^T r (gather over the CSR of P^T); K5: x += P e.
 // ---------------------------------------------------------------------------
 template <typename T, int D>

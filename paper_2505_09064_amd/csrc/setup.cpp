@@ -18,8 +18,10 @@
 //  * Prolongation columns with no nonzero weight are dropped.
 //  * Galerkin operators A_{l+1} = P_l^T A_l P_l (Section 3, equations (R), (Ac))
 //    by a row-wise block SpGEMM over the structural pattern.
-//  * Greedy first-fit colouring of each level in canonical order (the order of
-//    the parallel Gauss-Seidel; not part of the paper).
+//  * Gauss-Seidel visiting order (not part of the paper): single-vertex cells
+//    on the fine level, lattice cells of twice the finest spacing on coarse
+//    levels, greedy first-fit colouring of the cells (fewest colours among the
+//    canonical and mod-2 / mod-3 lattice-class visiting orders).
 //  * Dense Cholesky factor of the coarsest operator (Section 3 Step 2.3).
 //
 // Must be compiled without floating-point contraction (-ffp-contract=off):
@@ -454,26 +456,113 @@ void galerkin(const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
 }
 
 // --------------------------------------------------------------------------
-// greedy first-fit colouring in index order (diagonal ignored)
+// Gauss-Seidel order: cells and their greedy first-fit colouring
 // --------------------------------------------------------------------------
-int32_t greedy_color(const BlockCSR& A, std::vector<int32_t>& color) {
-  color.assign(A.n, -1);
+// First fit over the graph (ptr, adj) visiting the nodes in `order`; self
+// loops are ignored (a node is uncoloured when visited).
+int32_t greedy_color_in_order(const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
+                              const std::vector<int64_t>& order, std::vector<int32_t>& color) {
+  const int64_t n = static_cast<int64_t>(ptr.size()) - 1;
+  color.assign(n, -1);
   std::vector<int64_t> stamp;
   int32_t ncol = 0;
-  for (int64_t i = 0; i < A.n; ++i) {
-    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
-      const int32_t c = color[A.col[p]];
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = order[t];
+    for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+      const int32_t c = color[adj[p]];
       if (c >= 0) {
         if (static_cast<size_t>(c) >= stamp.size()) stamp.resize(c + 1, -1);
-        stamp[c] = i;
+        stamp[c] = t;
       }
     }
     int32_t c = 0;
-    while (static_cast<size_t>(c) < stamp.size() && stamp[c] == i) ++c;
+    while (static_cast<size_t>(c) < stamp.size() && stamp[c] == t) ++c;
     color[i] = c;
     ncol = std::max(ncol, c + 1);
   }
   return ncol;
+}
+
+// Fine level: every vertex is a cell, coloured in canonical order. Coarse
+// lattice levels: cells of side 2 * (finest region side of the level), in
+// canonical order of their cell keys; the colouring with the fewest colours
+// among the canonical, (cell key mod 2)-class and (cell key mod 3)-class
+// visiting orders is kept (ties keep the earlier order).
+void build_gs_order(Level& lv, bool lattice, int d) {
+  const int64_t n = lv.n;
+  std::vector<Key> ckeys;
+  if (!lattice) {
+    lv.cell.resize(n);
+    std::iota(lv.cell.begin(), lv.cell.end(), 0);
+    lv.ncells = n;
+  } else {
+    const uint64_t cs = 2 * side_of(lv.max_region_depth);
+    std::vector<Key> ck(n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) ck[i][a] = lv.keys[i][a] / cs;
+    ckeys = ck;
+    std::sort(ckeys.begin(), ckeys.end(), key_less);
+    ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
+    lv.ncells = static_cast<int64_t>(ckeys.size());
+    lv.cell.resize(n);
+    for (int64_t i = 0; i < n; ++i)
+      lv.cell[i] = static_cast<int32_t>(
+          std::lower_bound(ckeys.begin(), ckeys.end(), ck[i], key_less) - ckeys.begin());
+  }
+  // cell adjacency from the structural block pattern
+  const int64_t nc = lv.ncells;
+  std::vector<int64_t> vptr(nc + 1, 0);
+  for (int64_t i = 0; i < n; ++i) vptr[lv.cell[i] + 1]++;
+  for (int64_t c = 0; c < nc; ++c) vptr[c + 1] += vptr[c];
+  std::vector<int32_t> members(n);
+  {
+    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) members[fill[lv.cell[i]]++] = static_cast<int32_t>(i);
+  }
+  std::vector<int64_t> gptr(nc + 1, 0);
+  std::vector<int32_t> gadj;
+  {
+    std::vector<int32_t> tmp;
+    for (int64_t c = 0; c < nc; ++c) {
+      tmp.clear();
+      for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) {
+        const int32_t v = members[q];
+        for (int64_t p = lv.A.rowptr[v]; p < lv.A.rowptr[v + 1]; ++p)
+          tmp.push_back(lv.cell[lv.A.col[p]]);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      gadj.insert(gadj.end(), tmp.begin(), tmp.end());
+      gptr[c + 1] = static_cast<int64_t>(gadj.size());
+    }
+  }
+  std::vector<int64_t> order(nc);
+  std::iota(order.begin(), order.end(), 0);
+  int32_t best = greedy_color_in_order(gptr, gadj, order, lv.cell_color);
+  if (lattice) {
+    for (int q = 2; q <= 3; ++q) {
+      std::vector<int64_t> cls(nc, 0);
+      for (int64_t c = 0; c < nc; ++c) {
+        int64_t w = 1;
+        for (int a = 0; a < d; ++a) {
+          cls[c] += static_cast<int64_t>(ckeys[c][a] % q) * w;
+          w *= q;
+        }
+      }
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t a, int64_t b) { return cls[a] < cls[b]; });
+      std::vector<int32_t> cand;
+      const int32_t k = greedy_color_in_order(gptr, gadj, order, cand);
+      if (k < best) {
+        best = k;
+        lv.cell_color.swap(cand);
+      }
+    }
+  }
+  lv.ncolors = best;
+  lv.color.resize(n);
+  for (int64_t i = 0; i < n; ++i) lv.color[i] = lv.cell_color[lv.cell[i]];
 }
 
 // --------------------------------------------------------------------------
@@ -607,9 +696,10 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     Level& lv = H.levels.back();
     lv.n = static_cast<int64_t>(cur_keys.size());
     lv.keys = cur_keys;
-    if (R.size() == 1 && R[0].depth == 1) break;
     int Dstar = 0;
     for (const auto& r : R) Dstar = std::max(Dstar, r.depth);
+    lv.max_region_depth = Dstar;
+    if (R.size() == 1 && R[0].depth == 1) break;
     const uint64_t ps = side_of(Dstar - 1);
     std::vector<Region> Rn;
     std::vector<std::pair<Key, Key>> corner_parent;   // corner of a merged region -> parent lo
@@ -687,8 +777,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   coarsest.P = ScalarCSR();
   coarsest.color.assign(coarsest.n, 0);
   coarsest.ncolors = 0;
-  for (size_t l = 0; l + 1 < H.levels.size(); ++l)
-    H.levels[l].ncolors = greedy_color(H.levels[l].A, H.levels[l].color);
+  for (size_t l = 0; l + 1 < H.levels.size(); ++l) build_gs_order(H.levels[l], l > 0, d);
   dense_cholesky(coarsest.A, H.chol, H.n_coarse_dofs);
 }
 

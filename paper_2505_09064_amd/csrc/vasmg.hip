@@ -57,9 +57,17 @@ struct DevLevel {
   int ncolors = 0;
   int64_t nnz = 0;                 // off-diagonal blocks
   int G = 8;                       // lanes per block row
-  std::vector<int> color_ptr;      // host: device rows of colour c = [ptr[c], ptr[c+1])
+  std::vector<int> color_ptr;      // host: device rows (point levels) or cells (cell
+                                   // levels) of colour c = [ptr[c], ptr[c+1])
+  bool cells = false;              // coarse lattice level: Gauss-Seidel over cells
+  int ncells = 0;
+  int* cell_ptr = nullptr;         // cell levels: first device row of each cell
+  float* cellM32 = nullptr;        // cell levels: dense in-cell blocks (column-major)
+  double* cellM64 = nullptr;
   int* rowptr = nullptr;
-  int* split = nullptr;
+  int* split = nullptr;            // point levels: first block with col > row;
+                                   // cell levels: first block with col >= cell start
+  int* up_beg = nullptr;           // cell levels: first block with col >= cell end
   int* col = nullptr;
   int* perm = nullptr;             // device row -> canonical index
   float* val32 = nullptr;
@@ -147,89 +155,11 @@ namespace {
 // -------------------------------------------------------------------------
 // upload: colour-major renumbering, off-diagonal CSR + diagonal, transfers
 // -------------------------------------------------------------------------
-void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
+void upload_transfers(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
+                      const std::vector<int>& inv_next) {
   const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
-  const int d = C.d, dd = d * d, n = static_cast<int>(hl.n);
-  dl.n = n;
-  dl.d = d;
-  const bool coarsest = (l == C.L);
-  // device order: by colour, then canonical index (identity on the coarsest level)
-  std::vector<int> perm(n), inv(n);
-  if (coarsest) {
-    std::iota(perm.begin(), perm.end(), 0);
-    dl.ncolors = 1;
-    dl.color_ptr = {0, n};
-  } else {
-    dl.ncolors = hl.ncolors;
-    dl.color_ptr.assign(hl.ncolors + 1, 0);
-    for (int i = 0; i < n; ++i) dl.color_ptr[hl.color[i] + 1]++;
-    for (int c = 0; c < hl.ncolors; ++c) dl.color_ptr[c + 1] += dl.color_ptr[c];
-    std::vector<int> fill(dl.color_ptr.begin(), dl.color_ptr.end() - 1);
-    for (int i = 0; i < n; ++i) perm[fill[hl.color[i]]++] = i;
-  }
-  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
-  dl.perm = C.upload(perm);
-  if (coarsest && l > 0) return;   // a coarse coarsest level only needs its factor and vectors
-
-  // off-diagonal CSR in device numbering
-  std::vector<int> rowptr(n + 1, 0), split(n, 0);
-  for (int i = 0; i < n; ++i) {
-    const int c = perm[i];
-    rowptr[i + 1] = rowptr[i] + static_cast<int>(hl.A.rowptr[c + 1] - hl.A.rowptr[c] - 1);
-  }
-  const int64_t nnz = rowptr[n];
-  dl.nnz = nnz;
-  std::vector<int> col(nnz);
-  std::vector<double> diag(static_cast<size_t>(n) * dd);
-  std::vector<double> val(static_cast<size_t>(nnz) * dd);
-  {
-    std::vector<std::pair<int, int64_t>> row;
-    for (int i = 0; i < n; ++i) {
-      const int c = perm[i];
-      row.clear();
-      for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
-        const int j = hl.A.col[p];
-        if (j == c) {
-          std::copy(hl.A.val.begin() + p * dd, hl.A.val.begin() + (p + 1) * dd,
-                    diag.begin() + static_cast<int64_t>(i) * dd);
-        } else {
-          row.emplace_back(inv[j], p);
-        }
-      }
-      std::sort(row.begin(), row.end());
-      int k = rowptr[i];
-      split[i] = rowptr[i + 1];
-      bool found = false;
-      for (const auto& e : row) {
-        if (!found && e.first > i) {
-          split[i] = k;
-          found = true;
-        }
-        col[k] = e.first;
-        for (int t = 0; t < dd; ++t) val[static_cast<size_t>(t) * nnz + k] = hl.A.val[e.second * dd + t];
-        ++k;
-      }
-    }
-  }
-  const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
-  dl.G = std::min(64, std::max(4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
-  dl.rowptr = C.upload(rowptr);
-  dl.split = C.upload(split);
-  dl.col = C.upload(col);
-  if (need64) {
-    dl.val64 = C.upload(val);
-    dl.diag64 = C.upload(diag);
-    dl.has64 = true;
-  }
-  if (need32) {
-    std::vector<float> v32(val.begin(), val.end()), d32(diag.begin(), diag.end());
-    dl.val32 = C.upload(v32);
-    dl.diag32 = C.upload(d32);
-    dl.has32 = true;
-  }
-
-  if (coarsest) return;   // no transfer below the coarsest level
+  const int n = static_cast<int>(hl.n);
   // transfers P_l (rows: this level's device rows; cols: next level's device rows)
   const ScalarCSR& P = hl.P;
   const int nn = static_cast<int>(P.ncols);
@@ -271,19 +201,179 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   }
 }
 
+// Off-cell CSR (component-plane-major values) of the rows in device order.
+// cell_lo/cell_hi give each device row's cell range; blocks inside it are
+// handed to `in_cell` instead.
+template <class InCell>
+void build_offcell_csr(const Level& hl, const std::vector<int>& perm, const std::vector<int>& inv,
+                       const std::vector<int>& cell_lo, const std::vector<int>& cell_hi, int dd,
+                       std::vector<int>& rowptr, std::vector<int>& lo_end, std::vector<int>& up_beg,
+                       std::vector<int>& col, std::vector<double>& val, InCell in_cell) {
+  const int n = static_cast<int>(hl.n);
+  rowptr.assign(n + 1, 0);
+  lo_end.assign(n, 0);
+  up_beg.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const int c = perm[i];
+    int cnt = 0;
+    for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
+      const int j = inv[hl.A.col[p]];
+      if (j < cell_lo[i] || j >= cell_hi[i]) ++cnt;
+    }
+    rowptr[i + 1] = rowptr[i] + cnt;
+  }
+  const int64_t nnz = rowptr[n];
+  col.assign(nnz, 0);
+  val.assign(static_cast<size_t>(nnz) * dd, 0.0);
+  std::vector<std::pair<int, int64_t>> row;
+  for (int i = 0; i < n; ++i) {
+    const int c = perm[i];
+    row.clear();
+    for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
+      const int j = inv[hl.A.col[p]];
+      if (j < cell_lo[i] || j >= cell_hi[i])
+        row.emplace_back(j, p);
+      else
+        in_cell(i, j, hl.A.val.data() + p * dd);
+    }
+    std::sort(row.begin(), row.end());
+    int k = rowptr[i];
+    lo_end[i] = rowptr[i + 1];
+    up_beg[i] = rowptr[i + 1];
+    bool lo_set = false, up_set = false;
+    for (const auto& e : row) {
+      if (!lo_set && e.first >= cell_lo[i]) { lo_end[i] = k; lo_set = true; }
+      if (!up_set && e.first >= cell_hi[i]) { up_beg[i] = k; up_set = true; }
+      col[k] = e.first;
+      for (int t = 0; t < dd; ++t) val[static_cast<size_t>(t) * nnz + k] = hl.A.val[e.second * dd + t];
+      ++k;
+    }
+  }
+}
+
+void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
+  const Level& hl = C.H.levels[l];
+  DevLevel& dl = C.lev[l];
+  const int d = C.d, dd = d * d, n = static_cast<int>(hl.n);
+  dl.n = n;
+  dl.d = d;
+  const bool coarsest = (l == C.L);
+  dl.cells = !coarsest && l > 0;
+  // device order: colour, then cell, then canonical index (identity on the coarsest)
+  std::vector<int> perm(n), inv(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (coarsest) {
+    dl.ncolors = 1;
+    dl.color_ptr = {0, n};
+  } else {
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
+      return hl.cell[a] < hl.cell[b];
+    });
+    dl.ncolors = hl.ncolors;
+  }
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  dl.perm = C.upload(perm);
+  if (coarsest && l > 0) return;   // a coarse coarsest level only needs its factor and vectors
+
+  // cell of each device row (single rows on point levels)
+  std::vector<int> cell_lo(n), cell_hi(n), cell_ptr;
+  if (dl.cells) {
+    std::vector<int> ccp(dl.ncolors + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      if (i == 0 || hl.cell[perm[i]] != hl.cell[perm[i - 1]]) {
+        cell_ptr.push_back(i);
+        ccp[hl.color[perm[i]] + 1]++;
+      }
+    }
+    cell_ptr.push_back(n);
+    for (size_t c = 0; c + 1 < cell_ptr.size(); ++c)
+      if (cell_ptr[c + 1] - cell_ptr[c] > (1 << d))
+        throw vasmg::Error{VASMG_EINVAL, "internal: Gauss-Seidel cell larger than 2^d vertices"};
+    for (int c = 0; c < dl.ncolors; ++c) ccp[c + 1] += ccp[c];
+    dl.color_ptr = ccp;
+    dl.ncells = static_cast<int>(cell_ptr.size()) - 1;
+    for (int c = 0; c < dl.ncells; ++c)
+      for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) {
+        cell_lo[i] = cell_ptr[c];
+        cell_hi[i] = cell_ptr[c + 1];
+      }
+  } else {
+    if (!coarsest) {
+      dl.color_ptr.assign(dl.ncolors + 1, 0);
+      for (int i = 0; i < n; ++i) dl.color_ptr[hl.color[i] + 1]++;
+      for (int c = 0; c < dl.ncolors; ++c) dl.color_ptr[c + 1] += dl.color_ptr[c];
+    }
+    for (int i = 0; i < n; ++i) {
+      cell_lo[i] = i;
+      cell_hi[i] = i + 1;
+    }
+  }
+  std::vector<int> rowptr, lo_end, up_beg, col;
+  std::vector<double> val, diag, cellM;
+  if (dl.cells) {
+    const int NU = (1 << d) * d;
+    cellM.assign(static_cast<size_t>(dl.ncells) * NU * NU, 0.0);
+    std::vector<int> cell_of_row(n);
+    for (int c = 0; c < dl.ncells; ++c)
+      for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) cell_of_row[i] = c;
+    build_offcell_csr(hl, perm, inv, cell_lo, cell_hi, dd, rowptr, lo_end, up_beg, col, val,
+                      [&](int i, int j, const double* blk) {
+                        const int c = cell_of_row[i];
+                        const int ki = i - cell_ptr[c], kj = j - cell_ptr[c];
+                        double* M = cellM.data() + static_cast<size_t>(c) * NU * NU;
+                        for (int a = 0; a < d; ++a)
+                          for (int bb = 0; bb < d; ++bb)
+                            M[(kj * d + bb) * NU + (ki * d + a)] = blk[a * d + bb];
+                      });
+  } else {
+    diag.assign(static_cast<size_t>(n) * dd, 0.0);
+    build_offcell_csr(hl, perm, inv, cell_lo, cell_hi, dd, rowptr, lo_end, up_beg, col, val,
+                      [&](int i, int, const double* blk) {
+                        std::copy(blk, blk + dd, diag.begin() + static_cast<int64_t>(i) * dd);
+                      });
+  }
+  const int64_t nnz = rowptr[n];
+  dl.nnz = nnz;
+  const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
+  // lanes per block row: about two blocks per lane; cell levels use 16..64
+  dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
+  dl.rowptr = C.upload(rowptr);
+  dl.split = C.upload(lo_end);
+  dl.up_beg = C.upload(up_beg);
+  dl.col = C.upload(col);
+  if (dl.cells) dl.cell_ptr = C.upload(cell_ptr);
+  if (need64) {
+    dl.val64 = C.upload(val);
+    if (dl.cells)
+      dl.cellM64 = C.upload(cellM);
+    else
+      dl.diag64 = C.upload(diag);
+    dl.has64 = true;
+  }
+  if (need32) {
+    dl.val32 = C.upload(std::vector<float>(val.begin(), val.end()));
+    if (dl.cells)
+      dl.cellM32 = C.upload(std::vector<float>(cellM.begin(), cellM.end()));
+    else
+      dl.diag32 = C.upload(std::vector<float>(diag.begin(), diag.end()));
+    dl.has32 = true;
+  }
+  if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
+}
+
 // inverse permutation of level l's device numbering (canonical -> device)
 std::vector<int> device_inverse(const vasmg_ctx& C, int l) {
   const Level& hl = C.H.levels[l];
   const int n = static_cast<int>(hl.n);
-  std::vector<int> inv(n);
-  if (l == C.L) {
-    std::iota(inv.begin(), inv.end(), 0);
-    return inv;
-  }
-  std::vector<int> ptr(hl.ncolors + 1, 0);
-  for (int i = 0; i < n; ++i) ptr[hl.color[i] + 1]++;
-  for (int c = 0; c < hl.ncolors; ++c) ptr[c + 1] += ptr[c];
-  for (int i = 0; i < n; ++i) inv[i] = ptr[hl.color[i]]++;
+  std::vector<int> perm(n), inv(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (l != C.L)
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
+      return hl.cell[a] < hl.cell[b];
+    });
+  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
   return inv;
 }
 
@@ -369,6 +459,7 @@ struct LevelMats<float> {
   static const float* diag(const DevLevel& l) { return l.diag32; }
   static const float* pw(const DevLevel& l) { return l.p_w32; }
   static const float* ptw(const DevLevel& l) { return l.pt_w32; }
+  static const float* cellM(const DevLevel& l) { return l.cellM32; }
   static bool ok(const DevLevel& l) { return l.has32; }
 };
 template <>
@@ -377,6 +468,7 @@ struct LevelMats<double> {
   static const double* diag(const DevLevel& l) { return l.diag64; }
   static const double* pw(const DevLevel& l) { return l.p_w64; }
   static const double* ptw(const DevLevel& l) { return l.pt_w64; }
+  static const double* cellM(const DevLevel& l) { return l.cellM64; }
   static bool ok(const DevLevel& l) { return l.has64; }
 };
 
@@ -426,9 +518,56 @@ void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
   });
 }
 
+#define DISPATCH_GR(Gv, ...)                                  \
+  switch (Gv) {                                               \
+    case 16: { constexpr int GR = 16; __VA_ARGS__; } break;   \
+    case 32: { constexpr int GR = 32; __VA_ARGS__; } break;   \
+    default: { constexpr int GR = 64; __VA_ARGS__; } break;   \
+  }
+
+template <typename T, int D>
+void launch_gs_cells(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s_save,
+                     const int* done, hipStream_t st) {
+  const int c0 = lv.color_ptr[c], nc = lv.color_ptr[c + 1] - c0;
+  if (nc <= 0) return;
+  const T* M = LevelMats<T>::cellM(lv);
+  const T* v = LevelMats<T>::val(lv);
+  DISPATCH_GR(lv.G, {
+    const dim3 blk((1 << D) * GR);
+    if (mode == 0)
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 0>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+    else if (mode == 1)
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 1>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+    else
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 2>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+  });
+}
+
+template <typename T, int D, int KIND>
+void launch_cell_apply(const DevLevel& lv, const T* base, const T* x, T* out, const int* done,
+                       hipStream_t st) {
+  DISPATCH_GR(lv.G, {
+    hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND>), dim3(lv.ncells), dim3((1 << D) * GR), 0,
+                       st, lv.cell_ptr, lv.rowptr, lv.split, lv.up_beg, lv.col,
+                       LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::cellM(lv), base, x, out, done);
+  });
+}
+
 template <typename T, int D>
 void launch_gs_sweep(const DevLevel& lv, bool backward, bool zero_guess, const T* b, T* x,
                      T* s_save, const int* done, hipStream_t st) {
+  if (lv.cells) {
+    if (!backward) {
+      for (int c = 0; c < lv.ncolors; ++c)
+        launch_gs_cells<T, D>(lv, c, zero_guess ? 0 : 1, b, x, s_save, done, st);
+    } else {
+      for (int c = lv.ncolors - 1; c >= 0; --c) launch_gs_cells<T, D>(lv, c, 2, b, x, nullptr, done, st);
+    }
+    return;
+  }
   if (!backward) {
     for (int c = 0; c < lv.ncolors; ++c)
       launch_gs_color<T, D>(lv, c, zero_guess ? 0 : 1, b, x, s_save, done, st);
@@ -440,6 +579,10 @@ void launch_gs_sweep(const DevLevel& lv, bool backward, bool zero_guess, const T
 template <typename T, int D>
 void launch_residual_upper(const DevLevel& lv, const T* s, const T* x, T* r, const int* done,
                            hipStream_t st) {
+  if (lv.cells) {
+    launch_cell_apply<T, D, 0>(lv, s, x, r, done, st);
+    return;
+  }
   DISPATCH_G(lv.G, {
     hipLaunchKernelGGL((dev::k_residual_upper<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
                        dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.split, lv.col,
@@ -450,6 +593,10 @@ void launch_residual_upper(const DevLevel& lv, const T* s, const T* x, T* r, con
 template <typename T, int D>
 void launch_residual_full(const DevLevel& lv, const T* b, const T* x, T* r, const int* done,
                           hipStream_t st) {
+  if (lv.cells) {
+    launch_cell_apply<T, D, 1>(lv, b, x, r, done, st);
+    return;
+  }
   DISPATCH_G(lv.G, {
     hipLaunchKernelGGL((dev::k_residual_full<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
                        dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv),
@@ -925,9 +1072,9 @@ vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices
   return VASMG_OK;
 }
 
-vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* color,
-                                int64_t* rowptr, int32_t* cols, double* vals, int64_t* p_rowptr,
-                                int32_t* p_cols, double* p_vals) {
+vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* cell,
+                                int32_t* color, int64_t* rowptr, int32_t* cols, double* vals,
+                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals) {
   if (!h || level < 0 || level >= static_cast<int32_t>(h->H.levels.size())) {
     g_last_error = "null handle or level out of range";
     return VASMG_EINVAL;
@@ -941,6 +1088,9 @@ vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, in
   }
   if (color) {
     for (int64_t i = 0; i < lv.n; ++i) color[i] = lv.color.empty() ? 0 : lv.color[i];
+  }
+  if (cell) {
+    for (int64_t i = 0; i < lv.n; ++i) cell[i] = lv.cell.empty() ? 0 : lv.cell[i];
   }
   if (rowptr) std::copy(lv.A.rowptr.begin(), lv.A.rowptr.end(), rowptr);
   if (cols) std::copy(lv.A.col.begin(), lv.A.col.end(), cols);
@@ -988,7 +1138,10 @@ vasmg_status vasmg_spmv_device(vasmg_handle h, int32_t level, int32_t precision,
         yout = reinterpret_cast<T*>(h->Q);
       }
       debug_gather<T, D>(*h, level, d_x, xin, st);
-      launch_spmv<T, D>(lv, xin, yout, nullptr, 0, nullptr, st);
+      if (lv.cells)
+        launch_cell_apply<T, D, 2>(lv, nullptr, xin, yout, nullptr, st);
+      else
+        launch_spmv<T, D>(lv, xin, yout, nullptr, 0, nullptr, st);
       debug_scatter<T, D>(*h, level, yout, d_y, st);
     };
     if (precision == VASMG_FP64) {

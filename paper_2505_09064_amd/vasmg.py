@@ -85,7 +85,7 @@ def lib():
             "vasmg_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
             "vasmg_level_info": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
                                        C.POINTER(i64)]),
-            "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "vasmg_tree_info": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
             "vasmg_spmv_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_gs_sweep_device": (i32, [vp, i32, i32, i32, vp, vp, vp]),
@@ -232,6 +232,7 @@ class Solver:
         d = self.dim
         n, nb, pn = info["n_vertices"], info["n_blocks"], info["p_nnz"]
         keys = np.empty((n, d), dtype=np.int64)
+        cell = np.empty(n, dtype=np.int32)
         color = np.empty(n, dtype=np.int32)
         rowptr = np.empty(n + 1, dtype=np.int64)
         cols = np.empty(nb, dtype=np.int32)
@@ -239,9 +240,10 @@ class Solver:
         prow = np.empty(n + 1, dtype=np.int64)
         pcol = np.empty(pn, dtype=np.int32)
         pval = np.empty(pn, dtype=np.float64)
-        _check(lib().vasmg_export_level(self._h, level, _ptr(keys), _ptr(color), _ptr(rowptr),
-                                        _ptr(cols), _ptr(vals), _ptr(prow), _ptr(pcol), _ptr(pval)))
-        return dict(keys=keys, color=color, rowptr=rowptr, cols=cols, vals=vals,
+        _check(lib().vasmg_export_level(self._h, level, _ptr(keys), _ptr(cell), _ptr(color),
+                                        _ptr(rowptr), _ptr(cols), _ptr(vals), _ptr(prow),
+                                        _ptr(pcol), _ptr(pval)))
+        return dict(keys=keys, cell=cell, color=color, rowptr=rowptr, cols=cols, vals=vals,
                     p_rowptr=prow, p_cols=pcol, p_vals=pval, **info)
 
     def tree_info(self):

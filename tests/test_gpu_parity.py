@@ -86,7 +86,7 @@ def test_kernel_parity_per_level(name, prec):
         s.spmv_device(l, prec, _dev(x), y)
         assert _rel(_host(y).ravel(), A @ x.ravel()) < tol, (l, "spmv")
         # GS forward and backward sweeps from a nonzero guess
-        S = ColoredGS(A, d, o.colors[l])
+        S = ColoredGS(A, d, o.cells[l], o.cell_colors[l])
         for bw in (0, 1):
             xg = _dev(x)
             s.gs_sweep_device(l, prec, bw, _dev(b), xg)

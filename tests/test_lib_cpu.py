@@ -47,6 +47,7 @@ def _compare(mesh, oopts=None, **kw):
         S = sp.csr_matrix((np.ones(e["cols"].size), e["cols"], e["rowptr"]), shape=(n, n))
         assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs"
         if l < o.L:
+            assert np.array_equal(e["cell"], o.cells[l])
             assert np.array_equal(e["color"], o.colors[l])
             assert e["n_colors"] == o.colors[l].max() + 1
             P = sp.csr_matrix((e["p_vals"], e["p_cols"], e["p_rowptr"]), shape=o.P[l].shape)
