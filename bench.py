@@ -28,6 +28,32 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
+
+
+def cpu_baseline(n_grid: int = 33, reps: int = 3):
+    """The oracle (plain NumPy/SciPy FP64 V-ASMG-PCG, coloured Gauss-Seidel) on a
+    bounded sample of the workload: the same recipe at n_grid^3 vertices. Only the
+    solve phase is timed (median of reps); the rate is scaled to the full workload
+    by DOFs x iterations."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Oracle
+    from workloads import small3d
+    with threadpool_limits(limits=1):
+        m = small3d(n_grid, seed=1, fix="x0")
+        t0 = time.perf_counter()
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        t_setup = time.perf_counter() - t0
+        ts, its = [], 0
+        for _ in range(reps):
+            _, info = o.solve(m.rhs[0], 1e-6)
+            ts.append(info["solve_seconds"])
+            its = info["iterations"]
+    return dict(n_dofs=int(o.A[0].shape[0]), iterations=its, solve_s=float(np.median(ts)),
+                setup_s=t_setup, grid=n_grid)
+
+
 def time_solves(solver, d_rhs, d_x, n, rtol=1e-6):
     import torch
     out = []
@@ -47,6 +73,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -66,7 +93,8 @@ def main():
     d_x = torch.zeros_like(d_rhs)
 
     t0 = time.perf_counter()
-    mixed = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, verbose=1)
+    mixed = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, verbose=1,
+                               autotune=0 if args.no_autotune else 1)
     t_setup = time.perf_counter() - t0
     log(f"setup (mixed) {t_setup:.1f}s")
     for i in range(args.warmup):
@@ -85,7 +113,7 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        fp64 = V.Solver.from_mesh(mesh, precision=V.FP64)
+        fp64 = V.Solver.from_mesh(mesh, precision=V.FP64, autotune=0 if args.no_autotune else 1)
         time_solves(fp64, d_rhs, d_x, 1)
         r64 = time_solves(fp64, d_rhs, d_x, max(3, args.steps // 4))
         variants["fp64_vasmg"] = dict(ms_per_solve=float(np.mean([r[0] for r in r64])),
@@ -97,6 +125,37 @@ def main():
                                            iterations=rj[-1][1]["iterations"])
         jac.free()
         log(f"variants: {variants}")
+
+    # per-phase device time and algorithmic bytes of one iteration (event-timed
+    # launches on the solve's stream, same kernels and launch configuration)
+    phases = mixed.profile_iteration(3)
+    reps = 3
+    it_ms = sum(p["ms"] for p in phases) / reps
+    it_bytes = sum(p["bytes"] for p in phases) / reps
+    dom = max(phases, key=lambda p: p["ms"])
+    dom_launch_ms = dom["ms"] / dom["launches"]
+    dom_launch_bytes = dom["bytes"] / dom["launches"]
+    achieved = dom_launch_bytes / dom_launch_ms / 1e6          # GB/s
+    log(f"dominant phase: {dom['name']} level {dom['level']}: "
+        f"{dom['launches'] / reps:.0f} launches/iteration, {dom_launch_ms * 1e3:.2f} us and "
+        f"{dom_launch_bytes / 1e6:.2f} MB per launch -> {achieved:.0f} GB/s")
+    for p in sorted(phases, key=lambda p: -p["ms"])[:8]:
+        log(f"  {p['name']:13s} L{p['level']:2d} {p['ms'] / reps:7.3f} ms/it "
+            f"{p['bytes'] / p['ms'] / 1e6:6.0f} GB/s")
+    mixed.free()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline()
+        scale = (mesh.n_dofs / cb["n_dofs"]) * (its[0] / max(cb["iterations"], 1))
+        t_equiv = cb["solve_s"] * scale
+        cpu = {"value": 1.0 / t_equiv, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": (f"oracle FP64 V-ASMG-PCG solve phase (coloured GS, rtol 1e-6) on the "
+                          f"same recipe at {cb['grid']}^3 vertices ({cb['n_dofs']} DOFs, "
+                          f"{cb['iterations']} its, {cb['solve_s']:.2f} s median of 3), scaled by "
+                          f"DOFs x iterations to the {mesh.n_dofs}-DOF workload"),
+               "sample_solve_s": cb["solve_s"]}
+        log(f"cpu baseline: {cpu}")
 
     ms_per = float(np.mean(ms))
     line = {
@@ -110,7 +169,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle in f64 PCG",
+        "dtype": "f32 (V-cycle) + f64 (PCG)",
         "data": "synthetic",
         "config": {"workload": "3D P1 elasticity, 65^3 jittered Kuhn mesh (seed 1), clamped x=0, "
                                "f=(0,0,-1), 811,200 DOFs, V(1,1) V-ASMG-PCG rtol 1e-6",
@@ -122,6 +181,14 @@ def main():
         "rel_res_true": info["rel_res_true"],
         "setup_s": t_setup,
         "timed_region_s": t_total,
+        "iteration_ms_profiled": it_ms,
+        "iteration_bytes": it_bytes,
+        "solve_GBps": it_bytes * its[0] / (ms_per * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"{dom['name']} on level {dom['level']}",
+                     "launch_us": dom_launch_ms * 1e3, "launch_bytes": dom_launch_bytes},
+        "cpu_baseline": cpu,
         "variants": variants,
     }
     print(json.dumps(line), flush=True)

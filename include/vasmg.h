@@ -86,7 +86,10 @@ typedef struct {
   int32_t host_only;           /* 1 = build the hierarchy on the host only (no device
                                   upload; solves return VASMG_EDEVICE). Introspection.    */
   int32_t verbose;             /* 1 = print level statistics at setup                     */
-  int32_t reserved[7];
+  int32_t autotune;            /* 1 = time the candidate lanes-per-block-row of each
+                                  level's kernels at setup and keep the fastest (results
+                                  then differ from another handle's by rounding only)     */
+  int32_t reserved[6];
 } vasmg_options;
 
 typedef struct {
@@ -194,6 +197,28 @@ vasmg_status vasmg_prolong_device(vasmg_handle h, int32_t level, int32_t precisi
  * handle's precision. r, z: [n_free_vertices][dim] FP64, canonical order. */
 vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, double* d_z,
                                         void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement. One PCG iteration's device work (fine FP64 SpMV q = A p of
+ * Algorithm 2, the PCG vector updates, and one V-cycle of Algorithm 3) is
+ * replayed reps times outside the captured graphs with hipEvents around each
+ * phase; phases are aggregated by (name, level). names: spmv_f64, pcg_vectors,
+ * gs_fwd_zero, gs_fwd, residual, residual_full, restrict, coarse_solve,
+ * prolong, gs_bwd. bytes is the algorithmic HBM traffic of the phase (every
+ * matrix/vector array it touches read or written once per launch, the gathered
+ * neighbour vector once per launch). Uses the handle's work buffers (their
+ * contents are overwritten); level -1 = PCG vectors.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[32];
+  int32_t level;
+  int32_t launches;
+  double ms;
+  double bytes;
+} vasmg_phase_stat;
+
+vasmg_status vasmg_profile_iteration(vasmg_handle h, int32_t reps, void* stream,
+                                     vasmg_phase_stat* out, int32_t max_out, int32_t* n_out);
 
 #ifdef __cplusplus
 }

@@ -96,21 +96,55 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Broadcast of lane l's value to the wavefront (l uniform, all lanes active).
+__device__ __forceinline__ float bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return *p;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void block_fma(const T* __restrict__ val, int64_t nnz, int k,
+                                          const T* xj, T* acc) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll
+    for (int b = 0; b < D; ++b) acc[a] += ld_stream(val + (a * D + b) * nnz + k) * xj[b];
+  }
+}
+
 // Off-diagonal block row product over positions [kb, ke): acc += sum A_k x_col(k).
+// Two blocks per lane per step keep more loads in flight.
 template <typename T, int D, int G>
 __device__ __forceinline__ void row_product(int kb, int ke, int lane, const int* __restrict__ col,
                                             const T* __restrict__ val, int64_t nnz,
                                             const T* __restrict__ x, T* acc) {
   constexpr int DP = Pad<D>::value;
-  for (int k = kb + lane; k < ke; k += G) {
-    const int j = col[k];
+  int k = kb + lane;
+  for (; k + G < ke; k += 2 * G) {
+    const int j0 = ld_stream(col + k);
+    const int j1 = ld_stream(col + k + G);
+    T x0[D], x1[D];
+    VecIO<T, D>::load(x + static_cast<int64_t>(j0) * DP, x0);
+    VecIO<T, D>::load(x + static_cast<int64_t>(j1) * DP, x1);
+    block_fma<T, D>(val, nnz, k, x0, acc);
+    block_fma<T, D>(val, nnz, k + G, x1, acc);
+  }
+  if (k < ke) {
+    const int j = ld_stream(col + k);
     T xj[D];
     VecIO<T, D>::load(x + static_cast<int64_t>(j) * DP, xj);
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-      for (int b = 0; b < D; ++b) acc[a] += val[(a * D + b) * nnz + k] * xj[b];
-    }
+    block_fma<T, D>(val, nnz, k, xj, acc);
   }
 }
 
@@ -212,6 +246,20 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(
   const int g = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   if (g >= nrows) return;
   const int i = row0 + g;
+  // lane 0 fetches what it needs to finish the row before the row product
+  T dg[D * D], xi[D], bi[D];
+  if (lane == 0) {
+    const T* dp = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) dg[e] = dp[e];
+    VecIO<T, D>::load(b + static_cast<int64_t>(i) * DP, bi);
+    if (MODE == 0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) xi[a] = T(0);
+    } else {
+      VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+    }
+  }
   const int kb = rowptr[i], ks = split[i], ke = rowptr[i + 1];
   T lo[D], up[D];
 #pragma unroll
@@ -224,22 +272,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(
     if (MODE != 0) up[a] = group_sum<T, G>(up[a]);
   }
   if (lane != 0) return;
-  T xi[D], bi[D], rhs[D];
-  if (MODE == 0) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) xi[a] = T(0);
-  } else {
-    VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
-  }
-  VecIO<T, D>::load(b + static_cast<int64_t>(i) * DP, bi);
-  T s[D];
+  T s[D], rhs[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     s[a] = bi[a] - lo[a];
     rhs[a] = s[a] - up[a];
   }
   if (MODE != 2 && s_save) VecIO<T, D>::store(s_save + static_cast<int64_t>(i) * DP, s);
-  const T* dg = diag + static_cast<int64_t>(i) * D * D;
   if (MODE != 2) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -361,27 +400,37 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
   __shared__ T sh_lo[NV][D], sh_up[NV][D];
   const int c = cell0 + blockIdx.x;
   const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
-  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, true, MODE != 0,
-                              sh_lo, sh_up);
-  if (threadIdx.x >= 64) return;          // wavefront 0 finishes the cell
+  // wavefront 0 fetches its part of the in-cell solve first, so these loads
+  // overlap the off-cell products
   const int t = threadIdx.x;
   const bool own = t < n;
   const int k = own ? t / D : 0, a = own ? t % D : 0;
   const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
-  const T s_t = own ? b[xi] - sh_lo[k][a] : T(0);
+  T Mrow[NU];
+  T bt = T(0), xc = T(0);
+  if (t < 64) {
+    const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
+    if (own) {
+      bt = b[xi];
+      if (MODE != 0) xc = x[xi];
+    }
+  }
+  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, true, MODE != 0,
+                              sh_lo, sh_up);
+  if (t >= 64) return;                    // wavefront 0 finishes the cell
+  const T s_t = own ? bt - sh_lo[k][a] : T(0);
   const T sup = (own && MODE != 0) ? sh_up[k][a] : T(0);
   if (MODE != 2 && s_save && own) s_save[xi] = s_t;
-  T Mrow[NU];
-  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
-#pragma unroll
-  for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
-  T xc = (MODE == 0 || !own) ? T(0) : x[xi];
   T acc = s_t - sup;
   if (MODE != 0) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const T xu = __shfl(xc, u);
-      if (u != t) acc -= Mrow[u] * xu;
+      if (u < n) {
+        const T xu = bcast(xc, u);
+        if (u != t) acc -= Mrow[u] * xu;
+      }
     }
   }
   if (MODE != 2) {
@@ -394,7 +443,7 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
           delta = xn - xc;
           xc = xn;
         }
-        delta = __shfl(delta, u);
+        delta = bcast(delta, u);
         if (t != u) acc -= Mrow[u] * delta;
       }
     }
@@ -408,7 +457,7 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
           delta = xn - xc;
           xc = xn;
         }
-        delta = __shfl(delta, u);
+        delta = bcast(delta, u);
         if (t != u) acc -= Mrow[u] * delta;
       }
     }
@@ -446,8 +495,10 @@ __global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
   T mx = T(0);
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    const T xu = __shfl(xt, u);
-    if (own && u < n) mx += Mc[u * NU + t] * xu;
+    if (u < n) {
+      const T xu = bcast(xt, u);
+      if (own) mx += Mc[u * NU + t] * xu;
+    }
   }
   if (!own) return;
   if (KIND == 2)

@@ -55,8 +55,11 @@ struct DevLevel {
   int n = 0;
   int d = 0;
   int ncolors = 0;
-  int64_t nnz = 0;                 // off-diagonal blocks
-  int G = 8;                       // lanes per block row
+  int64_t nnz = 0;                 // off-diagonal (point) or off-cell (cell) blocks
+  int64_t nnz_lo = 0, nnz_up = 0;  // blocks coupling to earlier / later colours
+  int64_t p_nnz = 0;               // entries of P_l
+  int G = 8;                       // lanes per block row (Gauss-Seidel, residual)
+  int Gspmv = 8;                   // lanes per block row of the fine FP64 SpMV
   std::vector<int> color_ptr;      // host: device rows (point levels) or cells (cell
                                    // levels) of colour c = [ptr[c], ptr[c+1])
   bool cells = false;              // coarse lattice level: Gauss-Seidel over cells
@@ -187,6 +190,7 @@ void upload_transfers(vasmg_ctx& C, int l, bool need32, bool need64, const std::
         tw[q] = pw[k];
       }
   }
+  dl.p_nnz = static_cast<int64_t>(pidx.size());
   dl.p_ptr = C.upload(pptr);
   dl.p_idx = C.upload(pidx);
   dl.pt_ptr = C.upload(tptr);
@@ -335,9 +339,14 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   }
   const int64_t nnz = rowptr[n];
   dl.nnz = nnz;
+  for (int i = 0; i < n; ++i) {
+    dl.nnz_lo += lo_end[i] - rowptr[i];
+    dl.nnz_up += rowptr[i + 1] - up_beg[i];
+  }
   const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
   // lanes per block row: about two blocks per lane; cell levels use 16..64
   dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
+  dl.Gspmv = dl.G;
   dl.rowptr = C.upload(rowptr);
   dl.split = C.upload(lo_end);
   dl.up_beg = C.upload(up_beg);
@@ -427,7 +436,8 @@ void upload_all(vasmg_ctx& C) {
   // FP64 V-cycle: its fine right-hand side is the PCG residual itself
   if (!C.vc32) C.lev[0].b = C.R;
   // partial sums: the flat reduction grid, or one per workgroup of the fine SpMV
-  C.n_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / C.lev[0].G));
+  // (sized for the narrowest workgroup row count any lane width can give)
+  C.n_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / 64));
   C.partial = C.dalloc<double>(C.n_partial);
   C.sc = C.dalloc<Scalars>(1);
   HIP_CHECK(hipMemset(C.sc, 0, sizeof(Scalars)));
@@ -472,14 +482,17 @@ struct LevelMats<double> {
   static bool ok(const DevLevel& l) { return l.has64; }
 };
 
+// Returns the number of workgroups (= partial sums written when partial != NULL).
 template <typename T, int D>
-void launch_spmv(const DevLevel& lv, const T* x, T* y, double* partial, int n_partial,
-                 const int* done, hipStream_t st) {
-  const int G = lv.G;
+int launch_spmv(const DevLevel& lv, const T* x, T* y, double* partial, int n_partial,
+                const int* done, hipStream_t st) {
+  const int G = lv.Gspmv;
+  int used = 0;
   DISPATCH_G(G, {
     const int grid = grid_for(lv.n, dev::kBlock / GG);
     if (partial && grid > n_partial)
       throw vasmg::Error{VASMG_EINVAL, "internal: SpMV partial buffer too small"};
+    used = grid;
     if (partial)
       hipLaunchKernelGGL((dev::k_spmv<T, D, GG, true>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
                          lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::diag(lv),
@@ -489,12 +502,9 @@ void launch_spmv(const DevLevel& lv, const T* x, T* y, double* partial, int n_pa
                          lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz,
                          LevelMats<T>::diag(lv), x, y, partial, done);
   });
+  return used;
 }
 
-template <typename T, int D>
-int spmv_grid(const DevLevel& lv) {
-  return grid_for(lv.n, dev::kBlock / lv.G);
-}
 
 template <typename T, int D>
 void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s_save,
@@ -520,6 +530,7 @@ void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
 
 #define DISPATCH_GR(Gv, ...)                                  \
   switch (Gv) {                                               \
+    case 8: { constexpr int GR = 8; __VA_ARGS__; } break;     \
     case 16: { constexpr int GR = 16; __VA_ARGS__; } break;   \
     case 32: { constexpr int GR = 32; __VA_ARGS__; } break;   \
     default: { constexpr int GR = 64; __VA_ARGS__; } break;   \
@@ -624,35 +635,135 @@ void launch_fill(T* a, int64_t n, T v, hipStream_t st) {
                      dim3(dev::kBlock), 0, st, n, a, v);
 }
 
+// -------------------------------------------------------------------------
+// Phase profiler: brackets each phase of the schedule with events (outside
+// graphs) and accumulates launches, device time and algorithmic HBM bytes.
+// -------------------------------------------------------------------------
+struct PhaseStat {
+  std::string name;
+  int level;
+  int launches;
+  double ms;
+  double bytes;
+};
+
+struct Profiler {
+  hipStream_t st;
+  std::vector<PhaseStat> stats;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<size_t> pending_idx;
+  template <class F>
+  void phase(const std::string& name, int level, int launches, double bytes, F&& fn) {
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    HIP_CHECK(hipEventRecord(a, st));
+    fn();
+    HIP_CHECK(hipEventRecord(b, st));
+    size_t idx = stats.size();
+    for (size_t i = 0; i < stats.size(); ++i)
+      if (stats[i].name == name && stats[i].level == level) idx = i;
+    if (idx == stats.size()) stats.push_back({name, level, 0, 0.0, 0.0});
+    stats[idx].launches += launches;
+    stats[idx].bytes += bytes;
+    pending.emplace_back(a, b);
+    pending_idx.push_back(idx);
+  }
+  void finish() {
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < pending.size(); ++i) {
+      float ms = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&ms, pending[i].first, pending[i].second));
+      stats[pending_idx[i]].ms += ms;
+      (void)hipEventDestroy(pending[i].first);
+      (void)hipEventDestroy(pending[i].second);
+    }
+    pending.clear();
+    pending_idx.clear();
+  }
+};
+
+template <class F>
+void run_phase(Profiler* prof, const char* name, int level, int launches, double bytes, F&& fn) {
+  if (prof)
+    prof->phase(name, level, launches, bytes, fn);
+  else
+    fn();
+}
+
+// Algorithmic HBM bytes of the phases of one level (each array read or written
+// once per launch; the gathered neighbour vector counted once per launch).
+struct LevelBytes {
+  double gs_fwd0, gs_fwd, residual, gs_bwd, restrict_, prolong;
+};
+
+LevelBytes level_bytes(const vasmg_ctx& C, int l, int tb) {
+  const DevLevel& lv = C.lev[l];
+  const int D = C.d, DP = C.DP, dd = D * D;
+  const double blk = dd * tb + 4.0;                 // values + column index
+  const double n = lv.n, vec = n * DP * tb;
+  const int NU = (1 << D) * D;
+  const double own = lv.cells ? lv.ncells * (NU * NU * static_cast<double>(tb) + 4.0)
+                              : n * dd * static_cast<double>(tb);
+  const double rows = n * 12.0;                      // rowptr, lower end, upper begin
+  const int launches_per_sweep = lv.ncolors;
+  (void)launches_per_sweep;
+  LevelBytes b{};
+  b.gs_fwd0 = lv.nnz_lo * blk + rows + own + 4 * vec;        // b, x(w), s(w), x gathers
+  b.gs_fwd = (lv.nnz_lo + lv.nnz_up) * blk + rows + own + 5 * vec;
+  b.residual = lv.nnz_up * blk + rows + own + 4 * vec;       // s, x, gathers, r(w)
+  b.gs_bwd = (lv.nnz_lo + lv.nnz_up) * blk + rows + own + 4 * vec;
+  const double nn = lv.nnext;
+  b.restrict_ = lv.p_nnz * (4.0 + tb) + (nn + 1) * 4 + vec + nn * DP * tb;
+  b.prolong = lv.p_nnz * (4.0 + tb) + (n + 1) * 4 + nn * DP * tb + 2 * vec;
+  return b;
+}
+
 // One V-cycle: lev[0].b -> lev[0].x (Algorithm 3, recursive, zero initial guess).
 template <typename T, int D>
-void enqueue_vcycle(vasmg_ctx& C, const int* done, hipStream_t st) {
+void enqueue_vcycle(vasmg_ctx& C, const int* done, hipStream_t st, Profiler* prof = nullptr) {
   const int L = C.L;
   const int npre = C.opt.n_pre, npost = C.opt.n_post;
+  const int tb = sizeof(T);
   for (int l = 0; l < L; ++l) {
     DevLevel& lv = C.lev[l];
     T* b = static_cast<T*>(lv.b);
     T* x = static_cast<T*>(lv.x);
     T* s = static_cast<T*>(lv.s);
     T* r = static_cast<T*>(lv.r);
+    const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
     if (npre == 0) {
-      launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
-      launch_residual_full<T, D>(lv, b, x, r, done, st);
+      run_phase(prof, "residual_full", l, 2, by.gs_fwd, [&] {
+        launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
+        launch_residual_full<T, D>(lv, b, x, r, done, st);
+      });
     } else {
-      for (int k = 0; k < npre; ++k) launch_gs_sweep<T, D>(lv, false, k == 0, b, x, s, done, st);
-      launch_residual_upper<T, D>(lv, s, x, r, done, st);
+      for (int k = 0; k < npre; ++k)
+        run_phase(prof, k == 0 ? "gs_fwd_zero" : "gs_fwd", l, lv.ncolors,
+                  k == 0 ? by.gs_fwd0 : by.gs_fwd,
+                  [&] { launch_gs_sweep<T, D>(lv, false, k == 0, b, x, s, done, st); });
+      run_phase(prof, "residual", l, 1, by.residual,
+                [&] { launch_residual_upper<T, D>(lv, s, x, r, done, st); });
     }
-    launch_restrict<T, D>(lv, r, static_cast<T*>(C.lev[l + 1].b), done, st);
+    run_phase(prof, "restrict", l, 1, by.restrict_,
+              [&] { launch_restrict<T, D>(lv, r, static_cast<T*>(C.lev[l + 1].b), done, st); });
   }
-  hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
-                     static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
-                     static_cast<T*>(C.lev[L].x), done);
+  run_phase(prof, "coarse_solve", L, 1, static_cast<double>(C.n_coarse) * C.n_coarse * 8.0, [&] {
+    hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                       static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
+                       static_cast<T*>(C.lev[L].x), done);
+  });
   for (int l = L - 1; l >= 0; --l) {
     DevLevel& lv = C.lev[l];
     T* b = static_cast<T*>(lv.b);
     T* x = static_cast<T*>(lv.x);
-    launch_prolong<T, D>(lv, static_cast<const T*>(C.lev[l + 1].x), x, done, st);
-    for (int k = 0; k < npost; ++k) launch_gs_sweep<T, D>(lv, true, false, b, x, nullptr, done, st);
+    const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
+    run_phase(prof, "prolong", l, 1, by.prolong, [&] {
+      launch_prolong<T, D>(lv, static_cast<const T*>(C.lev[l + 1].x), x, done, st);
+    });
+    for (int k = 0; k < npost; ++k)
+      run_phase(prof, "gs_bwd", l, lv.ncolors, by.gs_bwd,
+                [&] { launch_gs_sweep<T, D>(lv, true, false, b, x, nullptr, done, st); });
   }
 }
 
@@ -671,9 +782,9 @@ template <int D>
 void enqueue_iter_A(vasmg_ctx& C, hipStream_t st) {
   const DevLevel& l0 = C.lev[0];
   const int* done = &C.sc->done;
-  launch_spmv<double, D>(l0, C.P, C.Q, C.partial, C.n_partial, done, st);
-  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_ALPHA>), dim3(1), dim3(1024), 0, st, C.partial,
-                     spmv_grid<double, D>(l0), C.sc);
+  const int np = launch_spmv<double, D>(l0, C.P, C.Q, C.partial, C.n_partial, done, st);
+  hipLaunchKernelGGL((dev::k_finalize<dev::FIN_ALPHA>), dim3(1), dim3(1024), 0, st, C.partial, np,
+                     C.sc);
   if (C.vc32)
     hipLaunchKernelGGL((dev::k_update_xr<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
                        C.sc, C.P, C.Q, C.X, C.R, static_cast<float*>(C.lev[0].b), C.partial);
@@ -720,6 +831,108 @@ void enqueue_iter_B(vasmg_ctx& C, hipStream_t st) {
     hipLaunchKernelGGL((dev::k_update_p<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
                        C.sc, z, C.P);
   }
+}
+
+// -------------------------------------------------------------------------
+// Autotuner: lanes per block row of each level, by timing the level's own
+// kernels (forward zero-guess sweep + residual + backward sweep, and the fine
+// FP64 SpMV) with hipEvents; the fastest median of three wins.
+// -------------------------------------------------------------------------
+template <typename T, int D>
+double time_level(vasmg_ctx& C, int l, hipStream_t st) {
+  DevLevel& lv = C.lev[l];
+  T* b = static_cast<T*>(lv.b);
+  T* x = static_cast<T*>(lv.x);
+  T* s = static_cast<T*>(lv.s);
+  T* r = static_cast<T*>(lv.r);
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  std::vector<float> t;
+  for (int rep = 0; rep < 4; ++rep) {
+    HIP_CHECK(hipEventRecord(e0, st));
+    launch_gs_sweep<T, D>(lv, false, true, b, x, s, nullptr, st);
+    launch_residual_upper<T, D>(lv, s, x, r, nullptr, st);
+    launch_gs_sweep<T, D>(lv, true, false, b, x, nullptr, nullptr, st);
+    HIP_CHECK(hipEventRecord(e1, st));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+template <int D>
+double time_spmv(vasmg_ctx& C, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  std::vector<float> t;
+  for (int rep = 0; rep < 4; ++rep) {
+    HIP_CHECK(hipEventRecord(e0, st));
+    launch_spmv<double, D>(C.lev[0], C.P, C.Q, C.partial, C.n_partial, nullptr, st);
+    HIP_CHECK(hipEventRecord(e1, st));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+template <int D>
+void autotune(vasmg_ctx& C) {
+  hipStream_t st = C.cap_stream;
+  const int last = C.opt.preconditioner == VASMG_PRECOND_VASMG ? C.L - 1 : -1;
+  for (int l = 0; l <= last; ++l) {
+    DevLevel& lv = C.lev[l];
+    const int64_t len = static_cast<int64_t>(lv.n) * C.DP;
+    if (C.vc32) {
+      launch_fill<float>(static_cast<float*>(lv.b), len, 1.0f, st);
+      launch_fill<float>(static_cast<float*>(lv.x), len, 0.0f, st);
+    } else {
+      launch_fill<double>(static_cast<double*>(lv.b), len, 1.0, st);
+      launch_fill<double>(static_cast<double*>(lv.x), len, 0.0, st);
+    }
+    std::vector<int> cand = lv.cells ? std::vector<int>{D == 3 ? 8 : 16, 16, 32, 64}
+                                     : std::vector<int>{4, 8, 16, 32};
+    double best = 1e30;
+    int bestG = lv.G;
+    for (int g : cand) {
+      lv.G = g;
+      const double ms = C.vc32 ? time_level<float, D>(C, l, st) : time_level<double, D>(C, l, st);
+      if (ms < best) {
+        best = ms;
+        bestG = g;
+      }
+    }
+    lv.G = bestG;
+    if (C.opt.verbose)
+      std::fprintf(stderr, "[vasmg] autotune level %d: %d lanes per row (%.3f ms per V(1,1) pass)\n",
+                   l, bestG, best);
+  }
+  launch_fill<double>(C.P, C.n0p, 1.0, st);
+  double best = 1e30;
+  int bestG = C.lev[0].Gspmv;
+  for (int g : {4, 8, 16, 32}) {
+    C.lev[0].Gspmv = g;
+    const double ms = time_spmv<D>(C, st);
+    if (ms < best) {
+      best = ms;
+      bestG = g;
+    }
+  }
+  C.lev[0].Gspmv = bestG;
+  if (C.opt.verbose)
+    std::fprintf(stderr, "[vasmg] autotune fine SpMV: %d lanes per row (%.3f ms)\n", bestG, best);
+  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 hipGraphExec_t capture(vasmg_ctx& C, void (*fn)(vasmg_ctx&, hipStream_t)) {
@@ -972,6 +1185,12 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
       HIP_CHECK(hipGetDevice(&C->device));
       upload_all(*C);
+      if (o.autotune) {
+        if (C->d == 2)
+          autotune<2>(*C);
+        else
+          autotune<3>(*C);
+      }
     }
     *out = C.release();
     return VASMG_OK;
@@ -1287,6 +1506,87 @@ vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, doubl
     }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(st));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_profile_iteration(vasmg_handle h, int32_t reps, void* stream,
+                                     vasmg_phase_stat* out, int32_t max_out, int32_t* n_out) {
+  try {
+    check_handle(h);
+    if (reps < 1 || !out || max_out < 1) throw vasmg::Error{VASMG_EINVAL, "bad reps/out"};
+    if (h->opt.preconditioner != VASMG_PRECOND_VASMG)
+      throw vasmg::Error{VASMG_EINVAL, "handle was not set up with the V-ASMG preconditioner"};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    vasmg_ctx& C = *h;
+    // defined inputs: p = 1, V-cycle right-hand side = 1, flags cleared
+    launch_fill<double>(C.P, C.n0p, 1.0, st);
+    if (C.vc32)
+      launch_fill<float>(static_cast<float*>(C.lev[0].b), C.n0p, 1.0f, st);
+    else
+      launch_fill<double>(static_cast<double*>(C.lev[0].b), C.n0p, 1.0, st);
+    const int zero = 0;
+    HIP_CHECK(hipMemcpyAsync(&C.sc->done, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    Profiler prof{st, {}, {}, {}};
+    const DevLevel& l0 = C.lev[0];
+    const double n0 = l0.n, dd = C.d * C.d;
+    const int tb = C.vc32 ? 4 : 8;
+    const double spmv_bytes = (l0.nnz_lo + l0.nnz_up) * (dd * 8 + 4.0) + (n0 + 1) * 4 +
+                              n0 * dd * 8 + 2 * C.n0p * 8.0 + n0 * 4;
+    const double vec_bytes = C.n0p * (6 * 8.0 + tb) + C.n0p * (8.0 + tb) + C.n0p * (16.0 + tb);
+    for (int r = 0; r < reps; ++r) {
+      auto body = [&](auto dtag) {
+        constexpr int D = decltype(dtag)::value;
+        run_phase(&prof, "spmv_f64", 0, 1, spmv_bytes, [&] {
+          launch_spmv<double, D>(l0, C.P, C.Q, C.partial, C.n_partial, nullptr, st);
+        });
+        run_phase(&prof, "pcg_vectors", -1, 3, vec_bytes, [&] {
+          if (C.vc32) {
+            hipLaunchKernelGGL((dev::k_update_xr<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                               C.n0p, C.sc, C.P, C.Q, C.X, C.R, static_cast<float*>(C.lev[0].b),
+                               C.partial);
+            hipLaunchKernelGGL((dev::k_dot<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                               C.n0p, C.R, static_cast<const float*>(C.lev[0].x), C.partial,
+                               nullptr);
+            hipLaunchKernelGGL((dev::k_update_p<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                               C.n0p, C.sc, static_cast<const float*>(C.lev[0].x), C.P);
+          } else {
+            hipLaunchKernelGGL((dev::k_update_xr<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0,
+                               st, C.n0p, C.sc, C.P, C.Q, C.X, C.R, static_cast<double*>(nullptr),
+                               C.partial);
+            hipLaunchKernelGGL((dev::k_dot<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                               C.n0p, C.R, static_cast<const double*>(C.lev[0].x), C.partial,
+                               nullptr);
+            hipLaunchKernelGGL((dev::k_update_p<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0,
+                               st, C.n0p, C.sc, static_cast<const double*>(C.lev[0].x), C.P);
+          }
+        });
+        if (C.vc32)
+          enqueue_vcycle<float, D>(C, C.zero_flag, st, &prof);
+        else
+          enqueue_vcycle<double, D>(C, C.zero_flag, st, &prof);
+      };
+      if (C.d == 2)
+        body(std::integral_constant<int, 2>());
+      else
+        body(std::integral_constant<int, 3>());
+      HIP_CHECK(hipGetLastError());
+      prof.finish();
+    }
+    const int n = static_cast<int>(std::min<size_t>(prof.stats.size(), max_out));
+    for (int i = 0; i < n; ++i) {
+      const PhaseStat& p = prof.stats[i];
+      std::memset(&out[i], 0, sizeof(out[i]));
+      std::snprintf(out[i].name, sizeof(out[i].name), "%s", p.name.c_str());
+      out[i].level = p.level;
+      out[i].launches = p.launches;
+      out[i].ms = p.ms;
+      out[i].bytes = p.bytes;
+    }
+    if (n_out) *n_out = n;
     return VASMG_OK;
   } catch (const vasmg::Error& e) {
     return fail_with(e);

@@ -28,7 +28,7 @@ EXPORTED = [
     "vasmg_default_options", "vasmg_setup", "vasmg_solve", "vasmg_solve_device", "vasmg_free",
     "vasmg_last_error", "vasmg_hierarchy_info", "vasmg_level_info", "vasmg_export_level",
     "vasmg_tree_info", "vasmg_spmv_device", "vasmg_gs_sweep_device", "vasmg_restrict_device",
-    "vasmg_prolong_device", "vasmg_apply_precond_device",
+    "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
 ]
 
 
@@ -49,8 +49,13 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("tree_vertices", C.c_int32),
                 ("coarsest_max_dofs", C.c_int64), ("max_iters", C.c_int32),
                 ("preconditioner", C.c_int32), ("profile", C.c_int32),
-                ("host_only", C.c_int32), ("verbose", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class PhaseStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("level", C.c_int32), ("launches", C.c_int32),
+                ("ms", C.c_double), ("bytes", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -92,6 +97,8 @@ def lib():
             "vasmg_restrict_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_prolong_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_apply_precond_device": (i32, [vp, vp, vp, vp]),
+            "vasmg_profile_iteration": (i32, [vp, i32, vp, C.POINTER(PhaseStat), i32,
+                                              C.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -267,6 +274,15 @@ class Solver:
     def prolong_device(self, level, precision, d_e, d_x, stream=None):
         _check(lib().vasmg_prolong_device(self._h, level, precision, _ptr(d_e), _ptr(d_x),
                                           _stream_ptr(stream)))
+
+    def profile_iteration(self, reps: int = 3, stream=None):
+        """Per-phase device time and algorithmic bytes of one PCG iteration."""
+        out = (PhaseStat * 128)()
+        n = C.c_int32()
+        _check(lib().vasmg_profile_iteration(self._h, reps, _stream_ptr(stream), out, 128,
+                                             C.byref(n)))
+        return [dict(name=o.name.decode(), level=o.level, launches=o.launches, ms=o.ms,
+                     bytes=o.bytes) for o in out[:n.value]]
 
     def apply_precond_device(self, d_r, d_z, stream=None):
         _check(lib().vasmg_apply_precond_device(self._h, _ptr(d_r), _ptr(d_z),

@@ -264,3 +264,16 @@ def test_full_size_3d_workload_against_oracle_golden():
     xs = x32[np.array(g["sample_vertices"])]
     assert np.abs(xs - np.array(g["sample_x"])).max() <= 1e-5 * g["x_norminf"]
     s.free()
+
+
+def test_autotuned_handle_matches_oracle():
+    """Autotuning only changes lanes per block row (summation order inside a row)."""
+    m = small3d(9, seed=5)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    xo, io = o.solve(m.rhs[0], 1e-6)
+    for prec, tol in ((V.FP64, 1e-8), (V.FP32_PRECOND, 1e-5)):
+        s = V.Solver.from_mesh(m, precision=prec, autotune=1)
+        x, info = s.solve(m.rhs[0], 1e-6)
+        assert abs(info["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= tol
+        s.free()
