@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="driver for rocprofv3 --pmc runs: a 256 MiB device copy (counter "
+                         "calibration) followed by one replayed PCG iteration of the workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
@@ -85,6 +88,18 @@ def main():
     from workloads import cfg2
 
     torch.cuda.set_device(0)
+    if args.counters:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)                       # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        mesh = cfg2()
+        s = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND)
+        for p in s.profile_iteration(1):
+            log(f"{p['name']:13s} L{p['level']:2d} launches {p['launches']:3d} "
+                f"bytes {p['bytes']:.0f} ms {p['ms']:.4f}")
+        s.free()
+        return
     t0 = time.perf_counter()
     mesh = cfg2()
     log(f"mesh {mesh.name}: {mesh.n_vertices} vertices, {mesh.elems.shape[0]} tets, "

@@ -1,19 +1,21 @@
 // HIP kernels of the V-ASMG-PCG solve phase for gfx950 (CDNA4, wave64).
 //
 // Data layout (per level, device numbering = vertices sorted by colour, then
-// canonical index):
-//   * off-diagonal blocks of A_l in CSR: rowptr[n+1], col[nnz] (ascending),
-//     split[n] = first position in the row whose column exceeds the row
-//     (so [rowptr, split) couples to earlier colours, [split, end) to later
-//     ones); values stored component-plane-major, val[(a*D+b)*nnz + k], so
-//     lanes walking consecutive blocks of a row read consecutive addresses;
-//   * diagonal blocks dense, diag[i*D*D + a*D + b];
+// cell, then canonical index):
+//   * the blocks coupling a row to earlier colours (L) and to later colours (U)
+//     are two separate CSR matrices, each with ascending columns and values
+//     stored component-plane-major, val[(a*D+b)*nnz + k]: lanes walking a row
+//     read consecutive addresses, and a sweep or residual that needs only one
+//     of the two streams one contiguous array;
+//   * fine level: diagonal blocks dense, diag[i*D*D + a*D + b]; coarse levels:
+//     the blocks inside a Gauss-Seidel cell (diagonal included) as a dense
+//     matrix per cell;
 //   * vectors vertex-major with a padded stride DP (2 in 2D, 4 in 3D) so a
 //     neighbour's components come in one 8/16-byte (FP32) or 16/32-byte (FP64)
 //     load; pad entries are kept at zero.
 // A block row is handled by a group of G lanes (G divides 64) that stride over
 // its blocks; partial sums are combined with cross-lane shuffles inside the
-// group and lane 0 of the group finishes the row.
+// group and lane 0 of the group (or wavefront 0 of a cell) finishes the row.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +29,15 @@ constexpr int kBlock = 256;
 template <int D>
 struct Pad {
   static constexpr int value = (D == 3) ? 4 : 2;
+};
+
+// One of the two off-diagonal block matrices (L or U) of a level.
+template <typename T>
+struct Part {
+  const int* __restrict__ ptr;   // [n+1]
+  const int* __restrict__ col;   // [nnz]
+  const T* __restrict__ val;     // [D*D][nnz]
+  int64_t nnz;
 };
 
 // ---- padded vector loads/stores -------------------------------------------
@@ -75,6 +86,16 @@ struct VecIO<double, 3> {
     *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], 0.0);
   }
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Renumber them so each XCD walks one contiguous range of rows or cells:
+// neighbouring rows then gather the same vector lines through the same L2.
+__device__ __forceinline__ int xcd_block() {
+  const int g = gridDim.x, b = blockIdx.x;
+  const int q = g >> 3, r = g & 7;
+  const int k = b & 7, j = b >> 3;
+  return (k < r) ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j;
+}
 
 template <typename T, int G>
 __device__ __forceinline__ T group_sum(T v) {
@@ -148,13 +169,17 @@ __device__ __forceinline__ void row_product(int kb, int ke, int lane, const int*
   }
 }
 
+template <typename T, int D, int G>
+__device__ __forceinline__ void part_product(const Part<T>& p, int i, int lane,
+                                             const T* __restrict__ x, T* acc) {
+  row_product<T, D, G>(p.ptr[i], p.ptr[i + 1], lane, p.col, p.val, p.nnz, x, acc);
+}
+
 // ---------------------------------------------------------------------------
 // K1: y = A x (diag + off-diagonal), optional partial dot x.y per workgroup.
 // ---------------------------------------------------------------------------
 template <typename T, int D, int G, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv(int n, const int* __restrict__ rowptr,
-                                                 const int* __restrict__ col,
-                                                 const T* __restrict__ val, int64_t nnz,
+__global__ __launch_bounds__(kBlock) void k_spmv(int n, Part<T> L, Part<T> U,
                                                  const T* __restrict__ diag,
                                                  const T* __restrict__ x, T* __restrict__ y,
                                                  double* __restrict__ partial,
@@ -162,13 +187,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int* __restrict__ 
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   const int lane = threadIdx.x % G;
-  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int i = xcd_block() * (kBlock / G) + threadIdx.x / G;
   double dot = 0.0;
   if (i < n) {
     T acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = T(0);
-    row_product<T, D, G>(rowptr[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+    part_product<T, D, G>(L, i, lane, x, acc);
+    part_product<T, D, G>(U, i, lane, x, acc);
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
     if (lane == 0) {
@@ -196,19 +222,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, const int* __restrict__ 
 // r = b - A x (full row), used when no saved lower-part sums exist.
 template <typename T, int D, int G>
 __global__ __launch_bounds__(kBlock) void k_residual_full(
-    int n, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const T* __restrict__ val, int64_t nnz, const T* __restrict__ diag,
-    const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r,
-    const int* __restrict__ done) {
+    int n, Part<T> L, Part<T> U, const T* __restrict__ diag, const T* __restrict__ b,
+    const T* __restrict__ x, T* __restrict__ r, const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   const int lane = threadIdx.x % G;
-  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int i = xcd_block() * (kBlock / G) + threadIdx.x / G;
   if (i >= n) return;
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  row_product<T, D, G>(rowptr[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+  part_product<T, D, G>(L, i, lane, x, acc);
+  part_product<T, D, G>(U, i, lane, x, acc);
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
   if (lane == 0) {
@@ -230,20 +255,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_full(
 // ---------------------------------------------------------------------------
 // K3: one colour of a point Gauss-Seidel sweep (Algorithm 1 in colour order).
 //   MODE 0: forward from a zero guess (only earlier colours are nonzero, so
-//           only [rowptr, split) is read); saves s_i = b_i - sum_{j<i} A_ij x_j
+//           only L is read); saves s_i = b_i - sum_{j<i} A_ij x_j
 //   MODE 1: forward from a nonzero guess; saves s_i as well
 //   MODE 2: backward (components in reverse order)
 // ---------------------------------------------------------------------------
 template <typename T, int D, int G, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gs_color(
-    int row0, int nrows, const int* __restrict__ rowptr, const int* __restrict__ split,
-    const int* __restrict__ col, const T* __restrict__ val, int64_t nnz,
-    const T* __restrict__ diag, const T* __restrict__ b, T* x, T* __restrict__ s_save,
-    const int* __restrict__ done) {
+    int row0, int nrows, Part<T> L, Part<T> U, const T* __restrict__ diag,
+    const T* __restrict__ b, T* x, T* __restrict__ s_save, const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   const int lane = threadIdx.x % G;
-  const int g = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int g = xcd_block() * (kBlock / G) + threadIdx.x / G;
   if (g >= nrows) return;
   const int i = row0 + g;
   // lane 0 fetches what it needs to finish the row before the row product
@@ -260,12 +283,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(
       VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
     }
   }
-  const int kb = rowptr[i], ks = split[i], ke = rowptr[i + 1];
   T lo[D], up[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
-  row_product<T, D, G>(kb, ks, lane, col, val, nnz, x, lo);
-  if (MODE != 0) row_product<T, D, G>(ks, ke, lane, col, val, nnz, x, up);
+  part_product<T, D, G>(L, i, lane, x, lo);
+  if (MODE != 0) part_product<T, D, G>(U, i, lane, x, up);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     lo[a] = group_sum<T, G>(lo[a]);
@@ -304,19 +326,17 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(
 // K2: r = s - D x - sum_{j > i} A_ij x_j after a forward sweep that saved s.
 template <typename T, int D, int G>
 __global__ __launch_bounds__(kBlock) void k_residual_upper(
-    int n, const int* __restrict__ rowptr, const int* __restrict__ split,
-    const int* __restrict__ col, const T* __restrict__ val, int64_t nnz,
-    const T* __restrict__ diag, const T* __restrict__ s_save, const T* __restrict__ x,
-    T* __restrict__ r, const int* __restrict__ done) {
+    int n, Part<T> U, const T* __restrict__ diag, const T* __restrict__ s_save,
+    const T* __restrict__ x, T* __restrict__ r, const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   const int lane = threadIdx.x % G;
-  const int i = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int i = xcd_block() * (kBlock / G) + threadIdx.x / G;
   if (i >= n) return;
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  row_product<T, D, G>(split[i], rowptr[i + 1], lane, col, val, nnz, x, acc);
+  part_product<T, D, G>(U, i, lane, x, acc);
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = group_sum<T, G>(acc[a]);
   if (lane == 0) {
@@ -337,9 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_upper(
 
 // ---------------------------------------------------------------------------
 // Coarse lattice levels: Gauss-Seidel over cells of at most NV = 2^D vertices.
-// Device rows of a cell are contiguous ([cell_ptr[c], cell_ptr[c+1])); the CSR
-// holds only blocks coupling to other cells, split per row into [rowptr,
-// lo_end) (earlier colours) and [up_beg, rowptr+1) (later colours); the blocks
+// Device rows of a cell are contiguous ([cell_ptr[c], cell_ptr[c+1])); L and U
+// hold only blocks coupling to other cells (earlier / later colours); the blocks
 // inside a cell, diagonal included, are a dense NU x NU matrix per cell
 // (NU = NV * D, column-major: cellM[c*NU*NU + u*NU + t] = M[t][u]).
 // One workgroup handles one cell: lane group g sums the off-cell part of the
@@ -357,21 +376,18 @@ struct CellShape {
 // wavefront) sums the off-cell part of the cell's g-th row; the sums meet in
 // LDS; wavefront 0 then runs the sequential sweep over the cell's unknowns.
 template <typename T, int D, int GR>
-__device__ __forceinline__ void cell_offcell_sums(int v0, int m, const int* __restrict__ rowptr,
-                                                  const int* __restrict__ lo_end,
-                                                  const int* __restrict__ up_beg,
-                                                  const int* __restrict__ col,
-                                                  const T* __restrict__ val, int64_t nnz,
-                                                  const T* __restrict__ x, bool want_lo,
-                                                  bool want_up, T (*sh_lo)[D], T (*sh_up)[D]) {
+__device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& L,
+                                                  const Part<T>& U, const T* __restrict__ x,
+                                                  bool want_lo, bool want_up, T (*sh_lo)[D],
+                                                  T (*sh_up)[D]) {
   const int g = threadIdx.x / GR, gl = threadIdx.x % GR;
   T lo[D], up[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
   if (g < m) {
     const int i = v0 + g;
-    if (want_lo) row_product<T, D, GR>(rowptr[i], lo_end[i], gl, col, val, nnz, x, lo);
-    if (want_up) row_product<T, D, GR>(up_beg[i], rowptr[i + 1], gl, col, val, nnz, x, up);
+    if (want_lo) part_product<T, D, GR>(L, i, gl, x, lo);
+    if (want_up) part_product<T, D, GR>(U, i, gl, x, up);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -390,15 +406,14 @@ __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const int* __re
 
 template <typename T, int D, int GR, int MODE>
 __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
-    int cell0, const int* __restrict__ cell_ptr, const int* __restrict__ rowptr,
-    const int* __restrict__ lo_end, const int* __restrict__ up_beg, const int* __restrict__ col,
-    const T* __restrict__ val, int64_t nnz, const T* __restrict__ cellM,
-    const T* __restrict__ b, T* x, T* __restrict__ s_save, const int* __restrict__ done) {
+    int cell0, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
+    const T* __restrict__ cellM, const T* __restrict__ b, T* x, T* __restrict__ s_save,
+    const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
   __shared__ T sh_lo[NV][D], sh_up[NV][D];
-  const int c = cell0 + blockIdx.x;
+  const int c = cell0 + xcd_block();
   const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
   // wavefront 0 fetches its part of the in-cell solve first, so these loads
   // overlap the off-cell products
@@ -417,8 +432,7 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
       if (MODE != 0) xc = x[xi];
     }
   }
-  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, true, MODE != 0,
-                              sh_lo, sh_up);
+  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, true, MODE != 0, sh_lo, sh_up);
   if (t >= 64) return;                    // wavefront 0 finishes the cell
   const T s_t = own ? bt - sh_lo[k][a] : T(0);
   const T sup = (own && MODE != 0) ? sh_up[k][a] : T(0);
@@ -471,40 +485,44 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
 //   KIND 2: SpMV: base = 0, both ranges, result negated (y = A x)
 template <typename T, int D, int GR, int KIND>
 __global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
-    const int* __restrict__ cell_ptr, const int* __restrict__ rowptr,
-    const int* __restrict__ lo_end, const int* __restrict__ up_beg, const int* __restrict__ col,
-    const T* __restrict__ val, int64_t nnz, const T* __restrict__ cellM,
+    const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
     const T* __restrict__ base, const T* __restrict__ x, T* __restrict__ out,
     const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
   __shared__ T sh_lo[NV][D], sh_up[NV][D];
-  const int c = blockIdx.x;
+  const int c = xcd_block();
   const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
-  cell_offcell_sums<T, D, GR>(v0, m, rowptr, lo_end, up_beg, col, val, nnz, x, KIND != 0, true,
-                              sh_lo, sh_up);
-  if (threadIdx.x >= 64) return;
+  // wavefront 0 fetches the in-cell block row, x and the base first
   const int t = threadIdx.x;
   const bool own = t < n;
   const int k = own ? t / D : 0, a = own ? t % D : 0;
   const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
+  T Mrow[NU];
+  T xt = T(0), bt = T(0);
+  if (t < 64) {
+    const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
+    if (own) {
+      xt = x[xi];
+      if (KIND != 2) bt = base[xi];
+    }
+  }
+  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, KIND != 0, true, sh_lo, sh_up);
+  if (t >= 64) return;
   const T off = own ? (KIND != 0 ? sh_lo[k][a] : T(0)) + sh_up[k][a] : T(0);
-  const T xt = own ? x[xi] : T(0);
-  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
   T mx = T(0);
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    if (u < n) {
-      const T xu = bcast(xt, u);
-      if (own) mx += Mc[u * NU + t] * xu;
-    }
+    if (u < n) mx += Mrow[u] * bcast(xt, u);
   }
   if (!own) return;
   if (KIND == 2)
     out[xi] = off + mx;
   else
-    out[xi] = base[xi] - off - mx;
+    out[xi] = bt - off - mx;
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int* __restri
                                                      const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
-  const int I = blockIdx.x * kBlock + threadIdx.x;
+  const int I = xcd_block() * kBlock + threadIdx.x;
   if (I >= nc) return;
   T acc[D];
 #pragma unroll
@@ -541,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __res
                                                         const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= nf) return;
   T acc[D];
   VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, acc);

@@ -67,15 +67,12 @@ struct DevLevel {
   int* cell_ptr = nullptr;         // cell levels: first device row of each cell
   float* cellM32 = nullptr;        // cell levels: dense in-cell blocks (column-major)
   double* cellM64 = nullptr;
-  int* rowptr = nullptr;
-  int* split = nullptr;            // point levels: first block with col > row;
-                                   // cell levels: first block with col >= cell start
-  int* up_beg = nullptr;           // cell levels: first block with col >= cell end
-  int* col = nullptr;
   int* perm = nullptr;             // device row -> canonical index
-  float* val32 = nullptr;
+  // off-diagonal blocks to earlier colours (L) and to later colours (U)
+  int *Lptr = nullptr, *Lcol = nullptr, *Uptr = nullptr, *Ucol = nullptr;
+  float *Lval32 = nullptr, *Uval32 = nullptr;
+  double *Lval64 = nullptr, *Uval64 = nullptr;
   float* diag32 = nullptr;
-  double* val64 = nullptr;
   double* diag64 = nullptr;
   // prolongation to the next level (device numbering on both sides)
   int nnext = 0;
@@ -347,13 +344,38 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   // lanes per block row: about two blocks per lane; cell levels use 16..64
   dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
   dl.Gspmv = dl.G;
-  dl.rowptr = C.upload(rowptr);
-  dl.split = C.upload(lo_end);
-  dl.up_beg = C.upload(up_beg);
-  dl.col = C.upload(col);
+  // split the off-cell blocks into the L (earlier colours) and U (later colours)
+  // matrices, each plane-major over its own blocks
+  std::vector<int> Lptr(n + 1, 0), Uptr(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    Lptr[i + 1] = Lptr[i] + (lo_end[i] - rowptr[i]);
+    Uptr[i + 1] = Uptr[i] + (rowptr[i + 1] - up_beg[i]);
+  }
+  const int64_t nL = Lptr[n], nU = Uptr[n];
+  std::vector<int> Lcol(nL), Ucol(nU);
+  std::vector<double> Lval(static_cast<size_t>(nL) * dd), Uval(static_cast<size_t>(nU) * dd);
+  for (int i = 0; i < n; ++i) {
+    for (int k = rowptr[i]; k < lo_end[i]; ++k) {
+      const int q = Lptr[i] + (k - rowptr[i]);
+      Lcol[q] = col[k];
+      for (int t = 0; t < dd; ++t) Lval[static_cast<size_t>(t) * nL + q] = val[static_cast<size_t>(t) * nnz + k];
+    }
+    for (int k = up_beg[i]; k < rowptr[i + 1]; ++k) {
+      const int q = Uptr[i] + (k - up_beg[i]);
+      Ucol[q] = col[k];
+      for (int t = 0; t < dd; ++t) Uval[static_cast<size_t>(t) * nU + q] = val[static_cast<size_t>(t) * nnz + k];
+    }
+  }
+  val.clear();
+  val.shrink_to_fit();
+  dl.Lptr = C.upload(Lptr);
+  dl.Lcol = C.upload(Lcol);
+  dl.Uptr = C.upload(Uptr);
+  dl.Ucol = C.upload(Ucol);
   if (dl.cells) dl.cell_ptr = C.upload(cell_ptr);
   if (need64) {
-    dl.val64 = C.upload(val);
+    dl.Lval64 = C.upload(Lval);
+    dl.Uval64 = C.upload(Uval);
     if (dl.cells)
       dl.cellM64 = C.upload(cellM);
     else
@@ -361,7 +383,8 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
     dl.has64 = true;
   }
   if (need32) {
-    dl.val32 = C.upload(std::vector<float>(val.begin(), val.end()));
+    dl.Lval32 = C.upload(std::vector<float>(Lval.begin(), Lval.end()));
+    dl.Uval32 = C.upload(std::vector<float>(Uval.begin(), Uval.end()));
     if (dl.cells)
       dl.cellM32 = C.upload(std::vector<float>(cellM.begin(), cellM.end()));
     else
@@ -465,7 +488,8 @@ template <typename T>
 struct LevelMats;
 template <>
 struct LevelMats<float> {
-  static const float* val(const DevLevel& l) { return l.val32; }
+  static dev::Part<float> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval32, l.nnz_lo}; }
+  static dev::Part<float> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval32, l.nnz_up}; }
   static const float* diag(const DevLevel& l) { return l.diag32; }
   static const float* pw(const DevLevel& l) { return l.p_w32; }
   static const float* ptw(const DevLevel& l) { return l.pt_w32; }
@@ -474,7 +498,8 @@ struct LevelMats<float> {
 };
 template <>
 struct LevelMats<double> {
-  static const double* val(const DevLevel& l) { return l.val64; }
+  static dev::Part<double> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval64, l.nnz_lo}; }
+  static dev::Part<double> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval64, l.nnz_up}; }
   static const double* diag(const DevLevel& l) { return l.diag64; }
   static const double* pw(const DevLevel& l) { return l.p_w64; }
   static const double* ptw(const DevLevel& l) { return l.pt_w64; }
@@ -495,12 +520,12 @@ int launch_spmv(const DevLevel& lv, const T* x, T* y, double* partial, int n_par
     used = grid;
     if (partial)
       hipLaunchKernelGGL((dev::k_spmv<T, D, GG, true>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
-                         lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::diag(lv),
+                         LevelMats<T>::L(lv), LevelMats<T>::U(lv), LevelMats<T>::diag(lv),
                          x, y, partial, done);
     else
       hipLaunchKernelGGL((dev::k_spmv<T, D, GG, false>), dim3(grid), dim3(dev::kBlock), 0, st,
-                         lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv), lv.nnz,
-                         LevelMats<T>::diag(lv), x, y, partial, done);
+                         lv.n, LevelMats<T>::L(lv), LevelMats<T>::U(lv), LevelMats<T>::diag(lv),
+                         x, y, partial, done);
   });
   return used;
 }
@@ -515,16 +540,16 @@ void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
     const int grid = grid_for(nr, dev::kBlock / GG);
     if (mode == 0)
       hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 0>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
-                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
-                         LevelMats<T>::diag(lv), b, x, s_save, done);
+                         nr, LevelMats<T>::L(lv), LevelMats<T>::U(lv), LevelMats<T>::diag(lv), b, x,
+                         s_save, done);
     else if (mode == 1)
       hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 1>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
-                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
-                         LevelMats<T>::diag(lv), b, x, s_save, done);
+                         nr, LevelMats<T>::L(lv), LevelMats<T>::U(lv), LevelMats<T>::diag(lv), b, x,
+                         s_save, done);
     else
       hipLaunchKernelGGL((dev::k_gs_color<T, D, GG, 2>), dim3(grid), dim3(dev::kBlock), 0, st, r0,
-                         nr, lv.rowptr, lv.split, lv.col, LevelMats<T>::val(lv), lv.nnz,
-                         LevelMats<T>::diag(lv), b, x, s_save, done);
+                         nr, LevelMats<T>::L(lv), LevelMats<T>::U(lv), LevelMats<T>::diag(lv), b, x,
+                         s_save, done);
   });
 }
 
@@ -542,18 +567,18 @@ void launch_gs_cells(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
   const int c0 = lv.color_ptr[c], nc = lv.color_ptr[c + 1] - c0;
   if (nc <= 0) return;
   const T* M = LevelMats<T>::cellM(lv);
-  const T* v = LevelMats<T>::val(lv);
+  const dev::Part<T> Lp = LevelMats<T>::L(lv), Up = LevelMats<T>::U(lv);
   DISPATCH_GR(lv.G, {
     const dim3 blk((1 << D) * GR);
     if (mode == 0)
       hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 0>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
-                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+                         Lp, Up, M, b, x, s_save, done);
     else if (mode == 1)
       hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 1>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
-                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+                         Lp, Up, M, b, x, s_save, done);
     else
       hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 2>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
-                         lv.rowptr, lv.split, lv.up_beg, lv.col, v, lv.nnz, M, b, x, s_save, done);
+                         Lp, Up, M, b, x, s_save, done);
   });
 }
 
@@ -562,8 +587,8 @@ void launch_cell_apply(const DevLevel& lv, const T* base, const T* x, T* out, co
                        hipStream_t st) {
   DISPATCH_GR(lv.G, {
     hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND>), dim3(lv.ncells), dim3((1 << D) * GR), 0,
-                       st, lv.cell_ptr, lv.rowptr, lv.split, lv.up_beg, lv.col,
-                       LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::cellM(lv), base, x, out, done);
+                       st, lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
+                       LevelMats<T>::cellM(lv), base, x, out, done);
   });
 }
 
@@ -596,8 +621,8 @@ void launch_residual_upper(const DevLevel& lv, const T* s, const T* x, T* r, con
   }
   DISPATCH_G(lv.G, {
     hipLaunchKernelGGL((dev::k_residual_upper<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
-                       dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.split, lv.col,
-                       LevelMats<T>::val(lv), lv.nnz, LevelMats<T>::diag(lv), s, x, r, done);
+                       dim3(dev::kBlock), 0, st, lv.n, LevelMats<T>::U(lv), LevelMats<T>::diag(lv),
+                       s, x, r, done);
   });
 }
 
@@ -610,8 +635,8 @@ void launch_residual_full(const DevLevel& lv, const T* b, const T* x, T* r, cons
   }
   DISPATCH_G(lv.G, {
     hipLaunchKernelGGL((dev::k_residual_full<T, D, GG>), dim3(grid_for(lv.n, dev::kBlock / GG)),
-                       dim3(dev::kBlock), 0, st, lv.n, lv.rowptr, lv.col, LevelMats<T>::val(lv),
-                       lv.nnz, LevelMats<T>::diag(lv), b, x, r, done);
+                       dim3(dev::kBlock), 0, st, lv.n, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
+                       LevelMats<T>::diag(lv), b, x, r, done);
   });
 }
 
@@ -801,7 +826,9 @@ void enqueue_iter_B(vasmg_ctx& C, hipStream_t st) {
   const int* done = &C.sc->done;
   const int pc = C.opt.preconditioner;
   if (pc == VASMG_PRECOND_VASMG) {
-    enqueue_precond<D>(C, done, st);
+    // the host launches this graph only while the iteration has not stopped, so
+    // the V-cycle kernels do not read the flag (it would head their load chains)
+    enqueue_precond<D>(C, nullptr, st);
     if (C.vc32) {
       hipLaunchKernelGGL((dev::k_dot<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p, C.R,
                          static_cast<const float*>(C.lev[0].x), C.partial, done);
