@@ -145,26 +145,29 @@ __device__ __forceinline__ void block_fma(const T* __restrict__ val, int64_t nnz
 }
 
 // Off-diagonal block row product over positions [kb, ke): acc += sum A_k x_col(k).
-// Two blocks per lane per step keep more loads in flight.
+// UN blocks per lane are loaded before any is used (4 in FP32, so a whole row of
+// a coarse level is in flight at once; 2 in FP64 to keep the register budget).
 template <typename T, int D, int G>
 __device__ __forceinline__ void row_product(int kb, int ke, int lane, const int* __restrict__ col,
                                             const T* __restrict__ val, int64_t nnz,
                                             const T* __restrict__ x, T* acc) {
   constexpr int DP = Pad<D>::value;
+  constexpr int UN = sizeof(T) == 4 ? 4 : 2;
   int k = kb + lane;
-  for (; k + G < ke; k += 2 * G) {
-    const int j0 = ld_stream(col + k);
-    const int j1 = ld_stream(col + k + G);
-    T x0[D], x1[D];
-    VecIO<T, D>::load(x + static_cast<int64_t>(j0) * DP, x0);
-    VecIO<T, D>::load(x + static_cast<int64_t>(j1) * DP, x1);
-    block_fma<T, D>(val, nnz, k, x0, acc);
-    block_fma<T, D>(val, nnz, k + G, x1, acc);
+  for (; k + (UN - 1) * G < ke; k += UN * G) {
+    int j[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) j[u] = col[k + u * G];
+    T xv[UN][D];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) VecIO<T, D>::load(x + static_cast<int64_t>(j[u]) * DP, xv[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) block_fma<T, D>(val, nnz, k + u * G, xv[u], acc);
   }
-  if (k < ke) {
-    const int j = ld_stream(col + k);
+  for (; k < ke; k += G) {
+    const int jj = col[k];
     T xj[D];
-    VecIO<T, D>::load(x + static_cast<int64_t>(j) * DP, xj);
+    VecIO<T, D>::load(x + static_cast<int64_t>(jj) * DP, xj);
     block_fma<T, D>(val, nnz, k, xj, acc);
   }
 }
@@ -528,7 +531,25 @@ __global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
 // ---------------------------------------------------------------------------
 // K4: restriction b_c = P^T r (gather over the CSR of P^T); K5: x += P e.
 // ---------------------------------------------------------------------------
-template <typename T, int D>
+// Both transfers are gathers over a scalar CSR (weights shared by the
+// components); GT lanes share a row so its entries are loaded together.
+template <typename T, int D, int GT>
+__device__ __forceinline__ void transfer_row(int pb, int pe, int lane, const int* __restrict__ idx,
+                                             const T* __restrict__ w, const T* __restrict__ v,
+                                             T* acc) {
+  constexpr int DP = Pad<D>::value;
+  for (int p = pb + lane; p < pe; p += GT) {
+    T e[D];
+    VecIO<T, D>::load(v + static_cast<int64_t>(idx[p]) * DP, e);
+    const T wp = w[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wp * e[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = group_sum<T, GT>(acc[a]);
+}
+
+template <typename T, int D, int GT>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int* __restrict__ ptr,
                                                      const int* __restrict__ idx,
                                                      const T* __restrict__ w,
@@ -536,22 +557,17 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int* __restri
                                                      const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
-  const int I = xcd_block() * kBlock + threadIdx.x;
+  const int lane = threadIdx.x % GT;
+  const int I = xcd_block() * (kBlock / GT) + threadIdx.x / GT;
   if (I >= nc) return;
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  for (int p = ptr[I]; p < ptr[I + 1]; ++p) {
-    T v[D];
-    VecIO<T, D>::load(r + static_cast<int64_t>(idx[p]) * DP, v);
-    const T wp = w[p];
-#pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += wp * v[a];
-  }
-  VecIO<T, D>::store(bc + static_cast<int64_t>(I) * DP, acc);
+  transfer_row<T, D, GT>(ptr[I], ptr[I + 1], lane, idx, w, r, acc);
+  if (lane == 0) VecIO<T, D>::store(bc + static_cast<int64_t>(I) * DP, acc);
 }
 
-template <typename T, int D>
+template <typename T, int D, int GT>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __restrict__ ptr,
                                                         const int* __restrict__ idx,
                                                         const T* __restrict__ w,
@@ -559,18 +575,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __res
                                                         const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
-  const int i = xcd_block() * kBlock + threadIdx.x;
+  const int lane = threadIdx.x % GT;
+  const int i = xcd_block() * (kBlock / GT) + threadIdx.x / GT;
   if (i >= nf) return;
+  T xi[D];
+  if (lane == 0) VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
   T acc[D];
-  VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, acc);
-  for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
-    T v[D];
-    VecIO<T, D>::load(e + static_cast<int64_t>(idx[p]) * DP, v);
-    const T wp = w[p];
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc[a] += wp * v[a];
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  transfer_row<T, D, GT>(ptr[i], ptr[i + 1], lane, idx, w, e, acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) xi[a] += acc[a];
+    VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, xi);
   }
-  VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, acc);
 }
 
 // ---------------------------------------------------------------------------

@@ -640,18 +640,21 @@ void launch_residual_full(const DevLevel& lv, const T* b, const T* x, T* r, cons
   });
 }
 
+// restriction rows (P^T) hold up to ~27 entries, prolongation rows up to 2^d
+constexpr int kRestrictLanes = 8, kProlongLanes = 4;
+
 template <typename T, int D>
 void launch_restrict(const DevLevel& lv, const T* r, T* bc, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL((dev::k_restrict<T, D>), dim3(grid_for(lv.nnext, dev::kBlock)),
-                     dim3(dev::kBlock), 0, st, lv.nnext, lv.pt_ptr, lv.pt_idx,
-                     LevelMats<T>::ptw(lv), r, bc, done);
+  hipLaunchKernelGGL((dev::k_restrict<T, D, kRestrictLanes>),
+                     dim3(grid_for(lv.nnext, dev::kBlock / kRestrictLanes)), dim3(dev::kBlock), 0,
+                     st, lv.nnext, lv.pt_ptr, lv.pt_idx, LevelMats<T>::ptw(lv), r, bc, done);
 }
 
 template <typename T, int D>
 void launch_prolong(const DevLevel& lv, const T* e, T* x, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL((dev::k_prolong_add<T, D>), dim3(grid_for(lv.n, dev::kBlock)),
-                     dim3(dev::kBlock), 0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv), e,
-                     x, done);
+  hipLaunchKernelGGL((dev::k_prolong_add<T, D, kProlongLanes>),
+                     dim3(grid_for(lv.n, dev::kBlock / kProlongLanes)), dim3(dev::kBlock), 0, st,
+                     lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv), e, x, done);
 }
 
 template <typename T>
