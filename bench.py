@@ -134,6 +134,16 @@ def main():
         variants["fp64_vasmg"] = dict(ms_per_solve=float(np.mean([r[0] for r in r64])),
                                       iterations=r64[-1][1]["iterations"])
         fp64.free()
+        # leaf capacity 27: the 3D analogue of the capacity under which the method
+        # reduces to geometric multigrid on uniform grids (the paper's Theorem 2)
+        c27 = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, leaf_capacity=27,
+                                 autotune=0 if args.no_autotune else 1)
+        time_solves(c27, d_rhs, d_x, 1)
+        rc = time_solves(c27, d_rhs, d_x, max(3, args.steps // 4))
+        variants["mixed_capacity27"] = dict(ms_per_solve=float(np.mean([r[0] for r in rc])),
+                                            iterations=rc[-1][1]["iterations"],
+                                            rel_res_true=rc[-1][1]["rel_res_true"])
+        c27.free()
         jac = V.Solver.from_mesh(mesh, precision=V.FP64, preconditioner=V.PRECOND_JACOBI)
         rj = time_solves(jac, d_rhs, d_x, 2)
         variants["fp64_jacobi_pcg"] = dict(ms_per_solve=float(np.mean([r[0] for r in rj])),
