@@ -89,7 +89,13 @@ typedef struct {
   int32_t autotune;            /* 1 = time the candidate lanes-per-block-row of each
                                   level's kernels at setup and keep the fastest (results
                                   then differ from another handle's by rounding only)     */
-  int32_t reserved[6];
+  int32_t block_rhs;           /* 0 = solve several right-hand sides one after another;
+                                  4, 8 or 16 = block width K: vasmg_solve(_device) with
+                                  n_rhs > 1 runs K columns at a time as K PCG recurrences
+                                  sharing every matrix read (vectors interleaved per
+                                  vertex); needs the V-ASMG preconditioner, n_pre >= 1 and
+                                  a coarsest level of at most 4096 / K DOFs (else EINVAL) */
+  int32_t reserved[5];
 } vasmg_options;
 
 typedef struct {

@@ -1,0 +1,565 @@
+// Block right-hand-side kernels: K independent PCG recurrences (one per load
+// case) that share every matrix read.
+//
+// Vectors interleave the columns per vertex, v[(row*K + k)*DP + a] (column k,
+// component a, padded stride DP): the K columns of one neighbour are K*DP
+// consecutive values, so the lanes of a row that own the K columns gather them
+// in one contiguous load while reading the same matrix block (a broadcast).
+// A row is handled by GL lanes = K columns x (GL/K) block slots; the slots
+// stride the row's blocks and are combined with cross-lane shuffles.
+// Per-column scalars (alpha, beta, rho, residual, stop flag) follow Algorithm 2
+// for every column separately; a column that has converged stops updating its
+// vectors while the others go on.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace vasmg {
+namespace dev {
+
+constexpr int kPointLanes = 16;   // lanes per block row, point levels (fine)
+constexpr int kCellLanes = 32;    // lanes per block row, cell levels
+
+// Sum over the GL/K block slots of a row group (lanes with equal column).
+template <typename T, int K, int GL>
+__device__ __forceinline__ T slot_sum(T v) {
+#pragma unroll
+  for (int off = K; off < GL; off <<= 1) v += __shfl_xor(v, off, GL);
+  return v;
+}
+
+// acc += sum over blocks [kb, ke) of A_blk x_col(blk)[column k]; slot s of S
+// takes blocks kb + s, kb + s + S, ...
+template <typename T, int D, int K, int S>
+__device__ __forceinline__ void mc_row_product(int kb, int ke, int slot, int k,
+                                               const int* __restrict__ col,
+                                               const T* __restrict__ val, int64_t nnz,
+                                               const T* __restrict__ x, T* acc) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int UN = sizeof(T) == 4 ? 4 : 2;
+  int p = kb + slot;
+  for (; p + (UN - 1) * S < ke; p += UN * S) {
+    int j[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) j[u] = col[p + u * S];
+    T xv[UN][D];
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+      VecIO<T, D>::load(x + (static_cast<int64_t>(j[u]) * K + k) * DP, xv[u]);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) block_fma<T, D>(val, nnz, p + u * S, xv[u], acc);
+  }
+  for (; p < ke; p += S) {
+    const int jj = col[p];
+    T xj[D];
+    VecIO<T, D>::load(x + (static_cast<int64_t>(jj) * K + k) * DP, xj);
+    block_fma<T, D>(val, nnz, p, xj, acc);
+  }
+}
+
+template <typename T, int D, int K, int S>
+__device__ __forceinline__ void mc_part_product(const Part<T>& p, int i, int slot, int k,
+                                                const T* __restrict__ x, T* acc) {
+  mc_row_product<T, D, K, S>(p.ptr[i], p.ptr[i + 1], slot, k, p.col, p.val, p.nnz, x, acc);
+}
+
+// Per-column block sums: thread t contributes v to column col_of(t); on return
+// thread t < K holds column t's sum (fixed order: ascending thread index).
+template <int K, class ColOf>
+__device__ __forceinline__ double block_sum_cols(double v, double* sh, ColOf col_of) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < K)
+    for (int j = 0; j < static_cast<int>(blockDim.x); ++j)
+      if (col_of(j) == static_cast<int>(threadIdx.x)) s += sh[j];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Fine-level FP64 SpMV y = A x per column, optional per-column partial x.y.
+// ---------------------------------------------------------------------------
+template <int D, int K, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_mc(int n, Part<double> L, Part<double> U,
+                                                    const double* __restrict__ diag,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ y,
+                                                    double* __restrict__ partial) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int GL = kPointLanes, S = GL / K;
+  const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
+  const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
+  double dot = 0.0;
+  if (i < n) {
+    double acc[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = 0.0;
+    mc_part_product<double, D, K, S>(L, i, slot, k, x, acc);
+    mc_part_product<double, D, K, S>(U, i, slot, k, x, acc);
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] = slot_sum<double, K, GL>(acc[a]);
+    if (slot == 0) {
+      double xi[D], yi[D];
+      const int64_t o = (static_cast<int64_t>(i) * K + k) * DP;
+      VecIO<double, D>::load(x + o, xi);
+      const double* dg = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = acc[a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) s += dg[a * D + b] * xi[b];
+        yi[a] = s;
+        if (DOT) dot += xi[a] * s;
+      }
+      VecIO<double, D>::store(y + o, yi);
+    }
+  }
+  if (DOT) {
+    __shared__ double sh[kBlock];
+    const double s = block_sum_cols<K>(dot, sh, [](int t) { return t % K; });
+    if (threadIdx.x < K) partial[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fine-level point Gauss-Seidel colour (MODE as in k_gs_color) and residual.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int K, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gs_color_mc(
+    int row0, int nrows, Part<T> L, Part<T> U, const T* __restrict__ diag,
+    const T* __restrict__ b, T* x, T* __restrict__ s_save) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int GL = kPointLanes, S = GL / K;
+  const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
+  const int g = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
+  if (g >= nrows) return;
+  const int i = row0 + g;
+  T lo[D], up[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
+  mc_part_product<T, D, K, S>(L, i, slot, k, x, lo);
+  if (MODE != 0) mc_part_product<T, D, K, S>(U, i, slot, k, x, up);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = slot_sum<T, K, GL>(lo[a]);
+    if (MODE != 0) up[a] = slot_sum<T, K, GL>(up[a]);
+  }
+  if (slot != 0) return;
+  const int64_t o = (static_cast<int64_t>(i) * K + k) * DP;
+  T dg[D * D], xi[D], bi[D];
+  const T* dp = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+  for (int e = 0; e < D * D; ++e) dg[e] = dp[e];
+  VecIO<T, D>::load(b + o, bi);
+  if (MODE == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) xi[a] = T(0);
+  } else {
+    VecIO<T, D>::load(x + o, xi);
+  }
+  T s[D], rhs[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    s[a] = bi[a] - lo[a];
+    rhs[a] = s[a] - up[a];
+  }
+  if (MODE != 2 && s_save) VecIO<T, D>::store(s_save + o, s);
+#pragma unroll
+  for (int aa = 0; aa < D; ++aa) {
+    const int a = (MODE == 2) ? D - 1 - aa : aa;
+    T t = rhs[a];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      if (c != a) t -= dg[a * D + c] * xi[c];
+    xi[a] = t / dg[a * D + a];
+  }
+  VecIO<T, D>::store(x + o, xi);
+}
+
+// r = s - D x - U x (after a forward sweep that saved s).
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_residual_upper_mc(
+    int n, Part<T> U, const T* __restrict__ diag, const T* __restrict__ s_save,
+    const T* __restrict__ x, T* __restrict__ r) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int GL = kPointLanes, S = GL / K;
+  const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
+  const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
+  if (i >= n) return;
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  mc_part_product<T, D, K, S>(U, i, slot, k, x, acc);
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = slot_sum<T, K, GL>(acc[a]);
+  if (slot != 0) return;
+  const int64_t o = (static_cast<int64_t>(i) * K + k) * DP;
+  T xi[D], si[D], ri[D];
+  VecIO<T, D>::load(x + o, xi);
+  VecIO<T, D>::load(s_save + o, si);
+  const T* dg = diag + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T v = si[a] - acc[a];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v -= dg[a * D + c] * xi[c];
+    ri[a] = v;
+  }
+  VecIO<T, D>::store(r + o, ri);
+}
+
+// ---------------------------------------------------------------------------
+// Cell levels. Workgroup = one cell: lane group g (kCellLanes lanes) sums the
+// off-cell part of row g for every column; the cell matrix is staged in LDS;
+// then thread k < K runs column k's sequential sweep over the cell's unknowns.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int K>
+struct CellLds {
+  static constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
+  T M[NU * NU];
+  T lo[NV][K][D];
+  T up[NV][K][D];
+};
+
+template <typename T, int D, int K>
+__device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L, const Part<T>& U,
+                                                const T* __restrict__ x, bool want_lo,
+                                                bool want_up, CellLds<T, D, K>& sh) {
+  constexpr int GL = kCellLanes, S = GL / K;
+  const int g = threadIdx.x / GL, lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
+  T lo[D], up[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
+  if (g < m) {
+    if (want_lo) mc_part_product<T, D, K, S>(L, v0 + g, slot, k, x, lo);
+    if (want_up) mc_part_product<T, D, K, S>(U, v0 + g, slot, k, x, up);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (want_lo) lo[a] = slot_sum<T, K, GL>(lo[a]);
+    if (want_up) up[a] = slot_sum<T, K, GL>(up[a]);
+  }
+  if (slot == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      sh.lo[g][k][a] = lo[a];
+      sh.up[g][k][a] = up[a];
+    }
+  }
+}
+
+template <typename T, int D, int K, int MODE>
+__global__ __launch_bounds__(CellShape<D>::NV * kCellLanes) void k_gs_cell_mc(
+    int cell0, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
+    const T* __restrict__ cellM, const T* __restrict__ b, T* x, T* __restrict__ s_save) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int NU = CellShape<D>::NU;
+  __shared__ CellLds<T, D, K> sh;
+  __shared__ T shx[NU][K], shr[NU][K];
+  const int c = cell0 + xcd_block();
+  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
+  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+  for (int e = threadIdx.x; e < NU * NU; e += blockDim.x) sh.M[e] = Mc[e];
+  mc_cell_offcell<T, D, K>(v0, m, L, U, x, true, MODE != 0, sh);
+  __syncthreads();
+  // stage each column's right-hand side (and old values) of the cell's unknowns
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int u = e / K, k = e % K, row = u / D, a = u % D;
+    const int64_t o = (static_cast<int64_t>(v0 + row) * K + k) * DP + a;
+    const T su = b[o] - sh.lo[row][k][a];
+    if (MODE != 2 && s_save) s_save[o] = su;
+    shr[u][k] = su - (MODE != 0 ? sh.up[row][k][a] : T(0));
+    shx[u][k] = MODE != 0 ? x[o] : T(0);
+  }
+  __syncthreads();
+  // thread k: column k's sequential sweep over the cell's unknowns
+  if (threadIdx.x < K) {
+    const int k = threadIdx.x;
+    for (int uu = 0; uu < n; ++uu) {
+      const int u = (MODE == 2) ? n - 1 - uu : uu;
+      T t = shr[u][k];
+#pragma unroll 4
+      for (int v = 0; v < n; ++v)
+        if (v != u) t -= sh.M[v * NU + u] * shx[v][k];
+      shx[u][k] = t / sh.M[u * NU + u];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int u = e / K, k = e % K;
+    x[(static_cast<int64_t>(v0 + u / D) * K + k) * DP + u % D] = shx[u][k];
+  }
+}
+
+// r = s - U x - M x on a cell (after a forward sweep that saved s).
+template <typename T, int D, int K>
+__global__ __launch_bounds__(CellShape<D>::NV * kCellLanes) void k_cell_residual_mc(
+    const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
+    const T* __restrict__ s_save, const T* __restrict__ x, T* __restrict__ r) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int NU = CellShape<D>::NU;
+  __shared__ CellLds<T, D, K> sh;
+  __shared__ T shx[NU][K];
+  const int c = xcd_block();
+  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
+  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+  for (int e = threadIdx.x; e < NU * NU; e += blockDim.x) sh.M[e] = Mc[e];
+  for (int e = threadIdx.x; e < NU * K; e += blockDim.x) {
+    const int u = e / K, k = e % K;
+    shx[u][k] = u < n ? x[(static_cast<int64_t>(v0 + u / D) * K + k) * DP + u % D] : T(0);
+  }
+  mc_cell_offcell<T, D, K>(v0, m, L, U, x, false, true, sh);
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
+    const int u = e / K, k = e % K;
+    const int row = u / D, a = u % D;
+    T mx = T(0);
+    for (int v = 0; v < n; ++v) mx += sh.M[v * NU + u] * shx[v][k];
+    const int64_t o = (static_cast<int64_t>(v0 + row) * K + k) * DP + a;
+    r[o] = s_save[o] - sh.up[row][k][a] - mx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transfers: b_c = P^T r and x += P e, lane k of a K-lane group = column k.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_restrict_mc(int nc, const int* __restrict__ ptr,
+                                                        const int* __restrict__ idx,
+                                                        const T* __restrict__ w,
+                                                        const T* __restrict__ r,
+                                                        T* __restrict__ bc) {
+  constexpr int DP = Pad<D>::value;
+  const int k = threadIdx.x % K;
+  const int I = xcd_block() * (kBlock / K) + threadIdx.x / K;
+  if (I >= nc) return;
+  T acc[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  for (int p = ptr[I]; p < ptr[I + 1]; ++p) {
+    T e[D];
+    VecIO<T, D>::load(r + (static_cast<int64_t>(idx[p]) * K + k) * DP, e);
+    const T wp = w[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wp * e[a];
+  }
+  VecIO<T, D>::store(bc + (static_cast<int64_t>(I) * K + k) * DP, acc);
+}
+
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_prolong_mc(int nf, const int* __restrict__ ptr,
+                                                       const int* __restrict__ idx,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ e, T* x) {
+  constexpr int DP = Pad<D>::value;
+  const int k = threadIdx.x % K;
+  const int i = xcd_block() * (kBlock / K) + threadIdx.x / K;
+  if (i >= nf) return;
+  const int64_t o = (static_cast<int64_t>(i) * K + k) * DP;
+  T xi[D], acc[D];
+  VecIO<T, D>::load(x + o, xi);
+#pragma unroll
+  for (int a = 0; a < D; ++a) acc[a] = T(0);
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+    T ev[D];
+    VecIO<T, D>::load(e + (static_cast<int64_t>(idx[p]) * K + k) * DP, ev);
+    const T wp = w[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wp * ev[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) xi[a] += acc[a];
+  VecIO<T, D>::store(x + o, xi);
+}
+
+// Coarsest solve L L^T e = b per column (FP64, one workgroup; n * K <= kCoarseMax).
+template <typename T, int D, int K>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve_mc(int n, const double* __restrict__ L,
+                                                            const T* __restrict__ b,
+                                                            T* __restrict__ x) {
+  constexpr int DP = Pad<D>::value;
+  __shared__ double y[kCoarseMax];
+  const int nk = n * K;
+  for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+    const int i = e / K, k = e % K;
+    y[e] = static_cast<double>(b[((i / D) * K + k) * DP + i % D]);
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x < K) y[j * K + threadIdx.x] /= L[static_cast<int64_t>(j) * n + j];
+    __syncthreads();
+    for (int e = (j + 1) * K + threadIdx.x; e < nk; e += blockDim.x)
+      y[e] -= L[static_cast<int64_t>(e / K) * n + j] * y[j * K + e % K];
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    if (threadIdx.x < K) y[j * K + threadIdx.x] /= L[static_cast<int64_t>(j) * n + j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < j * K; e += blockDim.x)
+      y[e] -= L[static_cast<int64_t>(j) * n + e / K] * y[j * K + e % K];
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+    const int i = e / K, k = e % K;
+    x[((i / D) * K + k) * DP + i % D] = static_cast<T>(y[e]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels over [row][K][DP] (flat grid-stride; the stride is a
+// multiple of K*DP, so every thread stays on one column).
+// ---------------------------------------------------------------------------
+template <int K, int DP>
+__device__ __forceinline__ int flat_col(int t) {
+  return (t / DP) % K;
+}
+
+// per-column scalar updates, one workgroup per column
+template <int MODE, int K>
+__global__ __launch_bounds__(kBlock) void k_finalize_mc(const double* __restrict__ partial, int np,
+                                                        Scalars* sc) {
+  __shared__ double sh[kBlock];
+  const int k = blockIdx.x;
+  Scalars* s = sc + k;
+  if (MODE != FIN_NORMF && MODE != FIN_TRUE && s->done) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += partial[static_cast<int64_t>(i) * K + k];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) finalize_scalar<MODE>(tot, s);
+}
+
+template <int K, int DP, typename TB>
+__global__ __launch_bounds__(kBlock) void k_dot_mc(int64_t n, const double* __restrict__ a,
+                                                   const TB* __restrict__ b,
+                                                   double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    v += a[i] * static_cast<double>(b[i]);
+  const double s = block_sum_cols<K>(v, sh, [](int t) { return flat_col<K, DP>(t); });
+  if (threadIdx.x < K) partial[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = s;
+}
+
+// r = F - q per column (r may be NULL), partial ||r||^2
+template <int K, int DP>
+__global__ __launch_bounds__(kBlock) void k_sub_norm_mc(int64_t n, const double* __restrict__ F,
+                                                        const double* __restrict__ q,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const double t = F[i] - q[i];
+    if (r) r[i] = t;
+    v += t * t;
+  }
+  const double s = block_sum_cols<K>(v, sh, [](int t) { return flat_col<K, DP>(t); });
+  if (threadIdx.x < K) partial[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = s;
+}
+
+// x += alpha_k p; r -= alpha_k q; b0 = (T) r; partial ||r||^2 (running columns)
+template <typename T, int K, int DP>
+__global__ __launch_bounds__(kBlock) void k_update_xr_mc(int64_t n, const Scalars* __restrict__ sc,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         T* __restrict__ b0,
+                                                         double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int k = flat_col<K, DP>(threadIdx.x);
+  const bool run = !sc[k].done;
+  const double alpha = sc[k].alpha;
+  double v = 0.0;
+  if (run) {
+    for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      if (b0) b0[i] = static_cast<T>(ri);
+      v += ri * ri;
+    }
+  }
+  const double s = block_sum_cols<K>(v, sh, [](int t) { return flat_col<K, DP>(t); });
+  if (threadIdx.x < K) partial[static_cast<int64_t>(blockIdx.x) * K + threadIdx.x] = s;
+}
+
+// p = z + beta_k p (running columns)
+template <typename T, int K, int DP>
+__global__ __launch_bounds__(kBlock) void k_update_p_mc(int64_t n, const Scalars* __restrict__ sc,
+                                                        const T* __restrict__ z,
+                                                        double* __restrict__ p) {
+  const int k = flat_col<K, DP>(threadIdx.x);
+  if (sc[k].done) return;
+  const double beta = sc[k].beta;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    p[i] = static_cast<double>(z[i]) + beta * p[i];
+}
+
+// columns with F = 0 have x = 0; a zero-guess start of such a column is done
+template <int K, int DP>
+__global__ __launch_bounds__(kBlock) void k_zero_cols_mc(int64_t n, const Scalars* __restrict__ sc,
+                                                         double* __restrict__ x) {
+  const int k = flat_col<K, DP>(threadIdx.x);
+  if (sc[k].normF != 0.0) return;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock)
+    x[i] = 0.0;
+}
+
+// per-column start: rtol, and (with an initial guess) stop columns whose
+// initial residual already meets it
+template <int K>
+__global__ void k_start_mc(Scalars* sc, double rtol, int have_x0) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  Scalars* s = sc + k;
+  s->rtol = rtol;
+  if (!(s->normF == s->normF) || s->normF > 1.7976931348623157e308) {
+    s->status = 5;
+    s->done = 1;
+  } else if (s->normF == 0.0) {
+    s->done = 1;
+  } else if (have_x0 && s->res_true / s->normF < rtol) {
+    s->done = 1;
+  }
+}
+
+// user layout [n_rhs][nv][D], columns c0 .. c0+nc-1 <-> [row][K][DP]
+template <int D, int K>
+__global__ __launch_bounds__(kBlock) void k_gather_user_mc(int n, const int* __restrict__ map,
+                                                           const double* __restrict__ src,
+                                                           int64_t nv, int c0, int nc,
+                                                           double* __restrict__ dst) {
+  constexpr int DP = Pad<D>::value;
+  const int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * K) return;
+  const int i = static_cast<int>(e / K), k = static_cast<int>(e % K);
+  const int64_t v = map[i];
+#pragma unroll
+  for (int a = 0; a < DP; ++a)
+    dst[e * DP + a] = (a < D && k < nc) ? src[(static_cast<int64_t>(c0 + k) * nv + v) * D + a] : 0.0;
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(kBlock) void k_scatter_user_mc(int n, const int* __restrict__ map,
+                                                            const double* __restrict__ src,
+                                                            int64_t nv, int c0, int nc,
+                                                            double* __restrict__ dst) {
+  constexpr int DP = Pad<D>::value;
+  const int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * K) return;
+  const int i = static_cast<int>(e / K), k = static_cast<int>(e % K);
+  if (k >= nc) return;
+  const int64_t v = map[i];
+#pragma unroll
+  for (int a = 0; a < D; ++a) dst[(static_cast<int64_t>(c0 + k) * nv + v) * D + a] = src[e * DP + a];
+}
+
+}  // namespace dev
+}  // namespace vasmg

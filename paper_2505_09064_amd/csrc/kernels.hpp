@@ -644,15 +644,9 @@ struct Scalars {
 
 enum FinMode { FIN_NORMF = 0, FIN_ALPHA = 1, FIN_RES = 2, FIN_BETA = 3, FIN_TRUE = 4 };
 
+// Scalar steps of Algorithm 2 from a finished reduction `tot`.
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partial, int np,
-                                                   Scalars* s) {
-  __shared__ double sh[1024];
-  if (MODE != FIN_NORMF && MODE != FIN_TRUE && s->done) return;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) v += partial[i];
-  const double tot = block_sum(v, sh);
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void finalize_scalar(double tot, Scalars* s) {
   if (MODE == FIN_NORMF) {
     s->normF = sqrt(tot);
     s->res = s->normF;
@@ -693,6 +687,17 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ pa
   } else {
     s->res_true = sqrt(tot);
   }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ partial, int np,
+                                                   Scalars* s) {
+  __shared__ double sh[1024];
+  if (MODE != FIN_NORMF && MODE != FIN_TRUE && s->done) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += partial[i];
+  const double tot = block_sum(v, sh);
+  if (threadIdx.x == 0) finalize_scalar<MODE>(tot, s);
 }
 
 // partial sums of a.b over a flat vector (grid-stride, fixed grid)

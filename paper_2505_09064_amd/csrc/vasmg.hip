@@ -23,6 +23,7 @@
 #include "../../include/vasmg.h"
 #include "hierarchy.hpp"
 #include "kernels.hpp"
+#include "block.hpp"
 
 using namespace vasmg;
 using dev::Scalars;
@@ -120,6 +121,15 @@ struct vasmg_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gA = nullptr, gB = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // block right-hand sides: K columns interleaved per vertex (K = 0: none)
+  int K = 0;
+  std::vector<void*> kb, kx, ks, kr;   // per level V-cycle vectors [n][K][DP]
+  double *kF = nullptr, *kX = nullptr, *kR = nullptr, *kP = nullptr, *kQ = nullptr;
+  double* kpartial = nullptr;
+  int kn_partial = 0;                  // partial sums per column
+  Scalars* ksc = nullptr;              // [K]
+  Scalars* kh_sc = nullptr;            // pinned host copy [K]
+  hipGraphExec_t kgA = nullptr, kgB = nullptr;
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -141,12 +151,15 @@ struct vasmg_ctx {
   ~vasmg_ctx() {
     if (gA) (void)hipGraphExecDestroy(gA);
     if (gB) (void)hipGraphExecDestroy(gB);
+    if (kgA) (void)hipGraphExecDestroy(kgA);
+    if (kgB) (void)hipGraphExecDestroy(kgB);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     if (h_sc) (void)hipHostFree(h_sc);
     if (h_rtol) (void)hipHostFree(h_rtol);
+    if (kh_sc) (void)hipHostFree(kh_sc);
   }
 };
 
@@ -1103,6 +1116,284 @@ int solve_one(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x
   return status;
 }
 
+// -------------------------------------------------------------------------
+// Block right-hand sides: K PCG recurrences that share every matrix read
+// (vectors [row][K][DP], per-column scalars; kernels in block.hpp).
+// -------------------------------------------------------------------------
+#define DISPATCH_K(Kv, ...)                                  \
+  switch (Kv) {                                              \
+    case 4: { constexpr int KK = 4; __VA_ARGS__; } break;    \
+    case 8: { constexpr int KK = 8; __VA_ARGS__; } break;    \
+    default: { constexpr int KK = 16; __VA_ARGS__; } break;  \
+  }
+
+void upload_block(vasmg_ctx& C, int K) {
+  if (K != 4 && K != 8 && K != 16)
+    throw vasmg::Error{VASMG_EINVAL, "block_rhs must be 0, 4, 8 or 16"};
+  if (C.opt.preconditioner != VASMG_PRECOND_VASMG || C.opt.n_pre < 1)
+    throw vasmg::Error{VASMG_EINVAL, "block_rhs needs the V-ASMG preconditioner with n_pre >= 1"};
+  if (C.n_coarse * K > dev::kCoarseMax)
+    throw vasmg::Error{VASMG_EINVAL, "block_rhs: coarsest level too large for K columns"};
+  C.K = K;
+  const int tb = C.vc32 ? 4 : 8;
+  const int nl = C.L + 1;
+  C.kb.assign(nl, nullptr);
+  C.kx.assign(nl, nullptr);
+  C.ks.assign(nl, nullptr);
+  C.kr.assign(nl, nullptr);
+  for (int l = 0; l < nl; ++l) {
+    const int64_t bytes = static_cast<int64_t>(C.lev[l].n) * K * C.DP * tb;
+    for (auto* v : {&C.kb, &C.kx, &C.ks, &C.kr}) {
+      (*v)[l] = C.dalloc<char>(bytes);
+      HIP_CHECK(hipMemset((*v)[l], 0, bytes));
+    }
+  }
+  const int64_t n = C.n0p * K;
+  for (double** v : {&C.kF, &C.kX, &C.kR, &C.kP, &C.kQ}) {
+    *v = C.dalloc<double>(n);
+    HIP_CHECK(hipMemset(*v, 0, sizeof(double) * n));
+  }
+  if (!C.vc32) C.kb[0] = C.kR;    // FP64 V-cycle: its fine right-hand side is r
+  C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanes));
+  C.kpartial = C.dalloc<double>(static_cast<int64_t>(C.kn_partial) * K);
+  C.ksc = C.dalloc<Scalars>(K);
+  HIP_CHECK(hipMemset(C.ksc, 0, sizeof(Scalars) * K));
+  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.kh_sc), sizeof(Scalars) * K));
+}
+
+template <int D, int K>
+int launch_spmv_mc(const vasmg_ctx& C, const double* x, double* y, double* partial,
+                   hipStream_t st) {
+  const DevLevel& lv = C.lev[0];
+  const int grid = grid_for(lv.n, dev::kBlock / dev::kPointLanes);
+  if (partial && grid > C.kn_partial)
+    throw vasmg::Error{VASMG_EINVAL, "internal: block SpMV partial buffer too small"};
+  if (partial)
+    hipLaunchKernelGGL((dev::k_spmv_mc<D, K, true>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
+                       LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y, partial);
+  else
+    hipLaunchKernelGGL((dev::k_spmv_mc<D, K, false>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
+                       LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y, partial);
+  return grid;
+}
+
+template <typename T, int D, int K>
+void launch_gs_sweep_mc(const DevLevel& lv, bool backward, bool zero_guess, const T* b, T* x,
+                        T* s, hipStream_t st) {
+  const dev::Part<T> Lp = LevelMats<T>::L(lv), Up = LevelMats<T>::U(lv);
+  for (int q = 0; q < lv.ncolors; ++q) {
+    const int c = backward ? lv.ncolors - 1 - q : q;
+    const int mode = backward ? 2 : (zero_guess ? 0 : 1);
+    const int r0 = lv.color_ptr[c], nr = lv.color_ptr[c + 1] - r0;
+    if (nr <= 0) continue;
+    if (lv.cells) {
+      const dim3 grid(nr), blk((1 << D) * dev::kCellLanes);
+      const T* M = LevelMats<T>::cellM(lv);
+      if (mode == 0)
+        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 0>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
+                           Up, M, b, x, s);
+      else if (mode == 1)
+        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 1>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
+                           Up, M, b, x, s);
+      else
+        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 2>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
+                           Up, M, b, x, static_cast<T*>(nullptr));
+    } else {
+      const dim3 grid(grid_for(nr, dev::kBlock / dev::kPointLanes)), blk(dev::kBlock);
+      const T* dg = LevelMats<T>::diag(lv);
+      if (mode == 0)
+        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 0>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
+                           b, x, s);
+      else if (mode == 1)
+        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 1>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
+                           b, x, s);
+      else
+        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 2>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
+                           b, x, static_cast<T*>(nullptr));
+    }
+  }
+}
+
+template <typename T, int D, int K>
+void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
+  const int L = C.L;
+  for (int l = 0; l < L; ++l) {
+    const DevLevel& lv = C.lev[l];
+    T* b = static_cast<T*>(C.kb[l]);
+    T* x = static_cast<T*>(C.kx[l]);
+    T* s = static_cast<T*>(C.ks[l]);
+    T* r = static_cast<T*>(C.kr[l]);
+    for (int k = 0; k < C.opt.n_pre; ++k) launch_gs_sweep_mc<T, D, K>(lv, false, k == 0, b, x, s, st);
+    if (lv.cells)
+      hipLaunchKernelGGL((dev::k_cell_residual_mc<T, D, K>), dim3(lv.ncells),
+                         dim3((1 << D) * dev::kCellLanes), 0, st, lv.cell_ptr, LevelMats<T>::L(lv),
+                         LevelMats<T>::U(lv), LevelMats<T>::cellM(lv), s, x, r);
+    else
+      hipLaunchKernelGGL((dev::k_residual_upper_mc<T, D, K>),
+                         dim3(grid_for(lv.n, dev::kBlock / dev::kPointLanes)), dim3(dev::kBlock), 0,
+                         st, lv.n, LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x, r);
+    hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K>), dim3(grid_for(lv.nnext, dev::kBlock / K)),
+                       dim3(dev::kBlock), 0, st, lv.nnext, lv.pt_ptr, lv.pt_idx,
+                       LevelMats<T>::ptw(lv), r, static_cast<T*>(C.kb[l + 1]));
+  }
+  hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K>), dim3(1), dim3(dev::kBlock), 0, st,
+                     static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.kb[L]),
+                     static_cast<T*>(C.kx[L]));
+  for (int l = L - 1; l >= 0; --l) {
+    const DevLevel& lv = C.lev[l];
+    T* b = static_cast<T*>(C.kb[l]);
+    T* x = static_cast<T*>(C.kx[l]);
+    hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K>), dim3(grid_for(lv.n, dev::kBlock / K)),
+                       dim3(dev::kBlock), 0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
+                       static_cast<const T*>(C.kx[l + 1]), x);
+    for (int k = 0; k < C.opt.n_post; ++k)
+      launch_gs_sweep_mc<T, D, K>(lv, true, false, b, x, nullptr, st);
+  }
+}
+
+// q = A p, alpha, x += alpha p, r -= alpha q, ||r|| and the stop flags (per column)
+template <int D, int K>
+void enqueue_iter_A_mc(vasmg_ctx& C, hipStream_t st) {
+  constexpr int DP = dev::Pad<D>::value;
+  const int64_t n = C.n0p * K;
+  const int np = launch_spmv_mc<D, K>(C, C.kP, C.kQ, C.kpartial, st);
+  hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_ALPHA, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                     C.kpartial, np, C.ksc);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_update_xr_mc<float, K, DP>), dim3(kFlatGrid), dim3(dev::kBlock), 0,
+                       st, n, C.ksc, C.kP, C.kQ, C.kX, C.kR, static_cast<float*>(C.kb[0]),
+                       C.kpartial);
+  else
+    hipLaunchKernelGGL((dev::k_update_xr_mc<double, K, DP>), dim3(kFlatGrid), dim3(dev::kBlock), 0,
+                       st, n, C.ksc, C.kP, C.kQ, C.kX, C.kR, static_cast<double*>(nullptr),
+                       C.kpartial);
+  hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_RES, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                     C.kpartial, kFlatGrid, C.ksc);
+}
+
+// z = B r, rho = r.z, beta, p = z + beta p (per column)
+template <int D, int K>
+void enqueue_iter_B_mc(vasmg_ctx& C, hipStream_t st) {
+  constexpr int DP = dev::Pad<D>::value;
+  const int64_t n = C.n0p * K;
+  if (C.vc32) {
+    enqueue_vcycle_mc<float, D, K>(C, st);
+    hipLaunchKernelGGL((dev::k_dot_mc<K, DP, float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, n,
+                       C.kR, static_cast<const float*>(C.kx[0]), C.kpartial);
+  } else {
+    enqueue_vcycle_mc<double, D, K>(C, st);
+    hipLaunchKernelGGL((dev::k_dot_mc<K, DP, double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                       n, C.kR, static_cast<const double*>(C.kx[0]), C.kpartial);
+  }
+  hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_BETA, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                     C.kpartial, kFlatGrid, C.ksc);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_update_p_mc<float, K, DP>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st,
+                       n, C.ksc, static_cast<const float*>(C.kx[0]), C.kP);
+  else
+    hipLaunchKernelGGL((dev::k_update_p_mc<double, K, DP>), dim3(kFlatGrid), dim3(dev::kBlock), 0,
+                       st, n, C.ksc, static_cast<const double*>(C.kx[0]), C.kP);
+}
+
+// Columns c0 .. c0+nc-1 (nc <= K) of the user arrays [n_rhs][nv][D]; the
+// unused columns of the block are zero and stop at once.
+template <int D, int K>
+int solve_block(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x, int c0, int nc,
+                double rtol, hipStream_t st, vasmg_solve_info* info) {
+  constexpr int DP = dev::Pad<D>::value;
+  if (!C.kgA) C.kgA = capture(C, &enqueue_iter_A_mc<D, K>);
+  if (!C.kgB) C.kgB = capture(C, &enqueue_iter_B_mc<D, K>);
+  const int n0 = C.n0;
+  const int64_t n = C.n0p * K;
+  const int64_t nv = C.H.n_mesh_vertices;
+  const int gflat = kFlatGrid;
+  const dim3 gk(grid_for(static_cast<int64_t>(n0) * K, dev::kBlock));
+  HIP_CHECK(hipEventRecord(C.ev[0], st));
+  hipLaunchKernelGGL((dev::k_gather_user_mc<D, K>), gk, dim3(dev::kBlock), 0, st, n0, C.user_map,
+                     d_rhs, nv, c0, nc, C.kF);
+  hipLaunchKernelGGL((dev::k_dot_mc<K, DP, double>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.kF,
+                     C.kF, C.kpartial);
+  hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_NORMF, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                     C.kpartial, gflat, C.ksc);
+  if (d_x0) {
+    hipLaunchKernelGGL((dev::k_gather_user_mc<D, K>), gk, dim3(dev::kBlock), 0, st, n0, C.user_map,
+                       d_x0, nv, c0, nc, C.kX);
+    hipLaunchKernelGGL((dev::k_zero_cols_mc<K, DP>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.ksc,
+                       C.kX);
+    launch_spmv_mc<D, K>(C, C.kX, C.kQ, nullptr, st);
+    hipLaunchKernelGGL((dev::k_sub_norm_mc<K, DP>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.kF,
+                       C.kQ, C.kR, C.kpartial);
+    hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_TRUE, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                       C.kpartial, gflat, C.ksc);
+  } else {
+    launch_fill<double>(C.kX, n, 0.0, st);
+    hipLaunchKernelGGL((dev::k_convert<double, double>), dim3(gflat), dim3(dev::kBlock), 0, st, n,
+                       C.kF, C.kR);
+  }
+  hipLaunchKernelGGL((dev::k_start_mc<K>), dim3(1), dim3(64), 0, st, C.ksc, rtol, d_x0 ? 1 : 0);
+  launch_fill<double>(C.kP, n, 0.0, st);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(gflat), dim3(dev::kBlock), 0, st, n,
+                       C.kR, static_cast<float*>(C.kb[0]));
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemcpyAsync(C.kh_sc, C.ksc, sizeof(Scalars) * K, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<double> normF(K);
+  bool all_done = true;
+  for (int k = 0; k < K; ++k) {
+    normF[k] = C.kh_sc[k].normF;
+    all_done = all_done && C.kh_sc[k].done;
+  }
+  if (!all_done) {
+    HIP_CHECK(hipGraphLaunch(C.kgB, st));
+    for (int it = 0; it < C.opt.max_iters; ++it) {
+      HIP_CHECK(hipGraphLaunch(C.kgA, st));
+      HIP_CHECK(hipMemcpyAsync(C.kh_sc, C.ksc, sizeof(Scalars) * K, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      all_done = true;
+      for (int k = 0; k < K; ++k) all_done = all_done && C.kh_sc[k].done;
+      if (all_done) break;
+      HIP_CHECK(hipGraphLaunch(C.kgB, st));
+    }
+  }
+  // true residuals, scatter
+  launch_spmv_mc<D, K>(C, C.kX, C.kQ, nullptr, st);
+  hipLaunchKernelGGL((dev::k_sub_norm_mc<K, DP>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.kF,
+                     C.kQ, static_cast<double*>(nullptr), C.kpartial);
+  hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_TRUE, K>), dim3(K), dim3(dev::kBlock), 0, st,
+                     C.kpartial, gflat, C.ksc);
+  launch_fill<double>(d_x + static_cast<int64_t>(c0) * nv * D, static_cast<int64_t>(nc) * nv * D, 0.0,
+                      st);                                       // fixed DOFs
+  hipLaunchKernelGGL((dev::k_scatter_user_mc<D, K>), gk, dim3(dev::kBlock), 0, st, n0, C.user_map,
+                     C.kX, nv, c0, nc, d_x);
+  HIP_CHECK(hipMemcpyAsync(C.kh_sc, C.ksc, sizeof(Scalars) * K, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipEventRecord(C.ev[1], st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipGetLastError());
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, C.ev[0], C.ev[1]));
+  int worst = VASMG_OK;
+  for (int k = 0; k < nc; ++k) {
+    const Scalars& sk = C.kh_sc[k];
+    int status = VASMG_OK;
+    if (!std::isfinite(normF[k]) || sk.status == 5)
+      status = VASMG_EBREAKDOWN;
+    else if (normF[k] != 0.0 && !(sk.res / normF[k] < rtol) && !(d_x0 && sk.iters == 0))
+      status = VASMG_ENOTCONV;
+    if (status != VASMG_OK && worst == VASMG_OK) worst = status;
+    if (info) {
+      vasmg_solve_info& f = info[k];
+      f.iterations = sk.iters;
+      f.converged = status == VASMG_OK ? 1 : 0;
+      f.rel_res = normF[k] > 0 ? sk.res / normF[k] : 0.0;
+      f.rel_res_true = normF[k] > 0 ? sk.res_true / normF[k] : 0.0;
+      f.t_solve_ms = ms;
+      f.t_spmv_ms = f.t_precond_ms = f.t_vector_ms = f.bytes_model = 0.0;
+    }
+  }
+  return worst;
+}
+
 vasmg_status fail_with(const vasmg::Error& e) {
   g_last_error = e.msg;
   return static_cast<vasmg_status>(e.status);
@@ -1195,6 +1486,8 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       throw vasmg::Error{VASMG_EINVAL, "unknown preconditioner"};
     if (o.max_iters <= 0) o.max_iters = 10000;
     if (o.coarsest_max_dofs < 0) throw vasmg::Error{VASMG_EINVAL, "coarsest_max_dofs < 0"};
+    if (o.block_rhs != 0 && o.block_rhs != 4 && o.block_rhs != 8 && o.block_rhs != 16)
+      throw vasmg::Error{VASMG_EINVAL, "block_rhs must be 0, 4, 8 or 16"};
     MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
                 mesh->E, mesh->nu, mesh->fixed};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
@@ -1215,6 +1508,7 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
       HIP_CHECK(hipGetDevice(&C->device));
       upload_all(*C);
+      if (o.block_rhs != 0) upload_block(*C, o.block_rhs);
       if (o.autotune) {
         if (C->d == 2)
           autotune<2>(*C);
@@ -1251,12 +1545,26 @@ vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const doubl
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t stride = h->H.n_mesh_vertices * h->d;
     int worst = VASMG_OK;
-    for (int c = 0; c < n_rhs; ++c) {
-      const int s = h->d == 2 ? solve_one<2>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
-                                              d_x + c * stride, rtol, st, info ? info + c : nullptr)
-                              : solve_one<3>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
-                                              d_x + c * stride, rtol, st, info ? info + c : nullptr);
-      if (s != VASMG_OK && worst == VASMG_OK) worst = s;
+    if (h->K > 0 && n_rhs > 1) {
+      // block solve: K columns at a time share every matrix read
+      for (int c0 = 0; c0 < n_rhs; c0 += h->K) {
+        const int nc = std::min(h->K, n_rhs - c0);
+        vasmg_solve_info* fi = info ? info + c0 : nullptr;
+        int s = VASMG_OK;
+        DISPATCH_K(h->K, {
+          s = h->d == 2 ? solve_block<2, KK>(*h, d_rhs, d_x0, d_x, c0, nc, rtol, st, fi)
+                        : solve_block<3, KK>(*h, d_rhs, d_x0, d_x, c0, nc, rtol, st, fi);
+        });
+        if (s != VASMG_OK && worst == VASMG_OK) worst = s;
+      }
+    } else {
+      for (int c = 0; c < n_rhs; ++c) {
+        const int s = h->d == 2 ? solve_one<2>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
+                                                d_x + c * stride, rtol, st, info ? info + c : nullptr)
+                                : solve_one<3>(*h, d_rhs + c * stride, d_x0 ? d_x0 + c * stride : nullptr,
+                                                d_x + c * stride, rtol, st, info ? info + c : nullptr);
+        if (s != VASMG_OK && worst == VASMG_OK) worst = s;
+      }
     }
     if (worst == VASMG_ENOTCONV) g_last_error = "PCG did not reach rtol within max_iters";
     if (worst == VASMG_EBREAKDOWN) g_last_error = "PCG breakdown (p^T A p <= 0 or not finite)";

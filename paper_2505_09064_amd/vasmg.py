@@ -50,7 +50,7 @@ class Options(C.Structure):
                 ("coarsest_max_dofs", C.c_int64), ("max_iters", C.c_int32),
                 ("preconditioner", C.c_int32), ("profile", C.c_int32),
                 ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("block_rhs", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class PhaseStat(C.Structure):

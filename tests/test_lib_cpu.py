@@ -123,6 +123,7 @@ def test_setup_rejects_invalid_input():
         _expect(V.EINVAL, fn)
     _expect(V.EDEGENERATE, lambda: small2d(6, fix="none"))
     _expect(V.EINVAL, lambda: small2d(5), leaf_capacity=-1)
+    _expect(V.EINVAL, lambda: small2d(5), block_rhs=5)
 
 
 def test_host_only_handle_refuses_device_calls():
@@ -139,5 +140,6 @@ def test_default_options():
     o = V.default_options(2)
     assert (o.leaf_capacity, o.n_pre, o.n_post, o.max_iters) == (4, 1, 1, 10000)
     assert V.default_options(3).leaf_capacity == 8
+    assert o.block_rhs == 0
     with pytest.raises(V.VasmgError):
         V.default_options(4)
