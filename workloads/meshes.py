@@ -291,8 +291,8 @@ def cfg3() -> Mesh:
     return Mesh("cfg3_2d_1025sq_graded_nu049", 2, coords, tris, E, nu, fixed, [F])
 
 
-def fourier_body_force(r: int, seed: int = 3):
-    """Column r of the 16 smooth random body forces (8 Fourier modes per component)."""
+def _fourier_modes(r: int, seed: int):
+    """Modes of load case r: per component, 8 (k in {1..4}^3, c ~ N(0,1)) pairs."""
     rng = np.random.default_rng([seed, r])
     modes = []
     for a in range(3):
@@ -302,6 +302,13 @@ def fourier_body_force(r: int, seed: int = 3):
             c = rng.normal()
             ma.append((k, c))
         modes.append(ma)
+    return modes
+
+
+def fourier_body_force(r: int, seed: int = 3):
+    """Column r of the smooth random body forces (8 Fourier modes per component):
+    f_a = sum_m c_m sin(pi k1 x) sin(pi k2 y) sin(pi k3 z)."""
+    modes = _fourier_modes(r, seed)
 
     def f(x, y, z):
         out = np.zeros((x.shape[0], 3))
@@ -313,10 +320,69 @@ def fourier_body_force(r: int, seed: int = 3):
     return f
 
 
+def load_fourier_tet(coords, elems, n_rhs: int, seed: int = 3, chunk: int = 1 << 18):
+    """The first n_rhs Fourier body-force load cases at once, by the same 4-point
+    degree-2 rule as load_function_tet (equal values up to summation order).
+
+    At each quadrature point the 64 products sin(pi k1 x) sin(pi k2 y)
+    sin(pi k3 z), k in {1..4}^3, times a [64, 3 n_rhs] coefficient matrix give
+    every load case's components; element slot s receives |e|/4 (B sum_q f_q +
+    (A - B) f_s), accumulated into the vertex rows by a sparse incidence product
+    that adds into the output in place. Elements go in chunks through work
+    arrays allocated once (first-touch page faults, not arithmetic, dominate
+    fresh large temporaries)."""
+    import scipy.sparse as sp
+    from scipy.sparse import _sparsetools
+    nv, ne = coords.shape[0], elems.shape[0]
+    R3 = 3 * n_rhs
+    Cm = np.zeros((64, R3))
+    for r in range(n_rhs):
+        for a, ma in enumerate(_fourier_modes(r, seed)):
+            for (k, c) in ma:
+                Cm[(k[0] - 1) * 16 + (k[1] - 1) * 4 + (k[2] - 1), 3 * r + a] += c
+    kk = np.pi * np.arange(1, 5)[:, None]
+    m = min(chunk, ne)
+    t = np.empty((3, 4, m))
+    t01 = np.empty((4, 4, m))
+    P = np.empty((4, 4, 4, m))
+    fq = np.empty((4, m, R3))
+    fsum = np.empty((m, R3))
+    share = np.empty((m, R3))
+    F = np.zeros((nv, R3))
+    for e0 in range(0, ne, chunk):
+        el = elems[e0:e0 + chunk]
+        n = el.shape[0]
+        vol4 = _measure(coords, el) / 4.0
+        X = coords[el]
+        for q in range(4):
+            lam = np.full(4, _TET_B); lam[q] = _TET_A
+            pq = np.einsum("k,ekd->de", lam, X)
+            for d in range(3):
+                np.multiply(kk, pq[d][None, :], out=t[d, :, :n])
+                np.sin(t[d, :, :n], out=t[d, :, :n])
+            np.multiply(t[0, :, None, :n], t[1, None, :, :n], out=t01[:, :, :n])
+            np.multiply(t01[:, :, None, :n], t[2, None, None, :, :n], out=P[:, :, :, :n])
+            Pv = P.reshape(64, m)[:, :n] if n == m else np.ascontiguousarray(P[:, :, :, :n]).reshape(64, n)
+            np.matmul(Pv.T, Cm, out=fq[q, :n])
+        np.add(fq[0, :n], fq[1, :n], out=fsum[:n])
+        np.add(fsum[:n], fq[2, :n], out=fsum[:n])
+        np.add(fsum[:n], fq[3, :n], out=fsum[:n])
+        fsum[:n] *= _TET_B
+        cols = np.arange(n)
+        for sl in range(4):
+            np.multiply(fq[sl, :n], _TET_A - _TET_B, out=share[:n])
+            share[:n] += fsum[:n]
+            share[:n] *= vol4[:, None]
+            S = sp.csr_matrix((np.ones(n), (el[:, sl], cols)), shape=(nv, n))
+            _sparsetools.csr_matvecs(nv, n, R3, S.indptr, S.indices, S.data,
+                                     share[:n].ravel(), F.ravel())
+    return [np.ascontiguousarray(F[:, 3 * r:3 * r + 3]) for r in range(n_rhs)]
+
+
 def cfg4(n: int = 129, n_rhs: int = 16) -> Mesh:
     """3D, 129^3 jittered grid (seed 3), clamped at x=0, 16 smooth random load cases."""
     m = small3d(n, seed=3, fix="x0")
-    m.rhs = [load_function_tet(m.coords, m.elems, fourier_body_force(r)) for r in range(n_rhs)]
+    m.rhs = load_fourier_tet(m.coords, m.elems, n_rhs)
     m.name = f"cfg4_3d_{n}cubed_{n_rhs}rhs"
     return m
 
