@@ -39,6 +39,7 @@ class OracleOptions:
     max_iters: int = 10000
     smoother: str = "colored"       # 'colored' | 'lex'
     flexible: bool = False
+    cycle: str = "V"                # 'V' | 'W' | 'additive' (oracle/vcycle.py)
 
 
 class Oracle:
@@ -114,10 +115,12 @@ class Oracle:
         self._vcycles = {}
 
     # ------------------------------------------------------------------
-    def vcycle(self, precision: str | None = None, smoother: str | None = None) -> VCycle:
+    def vcycle(self, precision: str | None = None, smoother: str | None = None,
+               cycle: str | None = None) -> VCycle:
         precision = precision or self.opts.precision
         smoother = smoother or self.opts.smoother
-        key = (precision, smoother)
+        cycle = cycle or self.opts.cycle
+        key = (precision, smoother, cycle)
         if key not in self._vcycles:
             dt = np.float32 if precision == "fp32" else np.float64
             if smoother == "colored":
@@ -128,7 +131,7 @@ class Oracle:
             else:
                 raise ValueError(smoother)
             self._vcycles[key] = VCycle(self.A, self.P, sm, self.coarsest, self.d,
-                                        self.opts.n_pre, self.opts.n_post, dt)
+                                        self.opts.n_pre, self.opts.n_post, dt, cycle)
         return self._vcycles[key]
 
     def apply_precond(self, r_free: np.ndarray, precision=None, smoother=None) -> np.ndarray:

@@ -16,6 +16,17 @@ two-level one). One application z = B r, from a zero initial guess:
 Algorithm 3's outer convergence loop is not used: a preconditioner application
 is exactly one cycle.
 
+Cycle modes (Section 3 names the V- and W-cycle; Section 4 defines the
+preconditioner as B_h = S_h + Pi B_0 Pi^T):
+  'V'         the recursion above, one coarse visit per level;
+  'W'         two visits of level l+1 per visit of level l; the second starts from
+              the first one's result (a cycle from the guess x0 returns
+              x0 + B (b - A x0)); the coarsest level, solved exactly, once;
+  'additive'  B r = S r + P_0 B_1 P_0^T r: S = the n_pre forward then n_post
+              backward sweeps from zero on the fine level (symmetric
+              Gauss-Seidel for V(1,1)), B_1 = one V-cycle of levels 1..L (the
+              auxiliary space's solver), both applied to the same r.
+
 In FP32 emulation (``dtype=np.float32``) the level matrices, weights and V-cycle
 vectors are single precision; the coarsest right-hand side is cast to FP64,
 solved in FP64 and cast back.
@@ -35,8 +46,11 @@ from .hierarchy import block_prolongation
 
 class VCycle:
     def __init__(self, A_levels, P_levels, smoothers, coarsest, d: int,
-                 n_pre: int = 1, n_post: int = 1, dtype=np.float64):
+                 n_pre: int = 1, n_post: int = 1, dtype=np.float64, cycle: str = "V"):
         """A_levels[0..L], P_levels[0..L-1] (scalar), smoothers[0..L-1], coarsest solver."""
+        if cycle not in ("V", "W", "additive"):
+            raise ValueError(cycle)
+        self.cycle = cycle
         self.L = len(A_levels) - 1
         self.dtype = dtype
         self.A = [A.astype(dtype).tocsr() for A in A_levels]
@@ -48,18 +62,30 @@ class VCycle:
         self.n_post = n_post
 
     def apply(self, r: np.ndarray) -> np.ndarray:
-        return self._cycle(0, np.asarray(r).astype(self.dtype))
+        r = np.asarray(r).astype(self.dtype)
+        if self.cycle == "additive" and self.L > 0:
+            S = self.smoothers[0]
+            z = np.zeros_like(r)
+            for _ in range(self.n_pre):
+                z = S.forward(r, z)
+            for _ in range(self.n_post):
+                z = S.backward(r, z)
+            e1 = self._cycle(1, self.PbT[0] @ r, None, "V")
+            return z + self.Pb[0] @ e1
+        return self._cycle(0, r, None, self.cycle)
 
-    def _cycle(self, l: int, b: np.ndarray) -> np.ndarray:
+    def _cycle(self, l: int, b: np.ndarray, x0, mode: str) -> np.ndarray:
         if l == self.L:
             return self.coarsest.solve(b.astype(np.float64)).astype(self.dtype)
         S = self.smoothers[l]
-        x = np.zeros_like(b)
+        x = np.zeros_like(b) if x0 is None else x0.copy()
         for _ in range(self.n_pre):
             x = S.forward(b, x)
         r = b - self.A[l] @ x
         bc = self.PbT[l] @ r
-        ec = self._cycle(l + 1, bc)
+        ec = self._cycle(l + 1, bc, None, mode)
+        if mode == "W" and l + 1 < self.L:
+            ec = self._cycle(l + 1, bc, ec, mode)
         x = x + self.Pb[l] @ ec
         for _ in range(self.n_post):
             x = S.backward(b, x)

@@ -283,3 +283,87 @@ def test_sparse_helpers():
     S = sp.csr_matrix(np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]]))
     col = hierarchy.greedy_coloring(S)
     assert list(col) == [0, 1, 0]
+
+
+def _closed_form_W(o, l, order_fn):
+    """W-cycle: as the V-cycle closed form with the coarse operator of two visits,
+    C = 2 B_{l+1} - B_{l+1} A_{l+1} B_{l+1} (x0 + B (b - A x0) applied twice from 0);
+    one visit of the coarsest level (exact solve)."""
+    A = o.A[l].toarray()
+    n = A.shape[0]
+    if l == o.L:
+        return np.linalg.inv(A)
+    p = order_fn(l)
+    Pm = np.zeros((n, n)); Pm[np.arange(n), p] = 1.0
+    M = Pm.T @ np.tril(Pm @ A @ Pm.T) @ Pm
+    Mi = np.linalg.inv(M)
+    Mbar = Mi + Mi.T - Mi.T @ A @ Mi
+    Pb = hierarchy.block_prolongation(o.P[l], o.d).toarray()
+    B1 = _closed_form_W(o, l + 1, order_fn)
+    if l + 1 < o.L:
+        A1 = o.A[l + 1].toarray()
+        C = 2.0 * B1 - B1 @ A1 @ B1
+    else:
+        C = B1
+    I = np.eye(n)
+    return Mbar + (I - Mi.T @ A) @ Pb @ C @ Pb.T @ (I - A @ Mi)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_w_cycle_closed_form_spd(dim):
+    m = small2d(9, seed=1) if dim == 2 else small3d(5, seed=2)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    assert o.L >= 3                      # the W-cycle differs from the V-cycle
+    n = o.A[0].shape[0]
+    B = dense_operator(lambda r: o.vcycle(cycle="W").apply(r), n)
+    Bc = _closed_form_W(o, 0, lambda l: _sweep_order(o, l))
+    assert np.abs(B - Bc).max() <= 1e-10 * np.abs(Bc).max()
+    assert np.abs(B - B.T).max() <= 1e-11 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+    BV = dense_operator(lambda r: o.vcycle(cycle="V").apply(r), n)
+    assert np.abs(B - BV).max() > 1e-6 * np.abs(BV).max()
+
+
+def test_w_cycle_equals_v_cycle_on_two_levels():
+    m = small2d(13, seed=3)          # levels of 242, 162, 50, ... DOFs
+    full = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed,
+               OracleOptions(coarsest_max_dofs=full.A[1].shape[0]))
+    assert o.L == 1
+    r = np.random.default_rng(0).normal(size=o.A[0].shape[0])
+    assert np.array_equal(o.vcycle(cycle="W").apply(r), o.vcycle(cycle="V").apply(r))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_additive_two_level_closed_form_spd(dim):
+    """B = Mbar_0^{-1} + P_0 B_1 P_0^T with B_1 the V-cycle of levels 1..L."""
+    m = _tiny(dim)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    n = o.A[0].shape[0]
+    B = dense_operator(lambda r: o.vcycle(cycle="additive").apply(r), n)
+    A = o.A[0].toarray()
+    p = _sweep_order(o, 0)
+    Pm = np.zeros((n, n)); Pm[np.arange(n), p] = 1.0
+    Mi = np.linalg.inv(Pm.T @ np.tril(Pm @ A @ Pm.T) @ Pm)
+    Mbar = Mi + Mi.T - Mi.T @ A @ Mi
+    Pb = hierarchy.block_prolongation(o.P[0], o.d).toarray()
+    Bc = Mbar + Pb @ _closed_form_B(o, 1, lambda l: _sweep_order(o, l)) @ Pb.T
+    assert np.abs(B - Bc).max() <= 1e-10 * np.abs(Bc).max()
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+
+
+def test_cycle_variants_converge():
+    m = small2d(33, seed=4)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    its = {}
+    for c in ("V", "W", "additive"):
+        o2 = Oracle.__new__(Oracle)
+        o2.__dict__.update(o.__dict__)
+        o2._vcycles = {}
+        o2.opts = OracleOptions(cycle=c)
+        x, info = o2.solve(m.rhs[0], 1e-8)
+        assert info["rel_res_true"] < 1e-8
+        its[c] = info["iterations"]
+    print(its)
+    assert its["W"] <= its["V"] + 1 and its["additive"] >= its["V"] - 1
