@@ -114,6 +114,90 @@ def bench_cfg4(args, V, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args, V):
+    """The serving stream: requests i = 0..N-1 (2D or 3D jittered meshes, DOFs
+    log-uniform in [1e3, 1e6], 1:100 materials), each a new mesh, so latency
+    includes the host setup. The single-stream rate is measured first by serving
+    the first 8 requests one at a time (one slot, one setup worker); then all N
+    arrive as a Poisson stream at 0.7x that rate into a server with 4 slots and 4
+    setup workers. Latency = done - arrival. The first 8 results must be
+    bitwise identical alone and in the mix."""
+    from workloads import request_mesh
+    N = max(8, args.requests)
+    t0 = time.perf_counter()
+    meshes = []
+    for i in range(N):
+        meshes.append(request_mesh(i))
+        if i % 8 == 7:
+            log(f"generated {i + 1}/{N} requests ({time.perf_counter() - t0:.1f}s)")
+    dofs = np.array([m.n_dofs for m in meshes])
+    opts = dict(precision=V.FP32_PRECOND)
+
+    # single stream: one request at a time end to end
+    srv = V.Server(slots=1, setup_workers=1, **opts)
+    alone = []
+    t0 = time.perf_counter()
+    for i in range(8):
+        rid = srv.submit(meshes[i], meshes[i].rhs[0], 1e-6)
+        alone.append(srv.wait(rid))
+    t_single = time.perf_counter() - t0
+    srv.close()
+    rate1 = 8.0 / t_single
+    lam = 0.7 * rate1
+    log(f"single stream: {rate1:.2f} requests/s (8 requests, {t_single:.1f}s); arrivals at {lam:.2f}/s")
+
+    rng = np.random.default_rng(7)
+    gaps = rng.exponential(1.0 / lam, size=N)
+    srv = V.Server(slots=4, setup_workers=4, **opts)
+    ids = []
+    t0 = time.perf_counter()
+    t_next = 0.0
+    for i in range(N):
+        t_next += gaps[i]
+        dt = t_next - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.submit(meshes[i], meshes[i].rhs[0], 1e-6))
+        if i % 8 == 7:
+            log(f"submitted {i + 1}/{N}, {srv.stats()}")
+    got = [srv.wait(r) for r in ids]
+    t_all = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    res = [g[1] for g in got]
+    ok = [r["status"] == V.OK for r in res]
+    lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
+    setup = np.array([r["t_setup_end_ms"] - r["t_setup_start_ms"] for r in res])
+    solve = np.array([r["info"]["t_solve_ms"] for r in res])
+    queue = np.array([r["t_admit_ms"] - r["t_setup_end_ms"] for r in res])
+    same = all(np.array_equal(got[i][0], alone[i][0]) for i in range(8))
+    overlap = 0
+    iv = sorted((r["t_admit_ms"], r["t_done_ms"]) for r in res)
+    for a in range(len(iv)):
+        for b in range(a + 1, len(iv)):
+            if iv[b][0] < iv[a][1]:
+                overlap += 1
+    line = {
+        "metric": "serving: requests/s and p50/p99 latency (setup + solve), rtol 1e-6",
+        "value": N / t_all, "unit": "requests/s", "n_gpus": 1, "steps": N, "warmup": 0,
+        "ms_per_step": 1e3 * t_all / N, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (V-cycle) + f64 (PCG)", "data": "synthetic",
+        "config": {"workload": f"{N} requests, 2D/3D jittered P1 elasticity meshes, DOFs "
+                               "log-uniform in [1e3, 1e6] (seeded per request), Poisson arrivals "
+                               "at 0.7x the single-stream rate, 4 slots, 4 setup workers",
+                   "dofs_min": int(dofs.min()), "dofs_max": int(dofs.max()),
+                   "dofs_mean": float(dofs.mean())},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "single_stream_requests_per_s": rate1, "arrival_rate": lam,
+        "mean_setup_ms": float(setup.mean()), "mean_solve_ms": float(solve.mean()),
+        "mean_admission_wait_ms": float(queue.mean()),
+        "all_ok": bool(all(ok)), "same_alone_and_in_mix": bool(same),
+        "overlapping_request_pairs_on_device": overlap,
+        "peak_device_bytes": int(st["peak_bytes"]), "budget_bytes": int(st["budget_bytes"]),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,9 +206,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--workload", choices=["cfg2", "cfg4"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "cfg4", "serve"], default="cfg2",
                     help="cfg2: the headline 65^3 workload (default); cfg4: 129^3 with 16 load "
-                         "cases, block solve against column-by-column solves")
+                         "cases, block solve against column-by-column solves; serve: the request "
+                         "stream through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--counters", action="store_true",
                     help="driver for rocprofv3 --pmc runs: a 256 MiB device copy (counter "
                          "calibration) followed by one replayed PCG iteration of the workload")
@@ -141,6 +227,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cfg4":
         bench_cfg4(args, V, torch)
+        return
+    if args.workload == "serve":
+        bench_serve(args, V)
         return
     if args.counters:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")

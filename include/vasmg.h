@@ -56,6 +56,8 @@ typedef enum {
 enum { VASMG_FP64 = 0, VASMG_FP32_PRECOND = 1 };
 enum { VASMG_TREE_ALL = 0, VASMG_TREE_FREE = 1 };
 enum { VASMG_PRECOND_VASMG = 0, VASMG_PRECOND_JACOBI = 1, VASMG_PRECOND_NONE = 2 };
+enum { VASMG_CYCLE_V = 0, VASMG_CYCLE_W = 1, VASMG_CYCLE_ADDITIVE = 2 };
+enum { VASMG_SMOOTHER_GS = 0, VASMG_SMOOTHER_JACOBI = 1 };
 
 /* Mesh: P1 triangles (dim 2, plane strain) or tetrahedra (dim 3); Section 2. */
 typedef struct {
@@ -95,7 +97,17 @@ typedef struct {
                                   sharing every matrix read (vectors interleaved per
                                   vertex); needs the V-ASMG preconditioner, n_pre >= 1 and
                                   a coarsest level of at most 4096 / K DOFs (else EINVAL) */
-  int32_t reserved[5];
+  int32_t cycle;               /* VASMG_CYCLE_V (default, Algorithm 3 recursive),
+                                  VASMG_CYCLE_W (two coarse visits per level, Section 3
+                                  cycle modes) or VASMG_CYCLE_ADDITIVE (Section 4's
+                                  B = S + P B_1 P^T: the fine-level sweeps from zero plus
+                                  the prolonged V-cycle of levels 1..L of P^T r)          */
+  int32_t smoother;            /* VASMG_SMOOTHER_GS (default: multicolour point GS,
+                                  Algorithm 1) or VASMG_SMOOTHER_JACOBI (damped
+                                  vertex-block Jacobi, Section 4's other S_h: omega =
+                                  (4/3) / lambda_max(D^-1 A), estimated per level by 30
+                                  power iterations at setup)                            */
+  int32_t reserved[3];
 } vasmg_options;
 
 typedef struct {
@@ -134,11 +146,87 @@ vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const doubl
                                 double* d_x, int32_t n_rhs, double rtol, void* stream,
                                 vasmg_solve_info* info);
 
+/* Upload a hierarchy built with host_only = 1 to the current HIP device (the
+ * device half of vasmg_setup, which then runs any block_rhs allocation and
+ * autotuning the options ask for). stream (a hipStream_t) may be NULL; if set,
+ * every device allocation of the handle is stream-ordered on it
+ * (hipMallocAsync, and hipFreeAsync at vasmg_free, which must then happen
+ * while the stream exists): a server can then upload, solve and free on one
+ * stream without synchronising the device. Errors: EINVAL (already uploaded),
+ * ENOMEM, EDEVICE. On failure the handle stays unusable for solves. */
+vasmg_status vasmg_upload(vasmg_handle h, void* stream);
+
+/* Device bytes of the handle: allocated bytes once uploaded, else an upper
+ * bound of what vasmg_upload will allocate (admission control). */
+vasmg_status vasmg_device_bytes(vasmg_handle h, int64_t* bytes);
+
 /* Release every host and device resource of h. NULL-safe. */
 void vasmg_free(vasmg_handle h);
 
 /* Message of the last failure on this thread ("" if none). */
 const char* vasmg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent solve requests (one mesh and
+ * one load case each) on one GPU. A request is set up on the host by one of
+ * setup_workers threads, admitted first in first out as soon as one of `slots`
+ * device slots is free and its device bytes (vasmg_device_bytes) fit the HBM
+ * budget next to the requests already resident, then uploaded, solved and
+ * freed on the slot's own stream; requests overlap on the device. Every request
+ * uses the server's options (autotuning off, so a result does not depend on
+ * what else is running; block_rhs ignored). Thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct vasmg_server* vasmg_server_handle;
+
+typedef struct {
+  int32_t slots;               /* concurrent device solves (streams), 1..64, default 4    */
+  int32_t setup_workers;       /* host threads building hierarchies, 1..64, default 4;
+                                  the host's cores are split evenly between them        */
+  int64_t hbm_budget_bytes;    /* device bytes resident requests may hold together;
+                                  0 = 80% of the device's free memory at creation       */
+  vasmg_options options;       /* solver options of every request (leaf_capacity 0 =
+                                  each request's dimension default)                      */
+} vasmg_server_config;
+
+typedef struct {
+  int64_t id;
+  int32_t status;              /* of the request's setup, upload or solve; ENOMEM if its
+                                  device bytes exceed the whole budget                  */
+  int32_t slot;                /* device slot that ran it (-1: none)                      */
+  int64_t device_bytes;        /* device bytes it held while resident                     */
+  double t_submit_ms, t_setup_start_ms, t_setup_end_ms, t_admit_ms, t_done_ms;
+                               /* server clock (ms since vasmg_server_create)             */
+  vasmg_solve_info info;       /* the solve's own report                                  */
+  char message[128];           /* why it failed ("" if status is OK)                      */
+} vasmg_request_result;
+
+typedef struct {
+  int64_t submitted, completed, waiting_setup, waiting_admission, running;
+  int64_t bytes_in_use, peak_bytes, budget_bytes;
+  double t_now_ms;
+} vasmg_server_counters;
+
+/* Defaults: 4 slots, 4 setup workers, 80% of free device memory, default options. */
+vasmg_status vasmg_server_default_config(vasmg_server_config* cfg);
+
+/* Start the server's threads on the current HIP device. EDEVICE without one. */
+vasmg_status vasmg_server_create(const vasmg_server_config* cfg, vasmg_server_handle* out);
+
+/* Queue a request; mesh and rhs ([n_vertices][dim], host) are copied, so the
+ * caller may free them on return. Returns its id at once. */
+vasmg_status vasmg_server_submit(vasmg_server_handle s, const vasmg_mesh* mesh, const double* rhs,
+                                 double rtol, int64_t* id);
+
+/* Block until request id has finished; x ([n_vertices][dim], host) may be NULL.
+ * Returns the request's status; each id can be waited for once. */
+vasmg_status vasmg_server_wait(vasmg_server_handle s, int64_t id, double* x,
+                               vasmg_request_result* res);
+
+/* Counters (requests, resident bytes, peak) at this moment. */
+vasmg_status vasmg_server_stats(vasmg_server_handle s, vasmg_server_counters* out);
+
+/* Finish every queued request, stop the threads and release everything. */
+void vasmg_server_destroy(vasmg_server_handle s);
 
 /* ---------------------------------------------------------------------------
  * Introspection (hierarchy produced by the setup; host data, no device use).

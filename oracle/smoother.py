@@ -117,3 +117,52 @@ class LexGS:
         out = np.empty_like(xc)
         out[self.perm] = xn
         return out.astype(self.dtype)
+
+
+def jacobi_lambda_max(A: sp.csr_matrix, d: int, iters: int = 30) -> float:
+    """Estimate of the largest eigenvalue of D^{-1} A (D = the d x d vertex blocks
+    of A): power iteration from the all-ones vector, then the Rayleigh quotient
+    v^T A v / v^T D v of the last iterate. FP64."""
+    A = A.astype(np.float64).tocsr()
+    n = A.shape[0]
+    nv = n // d
+    Dinv = _block_diag_inverse(A, d)
+    v = np.ones(n)
+    for _ in range(iters):
+        w = Dinv @ (A @ v)
+        v = w / np.linalg.norm(w)
+    D = sp.block_diag([A[k * d:(k + 1) * d, k * d:(k + 1) * d] for k in range(nv)], format="csr")
+    return float(v @ (A @ v)) / float(v @ (D @ v))
+
+
+def _block_diag_inverse(A: sp.csr_matrix, d: int) -> sp.csr_matrix:
+    nv = A.shape[0] // d
+    blocks = []
+    for k in range(nv):
+        blk = A[k * d:(k + 1) * d, k * d:(k + 1) * d].toarray()
+        blocks.append(np.linalg.inv(blk))
+    return sp.block_diag(blocks, format="csr")
+
+
+class BlockJacobi:
+    """Damped vertex-block Jacobi, one of the smoothers Section 4 names for S_h:
+    x <- x + omega D^{-1} (b - A x), D = the d x d diagonal block of each vertex,
+    omega = (4/3) / lambda_max(D^{-1} A) (the usual 2/3 when lambda_max = 2),
+    lambda_max from jacobi_lambda_max. Forward and backward sweeps are the same
+    step (Jacobi has no order). Pinned: the step equals the formula with dense
+    matrices; omega * lambda_max < 2 for the exact lambda_max (the cycle stays
+    symmetric positive definite)."""
+
+    def __init__(self, A: sp.csr_matrix, d: int, dtype=np.float64):
+        self.dtype = dtype
+        self.lam = jacobi_lambda_max(A, d)
+        self.omega = (4.0 / 3.0) / self.lam
+        self.A = A.astype(dtype).tocsr()
+        self.Dinv = _block_diag_inverse(A.astype(np.float64).tocsr(), d).astype(dtype)
+
+    def forward(self, b: np.ndarray, x: np.ndarray) -> np.ndarray:
+        om = self.dtype(self.omega)
+        return x + om * (self.Dinv @ (b - self.A @ x))
+
+    backward = forward
+

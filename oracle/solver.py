@@ -24,7 +24,7 @@ import scipy.sparse as sp
 
 from . import fem, hierarchy, tree
 from .pcg import pcg
-from .smoother import ColoredGS, LexGS
+from .smoother import BlockJacobi, ColoredGS, LexGS
 from .vcycle import VCycle
 
 
@@ -37,7 +37,7 @@ class OracleOptions:
     tree_vertices: str = "all"      # 'all' | 'free'
     coarsest_max_dofs: int = 0
     max_iters: int = 10000
-    smoother: str = "colored"       # 'colored' | 'lex'
+    smoother: str = "colored"       # 'colored' | 'lex' | 'jacobi'
     flexible: bool = False
     cycle: str = "V"                # 'V' | 'W' | 'additive' (oracle/vcycle.py)
 
@@ -128,6 +128,8 @@ class Oracle:
                       for l in range(self.L)]
             elif smoother == "lex":
                 sm = [LexGS(self.A[l], self.d, dt) for l in range(self.L)]
+            elif smoother == "jacobi":
+                sm = [BlockJacobi(self.A[l], self.d, dt) for l in range(self.L)]
             else:
                 raise ValueError(smoother)
             self._vcycles[key] = VCycle(self.A, self.P, sm, self.coarsest, self.d,

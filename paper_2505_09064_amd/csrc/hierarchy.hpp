@@ -82,4 +82,9 @@ struct SetupParams {
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
 void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);
 
+// Damped vertex-block Jacobi smoother data: inverse diagonal blocks [n][d][d]
+// (canonical order) and the largest eigenvalue of D^{-1} A by power iteration.
+void block_diag_inverse(const BlockCSR& A, std::vector<double>& out);
+double jacobi_lambda_max(const BlockCSR& A, const std::vector<double>& dinv, int iters);
+
 }  // namespace vasmg

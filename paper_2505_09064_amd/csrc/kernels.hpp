@@ -529,6 +529,32 @@ __global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
 }
 
 // ---------------------------------------------------------------------------
+// Damped vertex-block Jacobi step: x = omega D^{-1} v (FIRST, from a zero guess,
+// v = b) or x += omega D^{-1} v (v = the residual b - A x).
+// ---------------------------------------------------------------------------
+template <typename T, int D, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_jacobi_step(int n, const T* __restrict__ dinv, T omega,
+                                                        const T* __restrict__ v, T* __restrict__ x,
+                                                        const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T vi[D], xi[D];
+  VecIO<T, D>::load(v + static_cast<int64_t>(i) * DP, vi);
+  if (!FIRST) VecIO<T, D>::load(x + static_cast<int64_t>(i) * DP, xi);
+  const T* Di = dinv + static_cast<int64_t>(i) * D * D;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T t = T(0);
+#pragma unroll
+    for (int b = 0; b < D; ++b) t += Di[a * D + b] * vi[b];
+    xi[a] = FIRST ? omega * t : xi[a] + omega * t;
+  }
+  VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, xi);
+}
+
+// ---------------------------------------------------------------------------
 // K4: restriction b_c = P^T r (gather over the CSR of P^T); K5: x += P e.
 // ---------------------------------------------------------------------------
 // Both transfers are gathers over a scalar CSR (weights shared by the

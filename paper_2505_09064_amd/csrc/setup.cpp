@@ -782,3 +782,98 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
 }
 
 }  // namespace vasmg
+
+namespace vasmg {
+// OpenMP threads of the parallel regions the calling thread starts (setups
+// running side by side in a server each get their share of the cores).
+void set_host_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+}  // namespace vasmg
+
+namespace vasmg {
+
+// Inverse of every vertex's d x d diagonal block (Gauss-Jordan with partial
+// pivoting, FP64), [n][d][d] in canonical order.
+void block_diag_inverse(const BlockCSR& A, std::vector<double>& out) {
+  const int d = A.d, dd = d * d;
+  const int64_t n = A.n;
+  out.assign(static_cast<size_t>(n) * dd, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double a[9], inv[9];
+    for (int e = 0; e < dd; ++e) a[e] = 0.0;
+    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+      if (A.col[p] == i)
+        for (int e = 0; e < dd; ++e) a[e] = A.val[p * dd + e];
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) inv[r * d + c] = (r == c) ? 1.0 : 0.0;
+    for (int c = 0; c < d; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < d; ++r)
+        if (std::fabs(a[r * d + c]) > std::fabs(a[piv * d + c])) piv = r;
+      if (piv != c)
+        for (int k = 0; k < d; ++k) {
+          std::swap(a[c * d + k], a[piv * d + k]);
+          std::swap(inv[c * d + k], inv[piv * d + k]);
+        }
+      const double pv = a[c * d + c];
+      for (int k = 0; k < d; ++k) {
+        a[c * d + k] /= pv;
+        inv[c * d + k] /= pv;
+      }
+      for (int r = 0; r < d; ++r) {
+        if (r == c) continue;
+        const double f = a[r * d + c];
+        for (int k = 0; k < d; ++k) {
+          a[r * d + k] -= f * a[c * d + k];
+          inv[r * d + k] -= f * inv[c * d + k];
+        }
+      }
+    }
+    for (int e = 0; e < dd; ++e) out[static_cast<size_t>(i) * dd + e] = inv[e];
+  }
+}
+
+// Largest eigenvalue of D^{-1} A (D = the vertex blocks): power iteration from
+// the all-ones vector, then the Rayleigh quotient v^T A v / v^T D v (FP64).
+double jacobi_lambda_max(const BlockCSR& A, const std::vector<double>& dinv, int iters) {
+  const int d = A.d, dd = d * d;
+  const int64_t n = A.n, N = n * d;
+  std::vector<double> v(N, 1.0), w(N), y(N);
+  auto apply_A = [&](const std::vector<double>& x, std::vector<double>& out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+        const int64_t j = A.col[p];
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) acc[a] += A.val[p * dd + a * d + b] * x[j * d + b];
+      }
+      for (int a = 0; a < d; ++a) out[i * d + a] = acc[a];
+    }
+  };
+  for (int it = 0; it < iters; ++it) {
+    apply_A(v, y);
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) t += dinv[i * dd + a * d + b] * y[i * d + b];
+        w[i * d + a] = t;
+        nrm += t * t;
+      }
+    nrm = std::sqrt(nrm);
+    for (int64_t k = 0; k < N; ++k) v[k] = w[k] / nrm;
+  }
+  apply_A(v, y);
+  double num = 0.0, den = 0.0;
+  for (int64_t k = 0; k < N; ++k) num += v[k] * y[k];
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
+      if (A.col[p] == i)
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b) den += v[i * d + a] * A.val[p * dd + a * d + b] * v[i * d + b];
+  return num / den;
+}
+
+}  // namespace vasmg
+

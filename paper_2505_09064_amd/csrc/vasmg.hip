@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -75,6 +76,10 @@ struct DevLevel {
   double *Lval64 = nullptr, *Uval64 = nullptr;
   float* diag32 = nullptr;
   double* diag64 = nullptr;
+  // damped vertex-block Jacobi smoother (option smoother = JACOBI)
+  float* dinv32 = nullptr;
+  double* dinv64 = nullptr;
+  double omega = 0.0;
   // prolongation to the next level (device numbering on both sides)
   int nnext = 0;
   int* p_ptr = nullptr;
@@ -95,6 +100,43 @@ struct DevLevel {
 
 }  // namespace
 
+// Pinned host blocks for the per-iteration scalar read-back. Freeing pinned
+// memory synchronises the whole device (it would stall every other solve in
+// flight), so blocks are recycled through this pool and never freed.
+class PinnedPool {
+ public:
+  static constexpr size_t kBytes = 4096;
+  static constexpr int kBatch = 64;
+  void* get() {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!free_.empty()) {
+      void* p = free_.back();
+      free_.pop_back();
+      return p;
+    }
+    // one allocation per 64 blocks: pinned allocations are rare and early
+    char* p = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), kBytes * kBatch) != hipSuccess)
+      throw vasmg::Error{VASMG_ENOMEM, "pinned host allocation failed"};
+    for (int i = kBatch - 1; i > 0; --i) free_.push_back(p + static_cast<size_t>(i) * kBytes);
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<void*> free_;
+};
+
+PinnedPool& pinned_pool() {
+  static PinnedPool* pool = new PinnedPool;   // lives until the process ends
+  return *pool;
+}
+
 struct vasmg_ctx {
   Hierarchy H;
   vasmg_options opt{};
@@ -104,6 +146,9 @@ struct vasmg_ctx {
   bool vc32 = false;                // V-cycle precision FP32
   int device = 0;
   std::vector<void*> allocs;
+  hipStream_t alloc_stream = nullptr;   // set: stream-ordered allocations on it
+  int64_t dev_bytes = 0;                // device bytes allocated so far
+  void* pinned = nullptr;               // pinned block: h_sc, h_rtol, kh_sc
   std::vector<DevLevel> lev;
   double* chol = nullptr;           // coarsest factor
   int64_t n_coarse = 0;
@@ -135,17 +180,44 @@ struct vasmg_ctx {
   T* dalloc(int64_t count) {
     void* p = nullptr;
     if (count <= 0) count = 1;
-    hipError_t e = hipMalloc(&p, sizeof(T) * static_cast<size_t>(count));
+    const size_t bytes = sizeof(T) * static_cast<size_t>(count);
+    hipError_t e;
+    if (alloc_stream) {
+      e = hipMallocAsync(&p, bytes, alloc_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(alloc_stream);
+    } else {
+      e = hipMalloc(&p, bytes);
+    }
     if (e != hipSuccess)
-      throw vasmg::Error{VASMG_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) +
+      throw vasmg::Error{VASMG_ENOMEM, "device allocation of " + std::to_string(bytes) +
                                            " bytes failed: " + hipGetErrorString(e)};
     allocs.push_back(p);
+    dev_bytes += static_cast<int64_t>(bytes);
     return static_cast<T*>(p);
+  }
+  // Setup-time copies and clears: on the allocation stream when there is one
+  // (a server's handle must not touch the legacy null stream while other
+  // handles capture graphs), else the synchronous calls.
+  void copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    if (alloc_stream) {
+      HIP_CHECK(hipMemcpyAsync(dst, src, bytes, kind, alloc_stream));
+      HIP_CHECK(hipStreamSynchronize(alloc_stream));
+    } else {
+      HIP_CHECK(hipMemcpy(dst, src, bytes, kind));
+    }
+  }
+  void clear(void* p, size_t bytes) {
+    if (alloc_stream) {
+      HIP_CHECK(hipMemsetAsync(p, 0, bytes, alloc_stream));
+      HIP_CHECK(hipStreamSynchronize(alloc_stream));
+    } else {
+      HIP_CHECK(hipMemset(p, 0, bytes));
+    }
   }
   template <class T>
   T* upload(const std::vector<T>& v) {
     T* p = dalloc<T>(static_cast<int64_t>(v.size()));
-    if (!v.empty()) HIP_CHECK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) copy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
     return p;
   }
   ~vasmg_ctx() {
@@ -156,10 +228,13 @@ struct vasmg_ctx {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (void* p : allocs) (void)hipFree(p);
-    if (h_sc) (void)hipHostFree(h_sc);
-    if (h_rtol) (void)hipHostFree(h_rtol);
-    if (kh_sc) (void)hipHostFree(kh_sc);
+    for (void* p : allocs) {
+      if (alloc_stream)
+        (void)hipFreeAsync(p, alloc_stream);
+      else
+        (void)hipFree(p);
+    }
+    pinned_pool().put(pinned);
   }
 };
 
@@ -405,6 +480,21 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
     dl.has32 = true;
   }
   if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
+  if (!coarsest && C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
+    std::vector<double> dinv;
+    block_diag_inverse(hl.A, dinv);
+    const double lam = jacobi_lambda_max(hl.A, dinv, 30);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      throw vasmg::Error{VASMG_EDEGENERATE, "Jacobi smoother: no positive eigenvalue estimate"};
+    dl.omega = (4.0 / 3.0) / lam;
+    std::vector<double> dd_dev(dinv.size());
+    for (int i = 0; i < n; ++i)
+      std::copy(dinv.begin() + static_cast<int64_t>(perm[i]) * dd,
+                dinv.begin() + static_cast<int64_t>(perm[i] + 1) * dd,
+                dd_dev.begin() + static_cast<int64_t>(i) * dd);
+    if (need64) dl.dinv64 = C.upload(dd_dev);
+    if (need32) dl.dinv32 = C.upload(std::vector<float>(dd_dev.begin(), dd_dev.end()));
+  }
 }
 
 // inverse permutation of level l's device numbering (canonical -> device)
@@ -444,10 +534,10 @@ void upload_all(vasmg_ctx& C) {
     dl.x = C.dalloc<char>(len * T);
     dl.s = C.dalloc<char>(len * T);
     dl.r = C.dalloc<char>(len * T);
-    HIP_CHECK(hipMemset(dl.b, 0, len * T));
-    HIP_CHECK(hipMemset(dl.x, 0, len * T));
-    HIP_CHECK(hipMemset(dl.s, 0, len * T));
-    HIP_CHECK(hipMemset(dl.r, 0, len * T));
+    C.clear(dl.b, len * T);
+    C.clear(dl.x, len * T);
+    C.clear(dl.s, len * T);
+    C.clear(dl.r, len * T);
   }
   if (vasmg) {
     C.n_coarse = C.H.n_coarse_dofs;
@@ -461,13 +551,13 @@ void upload_all(vasmg_ctx& C) {
   {
     std::vector<int> um(C.n0);
     std::vector<int> perm0(C.n0);
-    HIP_CHECK(hipMemcpy(perm0.data(), C.lev[0].perm, sizeof(int) * C.n0, hipMemcpyDeviceToHost));
+    C.copy(perm0.data(), C.lev[0].perm, sizeof(int) * C.n0, hipMemcpyDeviceToHost);
     for (int i = 0; i < C.n0; ++i) um[i] = C.H.free_vertices[perm0[i]];
     C.user_map = C.upload(um);
   }
   for (double** v : {&C.F, &C.X, &C.R, &C.P, &C.Q, &C.Z}) {
     *v = C.dalloc<double>(C.n0p);
-    HIP_CHECK(hipMemset(*v, 0, sizeof(double) * C.n0p));
+    C.clear(*v, sizeof(double) * C.n0p);
   }
   // FP64 V-cycle: its fine right-hand side is the PCG residual itself
   if (!C.vc32) C.lev[0].b = C.R;
@@ -476,13 +566,16 @@ void upload_all(vasmg_ctx& C) {
   C.n_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / 64));
   C.partial = C.dalloc<double>(C.n_partial);
   C.sc = C.dalloc<Scalars>(1);
-  HIP_CHECK(hipMemset(C.sc, 0, sizeof(Scalars)));
+  C.clear(C.sc, sizeof(Scalars));
   C.zero_flag = C.dalloc<int>(1);
-  HIP_CHECK(hipMemset(C.zero_flag, 0, sizeof(int)));
-  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.h_sc), sizeof(Scalars)));
-  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.h_rtol), sizeof(double)));
+  C.clear(C.zero_flag, sizeof(int));
+  // pinned scalars: Scalars at 0, rtol at 256, block scalars [16] at 512
+  static_assert(512 + 16 * sizeof(Scalars) <= PinnedPool::kBytes, "pinned block too small");
+  C.pinned = pinned_pool().get();
+  C.h_sc = static_cast<Scalars*>(C.pinned);
+  C.h_rtol = reinterpret_cast<double*>(static_cast<char*>(C.pinned) + 256);
   for (auto& e : C.ev) HIP_CHECK(hipEventCreate(&e));
-  HIP_CHECK(hipStreamCreate(&C.cap_stream));
+  HIP_CHECK(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking));
 }
 
 // -------------------------------------------------------------------------
@@ -507,6 +600,7 @@ struct LevelMats<float> {
   static const float* pw(const DevLevel& l) { return l.p_w32; }
   static const float* ptw(const DevLevel& l) { return l.pt_w32; }
   static const float* cellM(const DevLevel& l) { return l.cellM32; }
+  static const float* dinv(const DevLevel& l) { return l.dinv32; }
   static bool ok(const DevLevel& l) { return l.has32; }
 };
 template <>
@@ -517,6 +611,7 @@ struct LevelMats<double> {
   static const double* pw(const DevLevel& l) { return l.p_w64; }
   static const double* ptw(const DevLevel& l) { return l.pt_w64; }
   static const double* cellM(const DevLevel& l) { return l.cellM64; }
+  static const double* dinv(const DevLevel& l) { return l.dinv64; }
   static bool ok(const DevLevel& l) { return l.has64; }
 };
 
@@ -657,6 +752,19 @@ void launch_residual_full(const DevLevel& lv, const T* b, const T* x, T* r, cons
 constexpr int kRestrictLanes = 8, kProlongLanes = 4;
 
 template <typename T, int D>
+void launch_jacobi(const DevLevel& lv, bool first, const T* v, T* x, const int* done,
+                   hipStream_t st) {
+  const dim3 grid(grid_for(lv.n, dev::kBlock)), blk(dev::kBlock);
+  const T om = static_cast<T>(lv.omega);
+  if (first)
+    hipLaunchKernelGGL((dev::k_jacobi_step<T, D, true>), grid, blk, 0, st, lv.n,
+                       LevelMats<T>::dinv(lv), om, v, x, done);
+  else
+    hipLaunchKernelGGL((dev::k_jacobi_step<T, D, false>), grid, blk, 0, st, lv.n,
+                       LevelMats<T>::dinv(lv), om, v, x, done);
+}
+
+template <typename T, int D>
 void launch_restrict(const DevLevel& lv, const T* r, T* bc, const int* done, hipStream_t st) {
   hipLaunchKernelGGL((dev::k_restrict<T, D, kRestrictLanes>),
                      dim3(grid_for(lv.nnext, dev::kBlock / kRestrictLanes)), dim3(dev::kBlock), 0,
@@ -761,51 +869,124 @@ LevelBytes level_bytes(const vasmg_ctx& C, int l, int tb) {
 }
 
 // One V-cycle: lev[0].b -> lev[0].x (Algorithm 3, recursive, zero initial guess).
+// One visit of level l of the multiplicative cycle (Algorithm 3, recursive):
+// smoothing from zero (zero_guess) or from the current x, residual, restriction,
+// `visits` coarse visits (2 for the W-cycle above the coarsest level),
+// prolongation and post-smoothing.
 template <typename T, int D>
-void enqueue_vcycle(vasmg_ctx& C, const int* done, hipStream_t st, Profiler* prof = nullptr) {
+void enqueue_level(vasmg_ctx& C, int l, bool zero_guess, const int* done, hipStream_t st,
+                   Profiler* prof) {
   const int L = C.L;
-  const int npre = C.opt.n_pre, npost = C.opt.n_post;
   const int tb = sizeof(T);
-  for (int l = 0; l < L; ++l) {
-    DevLevel& lv = C.lev[l];
-    T* b = static_cast<T*>(lv.b);
-    T* x = static_cast<T*>(lv.x);
-    T* s = static_cast<T*>(lv.s);
-    T* r = static_cast<T*>(lv.r);
-    const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
-    if (npre == 0) {
-      run_phase(prof, "residual_full", l, 2, by.gs_fwd, [&] {
-        launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
-        launch_residual_full<T, D>(lv, b, x, r, done, st);
-      });
-    } else {
-      for (int k = 0; k < npre; ++k)
-        run_phase(prof, k == 0 ? "gs_fwd_zero" : "gs_fwd", l, lv.ncolors,
-                  k == 0 ? by.gs_fwd0 : by.gs_fwd,
-                  [&] { launch_gs_sweep<T, D>(lv, false, k == 0, b, x, s, done, st); });
-      run_phase(prof, "residual", l, 1, by.residual,
-                [&] { launch_residual_upper<T, D>(lv, s, x, r, done, st); });
-    }
-    run_phase(prof, "restrict", l, 1, by.restrict_,
-              [&] { launch_restrict<T, D>(lv, r, static_cast<T*>(C.lev[l + 1].b), done, st); });
-  }
-  run_phase(prof, "coarse_solve", L, 1, static_cast<double>(C.n_coarse) * C.n_coarse * 8.0, [&] {
-    hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
-                       static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
-                       static_cast<T*>(C.lev[L].x), done);
-  });
-  for (int l = L - 1; l >= 0; --l) {
-    DevLevel& lv = C.lev[l];
-    T* b = static_cast<T*>(lv.b);
-    T* x = static_cast<T*>(lv.x);
-    const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
-    run_phase(prof, "prolong", l, 1, by.prolong, [&] {
-      launch_prolong<T, D>(lv, static_cast<const T*>(C.lev[l + 1].x), x, done, st);
+  if (l == L) {
+    run_phase(prof, "coarse_solve", L, 1, static_cast<double>(C.n_coarse) * C.n_coarse * 8.0, [&] {
+      hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                         static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
+                         static_cast<T*>(C.lev[L].x), done);
     });
-    for (int k = 0; k < npost; ++k)
+    return;
+  }
+  const int npre = C.opt.n_pre, npost = C.opt.n_post;
+  DevLevel& lv = C.lev[l];
+  T* b = static_cast<T*>(lv.b);
+  T* x = static_cast<T*>(lv.x);
+  T* s = static_cast<T*>(lv.s);
+  T* r = static_cast<T*>(lv.r);
+  const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
+  const bool jac = C.opt.smoother == VASMG_SMOOTHER_JACOBI;
+  if (jac) {
+    // damped block Jacobi: x = w D^-1 b from zero, then x += w D^-1 (b - A x)
+    run_phase(prof, "jacobi_pre", l, 2 * npre, npre * by.gs_fwd, [&] {
+      for (int k = 0; k < npre; ++k) {
+        if (zero_guess && k == 0) {
+          launch_jacobi<T, D>(lv, true, b, x, done, st);
+        } else {
+          launch_residual_full<T, D>(lv, b, x, r, done, st);
+          launch_jacobi<T, D>(lv, false, r, x, done, st);
+        }
+      }
+    });
+    run_phase(prof, "residual_full", l, 2, by.gs_fwd, [&] {
+      if (npre == 0 && zero_guess) launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
+      launch_residual_full<T, D>(lv, b, x, r, done, st);
+    });
+  } else if (npre == 0) {
+    run_phase(prof, "residual_full", l, 2, by.gs_fwd, [&] {
+      if (zero_guess) launch_fill<T>(x, static_cast<int64_t>(lv.n) * C.DP, T(0), st);
+      launch_residual_full<T, D>(lv, b, x, r, done, st);
+    });
+  } else {
+    for (int k = 0; k < npre; ++k) {
+      const bool z = zero_guess && k == 0;
+      run_phase(prof, z ? "gs_fwd_zero" : "gs_fwd", l, lv.ncolors, z ? by.gs_fwd0 : by.gs_fwd,
+                [&] { launch_gs_sweep<T, D>(lv, false, z, b, x, s, done, st); });
+    }
+    run_phase(prof, "residual", l, 1, by.residual,
+              [&] { launch_residual_upper<T, D>(lv, s, x, r, done, st); });
+  }
+  run_phase(prof, "restrict", l, 1, by.restrict_,
+            [&] { launch_restrict<T, D>(lv, r, static_cast<T*>(C.lev[l + 1].b), done, st); });
+  const int visits = (C.opt.cycle == VASMG_CYCLE_W && l + 1 < L) ? 2 : 1;
+  for (int v = 0; v < visits; ++v) enqueue_level<T, D>(C, l + 1, v == 0, done, st, prof);
+  run_phase(prof, "prolong", l, 1, by.prolong, [&] {
+    launch_prolong<T, D>(lv, static_cast<const T*>(C.lev[l + 1].x), x, done, st);
+  });
+  for (int k = 0; k < npost; ++k) {
+    if (jac)
+      run_phase(prof, "jacobi_post", l, 2, by.gs_bwd, [&] {
+        launch_residual_full<T, D>(lv, b, x, r, done, st);
+        launch_jacobi<T, D>(lv, false, r, x, done, st);
+      });
+    else
       run_phase(prof, "gs_bwd", l, lv.ncolors, by.gs_bwd,
                 [&] { launch_gs_sweep<T, D>(lv, true, false, b, x, nullptr, done, st); });
   }
+}
+
+// z = B r with r in lev[0].b, z in lev[0].x (V- or W-cycle, or the additive
+// two-level form S r + P_0 B_1 P_0^T r with B_1 the V-cycle of levels 1..L).
+template <typename T, int D>
+void enqueue_vcycle(vasmg_ctx& C, const int* done, hipStream_t st, Profiler* prof = nullptr) {
+  if (C.opt.cycle != VASMG_CYCLE_ADDITIVE || C.L == 0) {
+    enqueue_level<T, D>(C, 0, true, done, st, prof);
+    return;
+  }
+  const int tb = sizeof(T);
+  DevLevel& l0 = C.lev[0];
+  T* b = static_cast<T*>(l0.b);
+  T* x = static_cast<T*>(l0.x);
+  T* s = static_cast<T*>(l0.s);
+  const LevelBytes by = prof ? level_bytes(C, 0, tb) : LevelBytes{};
+  run_phase(prof, "restrict", 0, 1, by.restrict_,
+            [&] { launch_restrict<T, D>(l0, b, static_cast<T*>(C.lev[1].b), done, st); });
+  enqueue_level<T, D>(C, 1, true, done, st, prof);     // V-cycle below (cycle != W)
+  if (C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
+    T* r = static_cast<T*>(l0.r);
+    const int steps = C.opt.n_pre + C.opt.n_post;
+    if (steps == 0) launch_fill<T>(x, static_cast<int64_t>(l0.n) * C.DP, T(0), st);
+    for (int k = 0; k < steps; ++k)
+      run_phase(prof, "jacobi", 0, k == 0 ? 1 : 2, by.gs_fwd, [&] {
+        if (k == 0) {
+          launch_jacobi<T, D>(l0, true, b, x, done, st);
+        } else {
+          launch_residual_full<T, D>(l0, b, x, r, done, st);
+          launch_jacobi<T, D>(l0, false, r, x, done, st);
+        }
+      });
+  } else {
+    for (int k = 0; k < C.opt.n_pre; ++k)
+      run_phase(prof, k == 0 ? "gs_fwd_zero" : "gs_fwd", 0, l0.ncolors,
+                k == 0 ? by.gs_fwd0 : by.gs_fwd,
+                [&] { launch_gs_sweep<T, D>(l0, false, k == 0, b, x, s, done, st); });
+    if (C.opt.n_pre == 0)
+      launch_fill<T>(x, static_cast<int64_t>(l0.n) * C.DP, T(0), st);
+    for (int k = 0; k < C.opt.n_post; ++k)
+      run_phase(prof, "gs_bwd", 0, l0.ncolors, by.gs_bwd,
+                [&] { launch_gs_sweep<T, D>(l0, true, false, b, x, nullptr, done, st); });
+  }
+  run_phase(prof, "prolong", 0, 1, by.prolong, [&] {
+    launch_prolong<T, D>(l0, static_cast<const T*>(C.lev[1].x), x, done, st);
+  });
 }
 
 template <int D>
@@ -978,10 +1159,15 @@ void autotune(vasmg_ctx& C) {
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
+std::mutex g_capture_mutex;   // one graph capture at a time in the process
+
 hipGraphExec_t capture(vasmg_ctx& C, void (*fn)(vasmg_ctx&, hipStream_t)) {
+  std::lock_guard<std::mutex> lock(g_capture_mutex);
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
-  HIP_CHECK(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeThreadLocal));
+  // relaxed: other threads (a server's slots) may upload, copy or free meanwhile;
+  // the captured sequence itself is kernel launches only
+  HIP_CHECK(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeRelaxed));
   fn(C, C.cap_stream);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamEndCapture(C.cap_stream, &g));
@@ -1145,20 +1331,20 @@ void upload_block(vasmg_ctx& C, int K) {
     const int64_t bytes = static_cast<int64_t>(C.lev[l].n) * K * C.DP * tb;
     for (auto* v : {&C.kb, &C.kx, &C.ks, &C.kr}) {
       (*v)[l] = C.dalloc<char>(bytes);
-      HIP_CHECK(hipMemset((*v)[l], 0, bytes));
+      C.clear((*v)[l], bytes);
     }
   }
   const int64_t n = C.n0p * K;
   for (double** v : {&C.kF, &C.kX, &C.kR, &C.kP, &C.kQ}) {
     *v = C.dalloc<double>(n);
-    HIP_CHECK(hipMemset(*v, 0, sizeof(double) * n));
+    C.clear(*v, sizeof(double) * n);
   }
   if (!C.vc32) C.kb[0] = C.kR;    // FP64 V-cycle: its fine right-hand side is r
   C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanes));
   C.kpartial = C.dalloc<double>(static_cast<int64_t>(C.kn_partial) * K);
   C.ksc = C.dalloc<Scalars>(K);
-  HIP_CHECK(hipMemset(C.ksc, 0, sizeof(Scalars) * K));
-  HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&C.kh_sc), sizeof(Scalars) * K));
+  C.clear(C.ksc, sizeof(Scalars) * K);
+  C.kh_sc = reinterpret_cast<Scalars*>(static_cast<char*>(C.pinned) + 512);
 }
 
 template <int D, int K>
@@ -1394,6 +1580,59 @@ int solve_block(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d
   return worst;
 }
 
+bool device_available();
+
+// Device upload of a host-built hierarchy (+ block vectors, autotuning).
+// alloc_stream != NULL: allocations are stream-ordered on it.
+void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
+  if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
+  HIP_CHECK(hipGetDevice(&C.device));
+  C.alloc_stream = alloc_stream;
+  upload_all(C);
+  if (C.opt.block_rhs != 0) upload_block(C, C.opt.block_rhs);
+  if (C.opt.autotune) {
+    if (C.d == 2)
+      autotune<2>(C);
+    else
+      autotune<3>(C);
+  }
+  C.host_only = false;
+}
+
+// Upper bound of the device bytes upload_device will allocate, from the host
+// hierarchy (every stored block counted as off-diagonal, 5% + 1 MiB margin).
+int64_t estimate_device_bytes(const vasmg_ctx& C) {
+  const Hierarchy& H = C.H;
+  const int d = C.d, dd = d * d, DP = C.DP, NU = (1 << d) * d;
+  const bool vasmg = C.opt.preconditioner == VASMG_PRECOND_VASMG;
+  const int L = static_cast<int>(H.levels.size()) - 1;
+  const int last = vasmg ? L : 0;
+  const int64_t tbv = C.vc32 ? 4 : 8;
+  const int64_t K = C.opt.block_rhs;
+  int64_t b = 0;
+  for (int l = 0; l <= last; ++l) {
+    const Level& lv = H.levels[l];
+    const int64_t n = lv.n, nb = lv.A.nnzb();
+    const bool need64 = l == 0 || !C.vc32, need32 = C.vc32 && vasmg;
+    const int64_t vb = (need64 ? 8 : 0) + (need32 ? 4 : 0);
+    b += n * 4 + 2 * (n + 1) * 4 + nb * (4 + dd * vb);
+    if (l > 0 && l < L)
+      b += lv.ncells * (NU * NU * vb + 4) + 4 * (lv.ncolors + 2);
+    else
+      b += n * dd * vb;
+    if (l < L) {
+      const int64_t pn = static_cast<int64_t>(lv.P.col.size());
+      b += (n + 1) * 4 + (H.levels[l + 1].n + 1) * 4 + 2 * pn * (4 + vb);
+    }
+    b += 4 * n * DP * tbv * (1 + K);
+  }
+  const int64_t n0p = H.levels[0].n * DP;
+  b += 6 * n0p * 8 + H.levels[0].n * 4 + H.n_coarse_dofs * H.n_coarse_dofs * 8;
+  b += (std::max<int64_t>(kFlatGrid, H.levels[0].n / 4 + 1)) * 8 * (1 + K);
+  b += 5 * n0p * 8 * K;
+  return b + b / 20 + (1 << 20);
+}
+
 vasmg_status fail_with(const vasmg::Error& e) {
   g_last_error = e.msg;
   return static_cast<vasmg_status>(e.status);
@@ -1488,6 +1727,12 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
     if (o.coarsest_max_dofs < 0) throw vasmg::Error{VASMG_EINVAL, "coarsest_max_dofs < 0"};
     if (o.block_rhs != 0 && o.block_rhs != 4 && o.block_rhs != 8 && o.block_rhs != 16)
       throw vasmg::Error{VASMG_EINVAL, "block_rhs must be 0, 4, 8 or 16"};
+    if (o.cycle < VASMG_CYCLE_V || o.cycle > VASMG_CYCLE_ADDITIVE)
+      throw vasmg::Error{VASMG_EINVAL, "unknown cycle"};
+    if (o.smoother != VASMG_SMOOTHER_GS && o.smoother != VASMG_SMOOTHER_JACOBI)
+      throw vasmg::Error{VASMG_EINVAL, "unknown smoother"};
+    if (o.block_rhs != 0 && (o.cycle != VASMG_CYCLE_V || o.smoother != VASMG_SMOOTHER_GS))
+      throw vasmg::Error{VASMG_EINVAL, "block_rhs supports the Gauss-Seidel V-cycle only"};
     MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
                 mesh->E, mesh->nu, mesh->fixed};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
@@ -1504,18 +1749,7 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
                      static_cast<long long>(lv.n), static_cast<long long>(lv.A.nnzb()), lv.ncolors);
       }
     }
-    if (!C->host_only) {
-      if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
-      HIP_CHECK(hipGetDevice(&C->device));
-      upload_all(*C);
-      if (o.block_rhs != 0) upload_block(*C, o.block_rhs);
-      if (o.autotune) {
-        if (C->d == 2)
-          autotune<2>(*C);
-        else
-          autotune<3>(*C);
-      }
-    }
+    if (!C->host_only) upload_device(*C, nullptr);
     *out = C.release();
     return VASMG_OK;
   } catch (const vasmg::Error& e) {
@@ -1602,6 +1836,30 @@ vasmg_status vasmg_solve(vasmg_handle h, const double* rhs, const double* x0, do
     if (dx0) (void)hipFree(dx0);
     return fail_with(e);
   }
+}
+
+vasmg_status vasmg_upload(vasmg_handle h, void* stream) {
+  try {
+    if (!h) throw vasmg::Error{VASMG_EINVAL, "null handle"};
+    if (!h->host_only || !h->allocs.empty())
+      throw vasmg::Error{VASMG_EINVAL, "handle is already on the device"};
+    upload_device(*h, static_cast<hipStream_t>(stream));
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return VASMG_ENOMEM;
+  }
+}
+
+vasmg_status vasmg_device_bytes(vasmg_handle h, int64_t* bytes) {
+  if (!h || !bytes) {
+    g_last_error = "null handle or output";
+    return VASMG_EINVAL;
+  }
+  *bytes = h->host_only ? estimate_device_bytes(*h) : h->dev_bytes;
+  return VASMG_OK;
 }
 
 vasmg_status vasmg_hierarchy_info(vasmg_handle h, int32_t* n_levels, int64_t* n_dofs, int32_t* dim) {

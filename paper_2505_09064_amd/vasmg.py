@@ -20,6 +20,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EDEGENERATE = range(7)
 FP64, FP32_PRECOND = 0, 1
 TREE_ALL, TREE_FREE = 0, 1
 PRECOND_VASMG, PRECOND_JACOBI, PRECOND_NONE = 0, 1, 2
+CYCLE_V, CYCLE_W, CYCLE_ADDITIVE = 0, 1, 2
+SMOOTHER_GS, SMOOTHER_JACOBI = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV",
                 5: "EBREAKDOWN", 6: "EDEGENERATE"}
@@ -29,6 +31,8 @@ EXPORTED = [
     "vasmg_last_error", "vasmg_hierarchy_info", "vasmg_level_info", "vasmg_export_level",
     "vasmg_tree_info", "vasmg_spmv_device", "vasmg_gs_sweep_device", "vasmg_restrict_device",
     "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
+    "vasmg_upload", "vasmg_device_bytes", "vasmg_server_default_config", "vasmg_server_create",
+    "vasmg_server_submit", "vasmg_server_wait", "vasmg_server_stats", "vasmg_server_destroy",
 ]
 
 
@@ -50,7 +54,8 @@ class Options(C.Structure):
                 ("coarsest_max_dofs", C.c_int64), ("max_iters", C.c_int32),
                 ("preconditioner", C.c_int32), ("profile", C.c_int32),
                 ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
-                ("block_rhs", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("block_rhs", C.c_int32), ("cycle", C.c_int32), ("smoother", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class PhaseStat(C.Structure):
@@ -63,6 +68,35 @@ class SolveInfo(C.Structure):
                 ("rel_res_true", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_spmv_ms", C.c_double), ("t_precond_ms", C.c_double),
                 ("t_vector_ms", C.c_double), ("bytes_model", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("setup_workers", C.c_int32),
+                ("hbm_budget_bytes", C.c_int64), ("options", Options)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("slot", C.c_int32),
+                ("device_bytes", C.c_int64), ("t_submit_ms", C.c_double),
+                ("t_setup_start_ms", C.c_double), ("t_setup_end_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("info", SolveInfo),
+                ("message", C.c_char * 128)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("info", "message")}
+        d["info"] = self.info.as_dict()
+        d["message"] = self.message.decode(errors="replace")
+        return d
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64),
+                ("waiting_setup", C.c_int64), ("waiting_admission", C.c_int64),
+                ("running", C.c_int64), ("bytes_in_use", C.c_int64), ("peak_bytes", C.c_int64),
+                ("budget_bytes", C.c_int64), ("t_now_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +133,14 @@ def lib():
             "vasmg_apply_precond_device": (i32, [vp, vp, vp, vp]),
             "vasmg_profile_iteration": (i32, [vp, i32, vp, C.POINTER(PhaseStat), i32,
                                               C.POINTER(i32)]),
+            "vasmg_upload": (i32, [vp, vp]),
+            "vasmg_device_bytes": (i32, [vp, C.POINTER(i64)]),
+            "vasmg_server_default_config": (i32, [C.POINTER(ServerConfig)]),
+            "vasmg_server_create": (i32, [C.POINTER(ServerConfig), C.POINTER(vp)]),
+            "vasmg_server_submit": (i32, [vp, C.POINTER(Mesh), vp, dbl, C.POINTER(i64)]),
+            "vasmg_server_wait": (i32, [vp, i64, vp, C.POINTER(RequestResult)]),
+            "vasmg_server_stats": (i32, [vp, C.POINTER(ServerCounters)]),
+            "vasmg_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -287,3 +329,60 @@ class Solver:
     def apply_precond_device(self, d_r, d_z, stream=None):
         _check(lib().vasmg_apply_precond_device(self._h, _ptr(d_r), _ptr(d_z),
                                                 _stream_ptr(stream)))
+
+
+class Server:
+    """Continuous-batching solve server (vasmg_server_*): requests are set up on
+    host threads, admitted to device slots by HBM footprint, solved on the
+    slots' own streams, and collected with wait()."""
+
+    def __init__(self, slots: int = 4, setup_workers: int = 4, hbm_budget_bytes: int = 0, **opts):
+        cfg = ServerConfig()
+        _check(lib().vasmg_server_default_config(C.byref(cfg)))
+        cfg.slots, cfg.setup_workers, cfg.hbm_budget_bytes = slots, setup_workers, hbm_budget_bytes
+        for k, v in opts.items():
+            setattr(cfg.options, k, v)
+        h = C.c_void_p()
+        _check(lib().vasmg_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, mesh, rhs, rtol: float = 1e-6) -> int:
+        coords = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+        elems = np.ascontiguousarray(mesh.elems, dtype=np.int32)
+        nv, dim = coords.shape
+        ne = elems.shape[0]
+        E = np.ascontiguousarray(np.broadcast_to(np.asarray(mesh.E, dtype=np.float64), (ne,)))
+        nu = np.ascontiguousarray(np.broadcast_to(np.asarray(mesh.nu, dtype=np.float64), (ne,)))
+        fixed = np.ascontiguousarray(mesh.fixed, dtype=np.uint8).reshape(nv, dim)
+        F = np.ascontiguousarray(rhs, dtype=np.float64).reshape(nv, dim)
+        m = Mesh(dim, nv, _ptr(coords), ne, _ptr(elems), _ptr(E), _ptr(nu), _ptr(fixed))
+        rid = C.c_int64()
+        _check(lib().vasmg_server_submit(self._h, C.byref(m), _ptr(F), rtol, C.byref(rid)))
+        self._shapes[rid.value] = (nv, dim)     # the library copied every input
+        return rid.value
+
+    def wait(self, rid: int):
+        """(x [n_vertices, dim], result dict) of request rid; x is None on failure."""
+        nv, dim = self._shapes.pop(rid)
+        x = np.zeros((nv, dim))
+        res = RequestResult()
+        st = lib().vasmg_server_wait(self._h, rid, _ptr(x), C.byref(res))
+        return (x if st == OK else None), res.as_dict()
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib().vasmg_server_stats(self._h, C.byref(c)))
+        return c.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().vasmg_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

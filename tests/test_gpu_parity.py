@@ -277,3 +277,56 @@ def test_autotuned_handle_matches_oracle():
         assert abs(info["iterations"] - io["iterations"]) <= 1
         assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= tol
         s.free()
+
+
+@pytest.mark.parametrize("cycle", [V.CYCLE_W, V.CYCLE_ADDITIVE])
+@pytest.mark.parametrize("name", ["cfg1_2d", "small3d_n9"])
+def test_cycle_variants_parity(name, cycle):
+    """W-cycle and additive two-level preconditioner: the preconditioner
+    application and the FP64 solve against the oracle with the same cycle."""
+    cname = {V.CYCLE_W: "W", V.CYCLE_ADDITIVE: "additive"}[cycle]
+    m = MESHES[name]()
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(cycle=cname))
+    s = V.Solver.from_mesh(m, precision=V.FP64, cycle=cycle)
+    n = o.A[0].shape[0] // m.dim
+    r = np.random.default_rng(3).normal(size=(n, m.dim))
+    z = torch.zeros_like(_dev(r))
+    s.apply_precond_device(_dev(r), z)
+    assert _rel(_host(z).ravel(), o.apply_precond(r.ravel())) < 1e-11
+    xo, io = o.solve(m.rhs[0], 1e-8)
+    x, info = s.solve(m.rhs[0], 1e-8)
+    print(name, cname, "gpu", info["iterations"], "oracle", io["iterations"])
+    assert info["converged"] == 1
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    sm = V.Solver.from_mesh(m, precision=V.FP32_PRECOND, cycle=cycle)
+    x32, i32 = sm.solve(m.rhs[0], 1e-6)
+    assert i32["converged"] == 1 and i32["rel_res_true"] < 1e-6
+    s.free()
+    sm.free()
+    with pytest.raises(V.VasmgError):
+        V.Solver.from_mesh(m, block_rhs=4, cycle=cycle)
+
+
+@pytest.mark.parametrize("cycle", [V.CYCLE_V, V.CYCLE_ADDITIVE])
+@pytest.mark.parametrize("name", ["cfg1_2d", "small3d_n9"])
+def test_jacobi_smoother_parity(name, cycle):
+    """Damped vertex-block Jacobi smoother (omega from the power-iteration
+    estimate, computed independently by the oracle and the host setup)."""
+    cname = {V.CYCLE_V: "V", V.CYCLE_ADDITIVE: "additive"}[cycle]
+    m = MESHES[name]()
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed,
+               OracleOptions(cycle=cname, smoother="jacobi"))
+    s = V.Solver.from_mesh(m, precision=V.FP64, cycle=cycle, smoother=V.SMOOTHER_JACOBI)
+    n = o.A[0].shape[0] // m.dim
+    r = np.random.default_rng(4).normal(size=(n, m.dim))
+    z = torch.zeros_like(_dev(r))
+    s.apply_precond_device(_dev(r), z)
+    assert _rel(_host(z).ravel(), o.apply_precond(r.ravel())) < 1e-10
+    xo, io = o.solve(m.rhs[0], 1e-8)
+    x, info = s.solve(m.rhs[0], 1e-8)
+    print(name, cname, "jacobi gpu", info["iterations"], "oracle", io["iterations"])
+    assert info["converged"] == 1
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    s.free()

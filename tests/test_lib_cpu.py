@@ -143,3 +143,19 @@ def test_default_options():
     assert o.block_rhs == 0
     with pytest.raises(V.VasmgError):
         V.default_options(4)
+
+
+def test_device_bytes_estimate_and_no_device_paths():
+    import torch
+    m = small3d(7, seed=2)
+    s = V.Solver.from_mesh(m, host_only=1)
+    b = V.C.c_int64()
+    V._check(V.lib().vasmg_device_bytes(s._h, V.C.byref(b)))
+    A = s.export_level(0)
+    assert b.value > 8 * 9 * len(A["cols"])          # at least the fine FP64 blocks
+    if not torch.cuda.is_available():
+        assert V.lib().vasmg_upload(s._h, None) == V.EDEVICE
+        with pytest.raises(V.VasmgError) as ei:
+            V.Server(slots=1, setup_workers=1)
+        assert ei.value.status == V.EDEVICE
+    s.free()
