@@ -164,13 +164,23 @@ def bench_serve(args, V):
     t_all = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    # saturation: every request submitted at once (capacity of the batching)
+    srv2 = V.Server(slots=4, setup_workers=4, **opts)
+    t1 = time.perf_counter()
+    ids2 = [srv2.submit(m, m.rhs[0], 1e-6) for m in meshes]
+    got2 = [srv2.wait(r) for r in ids2]
+    t_sat = time.perf_counter() - t1
+    srv2.close()
+    lat2 = np.array([g[1]["t_done_ms"] - g[1]["t_submit_ms"] for g in got2])
+    log(f"saturated: {N / t_sat:.2f} requests/s")
     res = [g[1] for g in got]
-    ok = [r["status"] == V.OK for r in res]
+    ok = [r["status"] == V.OK for r in res] + [g[1]["status"] == V.OK for g in got2]
     lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
     setup = np.array([r["t_setup_end_ms"] - r["t_setup_start_ms"] for r in res])
     solve = np.array([r["info"]["t_solve_ms"] for r in res])
     queue = np.array([r["t_admit_ms"] - r["t_setup_end_ms"] for r in res])
-    same = all(np.array_equal(got[i][0], alone[i][0]) for i in range(8))
+    same = all(np.array_equal(got[i][0], alone[i][0]) and np.array_equal(got2[i][0], alone[i][0])
+               for i in range(8))
     overlap = 0
     iv = sorted((r["t_admit_ms"], r["t_done_ms"]) for r in res)
     for a in range(len(iv)):
@@ -189,6 +199,9 @@ def bench_serve(args, V):
                    "dofs_mean": float(dofs.mean())},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "single_stream_requests_per_s": rate1, "arrival_rate": lam,
+        "saturated_requests_per_s": N / t_sat,
+        "saturated_p50_ms": float(np.percentile(lat2, 50)),
+        "saturated_p99_ms": float(np.percentile(lat2, 99)),
         "mean_setup_ms": float(setup.mean()), "mean_solve_ms": float(solve.mean()),
         "mean_admission_wait_ms": float(queue.mean()),
         "all_ok": bool(all(ok)), "same_alone_and_in_mix": bool(same),
