@@ -30,6 +30,22 @@ def log(*a):
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 
+# HBM traffic of one launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
+# (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
+# source it was measured on: reported as null once kernels.hpp has changed.
+TRAFFIC_RECORD = {"kernels_sha256": "1a36b90b26d5ef6421c0205cb322e582f42068e14de030dfda2e476126f49a8e",
+                  "bytes_per_launch": 48582083}
+
+
+def traffic_per_launch():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2505_09064_amd", "csrc", "kernels.hpp")
+    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    if TRAFFIC_RECORD["kernels_sha256"] == sha:
+        return TRAFFIC_RECORD["bytes_per_launch"]
+    return None
+
 
 def cpu_baseline(n_grid: int = 33, reps: int = 3):
     """The oracle (plain NumPy/SciPy FP64 V-ASMG-PCG, coloured Gauss-Seidel) on a
@@ -250,7 +266,8 @@ def main():
         dst.copy_(src)                       # 256 MiB read + 256 MiB written
         torch.cuda.synchronize()
         mesh = cfg2()
-        s = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND)
+        s = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND,
+                               autotune=0 if args.no_autotune else 1)
         for p in s.profile_iteration(1):
             log(f"{p['name']:13s} L{p['level']:2d} launches {p['launches']:3d} "
                 f"bytes {p['bytes']:.0f} ms {p['ms']:.4f}")
@@ -385,7 +402,7 @@ def main():
         "iteration_bytes": it_bytes,
         "solve_GBps": it_bytes * its[0] / (ms_per * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_launch(),
                      "kernel": f"{dom['name']} on level {dom['level']}",
                      "launch_us": dom_launch_ms * 1e3, "launch_bytes": dom_launch_bytes},
         "cpu_baseline": cpu,

@@ -133,3 +133,27 @@ def test_block_rejected_configurations():
         with pytest.raises(V.VasmgError) as ei:
             V.Solver.from_mesh(m, **kw)
         assert ei.value.status == V.EINVAL
+
+
+def test_full_size_block_workload_properties():
+    """The 129^3 workload with 16 load cases (6,390,144 DOFs each), in the block
+    configuration bench.py --workload cfg4 times: every column reaches rtol in the
+    FP64 true residual, and sampled columns equal the same column solved alone by
+    the same handle (iterations +-1, FP32-preconditioner bar). The oracle cannot
+    solve this size in test time; these properties hold at any size."""
+    from workloads import load_fourier_tet
+    m = small3d(129, seed=3, fix="x0")
+    F = np.stack(load_fourier_tet(m.coords, m.elems, 16))
+    s = V.Solver.from_mesh(m, precision=V.FP32_PRECOND, block_rhs=16)
+    d_F = torch.from_numpy(F).to("cuda")
+    d_X = torch.zeros_like(d_F)
+    infos = s.solve_device(d_F, d_X, 1e-6)
+    X = d_X.cpu().numpy()
+    assert all(i["converged"] == 1 and i["rel_res_true"] < 1e-6 for i in infos)
+    for c in (0, 7, 15):
+        d_x1 = torch.zeros_like(d_F[c])
+        i1 = s.solve_device(d_F[c], d_x1, 1e-6)
+        x1 = d_x1.cpu().numpy()
+        assert abs(i1["iterations"] - infos[c]["iterations"]) <= 1
+        assert np.linalg.norm(X[c] - x1) / np.linalg.norm(x1) < 1e-5
+    s.free()
