@@ -17,12 +17,16 @@
 namespace vasmg {
 namespace dev {
 
-constexpr int kPointLanes = 16;   // lanes per block row, point levels (fine)
-constexpr int kCellLanes = 32;    // lanes per block row, cell levels
+// Lanes per block row (GL = K columns x GL/K block slots, inside one wavefront
+// so the slots combine with shuffles): point levels (fine) use 16 or 64, cell
+// levels 32 or 64, chosen per level from its row lengths.
+constexpr int kPointLanesNarrow = 16, kPointLanesWide = 64;
+constexpr int kCellLanesNarrow = 32, kCellLanesWide = 64;
 
 // Sum over the GL/K block slots of a row group (lanes with equal column).
 template <typename T, int K, int GL>
 __device__ __forceinline__ T slot_sum(T v) {
+  static_assert(GL <= 64 && GL % K == 0, "a row group lies inside one wavefront");
 #pragma unroll
   for (int off = K; off < GL; off <<= 1) v += __shfl_xor(v, off, GL);
   return v;
@@ -80,14 +84,14 @@ __device__ __forceinline__ double block_sum_cols(double v, double* sh, ColOf col
 // ---------------------------------------------------------------------------
 // Fine-level FP64 SpMV y = A x per column, optional per-column partial x.y.
 // ---------------------------------------------------------------------------
-template <int D, int K, bool DOT>
+template <int D, int K, int GL, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv_mc(int n, Part<double> L, Part<double> U,
                                                     const double* __restrict__ diag,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ y,
                                                     double* __restrict__ partial) {
   constexpr int DP = Pad<D>::value;
-  constexpr int GL = kPointLanes, S = GL / K;
+  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
   double dot = 0.0;
@@ -125,12 +129,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mc(int n, Part<double> L, Part<
 // ---------------------------------------------------------------------------
 // Fine-level point Gauss-Seidel colour (MODE as in k_gs_color) and residual.
 // ---------------------------------------------------------------------------
-template <typename T, int D, int K, int MODE>
+template <typename T, int D, int K, int GL, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gs_color_mc(
     int row0, int nrows, Part<T> L, Part<T> U, const T* __restrict__ diag,
     const T* __restrict__ b, T* x, T* __restrict__ s_save) {
   constexpr int DP = Pad<D>::value;
-  constexpr int GL = kPointLanes, S = GL / K;
+  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int g = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
   if (g >= nrows) return;
@@ -178,12 +182,12 @@ __global__ __launch_bounds__(kBlock) void k_gs_color_mc(
 }
 
 // r = s - D x - U x (after a forward sweep that saved s).
-template <typename T, int D, int K>
+template <typename T, int D, int K, int GL>
 __global__ __launch_bounds__(kBlock) void k_residual_upper_mc(
     int n, Part<T> U, const T* __restrict__ diag, const T* __restrict__ s_save,
     const T* __restrict__ x, T* __restrict__ r) {
   constexpr int DP = Pad<D>::value;
-  constexpr int GL = kPointLanes, S = GL / K;
+  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
   if (i >= n) return;
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_upper_mc(
 }
 
 // ---------------------------------------------------------------------------
-// Cell levels. Workgroup = one cell: lane group g (kCellLanes lanes) sums the
+// Cell levels. Workgroup = one cell: lane group g (GL lanes) sums the
 // off-cell part of row g for every column; the cell matrix is staged in LDS;
 // then thread k < K runs column k's sequential sweep over the cell's unknowns.
 // ---------------------------------------------------------------------------
@@ -222,11 +226,11 @@ struct CellLds {
   T up[NV][K][D];
 };
 
-template <typename T, int D, int K>
+template <typename T, int D, int K, int GL>
 __device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L, const Part<T>& U,
                                                 const T* __restrict__ x, bool want_lo,
                                                 bool want_up, CellLds<T, D, K>& sh) {
-  constexpr int GL = kCellLanes, S = GL / K;
+  constexpr int S = GL / K;
   const int g = threadIdx.x / GL, lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   T lo[D], up[D];
 #pragma unroll
@@ -249,52 +253,79 @@ __device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L,
   }
 }
 
+// In-cell sweep of two columns by one wavefront: lane 32h + t owns unknown t of
+// column k0 + h; each new value is broadcast to the column's lanes with lane
+// reads (the per-column analogue of k_gs_cell's sweep).
 template <typename T, int D, int K, int MODE>
-__global__ __launch_bounds__(CellShape<D>::NV * kCellLanes) void k_gs_cell_mc(
-    int cell0, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
-    const T* __restrict__ cellM, const T* __restrict__ b, T* x, T* __restrict__ s_save) {
+__device__ __forceinline__ void mc_cell_sweep_pair(int k0, int v0, int n, const T* __restrict__ Msh,
+                                                   const CellLds<T, D, K>& sh,
+                                                   const T* __restrict__ b, T* x,
+                                                   T* __restrict__ s_save) {
   constexpr int DP = Pad<D>::value;
   constexpr int NU = CellShape<D>::NU;
+  static_assert(NU <= 32, "a column's unknowns fit in half a wavefront");
+  const int lane = threadIdx.x & 63, h = lane >> 5, t = lane & 31;
+  const int k = k0 + h;
+  const bool own = t < n && k < K;
+  const int row = own ? t / D : 0, a = own ? t % D : 0;
+  const int64_t o = (static_cast<int64_t>(v0 + row) * K + (own ? k : 0)) * DP + a;
+  T Mrow[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) Mrow[u] = own ? Msh[u * NU + t] : T(0);
+  T xc = T(0), acc = T(0);
+  if (own) {
+    const T su = b[o] - sh.lo[row][k][a];
+    if (MODE != 2 && s_save) s_save[o] = su;
+    acc = su - (MODE != 0 ? sh.up[row][k][a] : T(0));
+    if (MODE != 0) xc = x[o];
+  }
+  if (MODE != 0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u < n) {
+        const T x0 = bcast(xc, u), x1 = bcast(xc, 32 + u);
+        if (u != t) acc -= Mrow[u] * (h ? x1 : x0);
+      }
+    }
+  }
+#pragma unroll
+  for (int uu = 0; uu < NU; ++uu) {
+    const int u = (MODE == 2) ? NU - 1 - uu : uu;
+    if (u < n) {
+      T delta = T(0);
+      if (t == u && own) {
+        const T xn = acc / Mrow[u];
+        delta = xn - xc;
+        xc = xn;
+      }
+      const T d0 = bcast(delta, u), d1 = bcast(delta, 32 + u);
+      if (t != u) acc -= Mrow[u] * (h ? d1 : d0);
+    }
+  }
+  if (own) x[o] = xc;
+}
+
+template <typename T, int D, int K, int GL, int MODE>
+__global__ __launch_bounds__(CellShape<D>::NV * GL) void k_gs_cell_mc(
+    int cell0, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
+    const T* __restrict__ cellM, const T* __restrict__ b, T* x, T* __restrict__ s_save) {
+  constexpr int NU = CellShape<D>::NU;
   __shared__ CellLds<T, D, K> sh;
-  __shared__ T shx[NU][K], shr[NU][K];
   const int c = cell0 + xcd_block();
   const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
   const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
   for (int e = threadIdx.x; e < NU * NU; e += blockDim.x) sh.M[e] = Mc[e];
-  mc_cell_offcell<T, D, K>(v0, m, L, U, x, true, MODE != 0, sh);
+  mc_cell_offcell<T, D, K, GL>(v0, m, L, U, x, true, MODE != 0, sh);
   __syncthreads();
-  // stage each column's right-hand side (and old values) of the cell's unknowns
-  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
-    const int u = e / K, k = e % K, row = u / D, a = u % D;
-    const int64_t o = (static_cast<int64_t>(v0 + row) * K + k) * DP + a;
-    const T su = b[o] - sh.lo[row][k][a];
-    if (MODE != 2 && s_save) s_save[o] = su;
-    shr[u][k] = su - (MODE != 0 ? sh.up[row][k][a] : T(0));
-    shx[u][k] = MODE != 0 ? x[o] : T(0);
-  }
-  __syncthreads();
-  // thread k: column k's sequential sweep over the cell's unknowns
-  if (threadIdx.x < K) {
-    const int k = threadIdx.x;
-    for (int uu = 0; uu < n; ++uu) {
-      const int u = (MODE == 2) ? n - 1 - uu : uu;
-      T t = shr[u][k];
-#pragma unroll 4
-      for (int v = 0; v < n; ++v)
-        if (v != u) t -= sh.M[v * NU + u] * shx[v][k];
-      shx[u][k] = t / sh.M[u * NU + u];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
-    const int u = e / K, k = e % K;
-    x[(static_cast<int64_t>(v0 + u / D) * K + k) * DP + u % D] = shx[u][k];
-  }
+  // wavefront w sweeps column pairs w, w + waves, ... (all lanes of a wave active)
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k0 = 2 * w; k0 < K; k0 += 2 * nw)
+    mc_cell_sweep_pair<T, D, K, MODE>(k0, v0, n, sh.M, sh, b, x, s_save);
 }
 
 // r = s - U x - M x on a cell (after a forward sweep that saved s).
-template <typename T, int D, int K>
-__global__ __launch_bounds__(CellShape<D>::NV * kCellLanes) void k_cell_residual_mc(
+template <typename T, int D, int K, int GL>
+__global__ __launch_bounds__(CellShape<D>::NV * GL) void k_cell_residual_mc(
     const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
     const T* __restrict__ s_save, const T* __restrict__ x, T* __restrict__ r) {
   constexpr int DP = Pad<D>::value;
@@ -309,7 +340,7 @@ __global__ __launch_bounds__(CellShape<D>::NV * kCellLanes) void k_cell_residual
     const int u = e / K, k = e % K;
     shx[u][k] = u < n ? x[(static_cast<int64_t>(v0 + u / D) * K + k) * DP + u % D] : T(0);
   }
-  mc_cell_offcell<T, D, K>(v0, m, L, U, x, false, true, sh);
+  mc_cell_offcell<T, D, K, GL>(v0, m, L, U, x, false, true, sh);
   __syncthreads();
   for (int e = threadIdx.x; e < n * K; e += blockDim.x) {
     const int u = e / K, k = e % K;

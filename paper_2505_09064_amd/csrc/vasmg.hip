@@ -62,6 +62,7 @@ struct DevLevel {
   int64_t p_nnz = 0;               // entries of P_l
   int G = 8;                       // lanes per block row (Gauss-Seidel, residual)
   int Gspmv = 8;                   // lanes per block row of the fine FP64 SpMV
+  int mcGL = 0;                    // block right-hand sides: lanes per block row
   std::vector<int> color_ptr;      // host: device rows (point levels) or cells (cell
                                    // levels) of colour c = [ptr[c], ptr[c+1])
   bool cells = false;              // coarse lattice level: Gauss-Seidel over cells
@@ -1340,26 +1341,54 @@ void upload_block(vasmg_ctx& C, int K) {
     C.clear(*v, sizeof(double) * n);
   }
   if (!C.vc32) C.kb[0] = C.kR;    // FP64 V-cycle: its fine right-hand side is r
-  C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanes));
+  C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanesNarrow));
+  // lanes per block row: the wide groups (8 / 4 block slots per column at K = 16)
+  // for long rows, so a row costs few rounds of dependent loads per lane
+  for (int l = 0; l < C.L; ++l) {
+    DevLevel& lv = C.lev[l];
+    const double avg = lv.n > 0 ? static_cast<double>(lv.nnz) / lv.n : 0.0;
+    if (lv.cells)
+      lv.mcGL = avg >= 48.0 ? dev::kCellLanesWide : dev::kCellLanesNarrow;
+    else
+      lv.mcGL = avg >= 24.0 ? dev::kPointLanesWide : dev::kPointLanesNarrow;
+  }
   C.kpartial = C.dalloc<double>(static_cast<int64_t>(C.kn_partial) * K);
   C.ksc = C.dalloc<Scalars>(K);
   C.clear(C.ksc, sizeof(Scalars) * K);
   C.kh_sc = reinterpret_cast<Scalars*>(static_cast<char*>(C.pinned) + 512);
 }
 
+#define DISPATCH_POINT_GL(GLv, ...)                                         \
+  if ((GLv) == dev::kPointLanesWide) {                                      \
+    constexpr int GL = dev::kPointLanesWide; __VA_ARGS__;                   \
+  } else {                                                                  \
+    constexpr int GL = dev::kPointLanesNarrow; __VA_ARGS__;                 \
+  }
+#define DISPATCH_CELL_GL(GLv, ...)                                          \
+  if ((GLv) == dev::kCellLanesWide) {                                       \
+    constexpr int GL = dev::kCellLanesWide; __VA_ARGS__;                    \
+  } else {                                                                  \
+    constexpr int GL = dev::kCellLanesNarrow; __VA_ARGS__;                  \
+  }
+
 template <int D, int K>
 int launch_spmv_mc(const vasmg_ctx& C, const double* x, double* y, double* partial,
                    hipStream_t st) {
   const DevLevel& lv = C.lev[0];
-  const int grid = grid_for(lv.n, dev::kBlock / dev::kPointLanes);
-  if (partial && grid > C.kn_partial)
-    throw vasmg::Error{VASMG_EINVAL, "internal: block SpMV partial buffer too small"};
-  if (partial)
-    hipLaunchKernelGGL((dev::k_spmv_mc<D, K, true>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
-                       LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y, partial);
-  else
-    hipLaunchKernelGGL((dev::k_spmv_mc<D, K, false>), dim3(grid), dim3(dev::kBlock), 0, st, lv.n,
-                       LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y, partial);
+  int grid = 0;
+  DISPATCH_POINT_GL(lv.mcGL, {
+    grid = grid_for(lv.n, dev::kBlock / GL);
+    if (partial && grid > C.kn_partial)
+      throw vasmg::Error{VASMG_EINVAL, "internal: block SpMV partial buffer too small"};
+    if (partial)
+      hipLaunchKernelGGL((dev::k_spmv_mc<D, K, GL, true>), dim3(grid), dim3(dev::kBlock), 0, st,
+                         lv.n, LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y,
+                         partial);
+    else
+      hipLaunchKernelGGL((dev::k_spmv_mc<D, K, GL, false>), dim3(grid), dim3(dev::kBlock), 0, st,
+                         lv.n, LevelMats<double>::L(lv), LevelMats<double>::U(lv), lv.diag64, x, y,
+                         partial);
+  });
   return grid;
 }
 
@@ -1373,29 +1402,33 @@ void launch_gs_sweep_mc(const DevLevel& lv, bool backward, bool zero_guess, cons
     const int r0 = lv.color_ptr[c], nr = lv.color_ptr[c + 1] - r0;
     if (nr <= 0) continue;
     if (lv.cells) {
-      const dim3 grid(nr), blk((1 << D) * dev::kCellLanes);
       const T* M = LevelMats<T>::cellM(lv);
-      if (mode == 0)
-        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 0>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
-                           Up, M, b, x, s);
-      else if (mode == 1)
-        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 1>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
-                           Up, M, b, x, s);
-      else
-        hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, 2>), grid, blk, 0, st, r0, lv.cell_ptr, Lp,
-                           Up, M, b, x, static_cast<T*>(nullptr));
+      DISPATCH_CELL_GL(lv.mcGL, {
+        const dim3 grid(nr), blk((1 << D) * GL);
+        if (mode == 0)
+          hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, GL, 0>), grid, blk, 0, st, r0, lv.cell_ptr,
+                             Lp, Up, M, b, x, s);
+        else if (mode == 1)
+          hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, GL, 1>), grid, blk, 0, st, r0, lv.cell_ptr,
+                             Lp, Up, M, b, x, s);
+        else
+          hipLaunchKernelGGL((dev::k_gs_cell_mc<T, D, K, GL, 2>), grid, blk, 0, st, r0, lv.cell_ptr,
+                             Lp, Up, M, b, x, static_cast<T*>(nullptr));
+      });
     } else {
-      const dim3 grid(grid_for(nr, dev::kBlock / dev::kPointLanes)), blk(dev::kBlock);
       const T* dg = LevelMats<T>::diag(lv);
-      if (mode == 0)
-        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 0>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
-                           b, x, s);
-      else if (mode == 1)
-        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 1>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
-                           b, x, s);
-      else
-        hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, 2>), grid, blk, 0, st, r0, nr, Lp, Up, dg,
-                           b, x, static_cast<T*>(nullptr));
+      DISPATCH_POINT_GL(lv.mcGL, {
+        const dim3 grid(grid_for(nr, dev::kBlock / GL)), blk(dev::kBlock);
+        if (mode == 0)
+          hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, GL, 0>), grid, blk, 0, st, r0, nr, Lp,
+                             Up, dg, b, x, s);
+        else if (mode == 1)
+          hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, GL, 1>), grid, blk, 0, st, r0, nr, Lp,
+                             Up, dg, b, x, s);
+        else
+          hipLaunchKernelGGL((dev::k_gs_color_mc<T, D, K, GL, 2>), grid, blk, 0, st, r0, nr, Lp,
+                             Up, dg, b, x, static_cast<T*>(nullptr));
+      });
     }
   }
 }
@@ -1410,14 +1443,19 @@ void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
     T* s = static_cast<T*>(C.ks[l]);
     T* r = static_cast<T*>(C.kr[l]);
     for (int k = 0; k < C.opt.n_pre; ++k) launch_gs_sweep_mc<T, D, K>(lv, false, k == 0, b, x, s, st);
-    if (lv.cells)
-      hipLaunchKernelGGL((dev::k_cell_residual_mc<T, D, K>), dim3(lv.ncells),
-                         dim3((1 << D) * dev::kCellLanes), 0, st, lv.cell_ptr, LevelMats<T>::L(lv),
-                         LevelMats<T>::U(lv), LevelMats<T>::cellM(lv), s, x, r);
-    else
-      hipLaunchKernelGGL((dev::k_residual_upper_mc<T, D, K>),
-                         dim3(grid_for(lv.n, dev::kBlock / dev::kPointLanes)), dim3(dev::kBlock), 0,
-                         st, lv.n, LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x, r);
+    if (lv.cells) {
+      DISPATCH_CELL_GL(lv.mcGL, {
+        hipLaunchKernelGGL((dev::k_cell_residual_mc<T, D, K, GL>), dim3(lv.ncells),
+                           dim3((1 << D) * GL), 0, st, lv.cell_ptr, LevelMats<T>::L(lv),
+                           LevelMats<T>::U(lv), LevelMats<T>::cellM(lv), s, x, r);
+      });
+    } else {
+      DISPATCH_POINT_GL(lv.mcGL, {
+        hipLaunchKernelGGL((dev::k_residual_upper_mc<T, D, K, GL>),
+                           dim3(grid_for(lv.n, dev::kBlock / GL)), dim3(dev::kBlock), 0, st, lv.n,
+                           LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x, r);
+      });
+    }
     hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K>), dim3(grid_for(lv.nnext, dev::kBlock / K)),
                        dim3(dev::kBlock), 0, st, lv.nnext, lv.pt_ptr, lv.pt_idx,
                        LevelMats<T>::ptw(lv), r, static_cast<T*>(C.kb[l + 1]));
