@@ -266,6 +266,37 @@ def test_full_size_3d_workload_against_oracle_golden():
     s.free()
 
 
+def test_full_size_graded_2d_against_oracle_golden():
+    """The 2D nearly incompressible workload at full size (1025^2 graded mesh,
+    nu = 0.49, 1:100 checkerboard materials, 2,093,058 DOFs, 20 levels): FP64
+    sampled solution values and iteration counts of the oracle; the FP32 V-cycle
+    inside FP64 PCG reaches rtol with its error against the FP64 oracle reported."""
+    path = os.path.join(GOLD, "cfg3_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference values not generated (tests/golden/make_oracle_golden.py)")
+    g = json.load(open(path))
+    from workloads import cfg3
+    m = cfg3()
+    idx = np.array(g["sample_vertices"])
+    s = V.Solver.from_mesh(m, precision=V.FP64)
+    x, info = s.solve(m.rhs[0], 1e-6)
+    print("cfg3 fp64 gpu", info["iterations"], "oracle", g["fp64"]["iterations"],
+          info["t_solve_ms"], "ms")
+    assert abs(info["iterations"] - g["fp64"]["iterations"]) <= 1
+    assert np.abs(x[idx] - np.array(g["sample_x"])).max() <= 1e-8 * g["x_norminf"]
+    assert abs(np.linalg.norm(x) - g["x_norm2"]) <= 1e-8 * g["x_norm2"]
+    s.free()
+    s = V.Solver.from_mesh(m, precision=V.FP32_PRECOND)
+    x32, info = s.solve(m.rhs[0], 1e-6)
+    err = np.abs(x32[idx] - np.array(g["sample_x"])).max() / g["x_norminf"]
+    print("cfg3 mixed gpu", info["iterations"], "oracle fp32-mode", g["fp32"]["iterations"],
+          info["t_solve_ms"], "ms", "sampled error vs FP64 oracle", err)
+    assert info["converged"] == 1 and info["rel_res_true"] < 1e-6
+    assert abs(info["iterations"] - g["fp32"]["iterations"]) <= 2
+    assert err <= 1e-5
+    s.free()
+
+
 def test_autotuned_handle_matches_oracle():
     """Autotuning only changes lanes per block row (summation order inside a row)."""
     m = small3d(9, seed=5)
