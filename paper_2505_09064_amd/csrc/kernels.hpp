@@ -172,6 +172,62 @@ __device__ __forceinline__ void row_product(int kb, int ke, int lane, const int*
   }
 }
 
+// Cell levels store every row's L and U blocks padded to whole quads of kQuad
+// consecutive blocks (padding: zero blocks pointing at the row itself), so a lane
+// takes a quad per step: one 16-byte load of its 4 columns, 4 neighbour
+// gathers, and per matrix plane one 16-byte (FP32) or two (FP64) loads. Rows
+// and plane strides are multiples of kQuad, so every such load is aligned.
+constexpr int kQuad = 4;
+
+template <typename T>
+struct Quad;
+template <>
+struct Quad<float> {
+  static __device__ __forceinline__ void load(const float* p, float* v) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+};
+template <>
+struct Quad<double> {
+  static __device__ __forceinline__ void load(const double* p, double* v) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+
+// acc += sum over the quads of positions [kb, ke) (multiples of kQuad).
+template <typename T, int D, int G>
+__device__ __forceinline__ void quad_product(int kb, int ke, int lane, const int* __restrict__ col,
+                                             const T* __restrict__ val, int64_t nnz,
+                                             const T* __restrict__ x, T* acc) {
+  constexpr int DP = Pad<D>::value;
+  for (int q = kb / kQuad + lane; q < ke / kQuad; q += G) {
+    const int4 j = reinterpret_cast<const int4*>(col)[q];
+    T xv[kQuad][D];
+    VecIO<T, D>::load(x + static_cast<int64_t>(j.x) * DP, xv[0]);
+    VecIO<T, D>::load(x + static_cast<int64_t>(j.y) * DP, xv[1]);
+    VecIO<T, D>::load(x + static_cast<int64_t>(j.z) * DP, xv[2]);
+    VecIO<T, D>::load(x + static_cast<int64_t>(j.w) * DP, xv[3]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        T v[kQuad];
+        Quad<T>::load(val + static_cast<int64_t>(a * D + b) * nnz + static_cast<int64_t>(q) * kQuad, v);
+        acc[a] += v[0] * xv[0][b] + v[1] * xv[1][b] + v[2] * xv[2][b] + v[3] * xv[3][b];
+      }
+    }
+  }
+}
+
+template <typename T, int D, int G>
+__device__ __forceinline__ void part_quad_product(const Part<T>& p, int i, int lane,
+                                                  const T* __restrict__ x, T* acc) {
+  quad_product<T, D, G>(p.ptr[i], p.ptr[i + 1], lane, p.col, p.val, p.nnz, x, acc);
+}
+
 template <typename T, int D, int G>
 __device__ __forceinline__ void part_product(const Part<T>& p, int i, int lane,
                                              const T* __restrict__ x, T* acc) {
@@ -389,8 +445,8 @@ __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& 
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
   if (g < m) {
     const int i = v0 + g;
-    if (want_lo) part_product<T, D, GR>(L, i, gl, x, lo);
-    if (want_up) part_product<T, D, GR>(U, i, gl, x, up);
+    if (want_lo) part_quad_product<T, D, GR>(L, i, gl, x, lo);
+    if (want_up) part_quad_product<T, D, GR>(U, i, gl, x, up);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {

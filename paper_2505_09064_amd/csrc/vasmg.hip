@@ -59,6 +59,7 @@ struct DevLevel {
   int ncolors = 0;
   int64_t nnz = 0;                 // off-diagonal (point) or off-cell (cell) blocks
   int64_t nnz_lo = 0, nnz_up = 0;  // blocks coupling to earlier / later colours
+  int64_t Lstride = 0, Ustride = 0; // stored L / U entries (plane stride; rows padded on cell levels)
   int64_t p_nnz = 0;               // entries of P_l
   int G = 8;                       // lanes per block row (Gauss-Seidel, residual)
   int Gspmv = 8;                   // lanes per block row of the fine FP64 SpMV
@@ -434,15 +435,25 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
   dl.Gspmv = dl.G;
   // split the off-cell blocks into the L (earlier colours) and U (later colours)
-  // matrices, each plane-major over its own blocks
+  // matrices, each plane-major over its own blocks. On cell levels every row is
+  // padded to whole quads of 4 blocks (zero blocks pointing at the row itself),
+  // so a lane reads 4 consecutive blocks with one 16-byte load per plane.
+  const int Q = dl.cells ? dev::kQuad : 1;
+  const auto padded = [Q](int len) { return (len + Q - 1) / Q * Q; };
   std::vector<int> Lptr(n + 1, 0), Uptr(n + 1, 0);
   for (int i = 0; i < n; ++i) {
-    Lptr[i + 1] = Lptr[i] + (lo_end[i] - rowptr[i]);
-    Uptr[i + 1] = Uptr[i] + (rowptr[i + 1] - up_beg[i]);
+    Lptr[i + 1] = Lptr[i] + padded(lo_end[i] - rowptr[i]);
+    Uptr[i + 1] = Uptr[i] + padded(rowptr[i + 1] - up_beg[i]);
   }
   const int64_t nL = Lptr[n], nU = Uptr[n];
+  dl.Lstride = nL;
+  dl.Ustride = nU;
   std::vector<int> Lcol(nL), Ucol(nU);
-  std::vector<double> Lval(static_cast<size_t>(nL) * dd), Uval(static_cast<size_t>(nU) * dd);
+  for (int i = 0; i < n; ++i) {
+    for (int q = Lptr[i]; q < Lptr[i + 1]; ++q) Lcol[q] = i;
+    for (int q = Uptr[i]; q < Uptr[i + 1]; ++q) Ucol[q] = i;
+  }
+  std::vector<double> Lval(static_cast<size_t>(nL) * dd, 0.0), Uval(static_cast<size_t>(nU) * dd, 0.0);
   for (int i = 0; i < n; ++i) {
     for (int k = rowptr[i]; k < lo_end[i]; ++k) {
       const int q = Lptr[i] + (k - rowptr[i]);
@@ -595,8 +606,8 @@ template <typename T>
 struct LevelMats;
 template <>
 struct LevelMats<float> {
-  static dev::Part<float> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval32, l.nnz_lo}; }
-  static dev::Part<float> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval32, l.nnz_up}; }
+  static dev::Part<float> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval32, l.Lstride}; }
+  static dev::Part<float> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval32, l.Ustride}; }
   static const float* diag(const DevLevel& l) { return l.diag32; }
   static const float* pw(const DevLevel& l) { return l.p_w32; }
   static const float* ptw(const DevLevel& l) { return l.pt_w32; }
@@ -606,8 +617,8 @@ struct LevelMats<float> {
 };
 template <>
 struct LevelMats<double> {
-  static dev::Part<double> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval64, l.nnz_lo}; }
-  static dev::Part<double> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval64, l.nnz_up}; }
+  static dev::Part<double> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval64, l.Lstride}; }
+  static dev::Part<double> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval64, l.Ustride}; }
   static const double* diag(const DevLevel& l) { return l.diag64; }
   static const double* pw(const DevLevel& l) { return l.p_w64; }
   static const double* ptw(const DevLevel& l) { return l.pt_w64; }
