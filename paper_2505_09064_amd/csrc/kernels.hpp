@@ -222,10 +222,16 @@ __device__ __forceinline__ void quad_product(int kb, int ke, int lane, const int
   }
 }
 
+// FP32 takes the quad step; FP64 keeps the per-block step on the same padded
+// rows (padding blocks are zeros): a quad of doubles costs more registers than it
+// saves in loads (occupancy 3-4 waves per SIMD, measured 20% slower).
 template <typename T, int D, int G>
 __device__ __forceinline__ void part_quad_product(const Part<T>& p, int i, int lane,
                                                   const T* __restrict__ x, T* acc) {
-  quad_product<T, D, G>(p.ptr[i], p.ptr[i + 1], lane, p.col, p.val, p.nnz, x, acc);
+  if constexpr (sizeof(T) == 4)
+    quad_product<T, D, G>(p.ptr[i], p.ptr[i + 1], lane, p.col, p.val, p.nnz, x, acc);
+  else
+    row_product<T, D, G>(p.ptr[i], p.ptr[i + 1], lane, p.col, p.val, p.nnz, x, acc);
 }
 
 template <typename T, int D, int G>
