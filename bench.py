@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "f17b3a5e42587a6b9a0c5556568c602967471bc94c9717f360198964e8a76f57",
-                  "bytes_per_launch": 48536301}
+TRAFFIC_RECORD = {"kernels_sha256": "721d352d08cfa4ce8c2a496b53f0636e023f7bdf155b6923b061e474770b18b2",
+                  "bytes_per_launch": 48543025}
 
 
 def traffic_per_launch():
