@@ -107,7 +107,12 @@ typedef struct {
                                   vertex-block Jacobi, Section 4's other S_h: omega =
                                   (4/3) / lambda_max(D^-1 A), estimated per level by 30
                                   power iterations at setup)                            */
-  int32_t reserved[3];
+  int32_t setup_device;        /* 0 = whole setup on the host (default); 1 = the Galerkin
+                                  coarse operators A_{l+1} = P_l^T A_l P_l (Section 3,
+                                  equation (Ac)) are formed on the current HIP device:
+                                  same columns, values equal to rounding (another order
+                                  of the FP64 sums), deterministic. Needs host_only = 0 */
+  int32_t reserved[2];
 } vasmg_options;
 
 typedef struct {
@@ -291,6 +296,12 @@ vasmg_status vasmg_prolong_device(vasmg_handle h, int32_t level, int32_t precisi
  * handle's precision. r, z: [n_free_vertices][dim] FP64, canonical order. */
 vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, double* d_z,
                                         void* stream);
+
+/* Test-only: caps the columns one symbolic pass of the device Galerkin product
+ * covers (its LDS bitmap window; 0 = the maximum, 65,536), so that small meshes
+ * reach the multi-pass path. Process-wide, read by setups that start afterwards.
+ * EINVAL if cols < 0. */
+vasmg_status vasmg_set_galerkin_window(int32_t cols);
 
 /* ---------------------------------------------------------------------------
  * Measurement. One PCG iteration's device work (fine FP64 SpMV q = A p of

@@ -6,6 +6,7 @@
   * csrc/vasmg.hip (kernels, device driver, C ABI) with hipcc for gfx950, packed
     FP32 instructions disabled;
   * csrc/server.hip (serving engine: host threads and streams over the C ABI);
+  * csrc/galerkin.hip (Galerkin coarse operators on the device, setup option);
   * linked into paper_2505_09064_amd/libvasmg.so.
 
 Run: python -m paper_2505_09064_amd.build   (or __graft_entry__.build()).
@@ -46,11 +47,13 @@ def build(verbose: bool = True) -> str:
     setup_o = os.path.join(BUILD, "setup.o")
     hip_o = os.path.join(BUILD, "vasmg.o")
     server_o = os.path.join(BUILD, "server.o")
+    galerkin_o = os.path.join(BUILD, "galerkin.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "server.hip"), "-o", server_o])
+    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "galerkin.hip"), "-o", galerkin_o])
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "vasmg.hip"), "-o", hip_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, hip_o, server_o, setup_o,
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, hip_o, server_o, galerkin_o, setup_o,
           "-lgomp", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB

@@ -1,0 +1,381 @@
+// Galerkin coarse operators on the device: A_{l+1} = P_l^T A_l P_l (Section 3,
+// equation (Ac); P = P_s (x) I_d, so every scalar weight scales a whole d x d
+// block).
+//
+// The product is formed as two row-wise sparse products, AP = A P and then
+// A_c = P^T (AP), each in three launches:
+//   1. symbolic count: the distinct columns of every output row, found with a
+//      bitmap in LDS over a window of columns (rows whose column range exceeds
+//      the window take several passes);
+//   2. symbolic fill: the same bitmap walk writes the columns, ascending, at
+//      offsets from the host's prefix sum of the counts;
+//   3. numeric: one thread per output block; it walks the row's contributions in
+//      a fixed order (X entries ascending, then Y entries ascending) and adds the
+//      ones that land on its column. No atomics: the result is the same bit for
+//      bit on every run and for every launch shape.
+// Values are FP64 throughout. The order of the sums differs from the host's
+// single-pass triple product, so the two agree to rounding, not bit for bit; the
+// column structure is identical.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hierarchy.hpp"
+#include "vasmg.h"
+
+namespace vasmg {
+namespace gal {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxWindowCols = 65536;   // LDS bitmap: 8 KiB per workgroup
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw Error{VASMG_EDEVICE, std::string("device Galerkin product: ") + what + ": " +
+                                   hipGetErrorString(e)};
+}
+
+// CSR operand on the device: scalar values ([nnz]) or d x d blocks ([nnz][d*d]).
+struct Csr {
+  const int64_t* __restrict__ ptr;
+  const int32_t* __restrict__ col;
+  const double* __restrict__ val;
+};
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Exclusive prefix sum of v over the workgroup; *total gets the sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  int base = 0, all = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    const int s = sh[w];
+    if (w < wave) base += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return base + inc - v;
+}
+
+// Row i of X * Y: its distinct columns, counted (FILL = false: cnt[i]) or written
+// ascending to ccol[cptr[i] ...] (FILL = true). One workgroup per row; thread t
+// takes the X entries t, t + 256, ... and their whole Y rows.
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_symbolic(int32_t nrows, Csr X, Csr Y, int window,
+                                                       int64_t* __restrict__ cnt,
+                                                       const int64_t* __restrict__ cptr,
+                                                       int32_t* __restrict__ ccol) {
+  __shared__ uint32_t bits[kMaxWindowCols / 32];
+  __shared__ int sh[2 * kWaves];
+  const int32_t i = blockIdx.x;
+  if (i >= nrows) return;
+  const int t = threadIdx.x;
+  const int64_t xb = X.ptr[i], xe = X.ptr[i + 1];
+
+  int lo = INT_MAX, hi = -1;
+  for (int64_t p = xb + t; p < xe; p += kThreads) {
+    const int k = X.col[p];
+    for (int64_t q = Y.ptr[k], qe = Y.ptr[k + 1]; q < qe; ++q) {
+      const int j = Y.col[q];
+      lo = min(lo, j);
+      hi = max(hi, j);
+    }
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((t & 63) == 0) {
+    sh[t >> 6] = lo;
+    sh[kWaves + (t >> 6)] = hi;
+  }
+  __syncthreads();
+  lo = INT_MAX;
+  hi = -1;
+  for (int w = 0; w < kWaves; ++w) {
+    lo = min(lo, sh[w]);
+    hi = max(hi, sh[kWaves + w]);
+  }
+  __syncthreads();
+
+  int64_t done = 0;   // columns of this row found in earlier windows
+  for (int64_t w0 = lo; w0 <= hi; w0 += window) {
+    const int ncols = static_cast<int>(min<int64_t>(window, hi - w0 + 1));
+    const int nwords = (ncols + 31) >> 5;
+    for (int w = t; w < nwords; w += kThreads) bits[w] = 0u;
+    __syncthreads();
+    for (int64_t p = xb + t; p < xe; p += kThreads) {
+      const int k = X.col[p];
+      for (int64_t q = Y.ptr[k], qe = Y.ptr[k + 1]; q < qe; ++q) {
+        const int64_t r = static_cast<int64_t>(Y.col[q]) - w0;
+        if (r >= 0 && r < ncols) atomicOr(&bits[r >> 5], 1u << (r & 31));
+      }
+    }
+    __syncthreads();
+    const int per = (nwords + kThreads - 1) / kThreads;
+    const int wb = min(t * per, nwords), we = min(wb + per, nwords);
+    int c = 0;
+    for (int w = wb; w < we; ++w) c += __popc(bits[w]);
+    int total = 0;
+    const int off = block_exclusive_scan(c, sh, &total);
+    if (FILL) {
+      int64_t pos = cptr[i] + done + off;
+      for (int w = wb; w < we; ++w) {
+        uint32_t b = bits[w];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          ccol[pos++] = static_cast<int32_t>(w0 + (static_cast<int64_t>(w) << 5) + bit);
+        }
+      }
+    }
+    done += total;
+    __syncthreads();   // the bitmap is cleared for the next window
+  }
+  if (!FILL && t == 0) cnt[i] = done;
+}
+
+// Values of row i of X * Y at the columns the symbolic pass wrote. XB: X holds
+// d x d blocks and Y scalars (A P); else X scalars and Y blocks (P^T (AP)).
+template <int D, bool XB>
+__global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr Y,
+                                                      const int64_t* __restrict__ cptr,
+                                                      const int32_t* __restrict__ ccol,
+                                                      double* __restrict__ cval) {
+  constexpr int DD = D * D;
+  constexpr int U = 8;
+  const int32_t i = blockIdx.x;
+  if (i >= nrows) return;
+  const int64_t cb = cptr[i], ce = cptr[i + 1];
+  const int64_t xb = X.ptr[i], xe = X.ptr[i + 1];
+  for (int64_t s0 = cb; s0 < ce; s0 += kThreads) {
+    if (s0 + (threadIdx.x & ~63) >= ce) break;   // this wave owns no block of the row
+    const int64_t s = s0 + threadIdx.x;
+    const int my = s < ce ? ccol[s] : -1;
+    double acc[DD];
+#pragma unroll
+    for (int e = 0; e < DD; ++e) acc[e] = 0.0;
+    for (int64_t p = xb; p < xe; ++p) {
+      const int k = X.col[p];
+      const int64_t qb = Y.ptr[k], qe = Y.ptr[k + 1];
+      auto add = [&](int64_t q) {
+        if constexpr (XB) {
+          const double w = Y.val[q];
+#pragma unroll
+          for (int e = 0; e < DD; ++e) acc[e] += X.val[p * DD + e] * w;
+        } else {
+          const double w = X.val[p];
+#pragma unroll
+          for (int e = 0; e < DD; ++e) acc[e] += w * Y.val[q * DD + e];
+        }
+      };
+      int64_t q = qb;
+      for (; q + U <= qe; q += U) {
+        int j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = Y.col[q + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (j[u] == my) add(q + u);
+      }
+      for (; q < qe; ++q)
+        if (Y.col[q] == my) add(q);
+    }
+    if (s < ce) {
+#pragma unroll
+      for (int e = 0; e < DD; ++e) cval[s * DD + e] = acc[e];
+    }
+  }
+}
+
+template <typename T>
+T* dmalloc(size_t n, const char* what) {
+  void* p = nullptr;
+  check(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)), what);
+  return static_cast<T*>(p);
+}
+
+// Device CSR owned by the product driver.
+struct DevCsr {
+  int64_t nrows = 0, nnz = 0;
+  int64_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  void release() {
+    (void)hipFree(ptr);
+    (void)hipFree(col);
+    (void)hipFree(val);
+    ptr = nullptr;
+    col = nullptr;
+    val = nullptr;
+    nrows = nnz = 0;
+  }
+  Csr view() const { return Csr{ptr, col, val}; }
+};
+
+}  // namespace gal
+
+struct GalerkinDevice {
+  hipStream_t st = nullptr;
+  int window = gal::kMaxWindowCols;
+  const BlockCSR* cached = nullptr;   // host operator whose device copy is `A`
+  gal::DevCsr A;
+  ~GalerkinDevice() {
+    A.release();
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace gal {
+
+void upload(DevCsr& D, int64_t nrows, const std::vector<int64_t>& ptr,
+            const std::vector<int32_t>& col, const std::vector<double>& val, hipStream_t st) {
+  D.nrows = nrows;
+  D.nnz = static_cast<int64_t>(col.size());
+  D.ptr = dmalloc<int64_t>(ptr.size(), "rowptr");
+  D.col = dmalloc<int32_t>(col.size(), "columns");
+  D.val = dmalloc<double>(val.size(), "values");
+  check(hipMemcpyAsync(D.ptr, ptr.data(), ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+  check(hipMemcpyAsync(D.col, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+  check(hipMemcpyAsync(D.val, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy");
+}
+
+// C = X * Y with one block operand (XB: X), columns ascending per row.
+template <int D, bool XB>
+void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols, DevCsr& C) {
+  constexpr int DD = D * D;
+  hipStream_t st = G.st;
+  const int64_t n = X.nrows;
+  if (n > INT32_MAX || ncols > INT32_MAX) throw Error{VASMG_EINVAL, "level too large for int32 indices"};
+  const int32_t n32 = static_cast<int32_t>(n);
+  C.nrows = n;
+  C.ptr = dmalloc<int64_t>(n + 1, "rowptr");
+  int64_t* cnt = dmalloc<int64_t>(n, "row counts");
+  if (n > 0)
+    hipLaunchKernelGGL(k_symbolic<false>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
+                       G.window, cnt, nullptr, nullptr);
+  check(hipGetLastError(), "symbolic count launch");
+  std::vector<int64_t> h(n + 1, 0);
+  check(hipMemcpyAsync(h.data() + 1, cnt, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+  check(hipStreamSynchronize(st), "symbolic count");
+  for (int64_t r = 0; r < n; ++r) h[r + 1] += h[r];
+  C.nnz = h[n];
+  check(hipMemcpyAsync(C.ptr, h.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+  C.col = dmalloc<int32_t>(C.nnz, "columns");
+  C.val = dmalloc<double>(C.nnz * DD, "values");
+  if (n > 0) {
+    hipLaunchKernelGGL(k_symbolic<true>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
+                       G.window, nullptr, C.ptr, C.col);
+    check(hipGetLastError(), "symbolic fill launch");
+    hipLaunchKernelGGL((k_numeric<D, XB>), dim3(n32), dim3(kThreads), 0, st, n32, X.view(),
+                       Y.view(), C.ptr, C.col, C.val);
+    check(hipGetLastError(), "numeric launch");
+  }
+  check(hipStreamSynchronize(st), "product");
+  (void)hipFree(cnt);
+}
+
+template <int D>
+void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
+  constexpr int DD = D * D;
+  hipStream_t st = G.st;
+  if (G.cached != &A) {
+    G.A.release();
+    upload(G.A, A.n, A.rowptr, A.col, A.val, st);
+    G.cached = &A;
+  }
+  // P and its transpose (rows = coarse vertices), built on the host: <= 2^d
+  // entries per P row
+  ScalarCSR PT;
+  PT.nrows = P.ncols;
+  PT.ncols = P.nrows;
+  PT.rowptr.assign(P.ncols + 1, 0);
+  for (int32_t c : P.col) PT.rowptr[c + 1]++;
+  for (int64_t r = 0; r < P.ncols; ++r) PT.rowptr[r + 1] += PT.rowptr[r];
+  PT.col.resize(P.col.size());
+  PT.val.resize(P.col.size());
+  {
+    std::vector<int64_t> fill(PT.rowptr.begin(), PT.rowptr.end() - 1);
+    for (int64_t r = 0; r < P.nrows; ++r)
+      for (int64_t p = P.rowptr[r]; p < P.rowptr[r + 1]; ++p) {
+        const int64_t q = fill[P.col[p]]++;
+        PT.col[q] = static_cast<int32_t>(r);
+        PT.val[q] = P.val[p];
+      }
+  }
+  DevCsr dP, dPT, AP, C;
+  try {
+    upload(dP, P.nrows, P.rowptr, P.col, P.val, st);
+    upload(dPT, PT.nrows, PT.rowptr, PT.col, PT.val, st);
+    product<D, true>(G, G.A, dP, P.ncols, AP);
+    product<D, false>(G, dPT, AP, P.ncols, C);
+    Ac.n = P.ncols;
+    Ac.d = D;
+    Ac.rowptr.resize(C.nrows + 1);
+    Ac.col.resize(C.nnz);
+    Ac.val.resize(C.nnz * DD);
+    check(hipMemcpyAsync(Ac.rowptr.data(), C.ptr, (C.nrows + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, st), "copy");
+    check(hipMemcpyAsync(Ac.col.data(), C.col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    check(hipMemcpyAsync(Ac.val.data(), C.val, C.nnz * DD * sizeof(double), hipMemcpyDeviceToHost, st),
+          "copy");
+    check(hipStreamSynchronize(st), "download");
+  } catch (...) {
+    dP.release();
+    dPT.release();
+    AP.release();
+    C.release();
+    throw;
+  }
+  dP.release();
+  dPT.release();
+  AP.release();
+  // the coarse operator stays resident as the next product's A
+  G.A.release();
+  G.A = C;
+  G.cached = &Ac;
+}
+
+}  // namespace gal
+
+GalerkinDevice* galerkin_device_create(int window_cols) {
+  auto* G = new GalerkinDevice();
+  if (window_cols > 0) G->window = std::min(window_cols, gal::kMaxWindowCols);
+  const hipError_t e = hipStreamCreateWithFlags(&G->st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete G;
+    gal::check(e, "stream");
+  }
+  return G;
+}
+
+void galerkin_device_destroy(GalerkinDevice* G) { delete G; }
+
+void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
+  auto& G = *static_cast<GalerkinDevice*>(ctx);
+  if (A.d == 2)
+    gal::galerkin_d<2>(G, A, P, Ac);
+  else
+    gal::galerkin_d<3>(G, A, P, Ac);
+}
+
+}  // namespace vasmg

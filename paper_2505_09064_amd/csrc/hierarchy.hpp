@@ -5,6 +5,7 @@
 #include <array>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace vasmg {
@@ -60,6 +61,8 @@ struct Hierarchy {
   double box_m = 0.0, box_M = 0.0;      // root box [m, M]^d
   int max_depth = 0;
   int capacity = 0;
+  // wall-clock milliseconds of the setup phases, in the order they ran
+  std::vector<std::pair<std::string, double>> phase_ms;
 };
 
 struct MeshView {
@@ -73,11 +76,24 @@ struct MeshView {
   const uint8_t* fixed;
 };
 
+// Galerkin product A_c = P^T A P (block A, scalar P shared by the components).
+using GalerkinFn = void (*)(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac);
+
 struct SetupParams {
   int capacity;                // leaf capacity (> 0)
   bool tree_free_only;         // tree over free vertices only
   int64_t coarsest_max_dofs;   // 0 = root level
+  GalerkinFn galerkin = nullptr;   // null: the host product (OpenMP)
+  void* galerkin_ctx = nullptr;
 };
+
+// Device Galerkin products (galerkin.hip): a context with its own stream that
+// keeps the last coarse operator resident as the next product's A.
+// window_cols > 0 caps the columns per symbolic pass (0 = the LDS maximum).
+struct GalerkinDevice;
+GalerkinDevice* galerkin_device_create(int window_cols);
+void galerkin_device_destroy(GalerkinDevice* g);
+void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac);
 
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
 void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);

@@ -28,6 +28,7 @@
 // tree decisions and level-1 weights are compared bit for bit with an
 // independent implementation.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -610,6 +611,12 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   H.d = d;
   H.n_mesh_vertices = m.nv;
   H.capacity = prm.capacity;
+  auto t0 = std::chrono::steady_clock::now();
+  auto mark = [&](const char* phase) {
+    const auto t1 = std::chrono::steady_clock::now();
+    H.phase_ms.emplace_back(phase, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    t0 = t1;
+  };
 
   // free vertices (fine canonical order = ascending mesh index)
   std::vector<int32_t> vfree(m.nv, -1);
@@ -635,6 +642,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     L0.n = nfree;
     assemble_fine(m, vfree, nfree, L0.A);
   }
+  mark("validate+assemble");
 
   // ---- region tree over the tree vertices (Section 3.1.1 Steps 1-2)
   std::vector<int32_t> tree_vtx;
@@ -644,6 +652,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   for (size_t i = 0; i < tree_vtx.size(); ++i) pos_in_tree[tree_vtx[i]] = static_cast<int32_t>(i);
   TreeResult T;
   build_tree(m.coords, tree_vtx, d, prm.capacity, T);
+  mark("tree");
   H.box_m = T.m;
   H.box_M = T.M;
   H.max_depth = T.max_depth;
@@ -689,6 +698,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     }
     cur_keys = triplets_to_csr(tr, nfree, H.levels[0].P);
   }
+  mark("P0");
 
   // ---- Section 3.1.2: merge the deepest regions until only the root is left
   while (true) {
@@ -763,6 +773,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     R.swap(Rn);
   }
 
+  mark("coarse regions+P");
   // ---- Galerkin operators, with optional truncation of the hierarchy
   size_t nlev = H.levels.size();
   for (size_t l = 0; l + 1 < nlev; ++l) {
@@ -770,15 +781,21 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
       nlev = l + 1;
       break;
     }
-    galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
+    if (prm.galerkin)
+      prm.galerkin(prm.galerkin_ctx, H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
+    else
+      galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
   }
   H.levels.resize(nlev);
+  mark("galerkin");
   Level& coarsest = H.levels.back();
   coarsest.P = ScalarCSR();
   coarsest.color.assign(coarsest.n, 0);
   coarsest.ncolors = 0;
   for (size_t l = 0; l + 1 < H.levels.size(); ++l) build_gs_order(H.levels[l], l > 0, d);
+  mark("cells+colours");
   dense_cholesky(coarsest.A, H.chol, H.n_coarse_dofs);
+  mark("coarsest factor");
 }
 
 }  // namespace vasmg

@@ -11,10 +11,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <chrono>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -32,6 +34,7 @@ using dev::Scalars;
 namespace {
 
 thread_local std::string g_last_error;
+std::atomic<int> g_galerkin_window{0};   // test hook: device Galerkin window (0 = max)
 
 #define HIP_CHECK(expr)                                                                    \
   do {                                                                                     \
@@ -1734,6 +1737,15 @@ extern "C" {
 
 const char* vasmg_last_error(void) { return g_last_error.c_str(); }
 
+vasmg_status vasmg_set_galerkin_window(int32_t cols) {
+  if (cols < 0) {
+    g_last_error = "vasmg_set_galerkin_window: cols must be >= 0";
+    return VASMG_EINVAL;
+  }
+  g_galerkin_window.store(cols);
+  return VASMG_OK;
+}
+
 vasmg_status vasmg_default_options(int32_t dim, vasmg_options* out) {
   if (!out || (dim != 2 && dim != 3)) {
     g_last_error = "vasmg_default_options: dim must be 2 or 3 and out non-null";
@@ -1782,10 +1794,22 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       throw vasmg::Error{VASMG_EINVAL, "unknown smoother"};
     if (o.block_rhs != 0 && (o.cycle != VASMG_CYCLE_V || o.smoother != VASMG_SMOOTHER_GS))
       throw vasmg::Error{VASMG_EINVAL, "block_rhs supports the Gauss-Seidel V-cycle only"};
+    if (o.setup_device != 0 && o.setup_device != 1)
+      throw vasmg::Error{VASMG_EINVAL, "setup_device must be 0 or 1"};
+    if (o.setup_device == 1 && o.host_only)
+      throw vasmg::Error{VASMG_EINVAL, "setup_device = 1 needs a device (host_only = 0)"};
     MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
                 mesh->E, mesh->nu, mesh->fixed};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
+    std::unique_ptr<GalerkinDevice, void (*)(GalerkinDevice*)> gdev(nullptr, galerkin_device_destroy);
+    if (o.setup_device == 1) {
+      if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device for setup_device = 1"};
+      gdev.reset(galerkin_device_create(g_galerkin_window.load()));
+      prm.galerkin = galerkin_device;
+      prm.galerkin_ctx = gdev.get();
+    }
     build_hierarchy(mv, prm, C->H);
+    gdev.reset();
     C->d = mesh->dim;
     C->DP = mesh->dim == 3 ? 4 : 2;
     C->L = static_cast<int>(C->H.levels.size()) - 1;
@@ -1797,8 +1821,16 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
         std::fprintf(stderr, "[vasmg] level %zu: %lld vertices, %lld blocks, %d colours\n", l,
                      static_cast<long long>(lv.n), static_cast<long long>(lv.A.nnzb()), lv.ncolors);
       }
+      for (const auto& ph : C->H.phase_ms)
+        std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", ph.first.c_str(), ph.second);
     }
-    if (!C->host_only) upload_device(*C, nullptr);
+    if (!C->host_only) {
+      const auto t0 = std::chrono::steady_clock::now();
+      upload_device(*C, nullptr);
+      if (o.verbose)
+        std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", "upload+autotune",
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
     *out = C.release();
     return VASMG_OK;
   } catch (const vasmg::Error& e) {

@@ -33,6 +33,7 @@ EXPORTED = [
     "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
     "vasmg_upload", "vasmg_device_bytes", "vasmg_server_default_config", "vasmg_server_create",
     "vasmg_server_submit", "vasmg_server_wait", "vasmg_server_stats", "vasmg_server_destroy",
+    "vasmg_set_galerkin_window",
 ]
 
 
@@ -55,7 +56,7 @@ class Options(C.Structure):
                 ("preconditioner", C.c_int32), ("profile", C.c_int32),
                 ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
                 ("block_rhs", C.c_int32), ("cycle", C.c_int32), ("smoother", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("setup_device", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class PhaseStat(C.Structure):
@@ -141,6 +142,7 @@ def lib():
             "vasmg_server_wait": (i32, [vp, i64, vp, C.POINTER(RequestResult)]),
             "vasmg_server_stats": (i32, [vp, C.POINTER(ServerCounters)]),
             "vasmg_server_destroy": (None, [vp]),
+            "vasmg_set_galerkin_window": (i32, [i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -386,3 +388,8 @@ class Server:
         except Exception:
             pass
 
+
+def set_galerkin_window(cols: int) -> None:
+    """Test hook: caps the columns of one symbolic pass of the device Galerkin
+    product (0 = the LDS maximum) for setups that start afterwards."""
+    _check(lib().vasmg_set_galerkin_window(int(cols)))
