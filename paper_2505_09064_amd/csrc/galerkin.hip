@@ -16,13 +16,21 @@
 // Values are FP64 throughout. The order of the sums differs from the host's
 // single-pass triple product, so the two agree to rounding, not bit for bit; the
 // column structure is identical.
+//
+// Every level's canonical operator stays resident until the device layout of the
+// level (colour-ordered rows, off-cell L / U parts, cell matrices or diagonals,
+// in the solve precisions) has been built from it by the layout kernels below;
+// the host receives each product's structure at once (cells and colours are
+// built from it) and its values from a background download.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hierarchy.hpp"
@@ -235,13 +243,25 @@ struct DevCsr {
 }  // namespace gal
 
 struct GalerkinDevice {
-  hipStream_t st = nullptr;
+  int device = 0;
+  hipStream_t st = nullptr;   // products and layouts
+  hipStream_t dl = nullptr;   // background value downloads
   int window = gal::kMaxWindowCols;
-  const BlockCSR* cached = nullptr;   // host operator whose device copy is `A`
-  gal::DevCsr A;
+  const BlockCSR* cached = nullptr;   // host operator of the last resident level
+  std::vector<gal::DevCsr> lev;       // resident canonical operators, by level
+  std::vector<std::thread> downloads;
+  std::mutex mu;
+  std::string dl_error;
+  void join() {
+    for (auto& t : downloads)
+      if (t.joinable()) t.join();
+    downloads.clear();
+  }
   ~GalerkinDevice() {
-    A.release();
+    join();
+    for (auto& L : lev) L.release();
     if (st) (void)hipStreamDestroy(st);
+    if (dl) (void)hipStreamDestroy(dl);
   }
 };
 
@@ -294,15 +314,33 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
   (void)hipFree(cnt);
 }
 
+// Copies the values of a resident product into Ac.val (allocated here, so the
+// pages are touched by this thread). Runs on its own thread and stream.
+void download_values(GalerkinDevice* G, BlockCSR* Ac, const double* src, size_t count) {
+  hipError_t e = hipSetDevice(G->device);
+  if (e == hipSuccess) {
+    Ac->val.resize(count);
+    e = hipMemcpyAsync(Ac->val.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, G->dl);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(G->dl);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> g(G->mu);
+    G->dl_error = std::string("device Galerkin product: value download: ") + hipGetErrorString(e);
+  }
+}
+
 template <int D>
-void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
+void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
+                bool coarsest) {
   constexpr int DD = D * D;
   hipStream_t st = G.st;
-  if (G.cached != &A) {
-    G.A.release();
-    upload(G.A, A.n, A.rowptr, A.col, A.val, st);
-    G.cached = &A;
+  if (G.lev.empty()) {
+    G.lev.emplace_back();
+    upload(G.lev.back(), A.n, A.rowptr, A.col, A.val, st);
+  } else if (G.cached != &A) {
+    throw Error{VASMG_EINVAL, "internal: device Galerkin products out of level order"};
   }
+  const DevCsr& dA = G.lev.back();
   // P and its transpose (rows = coarse vertices), built on the host: <= 2^d
   // entries per P row
   ScalarCSR PT;
@@ -326,18 +364,20 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
   try {
     upload(dP, P.nrows, P.rowptr, P.col, P.val, st);
     upload(dPT, PT.nrows, PT.rowptr, PT.col, PT.val, st);
-    product<D, true>(G, G.A, dP, P.ncols, AP);
+    product<D, true>(G, dA, dP, P.ncols, AP);
     product<D, false>(G, dPT, AP, P.ncols, C);
     Ac.n = P.ncols;
     Ac.d = D;
     Ac.rowptr.resize(C.nrows + 1);
     Ac.col.resize(C.nnz);
-    Ac.val.resize(C.nnz * DD);
     check(hipMemcpyAsync(Ac.rowptr.data(), C.ptr, (C.nrows + 1) * sizeof(int64_t),
                          hipMemcpyDeviceToHost, st), "copy");
     check(hipMemcpyAsync(Ac.col.data(), C.col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-    check(hipMemcpyAsync(Ac.val.data(), C.val, C.nnz * DD * sizeof(double), hipMemcpyDeviceToHost, st),
-          "copy");
+    if (coarsest) {
+      Ac.val.resize(C.nnz * DD);
+      check(hipMemcpyAsync(Ac.val.data(), C.val, C.nnz * DD * sizeof(double), hipMemcpyDeviceToHost, st),
+            "copy");
+    }
     check(hipStreamSynchronize(st), "download");
   } catch (...) {
     dP.release();
@@ -349,10 +389,119 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
   dP.release();
   dPT.release();
   AP.release();
-  // the coarse operator stays resident as the next product's A
-  G.A.release();
-  G.A = C;
+  G.lev.push_back(C);
   G.cached = &Ac;
+  if (!coarsest)
+    G.downloads.emplace_back(download_values, &G, &Ac, C.val, static_cast<size_t>(C.nnz * DD));
+}
+
+// ---------------------------------------------------------------------------
+// device layout of a level from its resident canonical operator
+// ---------------------------------------------------------------------------
+constexpr int kLayoutStage = 1024;   // device columns of one row staged in LDS
+
+// Off-cell blocks below / above the row's cell. One wavefront per device row.
+__global__ __launch_bounds__(kThreads) void k_layout_count(int n, Csr A, const int* __restrict__ perm,
+                                                           const int* __restrict__ inv,
+                                                           const int* __restrict__ lo_,
+                                                           const int* __restrict__ hi_,
+                                                           int* __restrict__ cntL,
+                                                           int* __restrict__ cntU) {
+  const int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int c = perm[i];
+  const int lo = lo_[i], hi = hi_[i];
+  int cl = 0, cu = 0;
+  for (int64_t p = A.ptr[c] + lane; p < A.ptr[c + 1]; p += 64) {
+    const int j = inv[A.col[p]];
+    cl += j < lo;
+    cu += j >= hi;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    cl += __shfl_xor(cl, o, 64);
+    cu += __shfl_xor(cu, o, 64);
+  }
+  if (lane == 0) {
+    cntL[i] = cl;
+    cntU[i] = cu;
+  }
+}
+
+// One wavefront per device row: the row's device columns are staged in LDS
+// (rows longer than the stage read them from memory), each off-cell block goes
+// to position (number of same-part blocks with a smaller column) of its part.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_layout_fill(Csr A, LayoutArgs a) {
+  constexpr int DD = D * D, NU = (1 << D) * D;
+  __shared__ int sj[kWaves][kLayoutStage];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kWaves + w;
+  const bool valid = i < a.n;
+  const int c = valid ? a.perm[i] : 0;
+  const int64_t rb = valid ? A.ptr[c] : 0, re = valid ? A.ptr[c + 1] : 0;
+  const int len = static_cast<int>(re - rb);
+  const bool staged = len <= kLayoutStage;
+  if (staged)
+    for (int e = lane; e < len; e += 64) sj[w][e] = a.inv[A.col[rb + e]];
+  __syncthreads();
+  if (!valid) return;
+  const int lo = a.lo[i], hi = a.hi[i];
+  auto col_of = [&](int e) { return staged ? sj[w][e] : a.inv[A.col[rb + e]]; };
+  for (int e = lane; e < len; e += 64) {
+    const int j = col_of(e);
+    const double* blk = A.val + (rb + e) * DD;
+    if (j < lo || j >= hi) {
+      const bool low = j < lo;
+      int rank = 0;
+      for (int f = 0; f < len; ++f) {
+        const int jf = col_of(f);
+        rank += jf < j && (low || jf >= hi);
+      }
+      const int64_t q = (low ? a.Lptr[i] : a.Uptr[i]) + rank;
+      const int64_t stride = low ? a.nL : a.nU;
+      (low ? a.Lcol : a.Ucol)[q] = j;
+      float* v32 = low ? a.L32 : a.U32;
+      double* v64 = low ? a.L64 : a.U64;
+#pragma unroll
+      for (int t = 0; t < DD; ++t) {
+        if (v64) v64[t * stride + q] = blk[t];
+        if (v32) v32[t * stride + q] = static_cast<float>(blk[t]);
+      }
+    } else if (a.cell_of_row) {
+      const int64_t base = static_cast<int64_t>(a.cell_of_row[i]) * NU * NU;
+      const int ki = i - lo, kj = j - lo;
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+          const int64_t m = base + (kj * D + s) * NU + (ki * D + r);
+          if (a.M64) a.M64[m] = blk[r * D + s];
+          if (a.M32) a.M32[m] = static_cast<float>(blk[r * D + s]);
+        }
+    } else {
+#pragma unroll
+      for (int t = 0; t < DD; ++t) {
+        if (a.M64) a.M64[static_cast<int64_t>(i) * DD + t] = blk[t];
+        if (a.M32) a.M32[static_cast<int64_t>(i) * DD + t] = static_cast<float>(blk[t]);
+      }
+    }
+  }
+  // padding of the rows' parts: column i, zero blocks
+  for (int part = 0; part < 2; ++part) {
+    const int64_t b = (part ? a.Uptr[i] : a.Lptr[i]) + (part ? a.cntU[i] : a.cntL[i]);
+    const int64_t e = part ? a.Uptr[i + 1] : a.Lptr[i + 1];
+    const int64_t stride = part ? a.nU : a.nL;
+    for (int64_t q = b + lane; q < e; q += 64) {
+      (part ? a.Ucol : a.Lcol)[q] = i;
+      float* v32 = part ? a.U32 : a.L32;
+      double* v64 = part ? a.U64 : a.L64;
+      for (int t = 0; t < DD; ++t) {
+        if (v64) v64[t * stride + q] = 0.0;
+        if (v32) v32[t * stride + q] = 0.0f;
+      }
+    }
+  }
 }
 
 }  // namespace gal
@@ -360,7 +509,9 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
 GalerkinDevice* galerkin_device_create(int window_cols) {
   auto* G = new GalerkinDevice();
   if (window_cols > 0) G->window = std::min(window_cols, gal::kMaxWindowCols);
-  const hipError_t e = hipStreamCreateWithFlags(&G->st, hipStreamNonBlocking);
+  hipError_t e = hipGetDevice(&G->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&G->st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&G->dl, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete G;
     gal::check(e, "stream");
@@ -370,12 +521,52 @@ GalerkinDevice* galerkin_device_create(int window_cols) {
 
 void galerkin_device_destroy(GalerkinDevice* G) { delete G; }
 
-void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
+void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac, bool coarsest) {
   auto& G = *static_cast<GalerkinDevice*>(ctx);
   if (A.d == 2)
-    gal::galerkin_d<2>(G, A, P, Ac);
+    gal::galerkin_d<2>(G, A, P, Ac, coarsest);
   else
-    gal::galerkin_d<3>(G, A, P, Ac);
+    gal::galerkin_d<3>(G, A, P, Ac, coarsest);
+}
+
+void galerkin_device_join(GalerkinDevice* G) {
+  G->join();
+  std::lock_guard<std::mutex> g(G->mu);
+  if (!G->dl_error.empty()) throw Error{VASMG_EDEVICE, G->dl_error};
+}
+
+bool galerkin_device_has(const GalerkinDevice* G, int l) {
+  return G && l >= 0 && l < static_cast<int>(G->lev.size());
+}
+
+void layout_count(GalerkinDevice* G, int l, const LayoutArgs& a, int* cntL, int* cntU) {
+  if (!galerkin_device_has(G, l) || G->lev[l].nrows != a.n)
+    throw Error{VASMG_EINVAL, "internal: no resident operator for this level's layout"};
+  const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
+  if (a.n > 0)
+    hipLaunchKernelGGL(gal::k_layout_count, dim3(grid), dim3(gal::kThreads), 0, G->st, a.n,
+                       G->lev[l].view(), a.perm, a.inv, a.lo, a.hi, cntL, cntU);
+  gal::check(hipGetLastError(), "layout count launch");
+  gal::check(hipStreamSynchronize(G->st), "layout count");
+}
+
+void layout_fill(GalerkinDevice* G, int l, const LayoutArgs& a) {
+  if (!galerkin_device_has(G, l) || G->lev[l].nrows != a.n)
+    throw Error{VASMG_EINVAL, "internal: no resident operator for this level's layout"};
+  if (a.M32) gal::check(hipMemsetAsync(a.M32, 0, a.m_len * sizeof(float), G->st), "clear");
+  if (a.M64) gal::check(hipMemsetAsync(a.M64, 0, a.m_len * sizeof(double), G->st), "clear");
+  const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
+  if (a.d != 2 && a.d != 3) throw Error{VASMG_EINVAL, "internal: layout dimension"};
+  if (a.n > 0) {
+    if (a.d == 2)
+      hipLaunchKernelGGL(gal::k_layout_fill<2>, dim3(grid), dim3(gal::kThreads), 0, G->st,
+                         G->lev[l].view(), a);
+    else
+      hipLaunchKernelGGL(gal::k_layout_fill<3>, dim3(grid), dim3(gal::kThreads), 0, G->st,
+                         G->lev[l].view(), a);
+  }
+  gal::check(hipGetLastError(), "layout fill launch");
+  gal::check(hipStreamSynchronize(G->st), "layout fill");
 }
 
 }  // namespace vasmg

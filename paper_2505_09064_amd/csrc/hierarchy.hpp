@@ -77,7 +77,9 @@ struct MeshView {
 };
 
 // Galerkin product A_c = P^T A P (block A, scalar P shared by the components).
-using GalerkinFn = void (*)(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac);
+// `coarsest`: A_c is the last level (its values are needed on the host at once).
+using GalerkinFn = void (*)(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
+                            bool coarsest);
 
 struct SetupParams {
   int capacity;                // leaf capacity (> 0)
@@ -87,13 +89,48 @@ struct SetupParams {
   void* galerkin_ctx = nullptr;
 };
 
-// Device Galerkin products (galerkin.hip): a context with its own stream that
-// keeps the last coarse operator resident as the next product's A.
-// window_cols > 0 caps the columns per symbolic pass (0 = the LDS maximum).
+// Device setup (galerkin.hip): a context with its own stream that keeps every
+// level's canonical FP64 operator resident (level 0 uploaded, the others the
+// products), hands the host each product's structure at once and its values
+// from a background download, and builds the device layout of a level from the
+// resident operator. window_cols > 0 caps the columns per symbolic pass of the
+// product (0 = the LDS maximum).
 struct GalerkinDevice;
 GalerkinDevice* galerkin_device_create(int window_cols);
-void galerkin_device_destroy(GalerkinDevice* g);
-void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac);
+void galerkin_device_destroy(GalerkinDevice* g);   // joins the downloads
+void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
+                     bool coarsest);
+// Waits for the background value downloads; throws their error, if any.
+void galerkin_device_join(GalerkinDevice* g);
+// True if level l's canonical operator is resident.
+bool galerkin_device_has(const GalerkinDevice* g, int l);
+
+// Device layout of one level from its resident canonical operator (device
+// pointers; the level's device rows i = 0..n-1 map to canonical rows perm[i],
+// canonical columns to device columns by inv; [lo[i], hi[i]) is row i's cell).
+//   count: cntL[i] / cntU[i] = off-cell blocks of row i to columns below lo[i] /
+//          at or above hi[i];
+//   fill:  L and U parts (rows at Lptr / Uptr, padded entries: column i, zero
+//          blocks), columns ascending, values plane-major with strides nL / nU in
+//          the requested precisions; in-cell blocks into the dense cell matrices
+//          (cell_of_row non-null: column-major NU x NU per cell, NU = 2^d d) or the
+//          diagonal blocks (cell_of_row null). M32 / M64 are zeroed first.
+struct LayoutArgs {
+  int d = 0;   // 2 or 3
+  int n = 0;
+  const int *perm = nullptr, *inv = nullptr, *lo = nullptr, *hi = nullptr;
+  const int* cell_of_row = nullptr;
+  const int *Lptr = nullptr, *Uptr = nullptr, *cntL = nullptr, *cntU = nullptr;
+  int64_t nL = 0, nU = 0;
+  int *Lcol = nullptr, *Ucol = nullptr;
+  float *L32 = nullptr, *U32 = nullptr;
+  double *L64 = nullptr, *U64 = nullptr;
+  float* M32 = nullptr;
+  double* M64 = nullptr;
+  int64_t m_len = 0;   // elements of M32 / M64
+};
+void layout_count(GalerkinDevice* g, int l, const LayoutArgs& a, int* cntL, int* cntU);
+void layout_fill(GalerkinDevice* g, int l, const LayoutArgs& a);
 
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
 void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);

@@ -781,9 +781,11 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
       nlev = l + 1;
       break;
     }
-    if (prm.galerkin)
-      prm.galerkin(prm.galerkin_ctx, H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
-    else
+    if (prm.galerkin) {
+      const bool coarsest =
+          l + 2 == nlev || (prm.coarsest_max_dofs > 0 && H.levels[l + 1].n * d <= prm.coarsest_max_dofs);
+      prm.galerkin(prm.galerkin_ctx, H.levels[l].A, H.levels[l].P, H.levels[l + 1].A, coarsest);
+    } else
       galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
   }
   H.levels.resize(nlev);

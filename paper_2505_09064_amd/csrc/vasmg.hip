@@ -180,6 +180,7 @@ struct vasmg_ctx {
   Scalars* ksc = nullptr;              // [K]
   Scalars* kh_sc = nullptr;            // pinned host copy [K]
   hipGraphExec_t kgA = nullptr, kgB = nullptr;
+  GalerkinDevice* gdev = nullptr;     // setup_device = 1, during the upload only
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -345,6 +346,13 @@ void build_offcell_csr(const Level& hl, const std::vector<int>& perm, const std:
   }
 }
 
+void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
+                         const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
+                         const std::vector<int>& cell_ptr);
+void upload_level_host(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
+                       const std::vector<int>& inv, const std::vector<int>& cell_lo,
+                       const std::vector<int>& cell_hi, const std::vector<int>& cell_ptr);
+
 void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
   const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
@@ -403,6 +411,144 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
       cell_hi[i] = i + 1;
     }
   }
+  if (galerkin_device_has(C.gdev, l)) {
+    upload_level_device(C, l, need32, need64, inv, cell_lo, cell_hi, cell_ptr);
+  } else {
+    upload_level_host(C, l, need32, need64, perm, inv, cell_lo, cell_hi, cell_ptr);
+  }
+  if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
+  if (!coarsest && C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
+    if (C.gdev) galerkin_device_join(C.gdev);   // the host values of the level
+    std::vector<double> dinv;
+    block_diag_inverse(hl.A, dinv);
+    const double lam = jacobi_lambda_max(hl.A, dinv, 30);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      throw vasmg::Error{VASMG_EDEGENERATE, "Jacobi smoother: no positive eigenvalue estimate"};
+    dl.omega = (4.0 / 3.0) / lam;
+    std::vector<double> dd_dev(dinv.size());
+    for (int i = 0; i < n; ++i)
+      std::copy(dinv.begin() + static_cast<int64_t>(perm[i]) * dd,
+                dinv.begin() + static_cast<int64_t>(perm[i] + 1) * dd,
+                dd_dev.begin() + static_cast<int64_t>(i) * dd);
+    if (need64) dl.dinv64 = C.upload(dd_dev);
+    if (need32) dl.dinv32 = C.upload(std::vector<float>(dd_dev.begin(), dd_dev.end()));
+  }
+}
+
+// Lanes per block row from the mean off-cell blocks per row: about two blocks per
+// lane; cell levels use 16..64.
+void set_lanes(DevLevel& dl) {
+  const double avg = dl.n > 0 ? static_cast<double>(dl.nnz) / dl.n : 1.0;
+  dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
+  dl.Gspmv = dl.G;
+}
+
+// Row pointers of the L or U part from per-row block counts; rows padded to
+// whole quads of 4 blocks on cell levels.
+std::vector<int> padded_ptr(const std::vector<int>& cnt, bool cells) {
+  const int Q = cells ? dev::kQuad : 1;
+  std::vector<int> ptr(cnt.size() + 1, 0);
+  for (size_t i = 0; i < cnt.size(); ++i) {
+    const int64_t next = static_cast<int64_t>(ptr[i]) + (cnt[i] + Q - 1) / Q * Q;
+    if (next > INT32_MAX) throw vasmg::Error{VASMG_EINVAL, "level too large for int32 row pointers"};
+    ptr[i + 1] = static_cast<int>(next);
+  }
+  return ptr;
+}
+
+// Device-built layout (setup_device = 1): the level's canonical operator is
+// resident from the device Galerkin products; only the renumbering, the cell
+// ranges and the row pointers travel.
+void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
+                         const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
+                         const std::vector<int>& cell_ptr) {
+  DevLevel& dl = C.lev[l];
+  const int d = C.d, dd = d * d, n = dl.n, NU = (1 << d) * d;
+  struct Temp {
+    std::vector<void*> p;
+    ~Temp() {
+      for (void* q : p) (void)hipFree(q);
+    }
+    int* up(const std::vector<int>& v) {
+      void* q = nullptr;
+      HIP_CHECK(hipMalloc(&q, std::max<size_t>(v.size(), 1) * sizeof(int)));
+      p.push_back(q);
+      if (!v.empty()) HIP_CHECK(hipMemcpy(q, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+      return static_cast<int*>(q);
+    }
+  } tmp;
+  LayoutArgs a;
+  a.d = d;
+  a.n = n;
+  a.perm = dl.perm;
+  a.inv = tmp.up(inv);
+  a.lo = tmp.up(cell_lo);
+  a.hi = tmp.up(cell_hi);
+  if (dl.cells) {
+    std::vector<int> cor(n);
+    for (int c = 0; c + 1 < static_cast<int>(cell_ptr.size()); ++c)
+      for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) cor[i] = c;
+    a.cell_of_row = tmp.up(cor);
+  }
+  std::vector<int> cntL(n, 0), cntU(n, 0);
+  int* d_cntL = tmp.up(cntL);
+  int* d_cntU = tmp.up(cntU);
+  layout_count(C.gdev, l, a, d_cntL, d_cntU);
+  HIP_CHECK(hipMemcpy(cntL.data(), d_cntL, n * sizeof(int), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(cntU.data(), d_cntU, n * sizeof(int), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    dl.nnz_lo += cntL[i];
+    dl.nnz_up += cntU[i];
+  }
+  dl.nnz = dl.nnz_lo + dl.nnz_up;
+  set_lanes(dl);
+  const std::vector<int> Lptr = padded_ptr(cntL, dl.cells), Uptr = padded_ptr(cntU, dl.cells);
+  const int64_t nL = Lptr[n], nU = Uptr[n];
+  dl.Lstride = nL;
+  dl.Ustride = nU;
+  dl.Lptr = C.upload(Lptr);
+  dl.Uptr = C.upload(Uptr);
+  dl.Lcol = C.dalloc<int>(nL);
+  dl.Ucol = C.dalloc<int>(nU);
+  if (dl.cells) dl.cell_ptr = C.upload(cell_ptr);
+  const int64_t m_len = dl.cells ? static_cast<int64_t>(dl.ncells) * NU * NU : static_cast<int64_t>(n) * dd;
+  if (need64) {
+    dl.Lval64 = C.dalloc<double>(nL * dd);
+    dl.Uval64 = C.dalloc<double>(nU * dd);
+    (dl.cells ? dl.cellM64 : dl.diag64) = C.dalloc<double>(m_len);
+    dl.has64 = true;
+  }
+  if (need32) {
+    dl.Lval32 = C.dalloc<float>(nL * dd);
+    dl.Uval32 = C.dalloc<float>(nU * dd);
+    (dl.cells ? dl.cellM32 : dl.diag32) = C.dalloc<float>(m_len);
+    dl.has32 = true;
+  }
+  a.Lptr = dl.Lptr;
+  a.Uptr = dl.Uptr;
+  a.cntL = d_cntL;
+  a.cntU = d_cntU;
+  a.nL = nL;
+  a.nU = nU;
+  a.Lcol = dl.Lcol;
+  a.Ucol = dl.Ucol;
+  a.L32 = dl.Lval32;
+  a.U32 = dl.Uval32;
+  a.L64 = dl.Lval64;
+  a.U64 = dl.Uval64;
+  a.M32 = dl.cells ? dl.cellM32 : dl.diag32;
+  a.M64 = dl.cells ? dl.cellM64 : dl.diag64;
+  a.m_len = m_len;
+  layout_fill(C.gdev, l, a);
+}
+
+// Host-built layout: off-cell CSR in device order, split and padded, uploaded.
+void upload_level_host(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
+                       const std::vector<int>& inv, const std::vector<int>& cell_lo,
+                       const std::vector<int>& cell_hi, const std::vector<int>& cell_ptr) {
+  const Level& hl = C.H.levels[l];
+  DevLevel& dl = C.lev[l];
+  const int d = C.d, dd = d * d, n = static_cast<int>(hl.n);
   std::vector<int> rowptr, lo_end, up_beg, col;
   std::vector<double> val, diag, cellM;
   if (dl.cells) {
@@ -429,25 +575,19 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   }
   const int64_t nnz = rowptr[n];
   dl.nnz = nnz;
+  std::vector<int> cntL(n), cntU(n);
   for (int i = 0; i < n; ++i) {
-    dl.nnz_lo += lo_end[i] - rowptr[i];
-    dl.nnz_up += rowptr[i + 1] - up_beg[i];
+    cntL[i] = lo_end[i] - rowptr[i];
+    cntU[i] = rowptr[i + 1] - up_beg[i];
+    dl.nnz_lo += cntL[i];
+    dl.nnz_up += cntU[i];
   }
-  const double avg = n > 0 ? static_cast<double>(nnz) / n : 1.0;
-  // lanes per block row: about two blocks per lane; cell levels use 16..64
-  dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
-  dl.Gspmv = dl.G;
+  set_lanes(dl);
   // split the off-cell blocks into the L (earlier colours) and U (later colours)
   // matrices, each plane-major over its own blocks. On cell levels every row is
   // padded to whole quads of 4 blocks (zero blocks pointing at the row itself),
   // so a lane reads 4 consecutive blocks with one 16-byte load per plane.
-  const int Q = dl.cells ? dev::kQuad : 1;
-  const auto padded = [Q](int len) { return (len + Q - 1) / Q * Q; };
-  std::vector<int> Lptr(n + 1, 0), Uptr(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    Lptr[i + 1] = Lptr[i] + padded(lo_end[i] - rowptr[i]);
-    Uptr[i + 1] = Uptr[i] + padded(rowptr[i + 1] - up_beg[i]);
-  }
+  const std::vector<int> Lptr = padded_ptr(cntL, dl.cells), Uptr = padded_ptr(cntU, dl.cells);
   const int64_t nL = Lptr[n], nU = Uptr[n];
   dl.Lstride = nL;
   dl.Ustride = nU;
@@ -493,22 +633,6 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
     else
       dl.diag32 = C.upload(std::vector<float>(diag.begin(), diag.end()));
     dl.has32 = true;
-  }
-  if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
-  if (!coarsest && C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
-    std::vector<double> dinv;
-    block_diag_inverse(hl.A, dinv);
-    const double lam = jacobi_lambda_max(hl.A, dinv, 30);
-    if (!(lam > 0.0) || !std::isfinite(lam))
-      throw vasmg::Error{VASMG_EDEGENERATE, "Jacobi smoother: no positive eigenvalue estimate"};
-    dl.omega = (4.0 / 3.0) / lam;
-    std::vector<double> dd_dev(dinv.size());
-    for (int i = 0; i < n; ++i)
-      std::copy(dinv.begin() + static_cast<int64_t>(perm[i]) * dd,
-                dinv.begin() + static_cast<int64_t>(perm[i] + 1) * dd,
-                dd_dev.begin() + static_cast<int64_t>(i) * dd);
-    if (need64) dl.dinv64 = C.upload(dd_dev);
-    if (need32) dl.dinv32 = C.upload(std::vector<float>(dd_dev.begin(), dd_dev.end()));
   }
 }
 
@@ -1809,7 +1933,6 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       prm.galerkin_ctx = gdev.get();
     }
     build_hierarchy(mv, prm, C->H);
-    gdev.reset();
     C->d = mesh->dim;
     C->DP = mesh->dim == 3 ? 4 : 2;
     C->L = static_cast<int>(C->H.levels.size()) - 1;
@@ -1826,7 +1949,11 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
     }
     if (!C->host_only) {
       const auto t0 = std::chrono::steady_clock::now();
+      C->gdev = gdev.get();
       upload_device(*C, nullptr);
+      if (gdev) galerkin_device_join(gdev.get());   // host copies of the level values
+      C->gdev = nullptr;
+      gdev.reset();
       if (o.verbose)
         std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", "upload+autotune",
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());

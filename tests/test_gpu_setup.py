@@ -14,6 +14,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import Oracle, OracleOptions
+from oracle.smoother import ColoredGS
 from workloads import cfg1, small2d, small3d
 
 torch = pytest.importorskip("torch")
@@ -25,6 +26,19 @@ pytestmark = pytest.mark.gpu
 def _levels(s):
     nl, _, _ = s.hierarchy_info()
     return [s.export_level(l) for l in range(nl)]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _bsr(e, d):
@@ -68,6 +82,70 @@ def test_device_galerkin_matches_oracle_and_host(name):
         assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs from the oracle"
     # the fine level is assembled on the host either way
     assert np.array_equal(Ld[0]["vals"], Lh[0]["vals"])
+    sd.free()
+    sh.free()
+
+
+@pytest.mark.parametrize("name", ["small3d", "small2d_x0", "graded"])
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+def test_device_layout_kernels_per_level(name, prec):
+    """The level layouts built on the device (colour-ordered rows, sorted and
+    quad-padded L / U parts, cell matrices or diagonals) drive the per-level
+    kernels to the oracle's results with the bars of the host-built layouts, and
+    on the fine level (assembled on the host, so the same FP64 values) to the
+    host-built layout's results bit for bit."""
+    mesh_fn, kw, oopts = CASES[name]
+    m = mesh_fn()
+    d = m.dim
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, oopts)
+    sd = V.Solver.from_mesh(m, precision=prec, setup_device=1, **kw)
+    sh = V.Solver.from_mesh(m, precision=prec, **kw)
+    rng = np.random.default_rng(4)
+    tol = 1e-13 if prec == V.FP64 else 2e-6
+    gtol = 1e-11 if prec == V.FP64 else 1e-4
+    for l in range(o.L):
+        A = o.A[l]
+        n = A.shape[0] // d
+        x = rng.normal(size=(n, d))
+        b = rng.normal(size=(n, d))
+        yd = torch.zeros((n, d), dtype=torch.float64, device="cuda")
+        yh = torch.zeros_like(yd)
+        sd.spmv_device(l, prec, _dev(x), yd)
+        sh.spmv_device(l, prec, _dev(x), yh)
+        assert _rel(_host(yd).ravel(), A @ x.ravel()) < tol, (l, "spmv")
+        if l == 0:
+            assert np.array_equal(_host(yd), _host(yh)), "fine SpMV not bitwise equal"
+        S = ColoredGS(A, d, o.cells[l], o.cell_colors[l])
+        for bw in (0, 1):
+            xd, xh = _dev(x), _dev(x)
+            sd.gs_sweep_device(l, prec, bw, _dev(b), xd)
+            sh.gs_sweep_device(l, prec, bw, _dev(b), xh)
+            ref = S.backward(b.ravel(), x.ravel()) if bw else S.forward(b.ravel(), x.ravel())
+            assert _rel(_host(xd).ravel(), ref) < gtol, (l, "gs", bw)
+            if l == 0:
+                assert np.array_equal(_host(xd), _host(xh)), ("fine GS not bitwise equal", bw)
+    sd.free()
+    sh.free()
+
+
+@pytest.mark.parametrize("kw", [dict(smoother=V.SMOOTHER_JACOBI), dict(block_rhs=8),
+                                dict(cycle=V.CYCLE_W), dict(preconditioner=V.PRECOND_JACOBI)])
+def test_device_setup_with_other_options(kw):
+    """Options that read the host copies of the level values (the Jacobi
+    smoother's diagonal inverses and eigenvalue estimate) or other device paths
+    (block right-hand sides, W-cycle, point Jacobi preconditioner) give the
+    host-setup handle's iteration counts."""
+    m = small3d(9, seed=5)
+    rng = np.random.default_rng(3)
+    n_rhs = 3 if "block_rhs" in kw else 1
+    F = rng.normal(size=(n_rhs, m.coords.shape[0], 3)) * (1 - m.fixed)[None]
+    sd = V.Solver.from_mesh(m, setup_device=1, **kw)
+    sh = V.Solver.from_mesh(m, **kw)
+    Xd, infd = sd.solve(F, 1e-8)
+    Xh, infh = sh.solve(F, 1e-8)
+    for a, b in zip(infd, infh):
+        assert a["converged"] == 1 and a["iterations"] == b["iterations"]
+    assert np.linalg.norm(Xd - Xh) / np.linalg.norm(Xh) < 1e-7
     sd.free()
     sh.free()
 
