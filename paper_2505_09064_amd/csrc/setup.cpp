@@ -38,6 +38,7 @@
 
 #ifdef _OPENMP
 #include <omp.h>
+#include <parallel/algorithm>
 #endif
 
 namespace vasmg {
@@ -322,31 +323,50 @@ struct Triplet {
 // Builds P from (row, column key, weight) triplets with nonzero weights; the
 // columns are the distinct keys in canonical order. Returns the column keys.
 std::vector<Key> triplets_to_csr(std::vector<Triplet>& tr, int64_t nrows, ScalarCSR& P) {
-  std::vector<Key> keys;
-  keys.reserve(tr.size());
-  for (const auto& t : tr) keys.push_back(t.key);
-  std::sort(keys.begin(), keys.end(), key_less);
+  const int64_t nt = static_cast<int64_t>(tr.size());
+  std::vector<Key> keys(nt);
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t) keys[t] = tr[t].key;
+  // equal keys are identical, so the sorted distinct keys do not depend on the
+  // thread count
+  __gnu_parallel::sort(keys.begin(), keys.end(), key_less);
   keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
   P.nrows = nrows;
   P.ncols = static_cast<int64_t>(keys.size());
   P.rowptr.assign(nrows + 1, 0);
   for (const auto& t : tr) P.rowptr[t.row + 1]++;
   for (int64_t i = 0; i < nrows; ++i) P.rowptr[i + 1] += P.rowptr[i];
-  P.col.assign(tr.size(), 0);
-  P.val.assign(tr.size(), 0.0);
+  std::vector<int32_t> colof(nt);
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < nt; ++t)
+    colof[t] = static_cast<int32_t>(std::lower_bound(keys.begin(), keys.end(), tr[t].key, key_less) -
+                                    keys.begin());
+  P.col.assign(nt, 0);
+  P.val.assign(nt, 0.0);
   std::vector<int64_t> fill(P.rowptr.begin(), P.rowptr.end() - 1);
-  for (const auto& t : tr) {
-    const int64_t c = std::lower_bound(keys.begin(), keys.end(), t.key, key_less) - keys.begin();
-    const int64_t p = fill[t.row]++;
-    P.col[p] = static_cast<int32_t>(c);
-    P.val[p] = t.w;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t p = fill[tr[t].row]++;
+    P.col[p] = colof[t];
+    P.val[p] = tr[t].w;
   }
-  // columns ascending within each row
+  // columns ascending within each row (distinct within a row)
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t i = 0; i < nrows; ++i) {
     const int64_t b = P.rowptr[i], e = P.rowptr[i + 1];
-    std::vector<std::pair<int32_t, double>> r;
-    for (int64_t p = b; p < e; ++p) r.emplace_back(P.col[p], P.val[p]);
-    std::sort(r.begin(), r.end());
+    std::pair<int32_t, double> r[64];
+    const int64_t len = e - b;
+    if (len > 64) {
+      std::vector<std::pair<int32_t, double>> v;
+      for (int64_t p = b; p < e; ++p) v.emplace_back(P.col[p], P.val[p]);
+      std::sort(v.begin(), v.end());
+      for (int64_t p = b; p < e; ++p) {
+        P.col[p] = v[p - b].first;
+        P.val[p] = v[p - b].second;
+      }
+      continue;
+    }
+    for (int64_t p = b; p < e; ++p) r[p - b] = {P.col[p], P.val[p]};
+    std::sort(r, r + len);
     for (int64_t p = b; p < e; ++p) {
       P.col[p] = r[p - b].first;
       P.val[p] = r[p - b].second;
@@ -367,7 +387,7 @@ std::vector<Key> region_corners(const std::vector<Region>& R, int d) {
       out.push_back(k);
     }
   }
-  std::sort(out.begin(), out.end(), key_less);
+  __gnu_parallel::sort(out.begin(), out.end(), key_less);
   out.erase(std::unique(out.begin(), out.end()), out.end());
   return out;
 }
@@ -502,7 +522,7 @@ void build_gs_order(Level& lv, bool lattice, int d) {
     for (int64_t i = 0; i < n; ++i)
       for (int a = 0; a < 3; ++a) ck[i][a] = lv.keys[i][a] / cs;
     ckeys = ck;
-    std::sort(ckeys.begin(), ckeys.end(), key_less);
+    __gnu_parallel::sort(ckeys.begin(), ckeys.end(), key_less);
     ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
     lv.ncells = static_cast<int64_t>(ckeys.size());
     lv.cell.resize(n);
@@ -520,12 +540,14 @@ void build_gs_order(Level& lv, bool lattice, int d) {
     std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
     for (int64_t i = 0; i < n; ++i) members[fill[lv.cell[i]]++] = static_cast<int32_t>(i);
   }
+  // each cell's neighbour list is independent: built in parallel, then packed
   std::vector<int64_t> gptr(nc + 1, 0);
   std::vector<int32_t> gadj;
   {
-    std::vector<int32_t> tmp;
+    std::vector<std::vector<int32_t>> nb(nc);
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < nc; ++c) {
-      tmp.clear();
+      auto& tmp = nb[c];
       for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) {
         const int32_t v = members[q];
         for (int64_t p = lv.A.rowptr[v]; p < lv.A.rowptr[v + 1]; ++p)
@@ -533,15 +555,23 @@ void build_gs_order(Level& lv, bool lattice, int d) {
       }
       std::sort(tmp.begin(), tmp.end());
       tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-      gadj.insert(gadj.end(), tmp.begin(), tmp.end());
-      gptr[c + 1] = static_cast<int64_t>(gadj.size());
     }
+    for (int64_t c = 0; c < nc; ++c) gptr[c + 1] = gptr[c] + static_cast<int64_t>(nb[c].size());
+    gadj.resize(gptr[nc]);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t c = 0; c < nc; ++c) std::copy(nb[c].begin(), nb[c].end(), gadj.begin() + gptr[c]);
   }
-  std::vector<int64_t> order(nc);
-  std::iota(order.begin(), order.end(), 0);
-  int32_t best = greedy_color_in_order(gptr, gadj, order, lv.cell_color);
-  if (lattice) {
-    for (int q = 2; q <= 3; ++q) {
+  // the candidate visiting orders are coloured side by side; the first order
+  // with the fewest colours wins, as in a sequential scan
+  const int n_orders = lattice ? 3 : 1;
+  std::vector<std::vector<int32_t>> cand(n_orders);
+  std::vector<int32_t> ncol(n_orders, 0);
+#pragma omp parallel for schedule(static, 1)
+  for (int o = 0; o < n_orders; ++o) {
+    std::vector<int64_t> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    if (o > 0) {
+      const int q = o + 1;
       std::vector<int64_t> cls(nc, 0);
       for (int64_t c = 0; c < nc; ++c) {
         int64_t w = 1;
@@ -550,17 +580,16 @@ void build_gs_order(Level& lv, bool lattice, int d) {
           w *= q;
         }
       }
-      std::iota(order.begin(), order.end(), 0);
       std::stable_sort(order.begin(), order.end(),
                        [&](int64_t a, int64_t b) { return cls[a] < cls[b]; });
-      std::vector<int32_t> cand;
-      const int32_t k = greedy_color_in_order(gptr, gadj, order, cand);
-      if (k < best) {
-        best = k;
-        lv.cell_color.swap(cand);
-      }
     }
+    ncol[o] = greedy_color_in_order(gptr, gadj, order, cand[o]);
   }
+  int best_o = 0;
+  for (int o = 1; o < n_orders; ++o)
+    if (ncol[o] < ncol[best_o]) best_o = o;
+  const int32_t best = ncol[best_o];
+  lv.cell_color.swap(cand[best_o]);
   lv.ncolors = best;
   lv.color.resize(n);
   for (int64_t i = 0; i < n; ++i) lv.color[i] = lv.cell_color[lv.cell[i]];
@@ -627,14 +656,16 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
       H.free_vertices.push_back(static_cast<int32_t>(v));
     }
   if (nfree == 0) fail(1, "every vertex is fixed: nothing to solve");
+  int64_t bad = m.ne;   // first inverted or degenerate element, if any
+#pragma omp parallel for schedule(static) reduction(min : bad)
   for (int64_t e = 0; e < m.ne; ++e) {
     const double* xs[4];
     for (int a = 0; a <= d; ++a) xs[a] = m.coords + int64_t(m.elems[e * (d + 1) + a]) * d;
     double G[4][3];
     const double det = p1_grads(d, xs, G);
-    if (!(det > 0.0) || !std::isfinite(det))
-      fail(1, "element " + std::to_string(e) + " is inverted or degenerate");
+    if (!(det > 0.0) || !std::isfinite(det)) bad = std::min(bad, e);
   }
+  if (bad < m.ne) fail(1, "element " + std::to_string(bad) + " is inverted or degenerate");
 
   H.levels.emplace_back();
   {
@@ -663,14 +694,15 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   std::vector<Region> R;
   R.reserve(tree_vtx.size());
   for (size_t i = 0; i < tree_vtx.size(); ++i) R.push_back({T.leaf_depth[i], T.leaf_lo[i]});
-  std::sort(R.begin(), R.end(), region_less);
+  __gnu_parallel::sort(R.begin(), R.end(), region_less);
   R.erase(std::unique(R.begin(), R.end(), region_eq), R.end());
 
   // ---- Step 4 + Section 3.2: P_0 by multilinear interpolation in the leaf
   std::vector<Key> cur_keys;
   {
-    std::vector<Triplet> tr;
-    tr.reserve(nfree << d);
+    // 2^d slots per row, filled in parallel; zero weights are dropped after
+    std::vector<Triplet> tr(static_cast<size_t>(nfree) << d, Triplet{0, Key{0, 0, 0}, 0.0});
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nfree; ++i) {
       const int32_t v = H.free_vertices[i];
       const int32_t t = pos_in_tree[v];
@@ -693,9 +725,11 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
           w = w * (up ? tup[a] : tdn[a]);
           if (up) k[a] += s;
         }
-        if (w != 0.0) tr.push_back({i, k, w});
+        tr[(i << d) + b] = {i, k, w};
       }
     }
+    tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
+             tr.end());
     cur_keys = triplets_to_csr(tr, nfree, H.levels[0].P);
   }
   mark("P0");
@@ -729,27 +763,36 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
         corner_parent.emplace_back(k, p.lo);
       }
     }
-    std::sort(Rn.begin(), Rn.end(), region_less);
+    __gnu_parallel::sort(Rn.begin(), Rn.end(), region_less);
     Rn.erase(std::unique(Rn.begin(), Rn.end(), region_eq), Rn.end());
-    std::sort(corner_parent.begin(), corner_parent.end(),
-              [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
-                return key_less(a.first, b.first);
-              });
+    // a total order (corner, then parent): deterministic for any thread count; a
+    // corner shared by two merged parents lies on their common face, where both
+    // give the same interpolation corners and weights
+    __gnu_parallel::sort(corner_parent.begin(), corner_parent.end(),
+                         [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
+                           if (a.first != b.first) return key_less(a.first, b.first);
+                           return key_less(a.second, b.second);
+                         });
     const std::vector<Key> next_all = region_corners(Rn, d);
-    std::vector<Triplet> tr;
-    tr.reserve(cur_keys.size() * 2);
-    for (int64_t i = 0; i < static_cast<int64_t>(cur_keys.size()); ++i) {
+    // 2^d slots per row, filled in parallel; zero weights are dropped after
+    const int64_t ncur = static_cast<int64_t>(cur_keys.size());
+    std::vector<Triplet> tr(static_cast<size_t>(ncur) << d, Triplet{0, Key{0, 0, 0}, 0.0});
+    int not_corner = 0;
+#pragma omp parallel for schedule(static) reduction(|| : not_corner)
+    for (int64_t i = 0; i < ncur; ++i) {
       const Key& kv = cur_keys[i];
       if (std::binary_search(next_all.begin(), next_all.end(), kv, key_less)) {
-        tr.push_back({i, kv, 1.0});
+        tr[i << d] = {i, kv, 1.0};
         continue;
       }
       auto it = std::lower_bound(corner_parent.begin(), corner_parent.end(), kv,
                                  [](const std::pair<Key, Key>& a, const Key& k) {
                                    return key_less(a.first, k);
                                  });
-      if (it == corner_parent.end() || it->first != kv)
-        fail(1, "internal error: interpolated vertex is not a corner of a merged region");
+      if (it == corner_parent.end() || it->first != kv) {
+        not_corner = 1;
+        continue;
+      }
       const Key plo = it->second;
       double up[3];
       for (int a = 0; a < d; ++a) {
@@ -764,9 +807,12 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
           w = w * (hi ? up[a] : 1.0 - up[a]);
           if (hi) k[a] += ps;
         }
-        if (w != 0.0) tr.push_back({i, k, w});
+        tr[(i << d) + b] = {i, k, w};
       }
     }
+    if (not_corner) fail(1, "internal error: interpolated vertex is not a corner of a merged region");
+    tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
+             tr.end());
     Level& prev = H.levels[H.levels.size() - 2];
     (void)prev;
     cur_keys = triplets_to_csr(tr, static_cast<int64_t>(cur_keys.size()), lv.P);
