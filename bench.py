@@ -129,7 +129,13 @@ def bench_cfg4(args, V, torch):
     ib = rb[-1][1]
     log(f"block: {ms_blk:.1f} ms for 16 cases, its {[i['iterations'] for i in ib]}")
     blk.free()
-    one = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, autotune=1)
+    # the column-by-column handle is built with the device setup (Galerkin
+    # products and level layouts on the device): same structure, values to rounding
+    t0 = time.perf_counter()
+    one = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, autotune=1, setup_device=1,
+                             verbose=1)
+    t_setup_dev = time.perf_counter() - t0
+    log(f"setup (single column, device) {t_setup_dev:.1f}s")
     time_solves(one, d_F[:1], d_X[:1], 1)
     rs = time_solves(one, d_F, d_X, 1)
     ms_seq = rs[-1][0]
@@ -148,6 +154,7 @@ def bench_cfg4(args, V, torch):
         "iterations": [int(i["iterations"]) for i in ib],
         "max_rel_res_true": float(max(i["rel_res_true"] for i in ib)),
         "setup_s": t_setup,
+        "setup_device_s": t_setup_dev,
         "column_by_column_ms": ms_seq,
         "column_by_column_iterations": [int(i["iterations"]) for i in iseq],
         "speedup_vs_column_by_column": ms_seq / ms_blk,
@@ -314,6 +321,15 @@ def main():
                                autotune=0 if args.no_autotune else 1)
     t_setup = time.perf_counter() - t0
     log(f"setup (mixed) {t_setup:.1f}s")
+    # the same hierarchy with the Galerkin products and level layouts on the device
+    t0 = time.perf_counter()
+    dev_setup = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, setup_device=1,
+                                   autotune=0 if args.no_autotune else 1)
+    t_setup_dev = time.perf_counter() - t0
+    dev_info = dev_setup.solve_device(d_rhs, d_x, 1e-6)
+    dev_setup.free()
+    log(f"setup (mixed, device Galerkin + layout) {t_setup_dev:.2f}s, "
+        f"{dev_info['iterations']} its")
     for i in range(args.warmup):
         info = mixed.solve_device(d_rhs, d_x, 1e-6)
         log(f"warmup {i}: {info['iterations']} its, {info['t_solve_ms']:.2f} ms")
@@ -426,6 +442,8 @@ def main():
         "device_ms_mean": float(np.mean(dev_ms)),
         "rel_res_true": info["rel_res_true"],
         "setup_s": t_setup,
+        "setup_device_s": t_setup_dev,
+        "setup_device_iterations": dev_info["iterations"],
         "timed_region_s": t_total,
         "iteration_ms_profiled": it_ms,
         "iteration_bytes": it_bytes,
