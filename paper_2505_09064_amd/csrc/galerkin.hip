@@ -21,7 +21,8 @@
 // level (colour-ordered rows, off-cell L / U parts, cell matrices or diagonals,
 // in the solve precisions) has been built from it by the layout kernels below;
 // the host receives each product's structure at once (cells and colours are
-// built from it) and its values from a background download.
+// built from it) and its values from a background download. The layout kernels
+// also serve uploads of host-built hierarchies (the operator copied in first).
 
 #include <hip/hip_runtime.h>
 
@@ -535,38 +536,42 @@ void galerkin_device_join(GalerkinDevice* G) {
   if (!G->dl_error.empty()) throw Error{VASMG_EDEVICE, G->dl_error};
 }
 
-bool galerkin_device_has(const GalerkinDevice* G, int l) {
-  return G && l >= 0 && l < static_cast<int>(G->lev.size());
+bool galerkin_device_operator(const GalerkinDevice* G, int l, DevOperator* out) {
+  if (!G || l < 0 || l >= static_cast<int>(G->lev.size())) return false;
+  const gal::DevCsr& L = G->lev[l];
+  *out = DevOperator{L.nrows, L.ptr, L.col, L.val};
+  return true;
 }
 
-void layout_count(GalerkinDevice* G, int l, const LayoutArgs& a, int* cntL, int* cntU) {
-  if (!galerkin_device_has(G, l) || G->lev[l].nrows != a.n)
-    throw Error{VASMG_EINVAL, "internal: no resident operator for this level's layout"};
+void* galerkin_device_stream(const GalerkinDevice* G) { return G ? static_cast<void*>(G->st) : nullptr; }
+
+void layout_count(const DevOperator& A, const LayoutArgs& a, int* cntL, int* cntU, void* stream) {
+  if (A.n != a.n) throw Error{VASMG_EINVAL, "internal: layout operator size"};
+  hipStream_t st = static_cast<hipStream_t>(stream);
   const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
   if (a.n > 0)
-    hipLaunchKernelGGL(gal::k_layout_count, dim3(grid), dim3(gal::kThreads), 0, G->st, a.n,
-                       G->lev[l].view(), a.perm, a.inv, a.lo, a.hi, cntL, cntU);
+    hipLaunchKernelGGL(gal::k_layout_count, dim3(grid), dim3(gal::kThreads), 0, st, a.n,
+                       gal::Csr{A.ptr, A.col, A.val}, a.perm, a.inv, a.lo, a.hi, cntL, cntU);
   gal::check(hipGetLastError(), "layout count launch");
-  gal::check(hipStreamSynchronize(G->st), "layout count");
+  gal::check(hipStreamSynchronize(st), "layout count");
 }
 
-void layout_fill(GalerkinDevice* G, int l, const LayoutArgs& a) {
-  if (!galerkin_device_has(G, l) || G->lev[l].nrows != a.n)
-    throw Error{VASMG_EINVAL, "internal: no resident operator for this level's layout"};
-  if (a.M32) gal::check(hipMemsetAsync(a.M32, 0, a.m_len * sizeof(float), G->st), "clear");
-  if (a.M64) gal::check(hipMemsetAsync(a.M64, 0, a.m_len * sizeof(double), G->st), "clear");
-  const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
+void layout_fill(const DevOperator& A, const LayoutArgs& a, void* stream) {
+  if (A.n != a.n) throw Error{VASMG_EINVAL, "internal: layout operator size"};
   if (a.d != 2 && a.d != 3) throw Error{VASMG_EINVAL, "internal: layout dimension"};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (a.M32) gal::check(hipMemsetAsync(a.M32, 0, a.m_len * sizeof(float), st), "clear");
+  if (a.M64) gal::check(hipMemsetAsync(a.M64, 0, a.m_len * sizeof(double), st), "clear");
+  const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
+  const gal::Csr op{A.ptr, A.col, A.val};
   if (a.n > 0) {
     if (a.d == 2)
-      hipLaunchKernelGGL(gal::k_layout_fill<2>, dim3(grid), dim3(gal::kThreads), 0, G->st,
-                         G->lev[l].view(), a);
+      hipLaunchKernelGGL(gal::k_layout_fill<2>, dim3(grid), dim3(gal::kThreads), 0, st, op, a);
     else
-      hipLaunchKernelGGL(gal::k_layout_fill<3>, dim3(grid), dim3(gal::kThreads), 0, G->st,
-                         G->lev[l].view(), a);
+      hipLaunchKernelGGL(gal::k_layout_fill<3>, dim3(grid), dim3(gal::kThreads), 0, st, op, a);
   }
   gal::check(hipGetLastError(), "layout fill launch");
-  gal::check(hipStreamSynchronize(G->st), "layout fill");
+  gal::check(hipStreamSynchronize(st), "layout fill");
 }
 
 }  // namespace vasmg

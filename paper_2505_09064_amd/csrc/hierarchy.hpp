@@ -102,12 +102,23 @@ void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR&
                      bool coarsest);
 // Waits for the background value downloads; throws their error, if any.
 void galerkin_device_join(GalerkinDevice* g);
-// True if level l's canonical operator is resident.
-bool galerkin_device_has(const GalerkinDevice* g, int l);
 
-// Device layout of one level from its resident canonical operator (device
-// pointers; the level's device rows i = 0..n-1 map to canonical rows perm[i],
-// canonical columns to device columns by inv; [lo[i], hi[i]) is row i's cell).
+// A level's canonical FP64 operator on the device (block CSR: int64 row
+// pointers, int32 columns, row-major d x d blocks).
+struct DevOperator {
+  int64_t n = 0;
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+};
+// Level l's resident operator from the device Galerkin products; false if none.
+bool galerkin_device_operator(const GalerkinDevice* g, int l, DevOperator* out);
+// The context's stream (a hipStream_t).
+void* galerkin_device_stream(const GalerkinDevice* g);
+
+// Device layout of one level from its canonical operator A (device pointers;
+// the level's device rows i = 0..n-1 map to canonical rows perm[i], canonical
+// columns to device columns by inv; [lo[i], hi[i]) is row i's cell).
 //   count: cntL[i] / cntU[i] = off-cell blocks of row i to columns below lo[i] /
 //          at or above hi[i];
 //   fill:  L and U parts (rows at Lptr / Uptr, padded entries: column i, zero
@@ -115,6 +126,8 @@ bool galerkin_device_has(const GalerkinDevice* g, int l);
 //          the requested precisions; in-cell blocks into the dense cell matrices
 //          (cell_of_row non-null: column-major NU x NU per cell, NU = 2^d d) or the
 //          diagonal blocks (cell_of_row null). M32 / M64 are zeroed first.
+// Both are enqueued on `stream` (a hipStream_t; null = the null stream) and
+// return after it has finished them.
 struct LayoutArgs {
   int d = 0;   // 2 or 3
   int n = 0;
@@ -129,8 +142,8 @@ struct LayoutArgs {
   double* M64 = nullptr;
   int64_t m_len = 0;   // elements of M32 / M64
 };
-void layout_count(GalerkinDevice* g, int l, const LayoutArgs& a, int* cntL, int* cntU);
-void layout_fill(GalerkinDevice* g, int l, const LayoutArgs& a);
+void layout_count(const DevOperator& A, const LayoutArgs& a, int* cntL, int* cntU, void* stream);
+void layout_fill(const DevOperator& A, const LayoutArgs& a, void* stream);
 
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
 void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);

@@ -247,7 +247,7 @@ struct vasmg_ctx {
 namespace {
 
 // -------------------------------------------------------------------------
-// upload: colour-major renumbering, off-diagonal CSR + diagonal, transfers
+// upload: colour-major renumbering, device-built level layouts, transfers
 // -------------------------------------------------------------------------
 void upload_transfers(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
                       const std::vector<int>& inv_next) {
@@ -296,63 +296,9 @@ void upload_transfers(vasmg_ctx& C, int l, bool need32, bool need64, const std::
   }
 }
 
-// Off-cell CSR (component-plane-major values) of the rows in device order.
-// cell_lo/cell_hi give each device row's cell range; blocks inside it are
-// handed to `in_cell` instead.
-template <class InCell>
-void build_offcell_csr(const Level& hl, const std::vector<int>& perm, const std::vector<int>& inv,
-                       const std::vector<int>& cell_lo, const std::vector<int>& cell_hi, int dd,
-                       std::vector<int>& rowptr, std::vector<int>& lo_end, std::vector<int>& up_beg,
-                       std::vector<int>& col, std::vector<double>& val, InCell in_cell) {
-  const int n = static_cast<int>(hl.n);
-  rowptr.assign(n + 1, 0);
-  lo_end.assign(n, 0);
-  up_beg.assign(n, 0);
-  for (int i = 0; i < n; ++i) {
-    const int c = perm[i];
-    int cnt = 0;
-    for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
-      const int j = inv[hl.A.col[p]];
-      if (j < cell_lo[i] || j >= cell_hi[i]) ++cnt;
-    }
-    rowptr[i + 1] = rowptr[i] + cnt;
-  }
-  const int64_t nnz = rowptr[n];
-  col.assign(nnz, 0);
-  val.assign(static_cast<size_t>(nnz) * dd, 0.0);
-  std::vector<std::pair<int, int64_t>> row;
-  for (int i = 0; i < n; ++i) {
-    const int c = perm[i];
-    row.clear();
-    for (int64_t p = hl.A.rowptr[c]; p < hl.A.rowptr[c + 1]; ++p) {
-      const int j = inv[hl.A.col[p]];
-      if (j < cell_lo[i] || j >= cell_hi[i])
-        row.emplace_back(j, p);
-      else
-        in_cell(i, j, hl.A.val.data() + p * dd);
-    }
-    std::sort(row.begin(), row.end());
-    int k = rowptr[i];
-    lo_end[i] = rowptr[i + 1];
-    up_beg[i] = rowptr[i + 1];
-    bool lo_set = false, up_set = false;
-    for (const auto& e : row) {
-      if (!lo_set && e.first >= cell_lo[i]) { lo_end[i] = k; lo_set = true; }
-      if (!up_set && e.first >= cell_hi[i]) { up_beg[i] = k; up_set = true; }
-      col[k] = e.first;
-      for (int t = 0; t < dd; ++t) val[static_cast<size_t>(t) * nnz + k] = hl.A.val[e.second * dd + t];
-      ++k;
-    }
-  }
-}
-
 void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
                          const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
                          const std::vector<int>& cell_ptr);
-void upload_level_host(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
-                       const std::vector<int>& inv, const std::vector<int>& cell_lo,
-                       const std::vector<int>& cell_hi, const std::vector<int>& cell_ptr);
-
 void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
   const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
@@ -411,11 +357,7 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
       cell_hi[i] = i + 1;
     }
   }
-  if (galerkin_device_has(C.gdev, l)) {
-    upload_level_device(C, l, need32, need64, inv, cell_lo, cell_hi, cell_ptr);
-  } else {
-    upload_level_host(C, l, need32, need64, perm, inv, cell_lo, cell_hi, cell_ptr);
-  }
+  upload_level_device(C, l, need32, need64, inv, cell_lo, cell_hi, cell_ptr);
   if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
   if (!coarsest && C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
     if (C.gdev) galerkin_device_join(C.gdev);   // the host values of the level
@@ -456,27 +398,57 @@ std::vector<int> padded_ptr(const std::vector<int>& cnt, bool cells) {
   return ptr;
 }
 
-// Device-built layout (setup_device = 1): the level's canonical operator is
-// resident from the device Galerkin products; only the renumbering, the cell
-// ranges and the row pointers travel.
+// Device memory that lives for one level's layout: stream-ordered on the upload
+// stream when there is one (a server slot's), else plain allocations.
+struct TempDev {
+  hipStream_t st = nullptr;
+  bool ordered = false;
+  std::vector<void*> p;
+  TempDev(hipStream_t s, bool o) : st(s), ordered(o) {}
+  TempDev(const TempDev&) = delete;
+  TempDev& operator=(const TempDev&) = delete;
+  ~TempDev() {
+    for (void* q : p) {
+      if (ordered)
+        (void)hipFreeAsync(q, st);
+      else
+        (void)hipFree(q);
+    }
+  }
+  template <class T>
+  T* up(const T* src, size_t n) {
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    HIP_CHECK(ordered ? hipMallocAsync(&q, bytes, st) : hipMalloc(&q, bytes));
+    p.push_back(q);
+    if (n) HIP_CHECK(hipMemcpyAsync(q, src, n * sizeof(T), hipMemcpyHostToDevice, st));
+    return static_cast<T*>(q);
+  }
+  template <class T>
+  T* up(const std::vector<T>& v) { return up(v.data(), v.size()); }
+};
+
+// Device layout of level l: built by the layout kernels from the level's
+// canonical FP64 operator, resident from the device Galerkin products
+// (setup_device = 1) or copied in from the host hierarchy for the layout only.
+// Only the renumbering, the cell ranges and the row pointers travel besides.
 void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
                          const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
                          const std::vector<int>& cell_ptr) {
+  const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
   const int d = C.d, dd = d * d, n = dl.n, NU = (1 << d) * d;
-  struct Temp {
-    std::vector<void*> p;
-    ~Temp() {
-      for (void* q : p) (void)hipFree(q);
-    }
-    int* up(const std::vector<int>& v) {
-      void* q = nullptr;
-      HIP_CHECK(hipMalloc(&q, std::max<size_t>(v.size(), 1) * sizeof(int)));
-      p.push_back(q);
-      if (!v.empty()) HIP_CHECK(hipMemcpy(q, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
-      return static_cast<int*>(q);
-    }
-  } tmp;
+  hipStream_t st = C.alloc_stream;
+  DevOperator A;
+  const bool resident = galerkin_device_operator(C.gdev, l, &A);
+  if (!st && resident) st = static_cast<hipStream_t>(galerkin_device_stream(C.gdev));
+  TempDev tmp(st, C.alloc_stream != nullptr);
+  if (!resident) {
+    A.n = hl.n;
+    A.ptr = tmp.up(hl.A.rowptr);
+    A.col = tmp.up(hl.A.col);
+    A.val = tmp.up(hl.A.val);
+  }
   LayoutArgs a;
   a.d = d;
   a.n = n;
@@ -493,15 +465,20 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
   std::vector<int> cntL(n, 0), cntU(n, 0);
   int* d_cntL = tmp.up(cntL);
   int* d_cntU = tmp.up(cntU);
-  layout_count(C.gdev, l, a, d_cntL, d_cntU);
-  HIP_CHECK(hipMemcpy(cntL.data(), d_cntL, n * sizeof(int), hipMemcpyDeviceToHost));
-  HIP_CHECK(hipMemcpy(cntU.data(), d_cntU, n * sizeof(int), hipMemcpyDeviceToHost));
+  layout_count(A, a, d_cntL, d_cntU, st);
+  HIP_CHECK(hipMemcpyAsync(cntL.data(), d_cntL, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(cntU.data(), d_cntU, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
   for (int i = 0; i < n; ++i) {
     dl.nnz_lo += cntL[i];
     dl.nnz_up += cntU[i];
   }
   dl.nnz = dl.nnz_lo + dl.nnz_up;
   set_lanes(dl);
+  // the L (earlier colours) and U (later colours) parts, each plane-major over its
+  // own blocks; on cell levels every row is padded to whole quads of 4 blocks
+  // (zero blocks pointing at the row itself), so a lane reads 4 consecutive
+  // blocks with one 16-byte load per plane
   const std::vector<int> Lptr = padded_ptr(cntL, dl.cells), Uptr = padded_ptr(cntU, dl.cells);
   const int64_t nL = Lptr[n], nU = Uptr[n];
   dl.Lstride = nL;
@@ -539,101 +516,7 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
   a.M32 = dl.cells ? dl.cellM32 : dl.diag32;
   a.M64 = dl.cells ? dl.cellM64 : dl.diag64;
   a.m_len = m_len;
-  layout_fill(C.gdev, l, a);
-}
-
-// Host-built layout: off-cell CSR in device order, split and padded, uploaded.
-void upload_level_host(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& perm,
-                       const std::vector<int>& inv, const std::vector<int>& cell_lo,
-                       const std::vector<int>& cell_hi, const std::vector<int>& cell_ptr) {
-  const Level& hl = C.H.levels[l];
-  DevLevel& dl = C.lev[l];
-  const int d = C.d, dd = d * d, n = static_cast<int>(hl.n);
-  std::vector<int> rowptr, lo_end, up_beg, col;
-  std::vector<double> val, diag, cellM;
-  if (dl.cells) {
-    const int NU = (1 << d) * d;
-    cellM.assign(static_cast<size_t>(dl.ncells) * NU * NU, 0.0);
-    std::vector<int> cell_of_row(n);
-    for (int c = 0; c < dl.ncells; ++c)
-      for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) cell_of_row[i] = c;
-    build_offcell_csr(hl, perm, inv, cell_lo, cell_hi, dd, rowptr, lo_end, up_beg, col, val,
-                      [&](int i, int j, const double* blk) {
-                        const int c = cell_of_row[i];
-                        const int ki = i - cell_ptr[c], kj = j - cell_ptr[c];
-                        double* M = cellM.data() + static_cast<size_t>(c) * NU * NU;
-                        for (int a = 0; a < d; ++a)
-                          for (int bb = 0; bb < d; ++bb)
-                            M[(kj * d + bb) * NU + (ki * d + a)] = blk[a * d + bb];
-                      });
-  } else {
-    diag.assign(static_cast<size_t>(n) * dd, 0.0);
-    build_offcell_csr(hl, perm, inv, cell_lo, cell_hi, dd, rowptr, lo_end, up_beg, col, val,
-                      [&](int i, int, const double* blk) {
-                        std::copy(blk, blk + dd, diag.begin() + static_cast<int64_t>(i) * dd);
-                      });
-  }
-  const int64_t nnz = rowptr[n];
-  dl.nnz = nnz;
-  std::vector<int> cntL(n), cntU(n);
-  for (int i = 0; i < n; ++i) {
-    cntL[i] = lo_end[i] - rowptr[i];
-    cntU[i] = rowptr[i + 1] - up_beg[i];
-    dl.nnz_lo += cntL[i];
-    dl.nnz_up += cntU[i];
-  }
-  set_lanes(dl);
-  // split the off-cell blocks into the L (earlier colours) and U (later colours)
-  // matrices, each plane-major over its own blocks. On cell levels every row is
-  // padded to whole quads of 4 blocks (zero blocks pointing at the row itself),
-  // so a lane reads 4 consecutive blocks with one 16-byte load per plane.
-  const std::vector<int> Lptr = padded_ptr(cntL, dl.cells), Uptr = padded_ptr(cntU, dl.cells);
-  const int64_t nL = Lptr[n], nU = Uptr[n];
-  dl.Lstride = nL;
-  dl.Ustride = nU;
-  std::vector<int> Lcol(nL), Ucol(nU);
-  for (int i = 0; i < n; ++i) {
-    for (int q = Lptr[i]; q < Lptr[i + 1]; ++q) Lcol[q] = i;
-    for (int q = Uptr[i]; q < Uptr[i + 1]; ++q) Ucol[q] = i;
-  }
-  std::vector<double> Lval(static_cast<size_t>(nL) * dd, 0.0), Uval(static_cast<size_t>(nU) * dd, 0.0);
-  for (int i = 0; i < n; ++i) {
-    for (int k = rowptr[i]; k < lo_end[i]; ++k) {
-      const int q = Lptr[i] + (k - rowptr[i]);
-      Lcol[q] = col[k];
-      for (int t = 0; t < dd; ++t) Lval[static_cast<size_t>(t) * nL + q] = val[static_cast<size_t>(t) * nnz + k];
-    }
-    for (int k = up_beg[i]; k < rowptr[i + 1]; ++k) {
-      const int q = Uptr[i] + (k - up_beg[i]);
-      Ucol[q] = col[k];
-      for (int t = 0; t < dd; ++t) Uval[static_cast<size_t>(t) * nU + q] = val[static_cast<size_t>(t) * nnz + k];
-    }
-  }
-  val.clear();
-  val.shrink_to_fit();
-  dl.Lptr = C.upload(Lptr);
-  dl.Lcol = C.upload(Lcol);
-  dl.Uptr = C.upload(Uptr);
-  dl.Ucol = C.upload(Ucol);
-  if (dl.cells) dl.cell_ptr = C.upload(cell_ptr);
-  if (need64) {
-    dl.Lval64 = C.upload(Lval);
-    dl.Uval64 = C.upload(Uval);
-    if (dl.cells)
-      dl.cellM64 = C.upload(cellM);
-    else
-      dl.diag64 = C.upload(diag);
-    dl.has64 = true;
-  }
-  if (need32) {
-    dl.Lval32 = C.upload(std::vector<float>(Lval.begin(), Lval.end()));
-    dl.Uval32 = C.upload(std::vector<float>(Uval.begin(), Uval.end()));
-    if (dl.cells)
-      dl.cellM32 = C.upload(std::vector<float>(cellM.begin(), cellM.end()));
-    else
-      dl.diag32 = C.upload(std::vector<float>(diag.begin(), diag.end()));
-    dl.has32 = true;
-  }
+  layout_fill(A, a, st);
 }
 
 // inverse permutation of level l's device numbering (canonical -> device)
@@ -1776,7 +1659,8 @@ void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
 }
 
 // Upper bound of the device bytes upload_device will allocate, from the host
-// hierarchy (every stored block counted as off-diagonal, 5% + 1 MiB margin).
+// hierarchy (every stored block counted as off-diagonal, the transient copy of
+// the largest level's canonical operator included, 5% + 1 MiB margin).
 int64_t estimate_device_bytes(const vasmg_ctx& C) {
   const Hierarchy& H = C.H;
   const int d = C.d, dd = d * d, DP = C.DP, NU = (1 << d) * d;
@@ -1802,6 +1686,14 @@ int64_t estimate_device_bytes(const vasmg_ctx& C) {
     }
     b += 4 * n * DP * tbv * (1 + K);
   }
+  // the largest level's canonical operator, copied in for its layout only, and the
+  // layout's per-row arrays
+  int64_t transient = 0;
+  for (int l = 0; l <= last; ++l) {
+    const Level& lv = H.levels[l];
+    transient = std::max(transient, lv.A.nnzb() * (4 + dd * 8) + (lv.n + 1) * 8 + 6 * lv.n * 4);
+  }
+  b += transient;
   const int64_t n0p = H.levels[0].n * DP;
   b += 6 * n0p * 8 + H.levels[0].n * 4 + H.n_coarse_dofs * H.n_coarse_dofs * 8;
   b += (std::max<int64_t>(kFlatGrid, H.levels[0].n / 4 + 1)) * 8 * (1 + K);
