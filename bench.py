@@ -165,7 +165,8 @@ def bench_cfg4(args, V, torch):
 def bench_serve(args, V):
     """The serving stream: requests i = 0..N-1 (2D or 3D jittered meshes, DOFs
     log-uniform in [1e3, 1e6], 1:100 materials), each a new mesh, so latency
-    includes the host setup. The single-stream rate is measured first by serving
+    includes its setup (Galerkin products on the device unless --host-setup). The
+    single-stream rate is measured first by serving
     the first 8 requests one at a time (one slot, one setup worker); then all N
     arrive as a Poisson stream at 0.7x that rate into a server with 4 slots and 4
     setup workers. Latency = done - arrival. The first 8 results must be
@@ -179,7 +180,7 @@ def bench_serve(args, V):
         if i % 8 == 7:
             log(f"generated {i + 1}/{N} requests ({time.perf_counter() - t0:.1f}s)")
     dofs = np.array([m.n_dofs for m in meshes])
-    opts = dict(precision=V.FP32_PRECOND)
+    opts = dict(precision=V.FP32_PRECOND, setup_device=0 if args.host_setup else 1)
 
     # single stream: one request at a time end to end
     srv = V.Server(slots=1, setup_workers=1, **opts)
@@ -244,7 +245,8 @@ def bench_serve(args, V):
                                "log-uniform in [1e3, 1e6] (seeded per request), Poisson arrivals "
                                "at 0.7x the single-stream rate, 4 slots, 4 setup workers",
                    "dofs_min": int(dofs.min()), "dofs_max": int(dofs.max()),
-                   "dofs_mean": float(dofs.mean())},
+                   "dofs_mean": float(dofs.mean()),
+                   "setup": "host" if args.host_setup else "Galerkin products on the device"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "single_stream_requests_per_s": rate1, "arrival_rate": lam,
         "saturated_requests_per_s": N / t_sat,
@@ -273,6 +275,9 @@ def main():
                          "16 load cases, block solve only; serve: the request stream through the "
                          "continuous-batching server")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--host-setup", action="store_true",
+                    help="serve: setup workers build the whole hierarchy on the host (default: "
+                         "their Galerkin products on the device)")
     ap.add_argument("--counters", action="store_true",
                     help="driver for rocprofv3 --pmc runs: a 256 MiB device copy (counter "
                          "calibration) followed by one replayed PCG iteration of the workload")

@@ -107,11 +107,15 @@ typedef struct {
                                   vertex-block Jacobi, Section 4's other S_h: omega =
                                   (4/3) / lambda_max(D^-1 A), estimated per level by 30
                                   power iterations at setup)                            */
-  int32_t setup_device;        /* 0 = whole setup on the host (default); 1 = the Galerkin
-                                  coarse operators A_{l+1} = P_l^T A_l P_l (Section 3,
-                                  equation (Ac)) are formed on the current HIP device:
-                                  same columns, values equal to rounding (another order
-                                  of the FP64 sums), deterministic. Needs host_only = 0 */
+  int32_t setup_device;        /* 0 = hierarchy built on the host (default); 1 = the
+                                  Galerkin coarse operators A_{l+1} = P_l^T A_l P_l
+                                  (Section 3, equation (Ac)) are formed on the current
+                                  HIP device: same columns, values equal to rounding
+                                  (another order of the FP64 sums), deterministic; the
+                                  level layouts are then built from the resident
+                                  operators. With host_only = 1 every value is brought
+                                  back and no device memory is kept (a server's setup
+                                  workers); EDEVICE without a device                     */
   int32_t reserved[2];
 } vasmg_options;
 
@@ -174,7 +178,9 @@ const char* vasmg_last_error(void);
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent solve requests (one mesh and
  * one load case each) on one GPU. A request is set up on the host by one of
- * setup_workers threads, admitted first in first out as soon as one of `slots`
+ * setup_workers threads (with options.setup_device = 1 its Galerkin products on
+ * the device, in transient memory outside the budget, ordered on the worker's
+ * own stream), admitted first in first out as soon as one of `slots`
  * device slots is free and its device bytes (vasmg_device_bytes) fit the HBM
  * budget next to the requests already resident, then uploaded, solved and
  * freed on the slot's own stream; requests overlap on the device. Every request

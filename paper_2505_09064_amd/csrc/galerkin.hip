@@ -216,10 +216,13 @@ __global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr 
   }
 }
 
+// Allocations and frees are ordered on the product stream: no device-wide
+// synchronisation, so a setup can run beside other threads' solves and graph
+// captures (a server's setup workers).
 template <typename T>
-T* dmalloc(size_t n, const char* what) {
+T* dmalloc(size_t n, hipStream_t st, const char* what) {
   void* p = nullptr;
-  check(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)), what);
+  check(hipMallocAsync(&p, std::max<size_t>(n, 1) * sizeof(T), st), what);
   return static_cast<T*>(p);
 }
 
@@ -229,10 +232,10 @@ struct DevCsr {
   int64_t* ptr = nullptr;
   int32_t* col = nullptr;
   double* val = nullptr;
-  void release() {
-    (void)hipFree(ptr);
-    (void)hipFree(col);
-    (void)hipFree(val);
+  void release(hipStream_t st) {
+    if (ptr) (void)hipFreeAsync(ptr, st);
+    if (col) (void)hipFreeAsync(col, st);
+    if (val) (void)hipFreeAsync(val, st);
     ptr = nullptr;
     col = nullptr;
     val = nullptr;
@@ -260,7 +263,8 @@ struct GalerkinDevice {
   }
   ~GalerkinDevice() {
     join();
-    for (auto& L : lev) L.release();
+    for (auto& L : lev) L.release(st);
+    if (st) (void)hipStreamSynchronize(st);
     if (st) (void)hipStreamDestroy(st);
     if (dl) (void)hipStreamDestroy(dl);
   }
@@ -272,9 +276,9 @@ void upload(DevCsr& D, int64_t nrows, const std::vector<int64_t>& ptr,
             const std::vector<int32_t>& col, const std::vector<double>& val, hipStream_t st) {
   D.nrows = nrows;
   D.nnz = static_cast<int64_t>(col.size());
-  D.ptr = dmalloc<int64_t>(ptr.size(), "rowptr");
-  D.col = dmalloc<int32_t>(col.size(), "columns");
-  D.val = dmalloc<double>(val.size(), "values");
+  D.ptr = dmalloc<int64_t>(ptr.size(), st, "rowptr");
+  D.col = dmalloc<int32_t>(col.size(), st, "columns");
+  D.val = dmalloc<double>(val.size(), st, "values");
   check(hipMemcpyAsync(D.ptr, ptr.data(), ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
   check(hipMemcpyAsync(D.col, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
   check(hipMemcpyAsync(D.val, val.data(), val.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy");
@@ -289,8 +293,8 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
   if (n > INT32_MAX || ncols > INT32_MAX) throw Error{VASMG_EINVAL, "level too large for int32 indices"};
   const int32_t n32 = static_cast<int32_t>(n);
   C.nrows = n;
-  C.ptr = dmalloc<int64_t>(n + 1, "rowptr");
-  int64_t* cnt = dmalloc<int64_t>(n, "row counts");
+  C.ptr = dmalloc<int64_t>(n + 1, st, "rowptr");
+  int64_t* cnt = dmalloc<int64_t>(n, st, "row counts");
   if (n > 0)
     hipLaunchKernelGGL(k_symbolic<false>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
                        G.window, cnt, nullptr, nullptr);
@@ -301,8 +305,8 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
   for (int64_t r = 0; r < n; ++r) h[r + 1] += h[r];
   C.nnz = h[n];
   check(hipMemcpyAsync(C.ptr, h.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
-  C.col = dmalloc<int32_t>(C.nnz, "columns");
-  C.val = dmalloc<double>(C.nnz * DD, "values");
+  C.col = dmalloc<int32_t>(C.nnz, st, "columns");
+  C.val = dmalloc<double>(C.nnz * DD, st, "values");
   if (n > 0) {
     hipLaunchKernelGGL(k_symbolic<true>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
                        G.window, nullptr, C.ptr, C.col);
@@ -312,7 +316,7 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
     check(hipGetLastError(), "numeric launch");
   }
   check(hipStreamSynchronize(st), "product");
-  (void)hipFree(cnt);
+  (void)hipFreeAsync(cnt, st);
 }
 
 // Copies the values of a resident product into Ac.val (allocated here, so the
@@ -381,15 +385,15 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     }
     check(hipStreamSynchronize(st), "download");
   } catch (...) {
-    dP.release();
-    dPT.release();
-    AP.release();
-    C.release();
+    dP.release(st);
+    dPT.release(st);
+    AP.release(st);
+    C.release(st);
     throw;
   }
-  dP.release();
-  dPT.release();
-  AP.release();
+  dP.release(st);
+  dPT.release(st);
+  AP.release(st);
   G.lev.push_back(C);
   G.cached = &Ac;
   if (!coarsest)

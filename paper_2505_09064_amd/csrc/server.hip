@@ -90,6 +90,7 @@ struct vasmg_server {
 
   void setup_loop(int host_threads) {
     vasmg::set_host_threads(host_threads);
+    if (cfg.options.setup_device) (void)hipSetDevice(device);   // device Galerkin products
     for (;;) {
       ReqPtr r;
       {

@@ -1812,8 +1812,6 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       throw vasmg::Error{VASMG_EINVAL, "block_rhs supports the Gauss-Seidel V-cycle only"};
     if (o.setup_device != 0 && o.setup_device != 1)
       throw vasmg::Error{VASMG_EINVAL, "setup_device must be 0 or 1"};
-    if (o.setup_device == 1 && o.host_only)
-      throw vasmg::Error{VASMG_EINVAL, "setup_device = 1 needs a device (host_only = 0)"};
     MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
                 mesh->E, mesh->nu, mesh->fixed};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
@@ -1825,6 +1823,10 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       prm.galerkin_ctx = gdev.get();
     }
     build_hierarchy(mv, prm, C->H);
+    if (gdev && o.host_only) {   // every value back on the host, no device memory kept
+      galerkin_device_join(gdev.get());
+      gdev.reset();
+    }
     C->d = mesh->dim;
     C->DP = mesh->dim == 3 ? 4 : 2;
     C->L = static_cast<int>(C->H.levels.size()) - 1;

@@ -56,6 +56,26 @@ def test_results_same_alone_and_in_the_mix(precision):
         assert 0 <= res["slot"] < 3 and res["device_bytes"] > 0
 
 
+def test_device_setup_workers():
+    """Setup workers that form the Galerkin products on the device (options
+    setup_device = 1, transient device memory ordered on each worker's stream)
+    while other requests solve and capture graphs: every result equals the same
+    request solved alone from a device setup, bit for bit, and takes the
+    iterations of a host setup."""
+    reqs = _requests()
+    srv = V.Server(slots=3, setup_workers=3, setup_device=1)
+    ids = [srv.submit(m, m.rhs[0], 1e-6) for m in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for m, (x, res) in zip(reqs, got):
+        assert res["status"] == V.OK, res
+        xa, ia = _alone(m, setup_device=1)
+        assert np.array_equal(x, xa), np.abs(x - xa).max()
+        _, ih = _alone(m)
+        assert res["info"]["iterations"] == ih["iterations"]
+        assert res["info"]["rel_res_true"] < 1e-6
+
+
 def test_budget_bounds_resident_bytes():
     reqs = _requests()
     # the estimate of each request, from a host-only handle

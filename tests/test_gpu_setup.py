@@ -191,12 +191,32 @@ def test_device_galerkin_solve_matches_host_setup(precision):
 
 def test_device_galerkin_rejected_configurations():
     m = small2d(9, seed=1)
-    for kw in (dict(setup_device=2), dict(setup_device=1, host_only=1)):
-        with pytest.raises(V.VasmgError) as ei:
-            V.Solver.from_mesh(m, **kw)
-        assert ei.value.status == V.EINVAL
+    with pytest.raises(V.VasmgError) as ei:
+        V.Solver.from_mesh(m, setup_device=2)
+    assert ei.value.status == V.EINVAL
     with pytest.raises(V.VasmgError):
         V.set_galerkin_window(-1)
+
+
+def test_device_galerkin_host_only_then_upload():
+    """setup_device = 1 with host_only = 1 (a server's setup workers): the products
+    are formed on the device and brought back whole; the host-only handle equals
+    the device-resident one bit for bit, and after vasmg_upload solves the same."""
+    m = small3d(9, seed=5)
+    sh = V.Solver.from_mesh(m, setup_device=1, host_only=1)
+    sd = V.Solver.from_mesh(m, setup_device=1)
+    for a, b in zip(_levels(sh), _levels(sd)):
+        for key in ("rowptr", "cols", "vals", "p_cols", "p_vals"):
+            assert np.array_equal(a[key], b[key]), key
+    V._check(V.lib().vasmg_upload(sh._h, None))
+    rng = np.random.default_rng(8)
+    F = rng.normal(size=(m.coords.shape[0], 3)) * (1 - m.fixed)
+    xh, ih = sh.solve(F, 1e-8)
+    xd, idv = sd.solve(F, 1e-8)
+    assert ih["iterations"] == idv["iterations"]
+    assert np.array_equal(xh, xd)
+    sh.free()
+    sd.free()
 
 
 def test_full_size_device_galerkin_matches_host():
