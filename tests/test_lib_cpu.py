@@ -159,3 +159,24 @@ def test_device_bytes_estimate_and_no_device_paths():
             V.Server(slots=1, setup_workers=1)
         assert ei.value.status == V.EDEVICE
     s.free()
+
+
+def test_setup_device_option_validation():
+    """setup_device takes 0 or 1 (EINVAL otherwise, checked before any device
+    call); without a device setup_device = 1 fails with EDEVICE, also host-only;
+    the Galerkin window hook rejects negative sizes and restores the default."""
+    import torch
+    m = small2d(9, seed=1)
+    with pytest.raises(V.VasmgError) as ei:
+        V.Solver.from_mesh(m, host_only=1, setup_device=3)
+    assert ei.value.status == V.EINVAL
+    assert V.default_options(3).setup_device == 0
+    if not torch.cuda.is_available():
+        for kw in (dict(setup_device=1), dict(setup_device=1, host_only=1)):
+            with pytest.raises(V.VasmgError) as ei:
+                V.Solver.from_mesh(m, **kw)
+            assert ei.value.status == V.EDEVICE
+    with pytest.raises(V.VasmgError) as ei:
+        V.set_galerkin_window(-5)
+    assert ei.value.status == V.EINVAL
+    V.set_galerkin_window(0)
