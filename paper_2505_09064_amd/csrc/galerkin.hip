@@ -253,6 +253,11 @@ struct GalerkinDevice {
   int window = gal::kMaxWindowCols;
   const BlockCSR* cached = nullptr;   // host operator of the last resident level
   std::vector<gal::DevCsr> lev;       // resident canonical operators, by level
+  struct Pending {
+    int level;
+    BlockCSR* host;
+  };
+  std::vector<Pending> pending;       // value downloads not started yet
   std::vector<std::thread> downloads;
   std::mutex mu;
   std::string dl_error;
@@ -262,7 +267,7 @@ struct GalerkinDevice {
     downloads.clear();
   }
   ~GalerkinDevice() {
-    join();
+    join();   // downloads not started by now are not needed
     for (auto& L : lev) L.release(st);
     if (st) (void)hipStreamSynchronize(st);
     if (st) (void)hipStreamDestroy(st);
@@ -319,15 +324,26 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
   (void)hipFreeAsync(cnt, st);
 }
 
-// Copies the values of a resident product into Ac.val (allocated here, so the
-// pages are touched by this thread). Runs on its own thread and stream.
-void download_values(GalerkinDevice* G, BlockCSR* Ac, const double* src, size_t count) {
+// Copies the values of resident level l into host->val (allocated here, so the
+// pages are touched by this thread); with free_after, then releases the level's
+// device copy (ordered on the download stream). Runs on its own thread.
+void download_values(GalerkinDevice* G, int l, BlockCSR* host, bool free_after) {
+  DevCsr L;
+  {
+    std::lock_guard<std::mutex> g(G->mu);
+    L = G->lev[l];
+  }
+  const size_t count = static_cast<size_t>(L.nnz) * host->d * host->d;
   hipError_t e = hipSetDevice(G->device);
   if (e == hipSuccess) {
-    Ac->val.resize(count);
-    e = hipMemcpyAsync(Ac->val.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, G->dl);
+    host->val.resize(count);
+    e = hipMemcpyAsync(host->val.data(), L.val, count * sizeof(double), hipMemcpyDeviceToHost, G->dl);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(G->dl);
+  if (e == hipSuccess && free_after) {
+    std::lock_guard<std::mutex> g(G->mu);
+    G->lev[l].release(G->dl);
+  }
   if (e != hipSuccess) {
     std::lock_guard<std::mutex> g(G->mu);
     G->dl_error = std::string("device Galerkin product: value download: ") + hipGetErrorString(e);
@@ -396,8 +412,7 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
   AP.release(st);
   G.lev.push_back(C);
   G.cached = &Ac;
-  if (!coarsest)
-    G.downloads.emplace_back(download_values, &G, &Ac, C.val, static_cast<size_t>(C.nnz * DD));
+  if (!coarsest) G.pending.push_back({static_cast<int>(G.lev.size()) - 1, &Ac});
 }
 
 // ---------------------------------------------------------------------------
@@ -534,7 +549,14 @@ void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR&
     gal::galerkin_d<3>(G, A, P, Ac, coarsest);
 }
 
+void galerkin_device_start_downloads(GalerkinDevice* G, bool free_after) {
+  for (const auto& p : G->pending)
+    G->downloads.emplace_back(gal::download_values, G, p.level, p.host, free_after);
+  G->pending.clear();
+}
+
 void galerkin_device_join(GalerkinDevice* G) {
+  galerkin_device_start_downloads(G, false);
   G->join();
   std::lock_guard<std::mutex> g(G->mu);
   if (!G->dl_error.empty()) throw Error{VASMG_EDEVICE, G->dl_error};

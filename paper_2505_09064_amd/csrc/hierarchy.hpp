@@ -92,7 +92,7 @@ struct SetupParams {
 // Device setup (galerkin.hip): a context with its own stream that keeps every
 // level's canonical FP64 operator resident (level 0 uploaded, the others the
 // products), hands the host each product's structure at once and its values
-// from a background download, and builds the device layout of a level from the
+// from background downloads, and builds the device layout of a level from the
 // resident operator. window_cols > 0 caps the columns per symbolic pass of the
 // product (0 = the LDS maximum).
 struct GalerkinDevice;
@@ -100,7 +100,12 @@ GalerkinDevice* galerkin_device_create(int window_cols);
 void galerkin_device_destroy(GalerkinDevice* g);   // joins the downloads
 void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
                      bool coarsest);
-// Waits for the background value downloads; throws their error, if any.
+// Starts the background downloads of the products' values into the host
+// hierarchy (levels other than the coarsest, whose values arrive at once);
+// free_after: each level's device copy is released once its values are home.
+void galerkin_device_start_downloads(GalerkinDevice* g, bool free_after);
+// Starts any download not started yet (keeping the device copies) and waits for
+// all of them; throws their error, if any.
 void galerkin_device_join(GalerkinDevice* g);
 
 // A level's canonical FP64 operator on the device (block CSR: int64 row

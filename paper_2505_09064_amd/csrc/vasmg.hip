@@ -181,6 +181,7 @@ struct vasmg_ctx {
   Scalars* kh_sc = nullptr;            // pinned host copy [K]
   hipGraphExec_t kgA = nullptr, kgB = nullptr;
   GalerkinDevice* gdev = nullptr;     // setup_device = 1, during the upload only
+  GalerkinDevice* gdev_bg = nullptr;  // owned: value downloads still running after setup
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -226,7 +227,16 @@ struct vasmg_ctx {
     if (!v.empty()) copy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
     return p;
   }
+  // Waits for the background downloads of the level values into H, if any.
+  void settle_host_values() {
+    if (!gdev_bg) return;
+    GalerkinDevice* g = gdev_bg;
+    gdev_bg = nullptr;
+    std::unique_ptr<GalerkinDevice, void (*)(GalerkinDevice*)> own(g, galerkin_device_destroy);
+    galerkin_device_join(g);
+  }
   ~vasmg_ctx() {
+    if (gdev_bg) galerkin_device_destroy(gdev_bg);   // joins the downloads writing into H
     if (gA) (void)hipGraphExecDestroy(gA);
     if (gB) (void)hipGraphExecDestroy(gB);
     if (kgA) (void)hipGraphExecDestroy(kgA);
@@ -1845,9 +1855,16 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       const auto t0 = std::chrono::steady_clock::now();
       C->gdev = gdev.get();
       upload_device(*C, nullptr);
-      if (gdev) galerkin_device_join(gdev.get());   // host copies of the level values
       C->gdev = nullptr;
-      gdev.reset();
+      if (gdev && o.smoother == VASMG_SMOOTHER_JACOBI) {
+        galerkin_device_join(gdev.get());   // already started by the Jacobi set-up
+        gdev.reset();
+      } else if (gdev) {
+        // the host copies of the level values arrive while the caller goes on;
+        // each level's device copy is released once its values are home
+        galerkin_device_start_downloads(gdev.get(), true);
+        C->gdev_bg = gdev.release();
+      }
       if (o.verbose)
         std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", "upload+autotune",
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -1995,6 +2012,11 @@ vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, in
   if (!h || level < 0 || level >= static_cast<int32_t>(h->H.levels.size())) {
     g_last_error = "null handle or level out of range";
     return VASMG_EINVAL;
+  }
+  try {
+    h->settle_host_values();
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
   }
   const Level& lv = h->H.levels[level];
   const int d = h->d;

@@ -280,3 +280,23 @@ def test_full_size_graded_2d_device_setup():
     assert abs(info["iterations"] - g["fp64"]["iterations"]) <= 1
     assert np.abs(x[idx] - np.array(g["sample_x"])).max() <= 1e-8 * g["x_norminf"]
     sd.free()
+
+
+def test_device_setup_background_downloads():
+    """After a device setup the FP64 level values reach the host in the
+    background: a handle freed at once (downloads in flight) releases cleanly, a
+    solve runs while they arrive, and an export waits for them and returns the
+    values of a second, settled handle bit for bit."""
+    m = small3d(11, seed=7)
+    for _ in range(3):
+        V.Solver.from_mesh(m, setup_device=1).free()
+    a = V.Solver.from_mesh(m, setup_device=1)
+    x, info = a.solve(m.rhs[0], 1e-8)
+    assert info["converged"] == 1
+    b = V.Solver.from_mesh(m, setup_device=1)
+    la = _levels(a)
+    lb = _levels(b)
+    for ea, eb in zip(la, lb):
+        assert np.array_equal(ea["vals"], eb["vals"])
+    a.free()
+    b.free()
