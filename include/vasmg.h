@@ -113,9 +113,13 @@ typedef struct {
                                   HIP device: same columns, values equal to rounding
                                   (another order of the FP64 sums), deterministic; the
                                   level layouts are then built from the resident
-                                  operators. With host_only = 1 every value is brought
-                                  back and no device memory is kept (a server's setup
-                                  workers); EDEVICE without a device                     */
+                                  operators, and the host copies of the FP64 level
+                                  values arrive in the background after vasmg_setup
+                                  returns (vasmg_export_level and vasmg_free wait for
+                                  them). With host_only = 1 every value is brought
+                                  back before vasmg_setup returns and no device memory
+                                  is kept (a server's setup workers); EDEVICE without a
+                                  device                                                  */
   int32_t reserved[2];
 } vasmg_options;
 
@@ -265,7 +269,9 @@ vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices
  *          cell in canonical order, then components (Algorithm 1 in that order).
  *   rowptr [n_vertices+1] int64, cols [n_blocks] int32, vals [n_blocks][dim][dim] FP64
  *   p_rowptr [n_vertices+1] int64, p_cols [p_nnz] int32, p_vals [p_nnz] FP64
- *     (scalar prolongation P_level from this level's vertices to the next's). */
+ *     (scalar prolongation P_level from this level's vertices to the next's).
+ * On a handle set up with setup_device = 1 it first waits for the background
+ * download of the level values (EDEVICE if that failed). */
 vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* cell,
                                 int32_t* color, int64_t* rowptr, int32_t* cols, double* vals,
                                 int64_t* p_rowptr, int32_t* p_cols, double* p_vals);

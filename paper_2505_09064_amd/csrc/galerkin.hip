@@ -30,6 +30,7 @@
 #include <climits>
 #include <cstdint>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -336,7 +337,13 @@ void download_values(GalerkinDevice* G, int l, BlockCSR* host, bool free_after) 
   const size_t count = static_cast<size_t>(L.nnz) * host->d * host->d;
   hipError_t e = hipSetDevice(G->device);
   if (e == hipSuccess) {
-    host->val.resize(count);
+    try {
+      host->val.resize(count);
+    } catch (const std::bad_alloc&) {
+      std::lock_guard<std::mutex> g(G->mu);
+      G->dl_error = "device Galerkin product: host allocation of the level values failed";
+      return;
+    }
     e = hipMemcpyAsync(host->val.data(), L.val, count * sizeof(double), hipMemcpyDeviceToHost, G->dl);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(G->dl);
