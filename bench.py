@@ -406,9 +406,11 @@ def main():
     log(f"dominant phase: {dom['name']} level {dom['level']}: "
         f"{dom['launches'] / reps:.0f} launches/iteration, {dom_launch_ms * 1e3:.2f} us and "
         f"{dom_launch_bytes / 1e6:.2f} MB per launch -> {achieved:.0f} GB/s")
-    for p in sorted(phases, key=lambda p: -p["ms"])[:8]:
-        log(f"  {p['name']:13s} L{p['level']:2d} {p['ms'] / reps:7.3f} ms/it "
-            f"{p['bytes'] / p['ms'] / 1e6:6.0f} GB/s")
+    log("phases of one iteration (event-timed launches):")
+    for p in sorted(phases, key=lambda p: -p["ms"]):
+        log(f"  {p['name']:13s} L{p['level']:2d} {p['launches'] / reps:4.0f} launches "
+            f"{p['ms'] / reps:7.4f} ms/it {1e3 * p['ms'] / max(p['launches'], 1):7.2f} us/launch "
+            f"{p['bytes'] / p['ms'] / 1e6:6.0f} GB/s {100 * p['ms'] / reps / it_ms:5.1f}%")
     mixed.free()
 
     cpu = None
