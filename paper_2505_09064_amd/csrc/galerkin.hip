@@ -531,6 +531,191 @@ __global__ __launch_bounds__(kThreads) void k_layout_fill(Csr A, LayoutArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// fine-level assembly (Section 2: the P1 element stiffness of linear
+// elasticity, summed element by element). This file is built without
+// floating-point contraction, and the arithmetic below follows the host
+// assembly operation by operation, so the values agree bit for bit.
+// ---------------------------------------------------------------------------
+struct MeshDev {
+  int d = 0, nvpe = 0;
+  const double* coords = nullptr;    // [nv][d]
+  const int32_t* elems = nullptr;    // [ne][d+1]
+  const double* E = nullptr;         // [ne]
+  const double* nu = nullptr;        // [ne]
+  const int32_t* vfree = nullptr;    // mesh vertex -> free index or -1
+  const int32_t* fine2mesh = nullptr;
+  const int64_t* vptr = nullptr;     // vertex -> elements (ascending)
+  const int32_t* velem = nullptr;
+};
+
+constexpr int kAsmStage = 512;   // element corners of one row staged in LDS
+
+// Free index of corner c of row i's element list (c = element slot * (d+1) + corner).
+__device__ __forceinline__ int asm_corner(const MeshDev& M, int64_t kb, int c) {
+  const int e = M.velem[kb + c / M.nvpe];
+  return M.vfree[M.elems[static_cast<int64_t>(e) * M.nvpe + c % M.nvpe]];
+}
+
+// Distinct free vertices sharing an element with row i's vertex (itself
+// included): counted (FILL = false) or written ascending (FILL = true). One
+// wavefront per row; a corner counts if no earlier corner names the same vertex.
+template <bool FILL>
+__global__ __launch_bounds__(kThreads) void k_asm_pattern(int n, MeshDev M, int64_t* __restrict__ cnt,
+                                                          const int64_t* __restrict__ rowptr,
+                                                          int32_t* __restrict__ col) {
+  __shared__ int sc[kWaves][kAsmStage];   // corners
+  __shared__ int sf[kWaves][kAsmStage];   // the vertex at its first occurrence, else -1
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kWaves + w;
+  const bool valid = i < n;
+  const int v = valid ? M.fine2mesh[i] : 0;
+  const int64_t kb = valid ? M.vptr[v] : 0, ke = valid ? M.vptr[v + 1] : 0;
+  const int T = static_cast<int>(ke - kb) * M.nvpe;
+  const bool staged = T <= kAsmStage;
+  auto corner = [&](int c) { return staged ? sc[w][c] : asm_corner(M, kb, c); };
+  auto first = [&](int c) {   // vertex of corner c if it is its first occurrence, else -1
+    const int f = corner(c);
+    if (f < 0) return -1;
+    for (int c2 = 0; c2 < c; ++c2)
+      if (corner(c2) == f) return -1;
+    return f;
+  };
+  if (staged)
+    for (int c = lane; c < T; c += 64) sc[w][c] = asm_corner(M, kb, c);
+  __syncthreads();
+  if (staged)
+    for (int c = lane; c < T; c += 64) sf[w][c] = first(c);
+  __syncthreads();
+  if (!valid) return;
+  auto first_of = [&](int c) { return staged ? sf[w][c] : first(c); };
+  int count = 0;
+  for (int c = lane; c < T; c += 64) {
+    const int f = first_of(c);
+    if (f < 0) continue;
+    ++count;
+    if (FILL) {
+      int rank = 0;
+      for (int c2 = 0; c2 < T; ++c2) {
+        const int g = first_of(c2);
+        rank += g >= 0 && g < f;
+      }
+      col[rowptr[i] + rank] = f;
+    }
+  }
+  if (!FILL) {
+    for (int o = 32; o > 0; o >>= 1) count += __shfl_xor(count, o, 64);
+    if (lane == 0) cnt[i] = count;
+  }
+}
+
+// Gradients of the barycentric functions of one element and the signed
+// determinant of its edge matrix X (rows x_a - x_0): grad lambda_a = row a of
+// X^{-T}, grad lambda_0 = -(sum of the others); inverse by cofactors.
+template <int D>
+__device__ __forceinline__ double asm_grads(const double* const* xs, double G[4][3]) {
+  double X[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int a = 0; a < D; ++a)
+    for (int k = 0; k < D; ++k) X[a][k] = xs[a + 1][k] - xs[0][k];
+  double det, inv[3][3];
+  if (D == 2) {
+    det = X[0][0] * X[1][1] - X[0][1] * X[1][0];
+    inv[0][0] = X[1][1] / det;
+    inv[0][1] = -X[0][1] / det;
+    inv[1][0] = -X[1][0] / det;
+    inv[1][1] = X[0][0] / det;
+  } else {
+    const double c00 = X[1][1] * X[2][2] - X[1][2] * X[2][1];
+    const double c01 = X[1][2] * X[2][0] - X[1][0] * X[2][2];
+    const double c02 = X[1][0] * X[2][1] - X[1][1] * X[2][0];
+    det = X[0][0] * c00 + X[0][1] * c01 + X[0][2] * c02;
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (X[0][2] * X[2][1] - X[0][1] * X[2][2]) / det;
+    inv[1][1] = (X[0][0] * X[2][2] - X[0][2] * X[2][0]) / det;
+    inv[2][1] = (X[0][1] * X[2][0] - X[0][0] * X[2][1]) / det;
+    inv[0][2] = (X[0][1] * X[1][2] - X[0][2] * X[1][1]) / det;
+    inv[1][2] = (X[0][2] * X[1][0] - X[0][0] * X[1][2]) / det;
+    inv[2][2] = (X[0][0] * X[1][1] - X[0][1] * X[1][0]) / det;
+  }
+  for (int a = 0; a < D; ++a)
+    for (int k = 0; k < D; ++k) G[a + 1][k] = inv[k][a];
+  for (int k = 0; k < D; ++k) {
+    double s = 0.0;
+    for (int a = 1; a <= D; ++a) s += G[a][k];
+    G[0][k] = -s;
+  }
+  return det;
+}
+
+// Values of row i: lane q owns block (i, col q) and adds, element by element in
+// ascending order, vol (mu (grad_a . grad_b) delta_ij + mu d_j phi_a d_i phi_b +
+// lambda d_i phi_a d_j phi_b) for the element's corner b at that column.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_asm_values(int n, MeshDev M,
+                                                         const int64_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         double* __restrict__ val) {
+  constexpr int DD = D * D, NV = D + 1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * kWaves + w;
+  if (i >= n) return;
+  const int v = M.fine2mesh[i];
+  const int64_t kb = M.vptr[v], ke = M.vptr[v + 1];
+  const int64_t rb = rowptr[i], re = rowptr[i + 1];
+  for (int64_t q = rb + lane; q < re; q += 64) {
+    const int j = col[q];
+    double acc[DD];
+    for (int t = 0; t < DD; ++t) acc[t] = 0.0;
+    for (int64_t k = kb; k < ke; ++k) {
+      const int e = M.velem[k];
+      const int32_t* ev = M.elems + static_cast<int64_t>(e) * NV;
+      int hit = -1, la = 0;
+      for (int a = 0; a < NV; ++a) {
+        if (ev[a] == v) la = a;
+        if (M.vfree[ev[a]] == j) hit = a;
+      }
+      if (hit < 0) continue;
+      const double* xs[4];
+      for (int a = 0; a < NV; ++a) xs[a] = M.coords + static_cast<int64_t>(ev[a]) * D;
+      double G[4][3];
+      const double det = asm_grads<D>(xs, G);
+      const double vol = fabs(det) / (D == 2 ? 2.0 : 6.0);
+      const double E = M.E[e], nu = M.nu[e];
+      const double mu = E / (2.0 * (1.0 + nu));
+      const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+      const int b = hit;
+      double gab = 0.0;
+      for (int k2 = 0; k2 < D; ++k2) gab += G[la][k2] * G[b][k2];
+      for (int ci = 0; ci < D; ++ci)
+        for (int cj = 0; cj < D; ++cj) {
+          double t = mu * G[la][cj] * G[b][ci] + lam * G[la][ci] * G[b][cj];
+          if (ci == cj) t += mu * gab;
+          acc[ci * D + cj] += vol * t;
+        }
+    }
+    for (int t = 0; t < DD; ++t) val[q * DD + t] = acc[t];
+  }
+}
+
+template <typename T>
+const T* upload_temp(const std::vector<T>& v, hipStream_t st, std::vector<void*>& owned) {
+  T* p = dmalloc<T>(v.size(), st, "mesh");
+  owned.push_back(p);
+  if (!v.empty())
+    check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st), "copy");
+  return p;
+}
+
+template <typename T>
+const T* upload_temp(const T* v, size_t count, hipStream_t st, std::vector<void*>& owned) {
+  T* p = dmalloc<T>(count, st, "mesh");
+  owned.push_back(p);
+  if (count) check(hipMemcpyAsync(p, v, count * sizeof(T), hipMemcpyHostToDevice, st), "copy");
+  return p;
+}
+
 }  // namespace gal
 
 GalerkinDevice* galerkin_device_create(int window_cols) {
@@ -555,6 +740,90 @@ void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR&
   else
     gal::galerkin_d<3>(G, A, P, Ac, coarsest);
 }
+
+void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& vfree,
+                     int64_t nfree, BlockCSR& A) {
+  auto& G = *static_cast<GalerkinDevice*>(ctx);
+  if (!G.lev.empty()) throw Error{VASMG_EINVAL, "internal: device assembly after other levels"};
+  if (nfree > INT32_MAX || m.ne > INT32_MAX)
+    throw Error{VASMG_EINVAL, "mesh too large for int32 indexing"};
+  hipStream_t st = G.st;
+  const int d = m.d, nvpe = d + 1, dd = d * d;
+  const int n = static_cast<int>(nfree);
+  std::vector<int64_t> vptr, velem64;
+  vertex_elements(m, vptr, velem64);
+  std::vector<int32_t> velem(velem64.begin(), velem64.end());
+  std::vector<int32_t> f2m(nfree);
+  for (int64_t v = 0; v < m.nv; ++v)
+    if (vfree[v] >= 0) f2m[vfree[v]] = static_cast<int32_t>(v);
+  std::vector<void*> owned;
+  gal::DevCsr A0;
+  auto release_temps = [&] {
+    for (void* p : owned) (void)hipFreeAsync(p, st);
+    owned.clear();
+  };
+  try {
+    gal::MeshDev M;
+    M.d = d;
+    M.nvpe = nvpe;
+    M.coords = gal::upload_temp(m.coords, static_cast<size_t>(m.nv) * d, st, owned);
+    M.elems = gal::upload_temp(m.elems, static_cast<size_t>(m.ne) * nvpe, st, owned);
+    M.E = gal::upload_temp(m.E, static_cast<size_t>(m.ne), st, owned);
+    M.nu = gal::upload_temp(m.nu, static_cast<size_t>(m.ne), st, owned);
+    M.vfree = gal::upload_temp(vfree, st, owned);
+    M.fine2mesh = gal::upload_temp(f2m, st, owned);
+    M.vptr = gal::upload_temp(vptr, st, owned);
+    M.velem = gal::upload_temp(velem, st, owned);
+    const int grid = (n + gal::kWaves - 1) / gal::kWaves;
+    int64_t* cnt = gal::dmalloc<int64_t>(n, st, "row counts");
+    owned.push_back(cnt);
+    if (n > 0)
+      hipLaunchKernelGGL(gal::k_asm_pattern<false>, dim3(grid), dim3(gal::kThreads), 0, st, n, M,
+                         cnt, nullptr, nullptr);
+    gal::check(hipGetLastError(), "assembly pattern launch");
+    A.n = nfree;
+    A.d = d;
+    A.rowptr.assign(nfree + 1, 0);
+    gal::check(hipMemcpyAsync(A.rowptr.data() + 1, cnt, n * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+               "copy");
+    gal::check(hipStreamSynchronize(st), "assembly pattern");
+    for (int64_t r = 0; r < nfree; ++r) A.rowptr[r + 1] += A.rowptr[r];
+    const int64_t nnz = A.rowptr[nfree];
+    A0.nrows = nfree;
+    A0.nnz = nnz;
+    A0.ptr = gal::dmalloc<int64_t>(nfree + 1, st, "rowptr");
+    A0.col = gal::dmalloc<int32_t>(nnz, st, "columns");
+    A0.val = gal::dmalloc<double>(nnz * dd, st, "values");
+    gal::check(hipMemcpyAsync(A0.ptr, A.rowptr.data(), (nfree + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st), "copy");
+    if (n > 0) {
+      hipLaunchKernelGGL(gal::k_asm_pattern<true>, dim3(grid), dim3(gal::kThreads), 0, st, n, M,
+                         nullptr, A0.ptr, A0.col);
+      gal::check(hipGetLastError(), "assembly columns launch");
+      if (d == 2)
+        hipLaunchKernelGGL(gal::k_asm_values<2>, dim3(grid), dim3(gal::kThreads), 0, st, n, M, A0.ptr,
+                           A0.col, A0.val);
+      else
+        hipLaunchKernelGGL(gal::k_asm_values<3>, dim3(grid), dim3(gal::kThreads), 0, st, n, M, A0.ptr,
+                           A0.col, A0.val);
+      gal::check(hipGetLastError(), "assembly values launch");
+    }
+    A.col.resize(nnz);
+    gal::check(hipMemcpyAsync(A.col.data(), A0.col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+               "copy");
+    gal::check(hipStreamSynchronize(st), "assembly");
+  } catch (...) {
+    release_temps();
+    A0.release(st);
+    throw;
+  }
+  release_temps();
+  G.lev.push_back(A0);
+  G.cached = &A;
+  G.pending.push_back({0, &A});
+}
+
+void galerkin_device_settle(void* ctx) { galerkin_device_join(static_cast<GalerkinDevice*>(ctx)); }
 
 void galerkin_device_start_downloads(GalerkinDevice* G, bool free_after) {
   for (const auto& p : G->pending)

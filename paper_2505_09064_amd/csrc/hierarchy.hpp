@@ -81,13 +81,25 @@ struct MeshView {
 using GalerkinFn = void (*)(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
                             bool coarsest);
 
+// Fine-level assembly of A (free vertices in ascending mesh order, vfree: mesh
+// vertex -> free index or -1); the structure must be on the host on return.
+using AssembleFn = void (*)(void* ctx, const MeshView& m, const std::vector<int32_t>& vfree,
+                            int64_t nfree, BlockCSR& A);
+// Brings every level's values to the host (values produced elsewhere).
+using SettleFn = void (*)(void* ctx);
+
 struct SetupParams {
   int capacity;                // leaf capacity (> 0)
   bool tree_free_only;         // tree over free vertices only
   int64_t coarsest_max_dofs;   // 0 = root level
   GalerkinFn galerkin = nullptr;   // null: the host product (OpenMP)
-  void* galerkin_ctx = nullptr;
+  AssembleFn assemble = nullptr;   // null: the host assembly (OpenMP)
+  SettleFn settle = nullptr;
+  void* galerkin_ctx = nullptr;    // context of the three callbacks
 };
+
+// Vertex -> element lists (elements ascending per vertex).
+void vertex_elements(const MeshView& m, std::vector<int64_t>& vptr, std::vector<int64_t>& velem);
 
 // Device setup (galerkin.hip): a context with its own stream that keeps every
 // level's canonical FP64 operator resident (level 0 uploaded, the others the
@@ -100,6 +112,13 @@ GalerkinDevice* galerkin_device_create(int window_cols);
 void galerkin_device_destroy(GalerkinDevice* g);   // joins the downloads
 void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac,
                      bool coarsest);
+// Fine-level assembly on the device (the same element order and arithmetic as
+// the host assembly, so the same values bit for bit): the structure comes back
+// at once, the values stay resident as level 0 and download in the background.
+void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& vfree,
+                     int64_t nfree, BlockCSR& A);
+// SettleFn: joins every download.
+void galerkin_device_settle(void* ctx);
 // Starts the background downloads of the products' values into the host
 // hierarchy (levels other than the coarsest, whose values arrive at once);
 // free_after: each level's device copy is released once its values are home.

@@ -145,20 +145,27 @@ double p1_grads(int d, const double* xs[4], double G[4][3]) {
 // --------------------------------------------------------------------------
 // fine-level assembly
 // --------------------------------------------------------------------------
-void assemble_fine(const MeshView& m, const std::vector<int32_t>& vfree, int64_t nfree,
-                   BlockCSR& A) {
-  const int d = m.d, nvpe = d + 1, dd = d * d;
-  // vertex -> elements
-  std::vector<int64_t> vptr(m.nv + 1, 0);
+}  // namespace
+
+void vertex_elements(const MeshView& m, std::vector<int64_t>& vptr, std::vector<int64_t>& velem) {
+  const int nvpe = m.d + 1;
+  vptr.assign(m.nv + 1, 0);
   for (int64_t e = 0; e < m.ne; ++e)
     for (int a = 0; a < nvpe; ++a) vptr[m.elems[e * nvpe + a] + 1]++;
   for (int64_t v = 0; v < m.nv; ++v) vptr[v + 1] += vptr[v];
-  std::vector<int64_t> velem(vptr[m.nv]);
-  {
-    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
-    for (int64_t e = 0; e < m.ne; ++e)
-      for (int a = 0; a < nvpe; ++a) velem[fill[m.elems[e * nvpe + a]]++] = e;
-  }
+  velem.assign(vptr[m.nv], 0);
+  std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+  for (int64_t e = 0; e < m.ne; ++e)
+    for (int a = 0; a < nvpe; ++a) velem[fill[m.elems[e * nvpe + a]]++] = e;
+}
+
+namespace {
+
+void assemble_fine(const MeshView& m, const std::vector<int32_t>& vfree, int64_t nfree,
+                   BlockCSR& A) {
+  const int d = m.d, nvpe = d + 1, dd = d * d;
+  std::vector<int64_t> vptr, velem;
+  vertex_elements(m, vptr, velem);
   std::vector<int32_t> fine2mesh(nfree);
   for (int64_t v = 0; v < m.nv; ++v)
     if (vfree[v] >= 0) fine2mesh[vfree[v]] = static_cast<int32_t>(v);
@@ -667,11 +674,17 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   }
   if (bad < m.ne) fail(1, "element " + std::to_string(bad) + " is inverted or degenerate");
 
+  // Levels never move once created (callbacks keep pointers to their operators):
+  // one level per tree depth at most, plus the fine level.
+  H.levels.reserve(kMaxDepth + 2);
   H.levels.emplace_back();
   {
     Level& L0 = H.levels.back();
     L0.n = nfree;
-    assemble_fine(m, vfree, nfree, L0.A);
+    if (prm.assemble)
+      prm.assemble(prm.galerkin_ctx, m, vfree, nfree, L0.A);
+    else
+      assemble_fine(m, vfree, nfree, L0.A);
   }
   mark("validate+assemble");
 
@@ -736,6 +749,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
 
   // ---- Section 3.1.2: merge the deepest regions until only the root is left
   while (true) {
+    if (H.levels.size() == H.levels.capacity()) fail(1, "internal error: too many levels");
     H.levels.emplace_back();
     Level& lv = H.levels.back();
     lv.n = static_cast<int64_t>(cur_keys.size());
@@ -842,6 +856,8 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   coarsest.ncolors = 0;
   for (size_t l = 0; l + 1 < H.levels.size(); ++l) build_gs_order(H.levels[l], l > 0, d);
   mark("cells+colours");
+  if (prm.settle && coarsest.A.val.size() != coarsest.A.col.size() * static_cast<size_t>(d * d))
+    prm.settle(prm.galerkin_ctx);   // a fine level that is also the coarsest: its values now
   dense_cholesky(coarsest.A, H.chol, H.n_coarse_dofs);
   mark("coarsest factor");
 }

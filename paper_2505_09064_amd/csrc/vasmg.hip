@@ -1830,6 +1830,8 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device for setup_device = 1"};
       gdev.reset(galerkin_device_create(g_galerkin_window.load()));
       prm.galerkin = galerkin_device;
+      prm.assemble = assemble_device;
+      prm.settle = galerkin_device_settle;
       prm.galerkin_ctx = gdev.get();
     }
     build_hierarchy(mv, prm, C->H);

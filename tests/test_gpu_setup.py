@@ -1,10 +1,10 @@
-"""GPU tests of the device Galerkin products (setup_device = 1): the coarse
-operators A_{l+1} = P_l^T A_l P_l of Section 3 formed on the device.
+"""GPU tests of the device setup (setup_device = 1): the fine assembly and the
+coarse operators A_{l+1} = P_l^T A_l P_l of Section 3 formed on the device.
 
 Parity bars: against the oracle's hierarchy the same as the host setup's (the
 column structure identical, values within 1e-13 of the largest entry of the
 level); against the host setup, identical integer structure (columns, cells,
-colours, keys, P) and values to rounding; between device setups, bitwise
+colours, keys, P), the fine level bit for bit and the coarse values to rounding; between device setups, bitwise
 equality (the numeric pass sums in a fixed order, independent of the launch and
 of the bitmap window). Solves from a device-built hierarchy take the iteration
 counts of the host-built one.
@@ -80,7 +80,7 @@ def test_device_galerkin_matches_oracle_and_host(name):
         S = sp.csr_matrix((np.ones(ed["cols"].size), ed["cols"], ed["rowptr"]),
                           shape=(ed["n_vertices"],) * 2)
         assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs from the oracle"
-    # the fine level is assembled on the host either way
+    # the device assembly follows the host's arithmetic: the same fine values bit for bit
     assert np.array_equal(Ld[0]["vals"], Lh[0]["vals"])
     sd.free()
     sh.free()
