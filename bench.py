@@ -107,6 +107,48 @@ def bench_block16(args, V, torch):
         "max_rel_res_true": float(max(i["rel_res_true"] for i in ib))}), flush=True)
 
 
+def bench_cfg3(args, V, torch):
+    """The 2D nearly incompressible graded workload: 1025^2 vertices with the map
+    x -> x^2, y -> y^2, nu = 0.49, E in {1, 100} on a random 8x8 checkerboard
+    (seed 2), 2,093,058 DOFs. FP32 V-cycle in FP64 PCG against all-FP64, both to
+    rtol 1e-6; the error of each against the FP64 oracle's solution (sampled
+    values stored by the oracle) is reported."""
+    from workloads import cfg3
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "cfg3_oracle.json")))
+    idx = np.array(gold["sample_vertices"])
+    ref = np.array(gold["sample_x"])
+    mesh = cfg3()
+    d_rhs = torch.from_numpy(mesh.rhs[0]).to("cuda")
+    d_x = torch.zeros_like(d_rhs)
+    res = {}
+    for name, prec in (("mixed", V.FP32_PRECOND), ("fp64", V.FP64)):
+        t0 = time.perf_counter()
+        s = V.Solver.from_mesh(mesh, precision=prec, setup_device=1)
+        t_setup = time.perf_counter() - t0
+        time_solves(s, d_rhs, d_x, max(1, args.warmup))
+        runs = time_solves(s, d_rhs, d_x, max(1, min(args.steps, 5)))
+        x = d_x.cpu().numpy()
+        info = runs[-1][1]
+        res[name] = {"ms": float(np.mean([r[0] for r in runs])), "iterations": info["iterations"],
+                     "rel_res_true": info["rel_res_true"], "setup_s": t_setup,
+                     "error_vs_fp64_oracle": float(np.abs(x[idx] - ref).max() / gold["x_norminf"])}
+        log(f"{name}: {res[name]}")
+        s.free()
+    ms = res["mixed"]["ms"]
+    print(json.dumps({
+        "metric": "V-ASMG-PCG time-to-rtol 1e-6, FP32-precond vs FP64", "value": 1e3 / ms,
+        "unit": "solves/s", "n_gpus": 1, "steps": max(1, min(args.steps, 5)), "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (V-cycle) + f64 (PCG)", "data": "synthetic",
+        "config": {"workload": "2D plane strain, 1025^2 graded mesh (x^2, y^2), nu=0.49, E in {1,100} "
+                               "on a random 8x8 checkerboard (seed 2), V(1,1) V-ASMG-PCG rtol 1e-6",
+                   "n_dofs": mesh.n_dofs},
+        "iterations": res["mixed"]["iterations"], "rel_res_true": res["mixed"]["rel_res_true"],
+        "error_vs_fp64_oracle": res["mixed"]["error_vs_fp64_oracle"],
+        "oracle_iterations": {"fp64": gold["fp64"]["iterations"], "fp32_mode": gold["fp32"]["iterations"]},
+        "fp64": res["fp64"]}), flush=True)
+
+
 def bench_cfg4(args, V, torch):
     """129^3 jittered Kuhn mesh (seed 3), clamped at x=0, 16 Fourier load cases,
     6,390,144 DOFs per case: one block solve (K = 16, FP32 V-cycle) against the
@@ -269,8 +311,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--workload", choices=["cfg2", "block16", "cfg4", "serve"], default="cfg2",
-                    help="cfg2: the headline 65^3 workload (default); cfg4: 129^3 with 16 load "
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "block16", "cfg4", "serve"],
+                    default="cfg2",
+                    help="cfg2: the headline 65^3 workload (default); cfg3: the graded 2D "
+                         "nu=0.49 workload, mixed vs FP64; cfg4: 129^3 with 16 load "
                          "cases, block solve against column-by-column solves; block16: the 65^3 mesh with "
                          "16 load cases, block solve only; serve: the request stream through the "
                          "continuous-batching server")
@@ -297,6 +341,9 @@ def main():
         return
     if args.workload == "block16":
         bench_block16(args, V, torch)
+        return
+    if args.workload == "cfg3":
+        bench_cfg3(args, V, torch)
         return
     if args.workload == "serve":
         bench_serve(args, V)
