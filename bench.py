@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "721d352d08cfa4ce8c2a496b53f0636e023f7bdf155b6923b061e474770b18b2",
-                  "bytes_per_launch": 48543025}
+TRAFFIC_RECORD = {"kernels_sha256": "8c8c757b7b09e579536bf11f9a5499bc20065ea991a04bf812f76de043f53f21",
+                  "bytes_per_launch": 48614829}
 
 
 def traffic_per_launch():
@@ -123,7 +123,8 @@ def bench_cfg3(args, V, torch):
     res = {}
     for name, prec in (("mixed", V.FP32_PRECOND), ("fp64", V.FP64)):
         t0 = time.perf_counter()
-        s = V.Solver.from_mesh(mesh, precision=prec, setup_device=1)
+        s = V.Solver.from_mesh(mesh, precision=prec, setup_device=1, verbose=1,
+                               autotune=0 if args.no_autotune else 1)
         t_setup = time.perf_counter() - t0
         time_solves(s, d_rhs, d_x, max(1, args.warmup))
         runs = time_solves(s, d_rhs, d_x, max(1, min(args.steps, 5)))

@@ -437,6 +437,28 @@ struct CellShape {
   static constexpr int NU = NV * D;
 };
 
+// Cells per workgroup: one per workgroup when a cell's NV * GR lanes fill a
+// wavefront or more (its wavefront 0 runs the in-cell sweep); otherwise as many
+// as share one wavefront (2D cells with 4 or 8 lanes per row), each with its own
+// lane segment for the off-cell sums and the in-cell sweep.
+template <int D, int GR>
+struct CellPack {
+  static constexpr int CT = (1 << D) * GR;                 // lanes per cell
+  static constexpr int CPW = CT >= 64 ? 1 : 64 / CT;
+  static constexpr int threads = CT * CPW;
+};
+
+// Value of lane u of the calling lane's cell segment (segment = cell slot):
+// the wavefront-wide read-lane when one cell owns the wavefront, else a
+// shuffle; every lane of the wavefront must call it.
+template <int CPW, int CT, typename T>
+__device__ __forceinline__ T cell_bcast(T v, int slot, int u) {
+  if constexpr (CPW == 1)
+    return bcast(v, u);
+  else
+    return __shfl(v, slot * CT + u, 64);
+}
+
 // Per-cell block of NV * GR threads: lane group g (GR lanes, inside one
 // wavefront) sums the off-cell part of the cell's g-th row; the sums meet in
 // LDS; wavefront 0 then runs the sequential sweep over the cell's unknowns.
@@ -444,8 +466,8 @@ template <typename T, int D, int GR>
 __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& L,
                                                   const Part<T>& U, const T* __restrict__ x,
                                                   bool want_lo, bool want_up, T (*sh_lo)[D],
-                                                  T (*sh_up)[D]) {
-  const int g = threadIdx.x / GR, gl = threadIdx.x % GR;
+                                                  T (*sh_up)[D], int tc) {
+  const int g = tc / GR, gl = tc % GR;
   T lo[D], up[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
@@ -470,25 +492,29 @@ __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& 
 }
 
 template <typename T, int D, int GR, int MODE>
-__global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
-    int cell0, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
+__global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_gs_cell(
+    int cell0, int ncell, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U,
     const T* __restrict__ cellM, const T* __restrict__ b, T* x, T* __restrict__ s_save,
     const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
-  __shared__ T sh_lo[NV][D], sh_up[NV][D];
-  const int c = cell0 + xcd_block();
-  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
-  // wavefront 0 fetches its part of the in-cell solve first, so these loads
-  // overlap the off-cell products
-  const int t = threadIdx.x;
+  constexpr int CT = CellPack<D, GR>::CT, CPW = CellPack<D, GR>::CPW;
+  __shared__ T sh_lo[CPW][NV][D], sh_up[CPW][NV][D];
+  const int slot = CPW == 1 ? 0 : threadIdx.x / CT;
+  const int t = CPW == 1 ? threadIdx.x : threadIdx.x % CT;
+  const int ci = xcd_block() * CPW + slot;
+  const bool live = CPW == 1 || ci < ncell;   // the last workgroup may hold fewer cells
+  const int c = cell0 + (live ? ci : 0);
+  const int v0 = cell_ptr[c], m = live ? cell_ptr[c + 1] - v0 : 0, n = m * D;
+  // the sweeping wavefront fetches its part of the in-cell solve first, so these
+  // loads overlap the off-cell products
   const bool own = t < n;
   const int k = own ? t / D : 0, a = own ? t % D : 0;
   const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
   T Mrow[NU];
   T bt = T(0), xc = T(0);
-  if (t < 64) {
+  if (threadIdx.x < 64) {
     const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
 #pragma unroll
     for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
@@ -497,47 +523,49 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
       if (MODE != 0) xc = x[xi];
     }
   }
-  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, true, MODE != 0, sh_lo, sh_up);
-  if (t >= 64) return;                    // wavefront 0 finishes the cell
-  const T s_t = own ? bt - sh_lo[k][a] : T(0);
-  const T sup = (own && MODE != 0) ? sh_up[k][a] : T(0);
+  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, true, MODE != 0, sh_lo[slot], sh_up[slot], t);
+  if (threadIdx.x >= 64) return;          // wavefront 0 finishes the cell(s)
+  const T s_t = own ? bt - sh_lo[slot][k][a] : T(0);
+  const T sup = (own && MODE != 0) ? sh_up[slot][k][a] : T(0);
   if (MODE != 2 && s_save && own) s_save[xi] = s_t;
   T acc = s_t - sup;
+  // with one cell per wavefront n is uniform and the guards below are the loop
+  // bounds; with several, every lane takes part in each broadcast
   if (MODE != 0) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      if (u < n) {
-        const T xu = bcast(xc, u);
-        if (u != t) acc -= Mrow[u] * xu;
+      if (CPW > 1 || u < n) {
+        const T xu = cell_bcast<CPW, CT>(xc, slot, u);
+        if (u != t && u < n) acc -= Mrow[u] * xu;
       }
     }
   }
   if (MODE != 2) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      if (u < n) {
+      if (CPW > 1 || u < n) {
         T delta = T(0);
-        if (t == u) {
+        if (t == u && u < n) {
           const T xn = acc / Mrow[u];
           delta = xn - xc;
           xc = xn;
         }
-        delta = bcast(delta, u);
-        if (t != u) acc -= Mrow[u] * delta;
+        delta = cell_bcast<CPW, CT>(delta, slot, u);
+        if (t != u && u < n) acc -= Mrow[u] * delta;
       }
     }
   } else {
 #pragma unroll
     for (int u = NU - 1; u >= 0; --u) {
-      if (u < n) {
+      if (CPW > 1 || u < n) {
         T delta = T(0);
-        if (t == u) {
+        if (t == u && u < n) {
           const T xn = acc / Mrow[u];
           delta = xn - xc;
           xc = xn;
         }
-        delta = bcast(delta, u);
-        if (t != u) acc -= Mrow[u] * delta;
+        delta = cell_bcast<CPW, CT>(delta, slot, u);
+        if (t != u && u < n) acc -= Mrow[u] * delta;
       }
     }
   }
@@ -549,24 +577,28 @@ __global__ __launch_bounds__((1 << D) * GR) void k_gs_cell(
 //   KIND 1: full residual: base = b, both ranges
 //   KIND 2: SpMV: base = 0, both ranges, result negated (y = A x)
 template <typename T, int D, int GR, int KIND>
-__global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
-    const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
+__global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_cell_apply(
+    int ncell, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
     const T* __restrict__ base, const T* __restrict__ x, T* __restrict__ out,
     const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
-  __shared__ T sh_lo[NV][D], sh_up[NV][D];
-  const int c = xcd_block();
-  const int v0 = cell_ptr[c], m = cell_ptr[c + 1] - v0, n = m * D;
+  constexpr int CT = CellPack<D, GR>::CT, CPW = CellPack<D, GR>::CPW;
+  __shared__ T sh_lo[CPW][NV][D], sh_up[CPW][NV][D];
+  const int slot = CPW == 1 ? 0 : threadIdx.x / CT;
+  const int t = CPW == 1 ? threadIdx.x : threadIdx.x % CT;
+  const int ci = xcd_block() * CPW + slot;
+  const bool live = CPW == 1 || ci < ncell;
+  const int c = live ? ci : 0;
+  const int v0 = cell_ptr[c], m = live ? cell_ptr[c + 1] - v0 : 0, n = m * D;
   // wavefront 0 fetches the in-cell block row, x and the base first
-  const int t = threadIdx.x;
   const bool own = t < n;
   const int k = own ? t / D : 0, a = own ? t % D : 0;
   const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
   T Mrow[NU];
   T xt = T(0), bt = T(0);
-  if (t < 64) {
+  if (threadIdx.x < 64) {
     const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
 #pragma unroll
     for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
@@ -575,13 +607,16 @@ __global__ __launch_bounds__((1 << D) * GR) void k_cell_apply(
       if (KIND != 2) bt = base[xi];
     }
   }
-  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, KIND != 0, true, sh_lo, sh_up);
-  if (t >= 64) return;
-  const T off = own ? (KIND != 0 ? sh_lo[k][a] : T(0)) + sh_up[k][a] : T(0);
+  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, KIND != 0, true, sh_lo[slot], sh_up[slot], t);
+  if (threadIdx.x >= 64) return;
+  const T off = own ? (KIND != 0 ? sh_lo[slot][k][a] : T(0)) + sh_up[slot][k][a] : T(0);
   T mx = T(0);
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    if (u < n) mx += Mrow[u] * bcast(xt, u);
+    if (CPW > 1 || u < n) {
+      const T xu = cell_bcast<CPW, CT>(xt, slot, u);
+      if (u < n) mx += Mrow[u] * xu;
+    }
   }
   if (!own) return;
   if (KIND == 2)

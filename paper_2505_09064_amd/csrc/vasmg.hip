@@ -388,10 +388,14 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
 }
 
 // Lanes per block row from the mean off-cell blocks per row: about two blocks per
-// lane; cell levels use 16..64.
+// lane; 3D cell levels use 16..64; 2D cell levels (short rows) about two quads of
+// 4 blocks per lane, 4..64, several cells sharing a wavefront below 16.
 void set_lanes(DevLevel& dl) {
   const double avg = dl.n > 0 ? static_cast<double>(dl.nnz) / dl.n : 1.0;
-  dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
+  if (dl.cells && dl.d == 2)
+    dl.G = std::min(64, std::max(4, pow2_ceil(static_cast<int>(std::ceil(avg / 8.0)))));
+  else
+    dl.G = std::min(64, std::max(dl.cells ? 16 : 4, pow2_ceil(static_cast<int>(std::ceil(avg / 2.0)))));
   dl.Gspmv = dl.G;
 }
 
@@ -695,6 +699,7 @@ void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
 
 #define DISPATCH_GR(Gv, ...)                                  \
   switch (Gv) {                                               \
+    case 4: { constexpr int GR = 4; __VA_ARGS__; } break;     \
     case 8: { constexpr int GR = 8; __VA_ARGS__; } break;     \
     case 16: { constexpr int GR = 16; __VA_ARGS__; } break;   \
     case 32: { constexpr int GR = 32; __VA_ARGS__; } break;   \
@@ -709,15 +714,16 @@ void launch_gs_cells(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
   const T* M = LevelMats<T>::cellM(lv);
   const dev::Part<T> Lp = LevelMats<T>::L(lv), Up = LevelMats<T>::U(lv);
   DISPATCH_GR(lv.G, {
-    const dim3 blk((1 << D) * GR);
+    using Pack = dev::CellPack<D, GR>;
+    const dim3 blk(Pack::threads), grid((nc + Pack::CPW - 1) / Pack::CPW);
     if (mode == 0)
-      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 0>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 0>), grid, blk, 0, st, c0, nc, lv.cell_ptr,
                          Lp, Up, M, b, x, s_save, done);
     else if (mode == 1)
-      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 1>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 1>), grid, blk, 0, st, c0, nc, lv.cell_ptr,
                          Lp, Up, M, b, x, s_save, done);
     else
-      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 2>), dim3(nc), blk, 0, st, c0, lv.cell_ptr,
+      hipLaunchKernelGGL((dev::k_gs_cell<T, D, GR, 2>), grid, blk, 0, st, c0, nc, lv.cell_ptr,
                          Lp, Up, M, b, x, s_save, done);
   });
 }
@@ -726,8 +732,10 @@ template <typename T, int D, int KIND>
 void launch_cell_apply(const DevLevel& lv, const T* base, const T* x, T* out, const int* done,
                        hipStream_t st) {
   DISPATCH_GR(lv.G, {
-    hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND>), dim3(lv.ncells), dim3((1 << D) * GR), 0,
-                       st, lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
+    using Pack = dev::CellPack<D, GR>;
+    hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND>),
+                       dim3((lv.ncells + Pack::CPW - 1) / Pack::CPW), dim3(Pack::threads), 0, st,
+                       lv.ncells, lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
                        LevelMats<T>::cellM(lv), base, x, out, done);
   });
 }
@@ -1157,7 +1165,8 @@ void autotune(vasmg_ctx& C) {
       launch_fill<double>(static_cast<double*>(lv.b), len, 1.0, st);
       launch_fill<double>(static_cast<double*>(lv.x), len, 0.0, st);
     }
-    std::vector<int> cand = lv.cells ? std::vector<int>{D == 3 ? 8 : 16, 16, 32, 64}
+    std::vector<int> cand = lv.cells ? (D == 3 ? std::vector<int>{8, 16, 32, 64}
+                                               : std::vector<int>{4, 8, 16, 32})
                                      : std::vector<int>{4, 8, 16, 32};
     double best = 1e30;
     int bestG = lv.G;
