@@ -301,6 +301,11 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
   C.nrows = n;
   C.ptr = dmalloc<int64_t>(n + 1, st, "rowptr");
   int64_t* cnt = dmalloc<int64_t>(n, st, "row counts");
+  struct FreeCounts {   // released on every path; C itself is the caller's
+    int64_t* p;
+    hipStream_t st;
+    ~FreeCounts() { (void)hipFreeAsync(p, st); }
+  } free_counts{cnt, st};
   if (n > 0)
     hipLaunchKernelGGL(k_symbolic<false>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
                        G.window, cnt, nullptr, nullptr);
@@ -322,7 +327,6 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
     check(hipGetLastError(), "numeric launch");
   }
   check(hipStreamSynchronize(st), "product");
-  (void)hipFreeAsync(cnt, st);
 }
 
 // Copies the values of resident level l into host->val (allocated here, so the
