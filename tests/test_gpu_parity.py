@@ -297,9 +297,11 @@ def test_full_size_graded_2d_against_oracle_golden():
     s.free()
 
 
-def test_autotuned_handle_matches_oracle():
-    """Autotuning only changes lanes per block row (summation order inside a row)."""
-    m = small3d(9, seed=5)
+@pytest.mark.parametrize("name", ["small3d_n9", "graded2d_n33_nu049", "cfg1_2d"])
+def test_autotuned_handle_matches_oracle(name):
+    """Autotuning only changes lanes per block row (summation order inside a row;
+    on 2D cell levels also how many cells share a wavefront: 4, 2 or 1)."""
+    m = MESHES[name]()
     o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
     xo, io = o.solve(m.rhs[0], 1e-6)
     for prec, tol in ((V.FP64, 1e-8), (V.FP32_PRECOND, 1e-5)):
