@@ -329,7 +329,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                          "the solver has no multi-GPU path (see DESIGN.md)"}))
+                          "the solver has no multi-GPU path"}))
         sys.exit(2)
 
     import torch

@@ -9,7 +9,7 @@ into their parents until only the root is left) and Section 3.2 (bilinear
 prolongation weights, identical for every displacement component). 3D is the
 octree analogue, as the paper states for its 2D presentation.
 
-Readings of the paper taken here (each also listed in the design doc):
+Readings of the paper taken here:
   * root box: one min and one max over all coordinates of all tree vertices,
     D1 = [m, M]^d (Step 1 takes the smaller of the x/y minima and the larger of
     the x/y maxima);
