@@ -300,3 +300,22 @@ def test_device_setup_background_downloads():
         assert np.array_equal(ea["vals"], eb["vals"])
     a.free()
     b.free()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_device_setup_single_level(dim):
+    """A hierarchy truncated to the fine level (coarsest_max_dofs above its DOFs):
+    the coarsest factor then needs the device-assembled fine values on the host at
+    once; the solve (one V-cycle = the exact solve) matches the host setup's."""
+    m = small2d(9, seed=2) if dim == 2 else small3d(4, seed=2)
+    kw = dict(coarsest_max_dofs=4000)
+    sd = V.Solver.from_mesh(m, setup_device=1, **kw)
+    sh = V.Solver.from_mesh(m, **kw)
+    assert sd.hierarchy_info()[0] == 1 == sh.hierarchy_info()[0]
+    assert np.array_equal(sd.export_level(0)["vals"], sh.export_level(0)["vals"])
+    xd, idv = sd.solve(m.rhs[0], 1e-10)
+    xh, ih = sh.solve(m.rhs[0], 1e-10)
+    assert idv["iterations"] == ih["iterations"] <= 2
+    assert np.array_equal(xd, xh)
+    sd.free()
+    sh.free()
