@@ -1,10 +1,13 @@
 // Block right-hand-side kernels: K independent PCG recurrences (one per load
 // case) that share every matrix read.
 //
-// Vectors interleave the columns per vertex, v[(row*K + k)*DP + a] (column k,
-// component a, padded stride DP): the K columns of one neighbour are K*DP
-// consecutive values, so the lanes of a row that own the K columns gather them
-// in one contiguous load while reading the same matrix block (a broadcast).
+// Vectors interleave the columns per vertex, v[(row*K + k)*VS + a] (column k,
+// component a, stride VS): the K columns of one neighbour are K*VS consecutive
+// values, so the lanes of a row that own the K columns gather them in one
+// contiguous load while reading the same matrix block (a broadcast). The fine
+// level keeps the padded stride (2 / 4: aligned vector loads, the layout of the
+// FP64 PCG vectors); the coarse levels, whose cell kernels are bound by these
+// gathers, store D components with no padding (3D: a quarter fewer bytes).
 // A row is handled by GL lanes = K columns x (GL/K) block slots; the slots
 // stride the row's blocks and are combined with cross-lane shuffles.
 // Per-column scalars (alpha, beta, rho, residual, stop flag) follow Algorithm 2
@@ -23,6 +26,28 @@ namespace dev {
 constexpr int kPointLanesNarrow = 16, kPointLanesWide = 64;
 constexpr int kCellLanesNarrow = 32, kCellLanesWide = 64;
 
+// D components at stride VS: aligned vector loads at the padded stride, else
+// component loads.
+template <typename T, int D, int VS>
+struct BlockVecIO {
+  static __device__ __forceinline__ void load(const T* p, T* v) {
+    if constexpr (VS == Pad<D>::value) {
+      VecIO<T, D>::load(p, v);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) v[a] = p[a];
+    }
+  }
+  static __device__ __forceinline__ void store(T* p, const T* v) {
+    if constexpr (VS == Pad<D>::value) {
+      VecIO<T, D>::store(p, v);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) p[a] = v[a];
+    }
+  }
+};
+
 // Sum over the GL/K block slots of a row group (lanes with equal column).
 template <typename T, int K, int GL>
 __device__ __forceinline__ T slot_sum(T v) {
@@ -34,12 +59,11 @@ __device__ __forceinline__ T slot_sum(T v) {
 
 // acc += sum over blocks [kb, ke) of A_blk x_col(blk)[column k]; slot s of S
 // takes blocks kb + s, kb + s + S, ...
-template <typename T, int D, int K, int S>
+template <typename T, int D, int K, int S, int VS>
 __device__ __forceinline__ void mc_row_product(int kb, int ke, int slot, int k,
                                                const int* __restrict__ col,
                                                const T* __restrict__ val, int64_t nnz,
                                                const T* __restrict__ x, T* acc) {
-  constexpr int DP = Pad<D>::value;
   constexpr int UN = sizeof(T) == 4 ? 4 : 2;
   int p = kb + slot;
   for (; p + (UN - 1) * S < ke; p += UN * S) {
@@ -49,22 +73,22 @@ __device__ __forceinline__ void mc_row_product(int kb, int ke, int slot, int k,
     T xv[UN][D];
 #pragma unroll
     for (int u = 0; u < UN; ++u)
-      VecIO<T, D>::load(x + (static_cast<int64_t>(j[u]) * K + k) * DP, xv[u]);
+      BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(j[u]) * K + k) * VS, xv[u]);
 #pragma unroll
     for (int u = 0; u < UN; ++u) block_fma<T, D>(val, nnz, p + u * S, xv[u], acc);
   }
   for (; p < ke; p += S) {
     const int jj = col[p];
     T xj[D];
-    VecIO<T, D>::load(x + (static_cast<int64_t>(jj) * K + k) * DP, xj);
+    BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(jj) * K + k) * VS, xj);
     block_fma<T, D>(val, nnz, p, xj, acc);
   }
 }
 
-template <typename T, int D, int K, int S>
+template <typename T, int D, int K, int S, int VS>
 __device__ __forceinline__ void mc_part_product(const Part<T>& p, int i, int slot, int k,
                                                 const T* __restrict__ x, T* acc) {
-  mc_row_product<T, D, K, S>(p.ptr[i], p.ptr[i + 1], slot, k, p.col, p.val, p.nnz, x, acc);
+  mc_row_product<T, D, K, S, VS>(p.ptr[i], p.ptr[i + 1], slot, k, p.col, p.val, p.nnz, x, acc);
 }
 
 // Per-column block sums: thread t contributes v to column col_of(t); on return
@@ -99,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mc(int n, Part<double> L, Part<
     double acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = 0.0;
-    mc_part_product<double, D, K, S>(L, i, slot, k, x, acc);
-    mc_part_product<double, D, K, S>(U, i, slot, k, x, acc);
+    mc_part_product<double, D, K, S, Pad<D>::value>(L, i, slot, k, x, acc);
+    mc_part_product<double, D, K, S, Pad<D>::value>(U, i, slot, k, x, acc);
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = slot_sum<double, K, GL>(acc[a]);
     if (slot == 0) {
@@ -142,8 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_color_mc(
   T lo[D], up[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
-  mc_part_product<T, D, K, S>(L, i, slot, k, x, lo);
-  if (MODE != 0) mc_part_product<T, D, K, S>(U, i, slot, k, x, up);
+  mc_part_product<T, D, K, S, Pad<D>::value>(L, i, slot, k, x, lo);
+  if (MODE != 0) mc_part_product<T, D, K, S, Pad<D>::value>(U, i, slot, k, x, up);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     lo[a] = slot_sum<T, K, GL>(lo[a]);
@@ -194,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_upper_mc(
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  mc_part_product<T, D, K, S>(U, i, slot, k, x, acc);
+  mc_part_product<T, D, K, S, Pad<D>::value>(U, i, slot, k, x, acc);
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = slot_sum<T, K, GL>(acc[a]);
   if (slot != 0) return;
@@ -236,8 +260,8 @@ __device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L,
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
   if (g < m) {
-    if (want_lo) mc_part_product<T, D, K, S>(L, v0 + g, slot, k, x, lo);
-    if (want_up) mc_part_product<T, D, K, S>(U, v0 + g, slot, k, x, up);
+    if (want_lo) mc_part_product<T, D, K, S, D>(L, v0 + g, slot, k, x, lo);
+    if (want_up) mc_part_product<T, D, K, S, D>(U, v0 + g, slot, k, x, up);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -261,7 +285,7 @@ __device__ __forceinline__ void mc_cell_sweep_pair(int k0, int v0, int n, const 
                                                    const CellLds<T, D, K>& sh,
                                                    const T* __restrict__ b, T* x,
                                                    T* __restrict__ s_save) {
-  constexpr int DP = Pad<D>::value;
+  constexpr int DP = D;   // coarse-level vectors: packed
   constexpr int NU = CellShape<D>::NU;
   static_assert(NU <= 32, "a column's unknowns fit in half a wavefront");
   const int lane = threadIdx.x & 63, h = lane >> 5, t = lane & 31;
@@ -328,7 +352,7 @@ template <typename T, int D, int K, int GL>
 __global__ __launch_bounds__(CellShape<D>::NV * GL) void k_cell_residual_mc(
     const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
     const T* __restrict__ s_save, const T* __restrict__ x, T* __restrict__ r) {
-  constexpr int DP = Pad<D>::value;
+  constexpr int DP = D;   // coarse-level vectors: packed
   constexpr int NU = CellShape<D>::NU;
   __shared__ CellLds<T, D, K> sh;
   __shared__ T shx[NU][K];
@@ -355,13 +379,13 @@ __global__ __launch_bounds__(CellShape<D>::NV * GL) void k_cell_residual_mc(
 // ---------------------------------------------------------------------------
 // Transfers: b_c = P^T r and x += P e, lane k of a K-lane group = column k.
 // ---------------------------------------------------------------------------
-template <typename T, int D, int K>
+// VF: stride of the fine level's vectors; the coarse level's are packed (D).
+template <typename T, int D, int K, int VF>
 __global__ __launch_bounds__(kBlock) void k_restrict_mc(int nc, const int* __restrict__ ptr,
                                                         const int* __restrict__ idx,
                                                         const T* __restrict__ w,
                                                         const T* __restrict__ r,
                                                         T* __restrict__ bc) {
-  constexpr int DP = Pad<D>::value;
   const int k = threadIdx.x % K;
   const int I = xcd_block() * (kBlock / K) + threadIdx.x / K;
   if (I >= nc) return;
@@ -370,46 +394,46 @@ __global__ __launch_bounds__(kBlock) void k_restrict_mc(int nc, const int* __res
   for (int a = 0; a < D; ++a) acc[a] = T(0);
   for (int p = ptr[I]; p < ptr[I + 1]; ++p) {
     T e[D];
-    VecIO<T, D>::load(r + (static_cast<int64_t>(idx[p]) * K + k) * DP, e);
+    BlockVecIO<T, D, VF>::load(r + (static_cast<int64_t>(idx[p]) * K + k) * VF, e);
     const T wp = w[p];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += wp * e[a];
   }
-  VecIO<T, D>::store(bc + (static_cast<int64_t>(I) * K + k) * DP, acc);
+  BlockVecIO<T, D, D>::store(bc + (static_cast<int64_t>(I) * K + k) * D, acc);
 }
 
-template <typename T, int D, int K>
+template <typename T, int D, int K, int VF>
 __global__ __launch_bounds__(kBlock) void k_prolong_mc(int nf, const int* __restrict__ ptr,
                                                        const int* __restrict__ idx,
                                                        const T* __restrict__ w,
                                                        const T* __restrict__ e, T* x) {
-  constexpr int DP = Pad<D>::value;
   const int k = threadIdx.x % K;
   const int i = xcd_block() * (kBlock / K) + threadIdx.x / K;
   if (i >= nf) return;
-  const int64_t o = (static_cast<int64_t>(i) * K + k) * DP;
+  const int64_t o = (static_cast<int64_t>(i) * K + k) * VF;
   T xi[D], acc[D];
-  VecIO<T, D>::load(x + o, xi);
+  BlockVecIO<T, D, VF>::load(x + o, xi);
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
   for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
     T ev[D];
-    VecIO<T, D>::load(e + (static_cast<int64_t>(idx[p]) * K + k) * DP, ev);
+    BlockVecIO<T, D, D>::load(e + (static_cast<int64_t>(idx[p]) * K + k) * D, ev);
     const T wp = w[p];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += wp * ev[a];
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) xi[a] += acc[a];
-  VecIO<T, D>::store(x + o, xi);
+  BlockVecIO<T, D, VF>::store(x + o, xi);
 }
 
 // Coarsest solve L L^T e = b per column (FP64, one workgroup; n * K <= kCoarseMax).
-template <typename T, int D, int K>
+// VS: stride of the coarsest level's vectors (padded if it is the fine level).
+template <typename T, int D, int K, int VS>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve_mc(int n, const double* __restrict__ L,
                                                             const T* __restrict__ b,
                                                             T* __restrict__ x) {
-  constexpr int DP = Pad<D>::value;
+  constexpr int DP = VS;
   __shared__ double y[kCoarseMax];
   const int nk = n * K;
   for (int e = threadIdx.x; e < nk; e += blockDim.x) {

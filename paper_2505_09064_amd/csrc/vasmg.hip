@@ -1369,7 +1369,9 @@ void upload_block(vasmg_ctx& C, int K) {
   C.ks.assign(nl, nullptr);
   C.kr.assign(nl, nullptr);
   for (int l = 0; l < nl; ++l) {
-    const int64_t bytes = static_cast<int64_t>(C.lev[l].n) * K * C.DP * tb;
+    // the fine level keeps the padded stride; coarse levels store D components
+    const int stride = l == 0 ? C.DP : C.d;
+    const int64_t bytes = static_cast<int64_t>(C.lev[l].n) * K * stride * tb;
     for (auto* v : {&C.kb, &C.kx, &C.ks, &C.kr}) {
       (*v)[l] = C.dalloc<char>(bytes);
       C.clear((*v)[l], bytes);
@@ -1496,20 +1498,37 @@ void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
                            LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x, r);
       });
     }
-    hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K>), dim3(grid_for(lv.nnext, dev::kBlock / K)),
-                       dim3(dev::kBlock), 0, st, lv.nnext, lv.pt_ptr, lv.pt_idx,
-                       LevelMats<T>::ptw(lv), r, static_cast<T*>(C.kb[l + 1]));
+    const dim3 rgrid(grid_for(lv.nnext, dev::kBlock / K));
+    if (l == 0)
+      hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K, dev::Pad<D>::value>), rgrid, dim3(dev::kBlock),
+                         0, st, lv.nnext, lv.pt_ptr, lv.pt_idx, LevelMats<T>::ptw(lv), r,
+                         static_cast<T*>(C.kb[l + 1]));
+    else
+      hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K, D>), rgrid, dim3(dev::kBlock), 0, st,
+                         lv.nnext, lv.pt_ptr, lv.pt_idx, LevelMats<T>::ptw(lv), r,
+                         static_cast<T*>(C.kb[l + 1]));
   }
-  hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K>), dim3(1), dim3(dev::kBlock), 0, st,
-                     static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.kb[L]),
-                     static_cast<T*>(C.kx[L]));
+  if (L == 0)
+    hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K, dev::Pad<D>::value>), dim3(1),
+                       dim3(dev::kBlock), 0, st, static_cast<int>(C.n_coarse), C.chol,
+                       static_cast<const T*>(C.kb[L]), static_cast<T*>(C.kx[L]));
+  else
+    hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                       static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.kb[L]),
+                       static_cast<T*>(C.kx[L]));
   for (int l = L - 1; l >= 0; --l) {
     const DevLevel& lv = C.lev[l];
     T* b = static_cast<T*>(C.kb[l]);
     T* x = static_cast<T*>(C.kx[l]);
-    hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K>), dim3(grid_for(lv.n, dev::kBlock / K)),
-                       dim3(dev::kBlock), 0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
-                       static_cast<const T*>(C.kx[l + 1]), x);
+    const dim3 pgrid(grid_for(lv.n, dev::kBlock / K));
+    if (l == 0)
+      hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K, dev::Pad<D>::value>), pgrid, dim3(dev::kBlock),
+                         0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
+                         static_cast<const T*>(C.kx[l + 1]), x);
+    else
+      hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K, D>), pgrid, dim3(dev::kBlock), 0, st, lv.n,
+                         lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
+                         static_cast<const T*>(C.kx[l + 1]), x);
     for (int k = 0; k < C.opt.n_post; ++k)
       launch_gs_sweep_mc<T, D, K>(lv, true, false, b, x, nullptr, st);
   }
