@@ -196,7 +196,9 @@ typedef struct vasmg_server* vasmg_server_handle;
 typedef struct {
   int32_t slots;               /* concurrent device solves (streams), 1..64, default 4    */
   int32_t setup_workers;       /* host threads building hierarchies, 1..64, default 4;
-                                  the host's cores are split evenly between them        */
+                                  a setup uses the host's threads divided by the
+                                  number of setups running or queued when it starts
+                                  (at most setup_workers)                                */
   int64_t hbm_budget_bytes;    /* device bytes resident requests may hold together;
                                   0 = 80% of the device's free memory at creation       */
   vasmg_options options;       /* solver options of every request (leaf_capacity 0 =

@@ -29,6 +29,7 @@
 
 namespace vasmg {
 void set_host_threads(int n);   // setup.cpp: OpenMP threads of the calling thread's setups
+int host_thread_budget();       // setup.cpp: the default OpenMP team size
 }
 
 namespace {
@@ -88,8 +89,10 @@ struct vasmg_server {
     cv.notify_all();
   }
 
-  void setup_loop(int host_threads) {
-    vasmg::set_host_threads(host_threads);
+  // hw_threads: the host's threads; a setup takes its share among the setups
+  // running or queued when it starts (a lone large mesh gets them all). The
+  // hierarchy does not depend on the thread count.
+  void setup_loop(int hw_threads) {
     if (cfg.options.setup_device) (void)hipSetDevice(device);   // device Galerkin products
     for (;;) {
       ReqPtr r;
@@ -100,6 +103,10 @@ struct vasmg_server {
         r = setup_q.front();
         setup_q.pop_front();
         ++setups_active;
+        // setups running or about to start (queued requests go to idle workers)
+        const int busy = std::min(cfg.setup_workers,
+                                  setups_active + static_cast<int>(setup_q.size()));
+        vasmg::set_host_threads(std::max(1, hw_threads / std::max(1, busy)));
       }
       r->res.t_setup_start_ms = now_ms();
       vasmg_mesh m{r->dim, r->nv, r->coords.data(), r->ne, r->elems.data(),
@@ -235,11 +242,12 @@ vasmg_status vasmg_server_create(const vasmg_server_config* cfg, vasmg_server_ha
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return VASMG_EDEVICE;
   s->budget = cfg->hbm_budget_bytes > 0 ? cfg->hbm_budget_bytes
                                         : static_cast<int64_t>(0.8 * static_cast<double>(free_b));
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int host_threads = std::max(1, static_cast<int>(hw) / cfg->setup_workers);
+  // the process's share of the host (OMP_NUM_THREADS where set), not every core
+  const int hw = std::max(1, std::min(static_cast<int>(std::thread::hardware_concurrency()),
+                                      vasmg::host_thread_budget()));
   vasmg_server* sp = s.get();
   for (int i = 0; i < cfg->setup_workers; ++i)
-    s->workers.emplace_back([sp, host_threads] { sp->setup_loop(host_threads); });
+    s->workers.emplace_back([sp, hw] { sp->setup_loop(hw); });
   for (int i = 0; i < cfg->slots; ++i) s->workers.emplace_back([sp, i] { sp->slot_loop(i); });
   *out = s.release();
   return VASMG_OK;

@@ -868,6 +868,8 @@ namespace vasmg {
 // OpenMP threads of the parallel regions the calling thread starts (setups
 // running side by side in a server each get their share of the cores).
 void set_host_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+// The calling thread's default OpenMP team size (OMP_NUM_THREADS, else the cores).
+int host_thread_budget() { return omp_get_max_threads(); }
 }  // namespace vasmg
 
 namespace vasmg {
