@@ -461,6 +461,27 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve_mc(int n, const double*
   }
 }
 
+// Small coarsest levels: x = A_c^{-1} b per column (n <= kCoarseInvMax).
+template <typename T, int D, int K, int VS>
+__global__ __launch_bounds__(kBlock) void k_coarse_apply_mc(int n, const double* __restrict__ Minv,
+                                                            const T* __restrict__ b,
+                                                            T* __restrict__ x) {
+  __shared__ double y[kCoarseMax];
+  const int nk = n * K;
+  for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+    const int i = e / K, k = e % K;
+    y[e] = static_cast<double>(b[((i / D) * K + k) * VS + i % D]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+    const int i = e / K, k = e % K;
+    const double* row = Minv + static_cast<int64_t>(i) * n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += row[j] * y[j * K + k];
+    x[((i / D) * K + k) * VS + i % D] = static_cast<T>(s);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // PCG vector kernels over [row][K][DP] (flat grid-stride; the stride is a
 // multiple of K*DP, so every thread stays on one column).

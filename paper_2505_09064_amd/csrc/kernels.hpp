@@ -748,6 +748,28 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[(i / D) * DP + (i % D)] = static_cast<T>(y[i]);
 }
 
+// K6, small coarsest levels (n <= kCoarseInvMax): x = A_c^{-1} b with the inverse
+// formed at setup from the same Cholesky factor; one pass instead of 2n
+// dependent steps. Row i is one thread's sum in ascending column order.
+constexpr int kCoarseInvMax = 256;
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __restrict__ Minv,
+                                                         const T* __restrict__ b, T* __restrict__ x,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  __shared__ double y[kCoarseInvMax];
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    y[i] = static_cast<double>(b[(i / D) * DP + (i % D)]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double* row = Minv + static_cast<int64_t>(i) * n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += row[j] * y[j];
+    x[(i / D) * DP + (i % D)] = static_cast<T>(s);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K7/K8: PCG vector kernels and device-side scalars (FP64, deterministic).
 // ---------------------------------------------------------------------------

@@ -156,6 +156,7 @@ struct vasmg_ctx {
   void* pinned = nullptr;               // pinned block: h_sc, h_rtol, kh_sc
   std::vector<DevLevel> lev;
   double* chol = nullptr;           // coarsest factor
+  double* cinv = nullptr;           // coarsest inverse (small coarsest levels), else null
   int64_t n_coarse = 0;
   // PCG state (FP64, padded, fine device numbering)
   int n0 = 0;
@@ -548,6 +549,29 @@ std::vector<int> device_inverse(const vasmg_ctx& C, int l) {
   return inv;
 }
 
+// A^{-1} = L^{-T} L^{-1} from the lower Cholesky factor L (row-major n x n), in
+// FP64; symmetric by construction (each pair of entries computed once).
+std::vector<double> coarse_inverse(const std::vector<double>& Lf, int64_t n) {
+  std::vector<double> Li(static_cast<size_t>(n * n), 0.0);   // L^{-1}, lower
+  for (int64_t j = 0; j < n; ++j) {
+    Li[j * n + j] = 1.0 / Lf[j * n + j];
+    for (int64_t i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int64_t k = j; k < i; ++k) s += Lf[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = -s / Lf[i * n + i];
+    }
+  }
+  std::vector<double> M(static_cast<size_t>(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int64_t k = i; k < n; ++k) s += Li[k * n + i] * Li[k * n + j];
+      M[i * n + j] = s;
+      M[j * n + i] = s;
+    }
+  return M;
+}
+
 void upload_all(vasmg_ctx& C) {
   const int nl = static_cast<int>(C.H.levels.size());
   C.L = nl - 1;
@@ -580,6 +604,7 @@ void upload_all(vasmg_ctx& C) {
     if (C.n_coarse > dev::kCoarseMax)
       throw vasmg::Error{VASMG_EINVAL, "coarsest level has more than 4096 DOFs"};
     C.chol = C.upload(C.H.chol);
+    if (C.n_coarse <= dev::kCoarseInvMax) C.cinv = C.upload(coarse_inverse(C.H.chol, C.n_coarse));
   }
   // PCG vectors
   C.n0 = static_cast<int>(C.H.levels[0].n);
@@ -920,9 +945,14 @@ void enqueue_level(vasmg_ctx& C, int l, bool zero_guess, const int* done, hipStr
   const int tb = sizeof(T);
   if (l == L) {
     run_phase(prof, "coarse_solve", L, 1, static_cast<double>(C.n_coarse) * C.n_coarse * 8.0, [&] {
-      hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
-                         static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
-                         static_cast<T*>(C.lev[L].x), done);
+      if (C.cinv)
+        hipLaunchKernelGGL((dev::k_coarse_apply<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                           static_cast<int>(C.n_coarse), C.cinv, static_cast<const T*>(C.lev[L].b),
+                           static_cast<T*>(C.lev[L].x), done);
+      else
+        hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                           static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.lev[L].b),
+                           static_cast<T*>(C.lev[L].x), done);
     });
     return;
   }
@@ -1508,14 +1538,21 @@ void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
                          lv.nnext, lv.pt_ptr, lv.pt_idx, LevelMats<T>::ptw(lv), r,
                          static_cast<T*>(C.kb[l + 1]));
   }
-  if (L == 0)
+  const int nco = static_cast<int>(C.n_coarse);
+  const T* bL = static_cast<const T*>(C.kb[L]);
+  T* xL = static_cast<T*>(C.kx[L]);
+  if (L == 0 && C.cinv)
+    hipLaunchKernelGGL((dev::k_coarse_apply_mc<T, D, K, dev::Pad<D>::value>), dim3(1),
+                       dim3(dev::kBlock), 0, st, nco, C.cinv, bL, xL);
+  else if (L == 0)
     hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K, dev::Pad<D>::value>), dim3(1),
-                       dim3(dev::kBlock), 0, st, static_cast<int>(C.n_coarse), C.chol,
-                       static_cast<const T*>(C.kb[L]), static_cast<T*>(C.kx[L]));
+                       dim3(dev::kBlock), 0, st, nco, C.chol, bL, xL);
+  else if (C.cinv)
+    hipLaunchKernelGGL((dev::k_coarse_apply_mc<T, D, K, D>), dim3(1), dim3(dev::kBlock), 0, st, nco,
+                       C.cinv, bL, xL);
   else
-    hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K, D>), dim3(1), dim3(dev::kBlock), 0, st,
-                       static_cast<int>(C.n_coarse), C.chol, static_cast<const T*>(C.kb[L]),
-                       static_cast<T*>(C.kx[L]));
+    hipLaunchKernelGGL((dev::k_coarse_solve_mc<T, D, K, D>), dim3(1), dim3(dev::kBlock), 0, st, nco,
+                       C.chol, bL, xL);
   for (int l = L - 1; l >= 0; --l) {
     const DevLevel& lv = C.lev[l];
     T* b = static_cast<T*>(C.kb[l]);
@@ -1733,7 +1770,7 @@ int64_t estimate_device_bytes(const vasmg_ctx& C) {
   }
   b += transient;
   const int64_t n0p = H.levels[0].n * DP;
-  b += 6 * n0p * 8 + H.levels[0].n * 4 + H.n_coarse_dofs * H.n_coarse_dofs * 8;
+  b += 6 * n0p * 8 + H.levels[0].n * 4 + H.n_coarse_dofs * H.n_coarse_dofs * 16;   // factor + inverse
   b += (std::max<int64_t>(kFlatGrid, H.levels[0].n / 4 + 1)) * 8 * (1 + K);
   b += 5 * n0p * 8 * K;
   return b + b / 20 + (1 << 20);
@@ -2239,7 +2276,10 @@ vasmg_status vasmg_apply_precond_device(vasmg_handle h, const double* d_r, doubl
       T* b = static_cast<T*>(h->lev[0].b);
       T* x = static_cast<T*>(h->lev[0].x);
       debug_gather<T, D>(*h, 0, d_r, b, st);
-      if (h->L == 0) {
+      if (h->L == 0 && h->cinv) {
+        hipLaunchKernelGGL((dev::k_coarse_apply<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
+                           static_cast<int>(h->n_coarse), h->cinv, b, x, h->zero_flag);
+      } else if (h->L == 0) {
         hipLaunchKernelGGL((dev::k_coarse_solve<T, D>), dim3(1), dim3(dev::kBlock), 0, st,
                            static_cast<int>(h->n_coarse), h->chol, b, x, h->zero_flag);
       } else {
