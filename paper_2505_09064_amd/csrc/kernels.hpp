@@ -771,6 +771,265 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __
 }
 
 // ---------------------------------------------------------------------------
+// The bottom of the cycle in one workgroup: the last few cell levels above a
+// small coarsest level (smoothing, residual, restriction, prolongation) and the
+// coarsest solve by the inverse, which would otherwise take 2 x colours + 3
+// launches per level, each too small to fill the chip. The levels' vectors
+// live in LDS; each wavefront updates one cell of the current colour (GR =
+// 64 / 2^d lanes per row) with the arithmetic of k_gs_cell / k_cell_apply, and
+// colours and phases are separated by workgroup barriers. Several levels are
+// fused only for the V-cycle (one visit per level); the first level may start
+// from a nonzero iterate (second visit of a W-cycle).
+// ---------------------------------------------------------------------------
+constexpr int kBottomThreads = 512;
+constexpr int kBottomLevels = 4;
+constexpr int kBottomLds = 56 * 1024;   // dynamic LDS for the levels' vectors
+
+template <typename T>
+struct BottomLevel {
+  int n = 0, ncolors = 0, ncells = 0, nnext = 0;
+  const int* color_ptr = nullptr;   // cells of each colour, [ncolors + 1]
+  const int* cell_ptr = nullptr;
+  Part<T> L{}, U{};
+  const T* cellM = nullptr;
+  const int *p_ptr = nullptr, *p_idx = nullptr;
+  const T* p_w = nullptr;
+  const int *pt_ptr = nullptr, *pt_idx = nullptr;
+  const T* pt_w = nullptr;
+};
+
+template <typename T>
+struct BottomArgs {
+  int nlev = 0, ncoarse = 0;
+  int npre = 1, npost = 1, zero_guess = 1;
+  const BottomLevel<T>* lev = nullptr;   // device array [nlev]
+  const double* Minv = nullptr;
+  const T* b = nullptr;   // first fused level's right-hand side (in)
+  T* x = nullptr;         // first fused level's iterate (in unless zero_guess, out)
+};
+
+// One level in LDS: right-hand side, iterate, saved s, residual, and copies of
+// the colour, cell and row pointers (the sweeps' dependent index loads).
+template <typename T>
+struct BottomVecs {
+  T *b, *x, *s, *r;
+  int *color_ptr, *cell_ptr, *Lptr, *Uptr;
+};
+
+// LDS elements of one level: four padded vectors (T) and its pointers (int).
+__host__ __device__ inline int bottom_vec_elems(int n, int dp) { return 4 * n * dp; }
+__host__ __device__ inline int bottom_int_elems(int n, int ncolors, int ncells) {
+  return (ncolors + 1) + (ncells + 1) + 2 * (n + 1);
+}
+
+// One cell by one wavefront (MODE as k_gs_cell: 0 zero-guess forward, 1 forward,
+// 2 backward); RES: compute r = s - U x - M x instead of a sweep.
+template <typename T, int D, int MODE, bool RES>
+__device__ __forceinline__ void bottom_cell(const BottomLevel<T>& lv, int c, const BottomVecs<T>& v) {
+  constexpr int DP = Pad<D>::value;
+  constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
+  constexpr int GR = 64 / NV;
+  const int lane = threadIdx.x & 63;
+  const int v0 = v.cell_ptr[c], m = v.cell_ptr[c + 1] - v0, n = m * D;
+  // the in-cell block row first, so its loads overlap the off-cell products
+  const int t = lane;
+  const bool own = t < n;
+  const int k = own ? t / D : 0, comp = own ? t % D : 0;
+  T Mrow[NU];
+  const T* Mc = lv.cellM + static_cast<int64_t>(c) * NU * NU;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
+  const int g = lane / GR, gl = lane % GR;
+  T lo[D], up[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) { lo[q] = T(0); up[q] = T(0); }
+  const bool want_lo = !RES, want_up = RES || MODE != 0;
+  if (g < m) {
+    const int i = v0 + g;
+    if (want_lo) part_quad_product<T, D, GR>(Part<T>{v.Lptr, lv.L.col, lv.L.val, lv.L.nnz}, i, gl, v.x, lo);
+    if (want_up) part_quad_product<T, D, GR>(Part<T>{v.Uptr, lv.U.col, lv.U.val, lv.U.nnz}, i, gl, v.x, up);
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    lo[q] = group_sum<T, GR>(lo[q]);
+    up[q] = group_sum<T, GR>(up[q]);
+  }
+  T my_lo = T(0), my_up = T(0);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {   // every lane takes part in each shuffle
+    const T l1 = __shfl(lo[q], k * GR, 64), u1 = __shfl(up[q], k * GR, 64);
+    if (q == comp) { my_lo = l1; my_up = u1; }
+  }
+  const int xi = (v0 + k) * DP + comp;
+  T xc = (own && (MODE != 0 || RES)) ? v.x[xi] : T(0);
+  if (RES) {
+    T mx = T(0);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u < n) mx += Mrow[u] * bcast(xc, u);
+    }
+    if (own) v.r[xi] = v.s[xi] - my_up - mx;
+    return;
+  }
+  const T s_t = own ? v.b[xi] - my_lo : T(0);
+  if (MODE != 2 && own) v.s[xi] = s_t;
+  T acc = s_t - (MODE != 0 ? my_up : T(0));
+  if (MODE != 0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if (u < n) {
+        const T xu = bcast(xc, u);
+        if (u != t) acc -= Mrow[u] * xu;
+      }
+    }
+  }
+#pragma unroll
+  for (int uu = 0; uu < NU; ++uu) {
+    const int u = MODE == 2 ? NU - 1 - uu : uu;
+    if (u < n) {
+      T delta = T(0);
+      if (t == u) {
+        const T xn = acc / Mrow[u];
+        delta = xn - xc;
+        xc = xn;
+      }
+      delta = bcast(delta, u);
+      if (t != u) acc -= Mrow[u] * delta;
+    }
+  }
+  if (own) v.x[xi] = xc;
+}
+
+template <typename T, int D, int MODE>
+__device__ __forceinline__ void bottom_sweep(const BottomLevel<T>& lv, const BottomVecs<T>& v) {
+  const int w = threadIdx.x >> 6, nw = kBottomThreads / 64;
+  for (int q = 0; q < lv.ncolors; ++q) {
+    const int col = MODE == 2 ? lv.ncolors - 1 - q : q;
+    for (int c = v.color_ptr[col] + w; c < v.color_ptr[col + 1]; c += nw)
+      bottom_cell<T, D, MODE, false>(lv, c, v);
+    __syncthreads();
+  }
+}
+
+// Gather over a scalar CSR (rows [0, nrows), weights shared by the components)
+// from the padded vector src into dst (ADD: dst += ...).
+template <typename T, int D, bool ADD, typename TD>
+__device__ __forceinline__ void bottom_transfer(int nrows, const int* ptr, const int* idx,
+                                                const T* w, const T* src, int sstride, TD* dst,
+                                                int dstride) {
+  for (int i = threadIdx.x; i < nrows; i += blockDim.x) {
+    T acc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc[q] = T(0);
+    for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+      const T wp = w[p];
+      const T* e = src + idx[p] * sstride;
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc[q] += wp * e[q];
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      if (ADD)
+        dst[i * dstride + q] += acc[q];
+      else
+        dst[i * dstride + q] = static_cast<TD>(acc[q]);
+    }
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a,
+                                                           const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DP = Pad<D>::value;
+  extern __shared__ __align__(16) unsigned char bottom_smem[];
+  __shared__ double cy[kCoarseInvMax];
+  __shared__ T cx[kCoarseInvMax];
+  // LDS: every level's vectors (T), then every level's pointers (int)
+  T* base = reinterpret_cast<T*>(bottom_smem);
+  int total = 0;
+  for (int j = 0; j < a.nlev; ++j) total += bottom_vec_elems(a.lev[j].n, DP);
+  int* ibase = reinterpret_cast<int*>(base + total);
+  auto vecs = [&](int k) {   // level k's LDS arrays
+    int off = 0, ioff = 0;
+    for (int j = 0; j < k; ++j) {
+      off += bottom_vec_elems(a.lev[j].n, DP);
+      ioff += bottom_int_elems(a.lev[j].n, a.lev[j].ncolors, a.lev[j].ncells);
+    }
+    const BottomLevel<T>& lv = a.lev[k];
+    const int len = lv.n * DP;
+    int* cp = ibase + ioff;
+    int* cl = cp + lv.ncolors + 1;
+    int* lp = cl + lv.ncells + 1;
+    return BottomVecs<T>{base + off, base + off + len, base + off + 2 * len, base + off + 3 * len,
+                         cp, cl, lp, lp + lv.n + 1};
+  };
+  // zero vectors, pointer copies; first level: b and (second W-cycle visit) x
+  // from HBM; deeper levels start at zero
+  {
+    for (int e = threadIdx.x; e < total; e += blockDim.x) base[e] = T(0);
+    for (int k = 0; k < a.nlev; ++k) {
+      const BottomLevel<T>& lv = a.lev[k];
+      const BottomVecs<T> v = vecs(k);
+      for (int e = threadIdx.x; e <= lv.ncolors; e += blockDim.x) v.color_ptr[e] = lv.color_ptr[e];
+      for (int e = threadIdx.x; e <= lv.ncells; e += blockDim.x) v.cell_ptr[e] = lv.cell_ptr[e];
+      for (int e = threadIdx.x; e <= lv.n; e += blockDim.x) {
+        v.Lptr[e] = lv.L.ptr[e];
+        v.Uptr[e] = lv.U.ptr[e];
+      }
+    }
+    __syncthreads();
+    const BottomVecs<T> v = vecs(0);
+    const int len = a.lev[0].n * DP;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+      v.b[e] = a.b[e];
+      if (!a.zero_guess) v.x[e] = a.x[e];
+    }
+    __syncthreads();
+  }
+  // down: pre-smoothing, residual r = s - U x - M x, restriction
+  for (int k = 0; k < a.nlev; ++k) {
+    const BottomLevel<T>& lv = a.lev[k];
+    const BottomVecs<T> v = vecs(k);
+    for (int it = 0; it < a.npre; ++it) {
+      if (it == 0 && (k > 0 || a.zero_guess))
+        bottom_sweep<T, D, 0>(lv, v);
+      else
+        bottom_sweep<T, D, 1>(lv, v);
+    }
+    const int w = threadIdx.x >> 6, nw = kBottomThreads / 64;
+    for (int c = w; c < lv.ncells; c += nw) bottom_cell<T, D, 1, true>(lv, c, v);
+    __syncthreads();
+    if (k + 1 < a.nlev)
+      bottom_transfer<T, D, false, T>(lv.nnext, lv.pt_ptr, lv.pt_idx, lv.pt_w, v.r, DP, vecs(k + 1).b, DP);
+    else   // the coarsest right-hand side, rounded to T as in the level vectors
+      bottom_transfer<T, D, false, double>(lv.nnext, lv.pt_ptr, lv.pt_idx, lv.pt_w, v.r, DP, cy, D);
+    __syncthreads();
+  }
+  // coarsest: x = A_c^{-1} b, rows in ascending column order (FP64)
+  for (int i = threadIdx.x; i < a.ncoarse; i += blockDim.x) {
+    const double* row = a.Minv + static_cast<int64_t>(i) * a.ncoarse;
+    double s = 0.0;
+    for (int j = 0; j < a.ncoarse; ++j) s += row[j] * cy[j];
+    cx[i] = static_cast<T>(s);
+  }
+  __syncthreads();
+  // up: prolongation x += P e, post-smoothing
+  for (int k = a.nlev - 1; k >= 0; --k) {
+    const BottomLevel<T>& lv = a.lev[k];
+    const BottomVecs<T> v = vecs(k);
+    if (k + 1 < a.nlev)
+      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, vecs(k + 1).x, DP, v.x, DP);
+    else
+      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, cx, D, v.x, DP);
+    __syncthreads();
+    for (int it = 0; it < a.npost; ++it) bottom_sweep<T, D, 2>(lv, v);
+  }
+  const BottomVecs<T> v = vecs(0);
+  for (int e = threadIdx.x; e < a.lev[0].n * DP; e += blockDim.x) a.x[e] = v.x[e];
+}
+
+// ---------------------------------------------------------------------------
 // K7/K8: PCG vector kernels and device-side scalars (FP64, deterministic).
 // ---------------------------------------------------------------------------
 struct Scalars {

@@ -72,6 +72,7 @@ struct DevLevel {
   bool cells = false;              // coarse lattice level: Gauss-Seidel over cells
   int ncells = 0;
   int* cell_ptr = nullptr;         // cell levels: first device row of each cell
+  int* color_ptr_dev = nullptr;    // device copy of color_ptr (fused bottom levels only)
   float* cellM32 = nullptr;        // cell levels: dense in-cell blocks (column-major)
   double* cellM64 = nullptr;
   int* perm = nullptr;             // device row -> canonical index
@@ -157,6 +158,12 @@ struct vasmg_ctx {
   std::vector<DevLevel> lev;
   double* chol = nullptr;           // coarsest factor
   double* cinv = nullptr;           // coarsest inverse (small coarsest levels), else null
+  // fused bottom (k_bottom): levels bottom_lo..L-1 and the coarsest solve in one
+  // workgroup; -1 when the cycle has none
+  int bottom_lo = -1;
+  int64_t bottom_vec = 0, bottom_int = 0;   // its LDS elements: vectors (T), pointers (int)
+  dev::BottomLevel<float>* bottom32 = nullptr;
+  dev::BottomLevel<double>* bottom64 = nullptr;
   int64_t n_coarse = 0;
   // PCG state (FP64, padded, fine device numbering)
   int n0 = 0;
@@ -572,6 +579,8 @@ std::vector<double> coarse_inverse(const std::vector<double>& Lf, int64_t n) {
   return M;
 }
 
+void select_bottom(vasmg_ctx& C);
+
 void upload_all(vasmg_ctx& C) {
   const int nl = static_cast<int>(C.H.levels.size());
   C.L = nl - 1;
@@ -605,6 +614,8 @@ void upload_all(vasmg_ctx& C) {
       throw vasmg::Error{VASMG_EINVAL, "coarsest level has more than 4096 DOFs"};
     C.chol = C.upload(C.H.chol);
     if (C.n_coarse <= dev::kCoarseInvMax) C.cinv = C.upload(coarse_inverse(C.H.chol, C.n_coarse));
+    if (C.cinv && C.L >= 2 && C.opt.smoother == VASMG_SMOOTHER_GS && C.opt.n_pre >= 1)
+      select_bottom(C);
   }
   // PCG vectors
   C.n0 = static_cast<int>(C.H.levels[0].n);
@@ -675,6 +686,69 @@ struct LevelMats<double> {
   static const double* dinv(const DevLevel& l) { return l.dinv64; }
   static bool ok(const DevLevel& l) { return l.has64; }
 };
+
+// cells per colour that the fused bottom takes in at most two rounds of its wavefronts
+constexpr int kBottomCellsPerColour = 2 * dev::kBottomThreads / 64;
+
+template <typename T>
+dev::BottomLevel<T>* upload_bottom(vasmg_ctx& C) {
+  std::vector<dev::BottomLevel<T>> v;
+  for (int l = C.bottom_lo; l < C.L; ++l) {
+    const DevLevel& lv = C.lev[l];
+    if (!LevelMats<T>::ok(lv)) return nullptr;
+    dev::BottomLevel<T> b;
+    b.n = lv.n;
+    b.ncolors = lv.ncolors;
+    b.ncells = lv.ncells;
+    b.nnext = lv.nnext;
+    b.color_ptr = lv.color_ptr_dev;
+    b.cell_ptr = lv.cell_ptr;
+    b.L = LevelMats<T>::L(lv);
+    b.U = LevelMats<T>::U(lv);
+    b.cellM = LevelMats<T>::cellM(lv);
+    b.p_ptr = lv.p_ptr;
+    b.p_idx = lv.p_idx;
+    b.p_w = LevelMats<T>::pw(lv);
+    b.pt_ptr = lv.pt_ptr;
+    b.pt_idx = lv.pt_idx;
+    b.pt_w = LevelMats<T>::ptw(lv);
+    v.push_back(b);
+  }
+  return C.upload(v);
+}
+
+// Chooses the levels of the fused bottom: from L-1 upwards, cell levels whose
+// colours hold few cells (each colour a round or two of the workgroup's
+// wavefronts) and whose LDS vectors fit together; one level for the W-cycle,
+// which visits the levels above L-1 twice.
+void select_bottom(vasmg_ctx& C) {
+  const int tb = C.lev[C.L - 1].has64 ? 8 : 4;
+  const int maxlev = C.opt.cycle == VASMG_CYCLE_W ? 1 : dev::kBottomLevels;
+  auto fits = [&](const DevLevel& lv) {
+    if (!lv.cells) return false;
+    for (int c = 0; c < lv.ncolors; ++c)
+      if (lv.color_ptr[c + 1] - lv.color_ptr[c] > kBottomCellsPerColour) return false;
+    return true;
+  };
+  int lo = C.L;
+  int64_t nvec = 0, nint = 0;
+  while (lo - 1 >= 1 && C.L - (lo - 1) <= maxlev) {
+    const DevLevel& lv = C.lev[lo - 1];
+    const int64_t e = dev::bottom_vec_elems(lv.n, C.DP);
+    const int64_t ie = dev::bottom_int_elems(lv.n, lv.ncolors, lv.ncells);
+    if (!fits(lv) || (nvec + e) * tb + (nint + ie) * 4 > dev::kBottomLds) break;
+    nvec += e;
+    nint += ie;
+    --lo;
+  }
+  if (lo == C.L) return;
+  C.bottom_lo = lo;
+  C.bottom_vec = nvec;
+  C.bottom_int = nint;
+  for (int l = lo; l < C.L; ++l) C.lev[l].color_ptr_dev = C.upload(C.lev[l].color_ptr);
+  C.bottom32 = upload_bottom<float>(C);
+  C.bottom64 = upload_bottom<double>(C);
+}
 
 // Returns the number of workgroups (= partial sums written when partial != NULL).
 template <typename T, int D>
@@ -933,6 +1007,17 @@ LevelBytes level_bytes(const vasmg_ctx& C, int l, int tb) {
   return b;
 }
 
+template <typename T>
+struct BottomOf;
+template <>
+struct BottomOf<float> {
+  static const dev::BottomLevel<float>* get(const vasmg_ctx& C) { return C.bottom32; }
+};
+template <>
+struct BottomOf<double> {
+  static const dev::BottomLevel<double>* get(const vasmg_ctx& C) { return C.bottom64; }
+};
+
 // One V-cycle: lev[0].b -> lev[0].x (Algorithm 3, recursive, zero initial guess).
 // One visit of level l of the multiplicative cycle (Algorithm 3, recursive):
 // smoothing from zero (zero_guess) or from the current x, residual, restriction,
@@ -963,6 +1048,31 @@ void enqueue_level(vasmg_ctx& C, int l, bool zero_guess, const int* done, hipStr
   T* s = static_cast<T*>(lv.s);
   T* r = static_cast<T*>(lv.r);
   const LevelBytes by = prof ? level_bytes(C, l, tb) : LevelBytes{};
+  const dev::BottomLevel<T>* bottom = BottomOf<T>::get(C);
+  if (l == C.bottom_lo && bottom) {
+    dev::BottomArgs<T> a;
+    a.nlev = L - l;
+    a.ncoarse = static_cast<int>(C.n_coarse);
+    a.npre = npre;
+    a.npost = npost;
+    a.zero_guess = zero_guess ? 1 : 0;
+    a.lev = bottom;
+    a.Minv = C.cinv;
+    a.b = b;
+    a.x = x;
+    double bytes = static_cast<double>(C.n_coarse) * C.n_coarse * 8.0;
+    if (prof)
+      for (int k = l; k < L; ++k) {
+        const LevelBytes bk = level_bytes(C, k, tb);
+        bytes += npre * bk.gs_fwd + bk.residual + bk.restrict_ + bk.prolong + npost * bk.gs_bwd;
+      }
+    const size_t lds = static_cast<size_t>(C.bottom_vec) * sizeof(T) + C.bottom_int * sizeof(int);
+    run_phase(prof, "bottom", l, 1, bytes, [&] {
+      hipLaunchKernelGGL((dev::k_bottom<T, D>), dim3(1), dim3(dev::kBottomThreads), lds, st, a,
+                         done);
+    });
+    return;
+  }
   const bool jac = C.opt.smoother == VASMG_SMOOTHER_JACOBI;
   if (jac) {
     // damped block Jacobi: x = w D^-1 b from zero, then x += w D^-1 (b - A x)

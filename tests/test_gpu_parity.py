@@ -363,3 +363,58 @@ def test_jacobi_smoother_parity(name, cycle):
     assert abs(info["iterations"] - io["iterations"]) <= 1
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
     s.free()
+
+
+def _expected_bottom(s, tb, cycle):
+    """First level of the fused bottom (levels lo..L-1 and the coarsest solve in
+    one workgroup) under the selection rule: Gauss-Seidel cell levels from L-1
+    upwards, at most 16 cells per colour, their LDS arrays within 56 KiB, at
+    most 4 levels (1 for the W-cycle), never level 0, coarsest solve by the
+    inverse (at most 256 DOFs)."""
+    nl, _, dim = s.hierarchy_info()
+    L = nl - 1
+    if L < 2 or s.level_info(L)["n_vertices"] * dim > 256:
+        return None
+    dp = 4 if dim == 3 else 2
+    maxlev = 1 if cycle == V.CYCLE_W else 4
+    lo, used = L, 0
+    while lo - 1 >= 1 and L - (lo - 1) <= maxlev:
+        e = s.export_level(lo - 1)
+        n, ncol = e["n_vertices"], e["n_colors"]
+        per = {}
+        for c, col in set(zip(e["cell"].tolist(), e["color"].tolist())):
+            per[col] = per.get(col, 0) + 1
+        ncells = len(set(e["cell"].tolist()))
+        size = 4 * n * dp * tb + 4 * ((ncol + 1) + (ncells + 1) + 2 * (n + 1))
+        if max(per.values()) > 16 or used + size > 56 * 1024:
+            break
+        used += size
+        lo -= 1
+    return None if lo == L else lo
+
+
+@pytest.mark.parametrize("cycle", [V.CYCLE_V, V.CYCLE_W])
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+@pytest.mark.parametrize("name", list(MESHES))
+def test_fused_bottom_selection(name, prec, cycle):
+    """The bottom levels run as one fused launch exactly where the selection rule
+    says (these meshes fuse 1 to 4 levels, so the preconditioner parity tests
+    above cover each depth in 2D and 3D, FP64 and FP32), and the preconditioner
+    with it still matches the oracle."""
+    m = MESHES[name]()
+    s = V.Solver.from_mesh(m, precision=prec, cycle=cycle)
+    lo = _expected_bottom(s, 8 if prec == V.FP64 else 4, cycle)
+    assert lo is not None
+    phases = s.profile_iteration(1)
+    bottom = [p for p in phases if p["name"] == "bottom"]
+    assert [p["level"] for p in bottom] == [lo]
+    assert max(p["level"] for p in phases) == lo
+    cname = {V.CYCLE_V: "V", V.CYCLE_W: "W"}[cycle]
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(cycle=cname))
+    n = o.A[0].shape[0] // m.dim
+    r = np.random.default_rng(4).normal(size=(n, m.dim))
+    z = torch.zeros_like(_dev(r))
+    s.apply_precond_device(_dev(r), z)
+    tol = 1e-11 if prec == V.FP64 else 1e-4
+    assert _rel(_host(z).ravel(), o.apply_precond(r.ravel(), precision="fp64")) < tol
+    s.free()
