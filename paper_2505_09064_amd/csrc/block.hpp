@@ -303,6 +303,7 @@ __device__ __forceinline__ void mc_cell_sweep_pair(int k0, int v0, int n, const 
     acc = su - (MODE != 0 ? sh.up[row][k][a] : T(0));
     if (MODE != 0) xc = x[o];
   }
+  const T rdg = own_reciprocal<T, NU>(Mrow, t, own);
   if (MODE != 0) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -318,7 +319,7 @@ __device__ __forceinline__ void mc_cell_sweep_pair(int k0, int v0, int n, const 
     if (u < n) {
       T delta = T(0);
       if (t == u && own) {
-        const T xn = acc / Mrow[u];
+        const T xn = acc * rdg;
         delta = xn - xc;
         xc = xn;
       }

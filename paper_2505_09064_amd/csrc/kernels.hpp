@@ -459,6 +459,18 @@ __device__ __forceinline__ T cell_bcast(T v, int slot, int u) {
     return __shfl(v, slot * CT + u, 64);
 }
 
+// Reciprocal of the lane's own diagonal entry Mrow[t] (1 for lanes without a
+// row), taken once before the sequential in-cell sweep: each of its steps then
+// costs a multiply instead of a division on the dependent chain.
+template <typename T, int NU>
+__device__ __forceinline__ T own_reciprocal(const T* Mrow, int t, bool own) {
+  T dg = T(1);
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (u == t) dg = Mrow[u];
+  return own ? T(1) / dg : T(1);
+}
+
 // Per-cell block of NV * GR threads: lane group g (GR lanes, inside one
 // wavefront) sums the off-cell part of the cell's g-th row; the sums meet in
 // LDS; wavefront 0 then runs the sequential sweep over the cell's unknowns.
@@ -529,6 +541,7 @@ __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_gs_cell(
   const T sup = (own && MODE != 0) ? sh_up[slot][k][a] : T(0);
   if (MODE != 2 && s_save && own) s_save[xi] = s_t;
   T acc = s_t - sup;
+  const T rdg = own_reciprocal<T, NU>(Mrow, t, own);
   // with one cell per wavefront n is uniform and the guards below are the loop
   // bounds; with several, every lane takes part in each broadcast
   if (MODE != 0) {
@@ -546,7 +559,7 @@ __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_gs_cell(
       if (CPW > 1 || u < n) {
         T delta = T(0);
         if (t == u && u < n) {
-          const T xn = acc / Mrow[u];
+          const T xn = acc * rdg;
           delta = xn - xc;
           xc = xn;
         }
@@ -560,7 +573,7 @@ __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_gs_cell(
       if (CPW > 1 || u < n) {
         T delta = T(0);
         if (t == u && u < n) {
-          const T xn = acc / Mrow[u];
+          const T xn = acc * rdg;
           delta = xn - xc;
           xc = xn;
         }
@@ -874,6 +887,7 @@ __device__ __forceinline__ void bottom_cell(const BottomLevel<T>& lv, int c, con
   const T s_t = own ? v.b[xi] - my_lo : T(0);
   if (MODE != 2 && own) v.s[xi] = s_t;
   T acc = s_t - (MODE != 0 ? my_up : T(0));
+  const T rdg = own_reciprocal<T, NU>(Mrow, t, own);
   if (MODE != 0) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -889,7 +903,7 @@ __device__ __forceinline__ void bottom_cell(const BottomLevel<T>& lv, int c, con
     if (u < n) {
       T delta = T(0);
       if (t == u) {
-        const T xn = acc / Mrow[u];
+        const T xn = acc * rdg;
         delta = xn - xc;
         xc = xn;
       }
