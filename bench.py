@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "5f01c8db88d708a6f1b24b29f45cb19cb464d5c3a9c0d91f81d47b5f70828d30",
-                  "bytes_per_launch": 48657484}
+TRAFFIC_RECORD = {"kernels_sha256": "1d38cc99f8dbdcd33a4003e2b4319f2a4fada2f9f90dc090f29b4cc330c8ab57",
+                  "bytes_per_launch": 48648769}
 
 
 def traffic_per_launch():
