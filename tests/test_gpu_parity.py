@@ -418,3 +418,24 @@ def test_fused_bottom_selection(name, prec, cycle):
     tol = 1e-11 if prec == V.FP64 else 1e-4
     assert _rel(_host(z).ravel(), o.apply_precond(r.ravel(), precision="fp64")) < tol
     s.free()
+
+
+@pytest.mark.parametrize("sweeps", [(2, 1), (1, 0), (2, 2), (0, 1)])
+@pytest.mark.parametrize("name", ["cfg1_2d", "small3d_n9"])
+def test_sweep_counts_parity(name, sweeps):
+    """Several or no pre- and post-smoothing sweeps per level: the preconditioner
+    application against the oracle with the same counts (FP64). With at least one
+    pre-sweep the bottom levels run fused (several sweeps per level inside one
+    workgroup); without, every level launches on its own."""
+    n_pre, n_post = sweeps
+    m = MESHES[name]()
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(n_pre=n_pre, n_post=n_post))
+    s = V.Solver.from_mesh(m, precision=V.FP64, n_pre=n_pre, n_post=n_post)
+    fused = [p["level"] for p in s.profile_iteration(1) if p["name"] == "bottom"]
+    assert fused == ([_expected_bottom(s, 8, V.CYCLE_V)] if n_pre >= 1 else [])
+    n = o.A[0].shape[0] // m.dim
+    r = np.random.default_rng(5).normal(size=(n, m.dim))
+    z = torch.zeros_like(_dev(r))
+    s.apply_precond_device(_dev(r), z)
+    assert _rel(_host(z).ravel(), o.apply_precond(r.ravel(), precision="fp64")) < 1e-11
+    s.free()
