@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "1d38cc99f8dbdcd33a4003e2b4319f2a4fada2f9f90dc090f29b4cc330c8ab57",
-                  "bytes_per_launch": 48648769}
+TRAFFIC_RECORD = {"kernels_sha256": "139ac9449ed8e5430e12be81d4908feae9621720a49d1866c90eb8a5a22539e9",
+                  "bytes_per_launch": 48555591}
 
 
 def traffic_per_launch():

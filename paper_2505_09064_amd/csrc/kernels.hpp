@@ -798,6 +798,20 @@ constexpr int kBottomThreads = 512;
 constexpr int kBottomLevels = 4;
 constexpr int kBottomLds = 56 * 1024;   // dynamic LDS for the levels' vectors
 
+// Pointers that k_bottom reads from its level table (device memory, not kernel
+// arguments) are generic to the compiler, which then emits flat loads: counted
+// against both the memory and the LDS wait counters, so LDS reads also wait for
+// the matrix loads in flight. Its matrix loads go through pointers in the global
+// address space instead.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+typedef int gint4 __attribute__((ext_vector_type(4)));
+typedef float gfloat4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(const T* p) {
+  return (gptr<T>)p;
+}
+
 template <typename T>
 struct BottomLevel {
   int n = 0, ncolors = 0, ncells = 0, nnext = 0;
@@ -835,6 +849,42 @@ __host__ __device__ inline int bottom_int_elems(int n, int ncolors, int ncells) 
   return (ncolors + 1) + (ncells + 1) + 2 * (n + 1);
 }
 
+// acc += the products of positions [kb, ke) of one part with the LDS iterate x:
+// quads of 4 blocks (FP32, one 16-byte load per plane) or single blocks (FP64),
+// loaded through global-address-space pointers.
+template <typename T, int D, int G>
+__device__ __forceinline__ void bottom_part(int kb, int ke, int lane, const int* col, const T* val,
+                                            int64_t nnz, const T* x, T* acc) {
+  constexpr int DP = Pad<D>::value;
+  const gptr<int> gc = to_global(col);
+  const gptr<T> gv = to_global(val);
+  if constexpr (sizeof(T) == 4) {
+    for (int q = kb / kQuad + lane; q < ke / kQuad; q += G) {
+      const gint4 j = *reinterpret_cast<gptr<gint4>>(gc + q * kQuad);
+      const int jj[kQuad] = {j.x, j.y, j.z, j.w};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const gfloat4 v = *reinterpret_cast<gptr<gfloat4>>(
+              gv + static_cast<int64_t>(a * D + b) * nnz + static_cast<int64_t>(q) * kQuad);
+          acc[a] += v.x * x[jj[0] * DP + b] + v.y * x[jj[1] * DP + b] + v.z * x[jj[2] * DP + b] +
+                    v.w * x[jj[3] * DP + b];
+        }
+      }
+    }
+  } else {
+    for (int k = kb + lane; k < ke; k += G) {
+      const int j = gc[k];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) acc[a] += gv[static_cast<int64_t>(a * D + b) * nnz + k] * x[j * DP + b];
+      }
+    }
+  }
+}
+
 // One cell by one wavefront (MODE as k_gs_cell: 0 zero-guess forward, 1 forward,
 // 2 backward); RES: compute r = s - U x - M x instead of a sweep.
 template <typename T, int D, int MODE, bool RES>
@@ -849,7 +899,7 @@ __device__ __forceinline__ void bottom_cell(const BottomLevel<T>& lv, int c, con
   const bool own = t < n;
   const int k = own ? t / D : 0, comp = own ? t % D : 0;
   T Mrow[NU];
-  const T* Mc = lv.cellM + static_cast<int64_t>(c) * NU * NU;
+  const gptr<T> Mc = to_global(lv.cellM) + static_cast<int64_t>(c) * NU * NU;
 #pragma unroll
   for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
   const int g = lane / GR, gl = lane % GR;
@@ -859,8 +909,8 @@ __device__ __forceinline__ void bottom_cell(const BottomLevel<T>& lv, int c, con
   const bool want_lo = !RES, want_up = RES || MODE != 0;
   if (g < m) {
     const int i = v0 + g;
-    if (want_lo) part_quad_product<T, D, GR>(Part<T>{v.Lptr, lv.L.col, lv.L.val, lv.L.nnz}, i, gl, v.x, lo);
-    if (want_up) part_quad_product<T, D, GR>(Part<T>{v.Uptr, lv.U.col, lv.U.val, lv.U.nnz}, i, gl, v.x, up);
+    if (want_lo) bottom_part<T, D, GR>(v.Lptr[i], v.Lptr[i + 1], gl, lv.L.col, lv.L.val, lv.L.nnz, v.x, lo);
+    if (want_up) bottom_part<T, D, GR>(v.Uptr[i], v.Uptr[i + 1], gl, lv.U.col, lv.U.val, lv.U.nnz, v.x, up);
   }
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -1022,7 +1072,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a,
   }
   // coarsest: x = A_c^{-1} b, rows in ascending column order (FP64)
   for (int i = threadIdx.x; i < a.ncoarse; i += blockDim.x) {
-    const double* row = a.Minv + static_cast<int64_t>(i) * a.ncoarse;
+    const gptr<double> row = to_global(a.Minv) + static_cast<int64_t>(i) * a.ncoarse;
     double s = 0.0;
     for (int j = 0; j < a.ncoarse; ++j) s += row[j] * cy[j];
     cx[i] = static_cast<T>(s);
