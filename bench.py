@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "139ac9449ed8e5430e12be81d4908feae9621720a49d1866c90eb8a5a22539e9",
-                  "bytes_per_launch": 48555591}
+TRAFFIC_RECORD = {"kernels_sha256": "43900f3a66a7dc60bc51e502d09ea84853036bc9ae422924f24385a67c8b8461",
+                  "bytes_per_launch": 48511440}
 
 
 def traffic_per_launch():

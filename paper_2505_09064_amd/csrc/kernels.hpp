@@ -796,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* __
 // ---------------------------------------------------------------------------
 constexpr int kBottomThreads = 512;
 constexpr int kBottomLevels = 4;
-constexpr int kBottomLds = 56 * 1024;   // dynamic LDS for the levels' vectors
+constexpr int kBottomLds = 56 * 1024;   // dynamic LDS: the levels' vectors and pointer copies
 
 // Pointers that k_bottom reads from its level table (device memory, not kernel
 // arguments) are generic to the compiler, which then emits flat loads: counted
