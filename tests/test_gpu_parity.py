@@ -313,10 +313,12 @@ def test_autotuned_handle_matches_oracle(name):
 
 
 @pytest.mark.parametrize("cycle", [V.CYCLE_W, V.CYCLE_ADDITIVE])
-@pytest.mark.parametrize("name", ["cfg1_2d", "small3d_n9"])
+@pytest.mark.parametrize("name", ["cfg1_2d", "small3d_n9", "mixed3d_n8"])
 def test_cycle_variants_parity(name, cycle):
     """W-cycle and additive two-level preconditioner: the preconditioner
-    application and the FP64 solve against the oracle with the same cycle."""
+    application and the FP64 solve against the oracle with the same cycle (on the
+    mixed-material mesh the fused bottom starts at level 1, where the additive form
+    enters the cycle)."""
     cname = {V.CYCLE_W: "W", V.CYCLE_ADDITIVE: "additive"}[cycle]
     m = MESHES[name]()
     o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(cycle=cname))
