@@ -722,6 +722,9 @@ dev::BottomLevel<T>* upload_bottom(vasmg_ctx& C) {
 // wavefronts) and whose LDS vectors fit together; one level for the W-cycle,
 // which visits the levels above L-1 twice.
 void select_bottom(vasmg_ctx& C) {
+  // the kernel restricts into (and prolongs from) the coarsest level's DOFs in LDS
+  if (static_cast<int64_t>(C.lev[C.L - 1].nnext) * C.d != C.n_coarse || C.n_coarse > dev::kCoarseInvMax)
+    return;
   const int tb = C.lev[C.L - 1].has64 ? 8 : 4;
   const int maxlev = C.opt.cycle == VASMG_CYCLE_W ? 1 : dev::kBottomLevels;
   auto fits = [&](const DevLevel& lv) {
