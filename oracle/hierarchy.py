@@ -17,8 +17,9 @@ derived from the structural block pattern; the sweep visits colours in order,
 the cells of a colour in any order (they are uncoupled) and the vertices of a
 cell one after the other in canonical order.
 
-Pins (tests/test_oracle_hierarchy.py): A_l symmetric positive definite, positive
-diagonal, coarse operators annihilate the interpolated rigid-body modes of the
+Pins (tests/test_oracle_solver.py, test_galerkin_spd_and_rigid_modes and
+test_cells_and_coloring): A_l symmetric positive definite, positive diagonal,
+coarse operators annihilate the interpolated rigid-body modes of the
 unconstrained operator, colouring validity.
 """
 from __future__ import annotations

@@ -9,9 +9,14 @@ preconditioner is applied only when the loop continues (Algorithm 2 applies it
 before its test; the extra application does not change U). beta is
 rho_new / rho_old as printed. The true residual is recomputed at exit.
 
-Pins (tests/test_oracle_pcg.py): on tiny systems the solution error is bounded
-by kappa(A) * rtol against a dense direct solve; with B = I, CG reaches rtol in
-at most n iterations; with B = A^{-1} it converges in one iteration.
+Pins (tests/test_oracle_solver.py, test_pcg_error_bound, test_plain_cg_within_n_iterations,
+test_coarsest_is_fine_level_gives_exact_inverse): on tiny systems the solution
+error is bounded by kappa(A) * rtol against a dense direct solve; with B = I,
+CG reaches rtol in at most n iterations; with B = A^{-1} it converges in one
+iteration. The flexible beta r_new^T (z_new - z_old) / rho_old
+(tests/test_oracle_precision.py): identical iterates to the printed beta under
+a fixed SPD preconditioner, different (and still converging) under one that
+varies between applications.
 """
 from __future__ import annotations
 

@@ -18,9 +18,12 @@ Two visiting orders:
     Section 2), in vertex order; realised with triangular solves, since one
     forward sweep is x_new = (D - L)^{-1} (b + S x_old).
 
-Pins (tests/test_oracle_smoother.py): a sweep equals a literal element-by-element
-Algorithm 1 loop on small dense matrices; the coloured sweep equals the
-lexicographic sweep of the colour-permuted matrix.
+Pins (tests/test_oracle_solver.py, test_gauss_seidel_orders): a sweep equals a
+literal element-by-element Algorithm 1 loop on small dense matrices; the
+coloured sweep equals the lexicographic sweep of the colour-permuted matrix.
+tests/test_oracle_precision.py: the float32 sweep equals a literal float32
+point loop up to summation order and is not FP64; the Jacobi step in
+test_oracle_solver.py, test_block_jacobi_smoother.
 """
 from __future__ import annotations
 

@@ -31,10 +31,15 @@ In FP32 emulation (``dtype=np.float32``) the level matrices, weights and V-cycle
 vectors are single precision; the coarsest right-hand side is cast to FP64,
 solved in FP64 and cast back.
 
-Pins (tests/test_oracle_vcycle.py): the dense operator of one cycle equals the
-closed form B_l = Mbar^{-1} + (I - M^{-T} A_l) P_l B_{l+1} P_l^T (I - A_l M^{-1})
-with Mbar^{-1} = M^{-1} + M^{-T} - M^{-T} A_l M^{-1}; B is symmetric positive
-definite; a one-level hierarchy gives B = A^{-1}.
+Pins (tests/test_oracle_solver.py, test_vcycle_closed_form_spd and the W-cycle
+and additive tests): the dense operator of one cycle equals the closed form
+B_l = Mbar^{-1} + (I - M^{-T} A_l) P_l B_{l+1} P_l^T (I - A_l M^{-1}) with
+Mbar^{-1} = M^{-1} + M^{-T} - M^{-T} A_l M^{-1}; B is symmetric positive
+definite; a one-level hierarchy gives B = A^{-1}. FP32 emulation
+(tests/test_oracle_precision.py): every stored operator, weight and smoother
+matrix is float32, the coarsest solve is FP64 (bitwise the rounded FP64 direct
+solve on a one-level hierarchy), and the cycle sits between 1e-9 and 1e-5 of
+the FP64 cycle.
 """
 from __future__ import annotations
 
