@@ -175,6 +175,25 @@ def _ptr(a) -> int:
     return a.ctypes.data
 
 
+def _check_tensor(t, shape, name, device=None):
+    """Raises ValueError unless t is a contiguous float64 tensor on a HIP device
+    (the handle's, when known) with exactly `shape`: the kernels index these
+    arrays by the handle's sizes and cannot check them."""
+    if t is None or not hasattr(t, "data_ptr") or not hasattr(t, "is_contiguous"):
+        raise ValueError(f"{name}: expected a torch tensor on a HIP device")
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: tensor is on {t.device}, not on a HIP device")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: tensor is on device {t.device.index}, the handle on {device}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -207,6 +226,11 @@ class Solver:
         _check(lib().vasmg_setup(C.byref(m), C.byref(opt), C.byref(h)))
         self._h = h
         self._arrays = None          # the library deep-copied the mesh
+        self.device = None           # HIP device the handle's memory lives on
+        if not opt.host_only:
+            import torch
+            if torch.cuda.is_available():
+                self.device = torch.cuda.current_device()
 
     @classmethod
     def from_mesh(cls, mesh, options: Options | None = None, **kw):
@@ -255,6 +279,16 @@ class Solver:
     def solve_device(self, d_rhs, d_x, rtol: float = 1e-6, d_x0=None, stream=None,
                      check: bool = True):
         """torch FP64 device tensors [n_rhs?, n_vertices, dim] (contiguous)."""
+        if not hasattr(d_rhs, "dim") or d_rhs.dim() not in (2, 3):
+            raise ValueError("d_rhs: expected a tensor [n_rhs?, n_vertices, dim]")
+        shape = ((self.n_vertices, self.dim) if d_rhs.dim() == 2
+                 else (d_rhs.shape[0], self.n_vertices, self.dim))
+        if d_rhs.dim() == 3 and d_rhs.shape[0] < 1:
+            raise ValueError("d_rhs: n_rhs must be >= 1")
+        _check_tensor(d_rhs, shape, "d_rhs", self.device)
+        _check_tensor(d_x, shape, "d_x", self.device)
+        if d_x0 is not None:
+            _check_tensor(d_x0, shape, "d_x0", self.device)
         n_rhs = 1 if d_rhs.dim() == 2 else d_rhs.shape[0]
         infos = (SolveInfo * n_rhs)()
         st = lib().vasmg_solve_device(self._h, _ptr(d_rhs), _ptr(d_x0), _ptr(d_x), n_rhs, rtol,
@@ -303,19 +337,35 @@ class Solver:
         return m.value, M.value, dep.value
 
     # -- single-step device entry points -----------------------------------
+    def _level_shape(self, level):
+        nl, _, _ = self.hierarchy_info()
+        if not 0 <= level < nl:
+            raise ValueError(f"level {level} out of range [0, {nl})")
+        return (self.level_info(level)["n_vertices"], self.dim)
+
     def spmv_device(self, level, precision, d_x, d_y, stream=None):
+        sh = self._level_shape(level)
+        _check_tensor(d_x, sh, "d_x", self.device)
+        _check_tensor(d_y, sh, "d_y", self.device)
         _check(lib().vasmg_spmv_device(self._h, level, precision, _ptr(d_x), _ptr(d_y),
                                        _stream_ptr(stream)))
 
     def gs_sweep_device(self, level, precision, backward, d_b, d_x, stream=None):
+        sh = self._level_shape(level)
+        _check_tensor(d_b, sh, "d_b", self.device)
+        _check_tensor(d_x, sh, "d_x", self.device)
         _check(lib().vasmg_gs_sweep_device(self._h, level, precision, int(backward), _ptr(d_b),
                                            _ptr(d_x), _stream_ptr(stream)))
 
     def restrict_device(self, level, precision, d_r, d_bc, stream=None):
+        _check_tensor(d_r, self._level_shape(level), "d_r", self.device)
+        _check_tensor(d_bc, self._level_shape(level + 1), "d_bc", self.device)
         _check(lib().vasmg_restrict_device(self._h, level, precision, _ptr(d_r), _ptr(d_bc),
                                            _stream_ptr(stream)))
 
     def prolong_device(self, level, precision, d_e, d_x, stream=None):
+        _check_tensor(d_e, self._level_shape(level + 1), "d_e", self.device)
+        _check_tensor(d_x, self._level_shape(level), "d_x", self.device)
         _check(lib().vasmg_prolong_device(self._h, level, precision, _ptr(d_e), _ptr(d_x),
                                           _stream_ptr(stream)))
 
@@ -329,6 +379,9 @@ class Solver:
                      bytes=o.bytes) for o in out[:n.value]]
 
     def apply_precond_device(self, d_r, d_z, stream=None):
+        sh = self._level_shape(0)
+        _check_tensor(d_r, sh, "d_r", self.device)
+        _check_tensor(d_z, sh, "d_z", self.device)
         _check(lib().vasmg_apply_precond_device(self._h, _ptr(d_r), _ptr(d_z),
                                                 _stream_ptr(stream)))
 

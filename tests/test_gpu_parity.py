@@ -441,3 +441,29 @@ def test_sweep_counts_parity(name, sweeps):
     s.apply_precond_device(_dev(r), z)
     assert _rel(_host(z).ravel(), o.apply_precond(r.ravel(), precision="fp64")) < 1e-11
     s.free()
+
+
+def test_binding_refuses_unsafe_device_tensors():
+    """Wrong dtype, shape, contiguity or a host tensor is refused by the binding
+    before any pointer reaches a kernel."""
+    m, o, s = _pair("small3d_n9", V.FP64)
+    nv, d = m.coords.shape
+    good = torch.zeros((nv, d), dtype=torch.float64, device="cuda")
+    bad = [torch.zeros((nv, d), dtype=torch.float32, device="cuda"),
+           torch.zeros((nv - 1, d), dtype=torch.float64, device="cuda"),
+           torch.zeros((d, nv), dtype=torch.float64, device="cuda").t(),
+           torch.zeros((nv, d), dtype=torch.float64)]
+    for b in bad:
+        with pytest.raises(ValueError):
+            s.solve_device(b, good, 1e-6)
+        with pytest.raises(ValueError):
+            s.solve_device(good.clone(), b, 1e-6)
+        with pytest.raises(ValueError):
+            s.solve_device(good.clone(), good, 1e-6, d_x0=b)
+    n0 = o.A[0].shape[0] // d
+    with pytest.raises(ValueError):
+        s.apply_precond_device(torch.zeros((n0 + 1, d), dtype=torch.float64, device="cuda"),
+                               torch.zeros((n0, d), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        s.gs_sweep_device(0, V.FP64, 0, torch.zeros((n0, d), dtype=torch.float32, device="cuda"),
+                          torch.zeros((n0, d), dtype=torch.float64, device="cuda"))

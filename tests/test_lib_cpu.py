@@ -180,3 +180,16 @@ def test_setup_device_option_validation():
         V.set_galerkin_window(-5)
     assert ei.value.status == V.EINVAL
     V.set_galerkin_window(0)
+
+
+def test_binding_refuses_tensors_it_cannot_pass_safely():
+    """The binding checks device tensors before handing their pointers to the
+    kernels (which index them by the handle's sizes)."""
+    torch = pytest.importorskip("torch")
+    from paper_2505_09064_amd.vasmg import _check_tensor
+    with pytest.raises(ValueError, match="HIP device"):
+        _check_tensor(torch.zeros((4, 3), dtype=torch.float64), (4, 3), "d_x")
+    with pytest.raises(ValueError, match="torch tensor"):
+        _check_tensor(np.zeros((4, 3)), (4, 3), "d_x")
+    with pytest.raises(ValueError, match="torch tensor"):
+        _check_tensor(None, (4, 3), "d_x")
