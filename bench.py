@@ -47,27 +47,74 @@ def traffic_per_launch():
     return None
 
 
-def cpu_baseline(n_grid: int = 33, reps: int = 3):
-    """The oracle (plain NumPy/SciPy FP64 V-ASMG-PCG, coloured Gauss-Seidel) on a
-    bounded sample of the workload: the same recipe at n_grid^3 vertices. Only the
-    solve phase is timed (median of reps); the rate is scaled to the full workload
-    by DOFs x iterations."""
+def host_cpu():
+    """Core count and CPU model of the machine the benchmark runs on."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(mesh, its_gpu: int, max_reps: int = 3, budget_s: float = 60.0):
+    """The oracle (plain NumPy/SciPy FP64 V-ASMG-PCG, coloured Gauss-Seidel in the
+    GPU's order) on the benchmarked workload itself, on one core: its setup is
+    timed apart, then the solve phase to rtol 1e-6 is timed up to max_reps times
+    (fewer once budget_s of solves have run); the median is reported."""
     from threadpoolctl import threadpool_limits
 
     from oracle import Oracle
-    from workloads import small3d
     with threadpool_limits(limits=1):
-        m = small3d(n_grid, seed=1, fix="x0")
         t0 = time.perf_counter()
-        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        o = Oracle(mesh.coords, mesh.elems, mesh.E, mesh.nu, mesh.fixed)
         t_setup = time.perf_counter() - t0
+        log(f"cpu baseline: oracle setup {t_setup:.1f}s")
         ts, its = [], 0
-        for _ in range(reps):
-            _, info = o.solve(m.rhs[0], 1e-6)
+        for r in range(max_reps):
+            _, info = o.solve(mesh.rhs[0], 1e-6)
             ts.append(info["solve_seconds"])
             its = info["iterations"]
+            log(f"cpu baseline: oracle solve {r}: {ts[-1]:.2f}s, {its} its")
+            if sum(ts) > budget_s:
+                break
     return dict(n_dofs=int(o.A[0].shape[0]), iterations=its, solve_s=float(np.median(ts)),
-                setup_s=t_setup, grid=n_grid)
+                reps=len(ts), setup_s=t_setup)
+
+
+def cpu_baseline_cfg1(reps: int = 10):
+    """The 33^2 manufactured-solution workload (1,922 DOFs): the plain method's
+    CPU seconds to rtol 1e-6 (oracle, FP64, one core), median of reps solves."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Oracle
+    from workloads import cfg1
+    m = cfg1()
+    with threadpool_limits(limits=1):
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        out = {}
+        for smoother in ("colored", "lex"):
+            ts, its = [], 0
+            for _ in range(reps):
+                _, info = o.solve(m.rhs[0], 1e-6, smoother=smoother)
+                ts.append(info["solve_seconds"])
+                its = info["iterations"]
+            out[smoother] = {"solve_s_median": float(np.median(ts)), "iterations": its,
+                             "reps": reps}
+    return out
 
 
 def time_solves(solver, d_rhs, d_x, n, rtol=1e-6):
@@ -205,17 +252,17 @@ def bench_cfg4(args, V, torch):
     print(json.dumps(line), flush=True)
 
 
-def bench_serve(args, V):
+def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
     """The serving stream: requests i = 0..N-1 (2D or 3D jittered meshes, DOFs
     log-uniform in [1e3, 1e6], 1:100 materials), each a new mesh, so latency
-    includes its setup (Galerkin products on the device unless --host-setup). The
-    single-stream rate is measured first by serving
-    the first 8 requests one at a time (one slot, one setup worker); then all N
-    arrive as a Poisson stream at 0.7x that rate into a server with 4 slots and 4
-    setup workers. Latency = done - arrival. The first 8 results must be
-    bitwise identical alone and in the mix."""
+    includes its setup (Galerkin products on the device unless host_setup). The
+    single-stream rate is measured first by serving the first 8 requests one at a
+    time (one slot, one setup worker); then all N arrive as a Poisson stream at
+    0.7x that rate into a server with 4 slots and 4 setup workers. Latency =
+    done - arrival. The first 8 results must be bitwise identical alone and in
+    the mix. Returns a dict of the figures."""
     from workloads import request_mesh
-    N = max(8, args.requests)
+    N = max(8, N)
     t0 = time.perf_counter()
     meshes = []
     for i in range(N):
@@ -223,7 +270,7 @@ def bench_serve(args, V):
         if i % 8 == 7:
             log(f"generated {i + 1}/{N} requests ({time.perf_counter() - t0:.1f}s)")
     dofs = np.array([m.n_dofs for m in meshes])
-    opts = dict(precision=V.FP32_PRECOND, setup_device=0 if args.host_setup else 1)
+    opts = dict(precision=V.FP32_PRECOND, setup_device=0 if host_setup else 1)
 
     # single stream: one request at a time end to end
     srv = V.Server(slots=1, setup_workers=1, **opts)
@@ -256,50 +303,66 @@ def bench_serve(args, V):
     t_all = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    # saturation: every request submitted at once (capacity of the batching)
-    srv2 = V.Server(slots=4, setup_workers=4, **opts)
-    t1 = time.perf_counter()
-    ids2 = [srv2.submit(m, m.rhs[0], 1e-6) for m in meshes]
-    got2 = [srv2.wait(r) for r in ids2]
-    t_sat = time.perf_counter() - t1
-    srv2.close()
-    lat2 = np.array([g[1]["t_done_ms"] - g[1]["t_submit_ms"] for g in got2])
-    log(f"saturated: {N / t_sat:.2f} requests/s")
+    got2, t_sat, lat2 = None, None, None
+    if saturated:
+        # saturation: every request submitted at once (capacity of the batching)
+        srv2 = V.Server(slots=4, setup_workers=4, **opts)
+        t1 = time.perf_counter()
+        ids2 = [srv2.submit(m, m.rhs[0], 1e-6) for m in meshes]
+        got2 = [srv2.wait(r) for r in ids2]
+        t_sat = time.perf_counter() - t1
+        srv2.close()
+        lat2 = np.array([g[1]["t_done_ms"] - g[1]["t_submit_ms"] for g in got2])
+        log(f"saturated: {N / t_sat:.2f} requests/s")
     res = [g[1] for g in got]
-    ok = [r["status"] == V.OK for r in res] + [g[1]["status"] == V.OK for g in got2]
+    ok = [r["status"] == V.OK for r in res] + [g[1]["status"] == V.OK for g in (got2 or [])]
     lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
     setup = np.array([r["t_setup_end_ms"] - r["t_setup_start_ms"] for r in res])
     solve = np.array([r["info"]["t_solve_ms"] for r in res])
     queue = np.array([r["t_admit_ms"] - r["t_setup_end_ms"] for r in res])
-    same = all(np.array_equal(got[i][0], alone[i][0]) and np.array_equal(got2[i][0], alone[i][0])
-               for i in range(8))
+    same = all(np.array_equal(got[i][0], alone[i][0]) and
+               (got2 is None or np.array_equal(got2[i][0], alone[i][0])) for i in range(8))
     overlap = 0
     iv = sorted((r["t_admit_ms"], r["t_done_ms"]) for r in res)
     for a in range(len(iv)):
         for b in range(a + 1, len(iv)):
             if iv[b][0] < iv[a][1]:
                 overlap += 1
-    line = {
-        "metric": "serving: requests/s and p50/p99 latency (setup + solve), rtol 1e-6",
-        "value": N / t_all, "unit": "requests/s", "n_gpus": 1, "steps": N, "warmup": 0,
-        "ms_per_step": 1e3 * t_all / N, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 (V-cycle) + f64 (PCG)", "data": "synthetic",
-        "config": {"workload": f"{N} requests, 2D/3D jittered P1 elasticity meshes, DOFs "
-                               "log-uniform in [1e3, 1e6] (seeded per request), Poisson arrivals "
-                               "at 0.7x the single-stream rate, 4 slots, 4 setup workers",
-                   "dofs_min": int(dofs.min()), "dofs_max": int(dofs.max()),
-                   "dofs_mean": float(dofs.mean()),
-                   "setup": "host" if args.host_setup else "Galerkin products on the device"},
+    out = {
+        "requests": N, "requests_per_s": N / t_all, "ms_per_request": 1e3 * t_all / N,
+        "dofs_min": int(dofs.min()), "dofs_max": int(dofs.max()), "dofs_mean": float(dofs.mean()),
+        "setup": "host" if host_setup else "Galerkin products on the device",
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "single_stream_requests_per_s": rate1, "arrival_rate": lam,
-        "saturated_requests_per_s": N / t_sat,
-        "saturated_p50_ms": float(np.percentile(lat2, 50)),
-        "saturated_p99_ms": float(np.percentile(lat2, 99)),
         "mean_setup_ms": float(setup.mean()), "mean_solve_ms": float(solve.mean()),
         "mean_admission_wait_ms": float(queue.mean()),
         "all_ok": bool(all(ok)), "same_alone_and_in_mix": bool(same),
         "overlapping_request_pairs_on_device": overlap,
         "peak_device_bytes": int(st["peak_bytes"]), "budget_bytes": int(st["budget_bytes"]),
+    }
+    if saturated:
+        out.update({"saturated_requests_per_s": N / t_sat,
+                    "saturated_p50_ms": float(np.percentile(lat2, 50)),
+                    "saturated_p99_ms": float(np.percentile(lat2, 99))})
+    return out
+
+
+def bench_serve(args, V):
+    """The serving stream as its own benchmark line (serve_leg)."""
+    r = serve_leg(V, args.requests, args.host_setup)
+    N = r["requests"]
+    line = {
+        "metric": "serving: requests/s and p50/p99 latency (setup + solve), rtol 1e-6",
+        "value": r["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": N, "warmup": 0,
+        "ms_per_step": r["ms_per_request"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (V-cycle) + f64 (PCG)", "data": "synthetic",
+        "config": {"workload": f"{N} requests, 2D/3D jittered P1 elasticity meshes, DOFs "
+                               "log-uniform in [1e3, 1e6] (seeded per request), Poisson arrivals "
+                               "at 0.7x the single-stream rate, 4 slots, 4 setup workers",
+                   "dofs_min": r["dofs_min"], "dofs_max": r["dofs_max"],
+                   "dofs_mean": r["dofs_mean"], "setup": r["setup"]},
+        **{k: v for k, v in r.items() if k not in ("requests", "requests_per_s", "ms_per_request",
+                                                   "dofs_min", "dofs_max", "dofs_mean", "setup")},
     }
     print(json.dumps(line), flush=True)
 
@@ -320,6 +383,10 @@ def main():
                          "16 load cases, block solve only; serve: the request stream through the "
                          "continuous-batching server")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving leg reported among the headline's variants")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="leave the serving leg out of the headline's variants")
     ap.add_argument("--host-setup", action="store_true",
                     help="serve: setup workers build the whole hierarchy on the host (default: "
                          "their Galerkin products on the device)")
@@ -439,7 +506,24 @@ def main():
         variants["fp64_jacobi_pcg"] = dict(ms_per_solve=float(np.mean([r[0] for r in rj])),
                                            iterations=rj[-1][1]["iterations"])
         jac.free()
+        # the small 2D manufactured-solution workload on the GPU (latency-bound)
+        from workloads import cfg1
+        m1 = cfg1()
+        d1 = torch.from_numpy(m1.rhs[0]).to("cuda")
+        x1 = torch.zeros_like(d1)
+        s1 = V.Solver.from_mesh(m1, precision=V.FP64)
+        time_solves(s1, d1, x1, 3)
+        r1 = time_solves(s1, d1, x1, 20)
+        t1 = np.array([r[0] for r in r1])
+        variants["cfg1_gpu_fp64"] = dict(
+            workload="2D plane strain, 33^2 jittered (seed 0), manufactured solution, 1,922 DOFs",
+            p50_ms=float(np.percentile(t1, 50)), p99_ms=float(np.percentile(t1, 99)),
+            iterations=r1[-1][1]["iterations"])
+        s1.free()
         log(f"variants: {variants}")
+        if not args.no_serve:
+            variants["serving"] = serve_leg(V, args.serve_requests)
+            log(f"serving: {variants['serving']}")
 
     # per-phase device time and algorithmic bytes of one iteration (event-timed
     # launches on the solve's stream, same kernels and launch configuration)
@@ -463,15 +547,21 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cb = cpu_baseline()
-        scale = (mesh.n_dofs / cb["n_dofs"]) * (its[0] / max(cb["iterations"], 1))
-        t_equiv = cb["solve_s"] * scale
-        cpu = {"value": 1.0 / t_equiv, "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": (f"oracle FP64 V-ASMG-PCG solve phase (coloured GS, rtol 1e-6) on the "
-                          f"same recipe at {cb['grid']}^3 vertices ({cb['n_dofs']} DOFs, "
-                          f"{cb['iterations']} its, {cb['solve_s']:.2f} s median of 3), scaled by "
-                          f"DOFs x iterations to the {mesh.n_dofs}-DOF workload"),
-               "sample_solve_s": cb["solve_s"]}
+        hc = host_cpu()
+        cb = cpu_baseline(mesh, its[0])
+        c1 = cpu_baseline_cfg1()
+        cpu = {"value": 1.0 / cb["solve_s"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": (f"the whole benchmarked workload ({cb['n_dofs']} DOFs): oracle FP64 "
+                          f"V-ASMG-PCG solve phase (coloured GS, rtol 1e-6, {cb['iterations']} its), "
+                          f"median of {cb['reps']} solves of {cb['solve_s']:.2f} s on one core "
+                          f"(threadpoolctl limit 1); oracle setup {cb['setup_s']:.1f} s not timed"),
+               "solve_s": cb["solve_s"], "reps": cb["reps"], "iterations": cb["iterations"],
+               "setup_s": cb["setup_s"],
+               "host": hc,
+               "cfg1_plain_method_cpu": dict(
+                   workload="2D plane strain, 33^2 jittered (seed 0), manufactured solution, "
+                            "1,922 DOFs, FP64 V(1,1) V-ASMG-PCG rtol 1e-6, oracle on one core",
+                   **c1)}
         log(f"cpu baseline: {cpu}")
 
     ms_per = float(np.mean(ms))
