@@ -1,5 +1,8 @@
 """Serving engine (vasmg_server_*): continuous batching of independent solve
-requests on one GPU. Each result is the same alone and in the mix (bitwise:
+requests on one GPU. Every served result matches the oracle's solve of the same
+request (FP64: 1e-8 relative error, +-1 iteration; FP32 V-cycle: +-1 iteration
+of the oracle's FP32 mode, 1e-5 of its FP64 solution). Each result is the same
+alone and in the mix (bitwise:
 the kernels are deterministic and autotuning is off in the server), the HBM
 budget bounds the bytes resident at once, a request that cannot fit or cannot be
 set up fails alone while the others complete, and every request's timestamps
@@ -7,6 +10,7 @@ are ordered submit <= setup <= admission <= done."""
 import numpy as np
 import pytest
 
+from oracle import Oracle
 from workloads import small2d, small3d
 
 torch = pytest.importorskip("torch")
@@ -28,6 +32,31 @@ def _requests():
     return out
 
 
+_oracle_cache = {}
+
+
+def _check_against_oracle(i, m, x, info, precision):
+    """A served result against the oracle's solve of the same request: FP64
+    within 1e-8 relative solution error and +-1 iteration; the FP32 V-cycle
+    within +-1 iteration of the oracle's FP32 mode and 1e-5 of its FP64
+    solution, reaching rtol in the FP64 true residual."""
+    if i not in _oracle_cache:
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        xo, io = o.solve(m.rhs[0], 1e-6)
+        _, io32 = o.solve(m.rhs[0], 1e-6, precision="fp32")
+        _oracle_cache[i] = (xo, io, io32)
+    xo, io, io32 = _oracle_cache[i]
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    assert info["rel_res_true"] < 1e-6
+    if precision == V.FP64:
+        assert abs(info["iterations"] - io["iterations"]) <= 1, (i, info["iterations"], io["iterations"])
+        assert err <= 1e-8, (i, err)
+    else:
+        assert abs(info["iterations"] - io32["iterations"]) <= 1, (i, info["iterations"],
+                                                                   io32["iterations"])
+        assert err <= 1e-5, (i, err)
+
+
 def _alone(m, **opt):
     s = V.Solver.from_mesh(m, autotune=0, **opt)
     x, info = s.solve(m.rhs[0], 1e-6)
@@ -44,8 +73,9 @@ def test_results_same_alone_and_in_the_mix(precision):
     st = srv.stats()
     srv.close()
     assert st["completed"] == len(reqs) and st["peak_bytes"] <= st["budget_bytes"]
-    for m, (x, res) in zip(reqs, got):
+    for i, (m, (x, res)) in enumerate(zip(reqs, got)):
         assert res["status"] == V.OK, res
+        _check_against_oracle(i, m, x, res["info"], precision)
         xa, ia = _alone(m, precision=precision)
         assert res["info"]["iterations"] == ia["iterations"]
         assert np.array_equal(x, xa), np.abs(x - xa).max()
@@ -67,8 +97,9 @@ def test_device_setup_workers():
     ids = [srv.submit(m, m.rhs[0], 1e-6) for m in reqs]
     got = [srv.wait(i) for i in ids]
     srv.close()
-    for m, (x, res) in zip(reqs, got):
+    for i, (m, (x, res)) in enumerate(zip(reqs, got)):
         assert res["status"] == V.OK, res
+        _check_against_oracle(i, m, x, res["info"], V.FP64)
         xa, ia = _alone(m, setup_device=1)
         assert np.array_equal(x, xa), np.abs(x - xa).max()
         _, ih = _alone(m)

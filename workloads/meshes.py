@@ -104,19 +104,31 @@ _KUHN = [  # offsets (dx,dy,dz) of the 4 vertices of the 6 Kuhn tetrahedra
 
 def grid3d(n: int, seed=None):
     """n^3 vertices on [0,1]^3; returns (coords, tets, boundary_mask)."""
-    ax = _axis(n, False)
-    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    return _grid3d(n, n, n, 1.0 / (n - 1), _axis(n, False), seed)
+
+
+def grid3d_box(nx: int, ny: int, nz: int, h: float, seed=None):
+    """nx x ny x nz vertices with spacing h on [0,(nx-1)h] x [0,(ny-1)h] x
+    [0,(nz-1)h]; returns (coords, tets, boundary_mask)."""
+    return _grid3d(nx, ny, nz, h, None, seed)
+
+
+def _grid3d(nx, ny, nz, h, axis, seed):
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     ii = ii.ravel(); jj = jj.ravel(); kk = kk.ravel()
-    coords = np.stack([ax[ii], ax[jj], ax[kk]], axis=1)
+    if axis is not None:
+        coords = np.stack([axis[ii], axis[jj], axis[kk]], axis=1)
+    else:
+        coords = np.stack([ii * h, jj * h, kk * h], axis=1).astype(np.float64)
     boundary = ((ii == 0) | (jj == 0) | (kk == 0)
-                | (ii == n - 1) | (jj == n - 1) | (kk == n - 1))
+                | (ii == nx - 1) | (jj == ny - 1) | (kk == nz - 1))
     if seed is not None:
-        coords = _jitter(coords, boundary, 1.0 / (n - 1), seed)
-    ck, cj, ci = np.meshgrid(np.arange(n - 1), np.arange(n - 1), np.arange(n - 1), indexing="ij")
-    base = (ci + n * (cj + n * ck)).ravel()
+        coords = _jitter(coords, boundary, h, seed)
+    ck, cj, ci = np.meshgrid(np.arange(nz - 1), np.arange(ny - 1), np.arange(nx - 1), indexing="ij")
+    base = (ci + nx * (cj + ny * ck)).ravel()
     tets = []
     for offs in _KUHN:
-        idx = [base + dx + n * (dy + n * dz) for (dx, dy, dz) in offs]
+        idx = [base + dx + nx * (dy + ny * dz) for (dx, dy, dz) in offs]
         # orientation of this tet type on the reference cube
         P = np.array(offs, dtype=np.float64)
         if np.linalg.det(P[1:] - P[0]) < 0:
@@ -248,6 +260,21 @@ def small3d(n: int = 5, seed=1, E: float = 1.0, nu: float = 0.3, fix: str = "x0"
     ne = tets.shape[0]
     F = load_constant(coords, tets, f)
     return Mesh(f"small3d_n{n}", 3, coords, tets, np.full(ne, E), np.full(ne, nu), fixed, [F])
+
+
+def box3d(nx: int, ny: int, nz: int, seed=1, E: float = 1.0, nu: float = 0.3,
+          f=(0.0, 0.0, -1.0)) -> Mesh:
+    """3D box of nx x ny x nz vertices, spacing h = 1/(nz-1) (so z spans [0,1]),
+    jittered by +-0.2h (seed), Kuhn tetrahedra, clamped at x=0, constant body
+    force f."""
+    h = 1.0 / (nz - 1)
+    coords, tets, _ = grid3d_box(nx, ny, nz, h, seed)
+    fixed = np.zeros((coords.shape[0], 3), dtype=np.uint8)
+    fixed[coords[:, 0] == 0.0] = 1
+    ne = tets.shape[0]
+    F = load_constant(coords, tets, f)
+    return Mesh(f"box3d_{nx}x{ny}x{nz}", 3, coords, tets, np.full(ne, E), np.full(ne, nu), fixed,
+                [F])
 
 
 def manufactured_mesh(n: int, seed=0, E: float = 1.0, nu: float = 0.3) -> Mesh:
