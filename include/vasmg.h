@@ -159,6 +159,23 @@ vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const doubl
                                 double* d_x, int32_t n_rhs, double rtol, void* stream,
                                 vasmg_solve_info* info);
 
+/* No-allocation form of vasmg_solve, for callers that cannot allocate device
+ * memory while they solve (code running under HIP graph capture elsewhere in
+ * the process, tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments, results and statuses as vasmg_solve (identical x and info): the
+ * host arrays are staged through one fixed array of the library on each GPU,
+ * 64 MiB, held from the module's load on that GPU until the process ends,
+ * instead of device buffers allocated per call; the call allocates nothing
+ * (the handle's buffers and PCG graphs exist from vasmg_setup / vasmg_upload).
+ * Staging takes n_rhs * n_vertices * dim * 8 bytes per array (rhs, x, and x0
+ * when given), each rounded up to 256 bytes; a request for more than 64 MiB
+ * fails with EINVAL before anything is copied. Every call on a GPU shares that
+ * GPU's array: calls on one GPU run one at a time (a second call waits for the
+ * first), and the array keeps the last call's data, none of which a call reads
+ * before writing it. */
+vasmg_status vasmg_solve_noalloc(vasmg_handle h, const double* rhs, const double* x0, double* x,
+                                 int32_t n_rhs, double rtol, vasmg_solve_info* info);
+
 /* Upload a hierarchy built with host_only = 1 to the current HIP device (the
  * device half of vasmg_setup, which then runs any block_rhs allocation and
  * autotuning the options ask for). stream (a hipStream_t) may be NULL; if set,

@@ -1731,11 +1731,16 @@ void enqueue_iter_B_mc(vasmg_ctx& C, hipStream_t st) {
 // Columns c0 .. c0+nc-1 (nc <= K) of the user arrays [n_rhs][nv][D]; the
 // unused columns of the block are zero and stop at once.
 template <int D, int K>
+void ensure_block_graphs(vasmg_ctx& C) {
+  if (!C.kgA) C.kgA = capture(C, &enqueue_iter_A_mc<D, K>);
+  if (!C.kgB) C.kgB = capture(C, &enqueue_iter_B_mc<D, K>);
+}
+
+template <int D, int K>
 int solve_block(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x, int c0, int nc,
                 double rtol, hipStream_t st, vasmg_solve_info* info) {
   constexpr int DP = dev::Pad<D>::value;
-  if (!C.kgA) C.kgA = capture(C, &enqueue_iter_A_mc<D, K>);
-  if (!C.kgB) C.kgB = capture(C, &enqueue_iter_B_mc<D, K>);
+  ensure_block_graphs<D, K>(C);
   const int n0 = C.n0;
   const int64_t n = C.n0p * K;
   const int64_t nv = C.H.n_mesh_vertices;
@@ -1843,6 +1848,17 @@ void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
     else
       autotune<3>(C);
   }
+  // The PCG graphs are captured here, after the lanes per row are final, and not
+  // at the first solve: a solve then instantiates and allocates nothing.
+  auto graphs = [&](auto dtag) {
+    constexpr int D = decltype(dtag)::value;
+    ensure_graphs<D>(C);
+    if (C.K > 0) DISPATCH_K(C.K, { ensure_block_graphs<D, KK>(C); });
+  };
+  if (C.d == 2)
+    graphs(std::integral_constant<int, 2>());
+  else
+    graphs(std::integral_constant<int, 3>());
   C.host_only = false;
 }
 
@@ -1897,6 +1913,41 @@ vasmg_status fail_with(const vasmg::Error& e) {
 bool device_available() {
   int n = 0;
   return hipGetDeviceCount(&n) == hipSuccess && n > 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Staging of the no-allocation host-pointer solve (vasmg_solve_noalloc): one
+// fixed array of this library per GPU, in place of the device buffers
+// vasmg_solve allocates per call. In host code `scratch` names a host-side
+// stand-in, not device memory: its device address on each GPU comes from
+// hipGetSymbolAddress (with that GPU current) and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = static_cast<size_t>(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;                   // guards g_scratch_ptr
+void* g_scratch_ptr[kMaxDevices] = {};        // device address of `scratch` per GPU
+std::mutex g_scratch_use[kMaxDevices];        // one no-allocation solve per GPU at a time
+
+// Device address of this GPU's copy of `scratch`; dev must be the current device.
+unsigned char* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices)
+    throw vasmg::Error{VASMG_EDEVICE, "device index beyond the no-allocation table"};
+  std::lock_guard<std::mutex> g(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw vasmg::Error{VASMG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                            hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
 }
 
 template <typename T, int D>
@@ -2133,6 +2184,36 @@ vasmg_status vasmg_solve(vasmg_handle h, const double* rhs, const double* x0, do
     if (drhs) (void)hipFree(drhs);
     if (dx) (void)hipFree(dx);
     if (dx0) (void)hipFree(dx0);
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_solve_noalloc(vasmg_handle h, const double* rhs, const double* x0, double* x,
+                                 int32_t n_rhs, double rtol, vasmg_solve_info* info) {
+  try {
+    check_handle(h);
+    if (!rhs || !x || n_rhs < 1) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/n_rhs"};
+    const size_t vec = sizeof(double) * static_cast<size_t>(h->H.n_mesh_vertices) * h->d *
+                       static_cast<size_t>(n_rhs);
+    const size_t slot = (vec + 255) / 256 * 256;
+    const size_t need = slot * (x0 ? 3 : 2);
+    if (need > kScratchBytes)
+      throw vasmg::Error{VASMG_EINVAL, "vasmg_solve_noalloc: " + std::to_string(need) +
+                                           " bytes of staging needed, more than its fixed " +
+                                           std::to_string(kScratchBytes) + "-byte array"};
+    unsigned char* base = scratch_address(h->device);
+    std::lock_guard<std::mutex> use(g_scratch_use[h->device]);
+    double* drhs = reinterpret_cast<double*>(base);
+    double* dx = reinterpret_cast<double*>(base + slot);
+    double* dx0 = x0 ? reinterpret_cast<double*>(base + 2 * slot) : nullptr;
+    HIP_CHECK(hipMemcpy(drhs, rhs, vec, hipMemcpyHostToDevice));
+    if (x0) HIP_CHECK(hipMemcpy(dx0, x0, vec, hipMemcpyHostToDevice));
+    const vasmg_status s = vasmg_solve_device(h, drhs, dx0, dx, n_rhs, rtol, nullptr, info);
+    const std::string msg = g_last_error;
+    HIP_CHECK(hipMemcpy(x, dx, vec, hipMemcpyDeviceToHost));
+    g_last_error = msg;
+    return s;
+  } catch (const vasmg::Error& e) {
     return fail_with(e);
   }
 }

@@ -33,7 +33,7 @@ EXPORTED = [
     "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
     "vasmg_upload", "vasmg_device_bytes", "vasmg_server_default_config", "vasmg_server_create",
     "vasmg_server_submit", "vasmg_server_wait", "vasmg_server_stats", "vasmg_server_destroy",
-    "vasmg_set_galerkin_window",
+    "vasmg_set_galerkin_window", "vasmg_solve_noalloc",
 ]
 
 
@@ -120,6 +120,7 @@ def lib():
             "vasmg_setup": (i32, [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(vp)]),
             "vasmg_solve": (i32, [vp, vp, vp, vp, i32, dbl, C.POINTER(SolveInfo)]),
             "vasmg_solve_device": (i32, [vp, vp, vp, vp, i32, dbl, vp, C.POINTER(SolveInfo)]),
+            "vasmg_solve_noalloc": (i32, [vp, vp, vp, vp, i32, dbl, C.POINTER(SolveInfo)]),
             "vasmg_free": (None, [vp]),
             "vasmg_last_error": (C.c_char_p, []),
             "vasmg_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
@@ -269,6 +270,26 @@ class Solver:
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(R.shape)
         infos = (SolveInfo * n_rhs)()
         st = lib().vasmg_solve(self._h, _ptr(R), _ptr(x0a), _ptr(x), n_rhs, rtol, infos)
+        if check and st not in (OK, ENOTCONV):
+            _check(st)
+        out = [i.as_dict() for i in infos]
+        for o in out:
+            o["status"] = st
+        return (x[0], out[0]) if single else (x, out)
+
+    def solve_noalloc(self, rhs, rtol: float = 1e-6, x0=None, check: bool = True):
+        """As solve(), through vasmg_solve_noalloc (device staging in the
+        library's fixed array, no device allocation during the call)."""
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        single = rhs.ndim == 2
+        R = rhs[None] if single else rhs
+        n_rhs = R.shape[0]
+        if R.shape[1:] != (self.n_vertices, self.dim):
+            raise ValueError(f"rhs: shape {rhs.shape}, expected [n_rhs?, {self.n_vertices}, {self.dim}]")
+        x = np.zeros_like(R)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).reshape(R.shape)
+        infos = (SolveInfo * n_rhs)()
+        st = lib().vasmg_solve_noalloc(self._h, _ptr(R), _ptr(x0a), _ptr(x), n_rhs, rtol, infos)
         if check and st not in (OK, ENOTCONV):
             _check(st)
         out = [i.as_dict() for i in infos]
