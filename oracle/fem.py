@@ -117,20 +117,32 @@ def component_major_perm(n_vertices: int, d: int) -> np.ndarray:
 
 
 def free_vertices(fixed: np.ndarray) -> np.ndarray:
-    """Vertices with no constrained component, ascending (their order is the fine
-    level's canonical order). Only fully fixed vertices are supported; a vertex
-    with some components fixed is rejected."""
+    """Vertices with at least one unconstrained component, ascending (their
+    order is the fine level's canonical order); fully fixed vertices are
+    eliminated (homogeneous Dirichlet conditions, Section 2)."""
     fixed = np.asarray(fixed).astype(bool)
-    part = fixed.any(axis=1) & ~fixed.all(axis=1)
-    if part.any():
-        raise NotImplementedError("partially constrained vertices are not supported")
-    return np.flatnonzero(~fixed.any(axis=1))
+    return np.flatnonzero(~fixed.all(axis=1))
 
 
-def restrict_free(K: sp.csr_matrix, free: np.ndarray, d: int) -> sp.csr_matrix:
-    """Eliminate the fixed DOFs (homogeneous Dirichlet: no lifting needed)."""
+def constrained_dofs(fixed: np.ndarray, free: np.ndarray) -> np.ndarray:
+    """Boolean mask over the DOFs of the kept vertices (vertex-major): True for
+    a fixed component of a partially constrained vertex."""
+    return np.asarray(fixed).astype(bool)[free].ravel()
+
+
+def restrict_free(K: sp.csr_matrix, free: np.ndarray, d: int,
+                  cmask: np.ndarray | None = None) -> sp.csr_matrix:
+    """Eliminate the fully fixed vertices (homogeneous Dirichlet: no lifting
+    needed); a fixed component of a kept vertex (cmask) gets an identity row and
+    column, which leaves the other DOFs' equations exactly those of eliminating
+    it (its value is 0)."""
     dofs = (free[:, None] * d + np.arange(d)[None, :]).ravel()
-    return K[dofs][:, dofs].tocsr()
+    A = K[dofs][:, dofs].tocsr()
+    if cmask is not None and cmask.any():
+        keep = sp.diags((~cmask).astype(np.float64))
+        A = (keep @ A @ keep + sp.diags(cmask.astype(np.float64))).tocsr()
+        A.sort_indices()
+    return A
 
 
 def fine_pattern(elems: np.ndarray, free: np.ndarray, n_vertices: int) -> sp.csr_matrix:

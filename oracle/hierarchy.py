@@ -12,10 +12,13 @@ The multicolouring is not in the paper (its Gauss-Seidel is sequential); it
 fixes the order in which the GPU's parallel Gauss-Seidel visits the vertices.
 On the fine level every vertex is its own cell; on coarse levels vertices are
 grouped into lattice cells of twice the level's finest spacing (at most 2^d
-vertices). Cells are coloured greedily (first fit) on the cell adjacency graph
-derived from the structural block pattern; the sweep visits colours in order,
-the cells of a colour in any order (they are uncoupled) and the vertices of a
-cell one after the other in canonical order.
+vertices), and cells into colour blocks (block_steps: 3D levels whose
+couplings reach 3 or 4 lattice steps take blocks of 4 steps, up to 8 cells;
+otherwise a block is one cell). Blocks are coloured greedily (first fit) on
+the block adjacency graph derived from the structural block pattern; the sweep
+visits colours in order, the blocks of a colour in any order (they are
+uncoupled), the cells of a block in canonical order and the vertices of a cell
+in canonical order.
 
 Pins (tests/test_oracle_solver.py, test_galerkin_spd_and_rigid_modes and
 test_cells_and_coloring): A_l symmetric positive definite, positive diagonal,
@@ -34,12 +37,35 @@ def block_prolongation(P: sp.csr_matrix, d: int) -> sp.csr_matrix:
     return sp.kron(P, sp.identity(d, format="csr"), format="csr")
 
 
-def galerkin(A: sp.csr_matrix, P: sp.csr_matrix, d: int) -> sp.csr_matrix:
-    """A_{l+1} = P_l^T A_l P_l (Section 3, equations (R) and (Ac))."""
-    Pb = block_prolongation(P, d)
+def galerkin(A: sp.csr_matrix, P: sp.csr_matrix, d: int, cmask: np.ndarray | None = None,
+             cmask_next: np.ndarray | None = None) -> sp.csr_matrix:
+    """A_{l+1} = P_l^T A_l P_l (Section 3, equations (R) and (Ac)). With
+    constrained DOFs (cmask, see masked_prolongation) the block prolongation's
+    rows of the level's fixed components are zero, and every coarse DOF whose
+    column is then empty (cmask_next) gets an identity row and column."""
+    Pb = block_prolongation(P, d) if cmask is None else masked_prolongation(P, d, cmask)
     Ac = (Pb.T @ A @ Pb).tocsr()
+    if cmask_next is not None and cmask_next.any():
+        Ac = (Ac + sp.diags(cmask_next.astype(np.float64))).tocsr()
     Ac.sort_indices()
     return Ac
+
+
+def masked_prolongation(P: sp.csr_matrix, d: int, cmask: np.ndarray) -> sp.csr_matrix:
+    """P (x) I_d with zero rows at the level's constrained DOFs (cmask)."""
+    Pb = block_prolongation(P, d)
+    if cmask is None or not cmask.any():
+        return Pb
+    return (sp.diags((~cmask).astype(np.float64)) @ Pb).tocsr()
+
+
+def coarse_constraints(P: sp.csr_matrix, d: int, cmask: np.ndarray) -> np.ndarray:
+    """Constrained DOFs of the next level: a coarse component is constrained when
+    every fine vertex interpolating from that coarse vertex has the component
+    fixed (its column of the masked prolongation is empty)."""
+    Pm = masked_prolongation(P, d, cmask)
+    nnz = np.asarray((abs(Pm) > 0).sum(axis=0)).ravel()
+    return nnz == 0
 
 
 def galerkin_pattern(S: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
@@ -98,6 +124,31 @@ def cell_partition(keys: np.ndarray, cell_side: int):
     d = keys.shape[1]
     uniq, inv = np.unique(ck[:, ::-1], axis=0, return_inverse=True)
     return inv.ravel().astype(np.int64), uniq[:, ::-1].copy()
+
+
+def coupling_reach(S: sp.csr_matrix, keys: np.ndarray, h: int) -> int:
+    """Largest per-axis lattice distance, in steps of h, between two coupled
+    vertices of a lattice level (structural pattern S, integer keys)."""
+    C = S.tocoo()
+    if C.nnz == 0:
+        return 0
+    return int(np.abs(keys[C.row] - keys[C.col]).max() // h)
+
+
+def block_steps(reach: int, d: int, mode: str) -> int:
+    """Side, in lattice steps, of the colour blocks of a 3D lattice level.
+
+    Cells of side 2 steps are grouped into colour blocks: a colour is given to
+    a block, and a sweep visits the cells of a block one after the other. Two
+    blocks of side s whose indices differ by 2 along an axis are at least s + 1
+    steps apart, so when the coupling reach is at most s only neighbouring
+    blocks couple and 2^d colours suffice. Side 4 (up to 8 cells) is used when
+    the reach is 3 or 4 steps ('auto', 3D only); otherwise a block is one cell."""
+    if mode == "off" or d != 3:
+        return 2
+    if mode != "auto":
+        raise ValueError(mode)
+    return 4 if 2 < reach <= 4 else 2
 
 
 def cell_graph(S: sp.csr_matrix, cell_of: np.ndarray, n_cells: int) -> sp.csr_matrix:

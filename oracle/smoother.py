@@ -9,10 +9,11 @@ once in exactly the reverse order after it (Section 3, Step 2.5). Algorithm 1's
 error-based exit is not used inside a V-cycle (a fixed number of sweeps).
 
 Two visiting orders:
-  * ``colored`` (the order the GPU uses): colours ascending, the cells of a
-    colour, the vertices of a cell in canonical order, components ascending; the
-    backward sweep is the exact reverse. Cells of one colour are not coupled, so
-    the same position of all of them can be updated at once for each component.
+  * ``colored`` (the order the GPU uses): colours ascending, the colour blocks
+    of a colour, the cells of a block and the vertices of a cell in canonical
+    order, components ascending; the backward sweep is the exact reverse.
+    Blocks of one colour are not coupled, so the same position of all of them
+    can be updated at once for each component.
   * ``lex`` (the paper's order): all first components, then all second
     components, ... (the component-major unknown vector [U1; U2; ...] of
     Section 2), in vertex order; realised with triangular solves, since one
@@ -33,30 +34,33 @@ from scipy.sparse.linalg import spsolve_triangular
 
 
 class ColoredGS:
-    """Point GS over (colour, cell, vertex, component) on a vertex-major scalar CSR matrix.
+    """Point GS over (colour, block, cell, vertex, component) on a vertex-major
+    scalar CSR matrix.
 
-    cell_of[v] is the cell of vertex v, cell_color[c] the colour of cell c. The
-    forward sweep visits colours ascending; cells of one colour are uncoupled,
-    so for each position p inside a cell (vertices in ascending order) and each
-    component, the p-th vertices of all cells of the colour are updated at once.
-    The backward sweep is the exact reverse.
+    block_of[v] is the colour block of vertex v, block_color[k] the colour of
+    block k, and cell_of[v] (optional; default: the block) the cell inside the
+    block. The forward sweep visits colours ascending; blocks of one colour are
+    uncoupled, so for each position p inside a block (cells ascending, then
+    vertices ascending) and each component, the p-th vertices of all blocks of
+    the colour are updated at once. The backward sweep is the exact reverse.
     """
 
-    def __init__(self, A: sp.csr_matrix, d: int, cell_of: np.ndarray, cell_color: np.ndarray,
-                 dtype=np.float64):
+    def __init__(self, A: sp.csr_matrix, d: int, block_of: np.ndarray, block_color: np.ndarray,
+                 dtype=np.float64, cell_of: np.ndarray | None = None):
         self.d = d
         self.dtype = dtype
         A = A.astype(dtype).tocsr()
         diag = A.diagonal()
         n = A.shape[0] // d
-        color = cell_color[cell_of]
-        order = np.lexsort((np.arange(n), cell_of, color))      # colour, cell, vertex
+        color = block_color[block_of]
+        sub = block_of if cell_of is None else cell_of
+        order = np.lexsort((np.arange(n), sub, block_of, color))   # colour, block, cell, vertex
         pos = np.zeros(n, dtype=np.int64)
-        prev_cell, k = -1, 0
+        prev_block, k = -1, 0
         for v in order:
-            k = k + 1 if cell_of[v] == prev_cell else 0
+            k = k + 1 if block_of[v] == prev_block else 0
             pos[v] = k
-            prev_cell = cell_of[v]
+            prev_block = block_of[v]
         ncol = int(color.max()) + 1 if n else 0
         self.parts = []          # per (colour, position): per component (rows, A[rows], a_ii)
         for c in range(ncol):
@@ -122,15 +126,19 @@ class LexGS:
         return out.astype(self.dtype)
 
 
-def jacobi_lambda_max(A: sp.csr_matrix, d: int, iters: int = 30) -> float:
+def jacobi_lambda_max(A: sp.csr_matrix, d: int, iters: int = 30,
+                      cmask: np.ndarray | None = None) -> float:
     """Estimate of the largest eigenvalue of D^{-1} A (D = the d x d vertex blocks
-    of A): power iteration from the all-ones vector, then the Rayleigh quotient
-    v^T A v / v^T D v of the last iterate. FP64."""
+    of A): power iteration from the all-ones vector on the unconstrained DOFs
+    (0 on constrained ones, whose identity rows keep them 0), then the Rayleigh
+    quotient v^T A v / v^T D v of the last iterate. FP64."""
     A = A.astype(np.float64).tocsr()
     n = A.shape[0]
     nv = n // d
     Dinv = _block_diag_inverse(A, d)
     v = np.ones(n)
+    if cmask is not None:
+        v[cmask] = 0.0
     for _ in range(iters):
         w = Dinv @ (A @ v)
         v = w / np.linalg.norm(w)
@@ -156,9 +164,9 @@ class BlockJacobi:
     matrices; omega * lambda_max < 2 for the exact lambda_max (the cycle stays
     symmetric positive definite)."""
 
-    def __init__(self, A: sp.csr_matrix, d: int, dtype=np.float64):
+    def __init__(self, A: sp.csr_matrix, d: int, dtype=np.float64, cmask=None):
         self.dtype = dtype
-        self.lam = jacobi_lambda_max(A, d)
+        self.lam = jacobi_lambda_max(A, d, cmask=cmask)
         self.omega = (4.0 / 3.0) / self.lam
         self.A = A.astype(dtype).tocsr()
         self.Dinv = _block_diag_inverse(A.astype(np.float64).tocsr(), d).astype(dtype)

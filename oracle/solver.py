@@ -12,7 +12,8 @@ Options mirror the C library's: leaf_capacity (4 in 2D as in Section 3.1.1; 8 in
 3D), n_pre/n_post sweeps, precision ('fp64' or 'fp32' V-cycle), tree vertices
 ('all' mesh vertices, as in Section 3.1.1, or only 'free' ones),
 coarsest_max_dofs (0 = coarsen to the root region, as in Section 3.1.2),
-smoother order ('colored' or the paper's 'lex').
+smoother order ('colored' or the paper's 'lex'), colour blocks ('auto' or
+'off': every cell its own colour block).
 """
 from __future__ import annotations
 
@@ -38,6 +39,7 @@ class OracleOptions:
     coarsest_max_dofs: int = 0
     max_iters: int = 10000
     smoother: str = "colored"       # 'colored' | 'lex' | 'jacobi'
+    color_blocks: str = "off"       # 'off' | 'auto' (oracle/hierarchy.py block_steps)
     flexible: bool = False
     cycle: str = "V"                # 'V' | 'W' | 'additive' (oracle/vcycle.py)
 
@@ -56,12 +58,14 @@ class Oracle:
         cap = opts.leaf_capacity or (4 if d == 2 else 8)
         self.capacity = cap
 
-        # Section 2: stiffness matrix, Dirichlet elimination
+        # Section 2: stiffness matrix, Dirichlet elimination (fully fixed vertices
+        # eliminated, fixed components of the other vertices as identity rows)
         self.K = fem.assemble(coords, elems, E, nu)
         self.free = fem.free_vertices(fixed)
         if self.free.size == 0:
             raise ValueError("no free vertices")
-        A0 = fem.restrict_free(self.K, self.free, d)
+        cmask0 = fem.constrained_dofs(fixed, self.free)
+        A0 = fem.restrict_free(self.K, self.free, d, cmask0)
         S0 = fem.fine_pattern(elems, self.free, nvtx)
 
         # Section 3.1 / 3.2: tree, levels, prolongations
@@ -76,40 +80,60 @@ class Oracle:
         self.levels = tree.build_levels(coords[tree_idx], coords[self.free],
                                         pos_in_tree[self.free], cap)
 
-        # Section 3 setup step: Galerkin operators and structural patterns
+        # Section 3 setup step: Galerkin operators and structural patterns; the
+        # constrained DOFs of each level (none without partial constraints)
         A = [A0]
         S = [S0]
+        cm = [cmask0]
         for P in self.levels.prolong:
-            A.append(hierarchy.galerkin(A[-1], P, d))
+            cm.append(hierarchy.coarse_constraints(P, d, cm[-1]))
+            A.append(hierarchy.galerkin(A[-1], P, d, cm[-2], cm[-1]))
             S.append(hierarchy.galerkin_pattern(S[-1], P))
         P_list = list(self.levels.prolong)
         # optional truncation: first level small enough becomes the coarsest
         if opts.coarsest_max_dofs > 0:
             for l, Al in enumerate(A):
                 if Al.shape[0] <= opts.coarsest_max_dofs:
-                    A, S, P_list = A[:l + 1], S[:l + 1], P_list[:l]
+                    A, S, P_list, cm = A[:l + 1], S[:l + 1], P_list[:l], cm[:l + 1]
                     break
         self.A = A
         self.S = S
         self.P = P_list
+        self.cmask = cm
         self.L = len(A) - 1
         # Gauss-Seidel visiting order: cells (single vertices on the fine level,
-        # lattice cells of twice the finest spacing on coarse levels), coloured
-        self.cells, self.cell_colors, self.colors = [], [], []
+        # lattice cells of twice the finest spacing on coarse levels) grouped
+        # into colour blocks, which are coloured
+        self.cells, self.blocks, self.block_colors, self.cell_colors, self.colors = [], [], [], [], []
+        self.block_steps = []
         for l in range(self.L):
             n = A[l].shape[0] // d
             if l == 0:
-                cell_of, ckeys, ncell = np.arange(n), None, n
+                cell_of = block_of = np.arange(n)
+                bkeys, steps = None, 1
             else:
                 keys = self.levels.level_keys(l)
                 dstar = int(self.levels.regions[l - 1][0].max())
-                cell_of, ckeys = hierarchy.cell_partition(keys, 2 * int(tree.side_of(dstar)))
-                ncell = ckeys.shape[0]
-            G = hierarchy.cell_graph(S[l], cell_of, ncell)
-            cc = hierarchy.choose_cell_coloring(G, ckeys)
+                h = int(tree.side_of(dstar))
+                cell_of, ckeys = hierarchy.cell_partition(keys, 2 * h)
+                steps = hierarchy.block_steps(hierarchy.coupling_reach(S[l], keys, h), d,
+                                              opts.color_blocks)
+                if steps == 2:
+                    block_of, bkeys = cell_of, ckeys
+                else:
+                    block_of, bkeys = hierarchy.cell_partition(keys, steps * h)
+            nblock = int(block_of.max()) + 1 if n else 0
+            G = hierarchy.cell_graph(S[l], block_of, nblock)
+            bc = hierarchy.choose_cell_coloring(G, bkeys)
             self.cells.append(cell_of)
+            self.blocks.append(block_of)
+            self.block_colors.append(bc)
+            self.block_steps.append(steps)
+            ncell = int(cell_of.max()) + 1 if n else 0
+            cc = np.zeros(ncell, dtype=np.int64)
+            cc[cell_of] = bc[block_of]
             self.cell_colors.append(cc)
-            self.colors.append(cc[cell_of])
+            self.colors.append(bc[block_of])
         self.coarsest = hierarchy.CoarsestSolver(A[self.L])
         self.setup_seconds = time.perf_counter() - t0
         self._vcycles = {}
@@ -124,17 +148,22 @@ class Oracle:
         if key not in self._vcycles:
             dt = np.float32 if precision == "fp32" else np.float64
             if smoother == "colored":
-                sm = [ColoredGS(self.A[l], self.d, self.cells[l], self.cell_colors[l], dt)
-                      for l in range(self.L)]
+                sm = [self.gs(l, dt) for l in range(self.L)]
             elif smoother == "lex":
                 sm = [LexGS(self.A[l], self.d, dt) for l in range(self.L)]
             elif smoother == "jacobi":
-                sm = [BlockJacobi(self.A[l], self.d, dt) for l in range(self.L)]
+                sm = [BlockJacobi(self.A[l], self.d, dt, self.cmask[l]) for l in range(self.L)]
             else:
                 raise ValueError(smoother)
             self._vcycles[key] = VCycle(self.A, self.P, sm, self.coarsest, self.d,
-                                        self.opts.n_pre, self.opts.n_post, dt, cycle)
+                                        self.opts.n_pre, self.opts.n_post, dt, cycle,
+                                        cmask=self.cmask)
         return self._vcycles[key]
+
+    def gs(self, l: int, dtype=np.float64) -> ColoredGS:
+        """The coloured Gauss-Seidel sweeps of level l (the order the GPU uses)."""
+        return ColoredGS(self.A[l], self.d, self.blocks[l], self.block_colors[l], dtype,
+                         cell_of=self.cells[l])
 
     def apply_precond(self, r_free: np.ndarray, precision=None, smoother=None) -> np.ndarray:
         """z = B r on free DOFs (vertex-major, fine canonical order)."""
@@ -142,8 +171,11 @@ class Oracle:
         return vc.apply(r_free).astype(np.float64)
 
     def to_free(self, F: np.ndarray) -> np.ndarray:
-        """[n_vertices, d] -> free-DOF vector (vertex-major)."""
-        return np.asarray(F, dtype=np.float64)[self.free].ravel()
+        """[n_vertices, d] -> free-DOF vector (vertex-major); fixed components of
+        the kept vertices are 0 (their entries of F are ignored)."""
+        v = np.asarray(F, dtype=np.float64)[self.free].ravel().copy()
+        v[self.cmask[0]] = 0.0
+        return v
 
     def from_free(self, x: np.ndarray) -> np.ndarray:
         out = np.zeros((self.n_vertices, self.d))
@@ -183,5 +215,7 @@ class Oracle:
             nb = self.S[l].nnz
             out.append(dict(level=l, n_vertices=nv, n_dofs=A.shape[0], n_blocks=int(nb),
                             n_colors=int(self.colors[l].max() + 1) if l < self.L else 0,
-                            n_cells=int(self.cell_colors[l].size) if l < self.L else 0))
+                            n_cells=int(self.cell_colors[l].size) if l < self.L else 0,
+                            n_color_blocks=int(self.block_colors[l].size) if l < self.L else 0,
+                            block_steps=self.block_steps[l] if l < self.L else 0))
         return out

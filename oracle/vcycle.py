@@ -46,20 +46,23 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .hierarchy import block_prolongation
+from .hierarchy import masked_prolongation
 
 
 class VCycle:
     def __init__(self, A_levels, P_levels, smoothers, coarsest, d: int,
-                 n_pre: int = 1, n_post: int = 1, dtype=np.float64, cycle: str = "V"):
-        """A_levels[0..L], P_levels[0..L-1] (scalar), smoothers[0..L-1], coarsest solver."""
+                 n_pre: int = 1, n_post: int = 1, dtype=np.float64, cycle: str = "V",
+                 cmask=None):
+        """A_levels[0..L], P_levels[0..L-1] (scalar), smoothers[0..L-1], coarsest
+        solver; cmask[l]: constrained DOFs of level l (zero prolongation rows)."""
         if cycle not in ("V", "W", "additive"):
             raise ValueError(cycle)
         self.cycle = cycle
         self.L = len(A_levels) - 1
         self.dtype = dtype
         self.A = [A.astype(dtype).tocsr() for A in A_levels]
-        self.Pb = [block_prolongation(P, d).astype(dtype).tocsr() for P in P_levels]
+        self.Pb = [masked_prolongation(P, d, None if cmask is None else cmask[l]).astype(dtype).tocsr()
+                   for l, P in enumerate(P_levels)]
         self.PbT = [Pb.T.tocsr() for Pb in self.Pb]
         self.smoothers = smoothers
         self.coarsest = coarsest

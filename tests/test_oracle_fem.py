@@ -120,11 +120,16 @@ def test_manufactured_solution_converges_at_second_order():
     assert errs[-1] < 1e-3
 
 
-def test_partial_constraints_rejected():
+def test_partially_fixed_vertices_keep_their_block():
+    """Only fully fixed vertices are eliminated; a fixed component of another
+    vertex gets an identity row and column (tests/test_oracle_constraints.py
+    pins that this equals eliminating it)."""
     fixed = np.zeros((4, 2), np.uint8)
     fixed[0, 0] = 1
-    with pytest.raises(NotImplementedError):
-        fem.free_vertices(fixed)
+    fixed[1] = 1
+    free = fem.free_vertices(fixed)
+    assert np.array_equal(free, [0, 2, 3])
+    assert np.array_equal(fem.constrained_dofs(fixed, free), [1, 0, 0, 0, 0, 0])
 
 
 def test_fine_pattern_matches_matrix():

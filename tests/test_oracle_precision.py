@@ -26,7 +26,6 @@ import pytest
 import scipy.linalg as sla
 
 from oracle import Oracle, OracleOptions
-from oracle.smoother import ColoredGS
 from workloads import small2d, small3d
 
 U32 = float(np.finfo(np.float32).eps) / 2      # unit roundoff of float32
@@ -81,14 +80,11 @@ def test_fp32_coarsest_solve_is_fp64():
     assert np.abs(z - ref).max() < np.abs(z_bad - ref).max() / 4
 
 
-def _literal_point_gs32(A, d, cell_of, cell_color, b, x):
-    """Point Gauss-Seidel (Algorithm 1) with float32 scalars, in the coloured
-    order: colours ascending, cells, vertices, components; each unknown is
+def _literal_point_gs32(A, d, order, b, x):
+    """Point Gauss-Seidel (Algorithm 1) with float32 scalars, visiting the
+    vertices in `order` and their components ascending; each unknown is
     replaced by (b_i - sum_{j != i} a_ij x_j) / a_ii, summed left to right."""
     A = A.tocsr()
-    n = A.shape[0] // d
-    color = cell_color[cell_of]
-    order = np.lexsort((np.arange(n), cell_of, color))
     x = [np.float32(v) for v in x]
     for v in order:
         for a in range(d):
@@ -116,11 +112,14 @@ def test_fp32_sweep_is_single_precision_gauss_seidel(dim):
         n = A.shape[0]
         b = rng.normal(size=n).astype(np.float32)
         x = rng.normal(size=n).astype(np.float32)
-        S32 = ColoredGS(A, dim, o.cells[l], o.cell_colors[l], np.float32)
-        S64 = ColoredGS(A, dim, o.cells[l], o.cell_colors[l], np.float64)
+        S32 = o.gs(l, np.float32)
+        S64 = o.gs(l, np.float64)
         y32 = S32.forward(b, x).astype(np.float64)
         y64 = S64.forward(b.astype(np.float64), x.astype(np.float64))
-        lit = _literal_point_gs32(A, dim, o.cells[l], o.cell_colors[l], b, x)
+        nv = A.shape[0] // dim
+        order = np.lexsort((np.arange(nv), o.cells[l], o.blocks[l],
+                            o.block_colors[l][o.blocks[l]]))
+        lit = _literal_point_gs32(A, dim, order, b, x)
         scale = np.abs(y64).max()
         # same arithmetic as a float32 loop up to summation order ...
         assert np.abs(y32 - lit).max() <= 64 * U32 * scale, l

@@ -3,8 +3,10 @@
   * Galerkin operators (Section 3, equations (R), (Ac)): symmetric positive
     definite after the boundary conditions, positive diagonal, and for the
     unconstrained operator they annihilate the interpolated rigid-body modes.
-  * Gauss-Seidel cells and colouring: coupled vertices of different cells never
-    share a colour, cells are lattice blocks of at most 2^d vertices.
+  * Gauss-Seidel cells, colour blocks and colouring: cells are lattice blocks of
+    at most 2^d vertices, colour blocks whole cells on a lattice of 2 or 4 steps
+    (4 only where the couplings reach 3 or 4 steps, so that 2^d colours
+    suffice), coupled vertices of different colour blocks never share a colour.
   * Gauss-Seidel (Section 2.1, Algorithm 1): equals a literal element-by-element
     loop in the same unknown order; one forward sweep from zero equals a
     lower-triangular solve; backward is the exact reverse order.
@@ -63,24 +65,22 @@ def test_galerkin_spd_and_rigid_modes(dim):
 
 
 def _sweep_order(o, l):
-    """Unknown order of the coloured sweep: colours, cells, vertices, components."""
+    """Unknown order of the coloured sweep: colours, colour blocks, cells,
+    vertices, components."""
     d = o.d
-    cell, cc = o.cells[l], o.cell_colors[l]
+    cell, block = o.cells[l], o.blocks[l]
     n = cell.size
-    verts = np.lexsort((np.arange(n), cell, cc[cell]))
+    verts = np.lexsort((np.arange(n), cell, block, o.block_colors[l][block]))
     return np.array([v * d + a for v in verts for a in range(d)])
 
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_cells_and_coloring(dim):
     m = small2d(17, seed=1) if dim == 2 else small3d(9, seed=2)
-    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="auto"))
     for l in range(o.L):
         S = o.S[l].tocoo()
         cell, col = o.cells[l], o.colors[l]
-        # vertices of different cells that are coupled never share a colour
-        off = cell[S.row] != cell[S.col]
-        assert np.all(col[S.row[off]] != col[S.col[off]])
         sizes = np.bincount(cell)
         assert sizes.max() <= (1 if l == 0 else 2 ** dim)
         if l == 0:
@@ -92,12 +92,40 @@ def test_cells_and_coloring(dim):
             ck = keys // side
             for c in np.unique(cell):
                 assert np.all(ck[cell == c] == ck[cell == c][0])
+        # colour blocks: whole cells, lattice blocks of block_steps lattice steps,
+        # coupled vertices of different blocks never share a colour
+        block = o.blocks[l]
+        for c in np.unique(cell):
+            assert np.unique(block[cell == c]).size == 1
+        offb = block[S.row] != block[S.col]
+        assert np.all(col[S.row[offb]] == o.block_colors[l][block[S.row[offb]]])
+        assert np.all(col[S.row[offb]] != col[S.col[offb]])
+        if l > 0:
+            h = int(tree.side_of(int(o.levels.regions[l - 1][0].max())))
+            steps = o.block_steps[l]
+            assert steps in (2, 4)
+            bk = keys // (steps * h)
+            for k in np.unique(block):
+                assert np.all(bk[block == k] == bk[block == k][0])
+            reach = hierarchy.coupling_reach(o.S[l], keys, h)
+            if steps == 4:
+                # blocks two apart along an axis are uncoupled: 2^d colours suffice
+                assert dim == 3 and 2 < reach <= 4
+                assert o.block_colors[l].max() + 1 <= 2 ** dim
+            else:
+                assert np.array_equal(block, cell)
+                assert dim == 2 or not 2 < reach <= 4
         # the chosen colouring is the best of the greedy visiting orders
-        G = hierarchy.cell_graph(o.S[l], cell, sizes.size)
-        canon = hierarchy.greedy_coloring_in_order(G, np.arange(sizes.size))
-        assert o.cell_colors[l].max() <= canon.max()
+        nb = int(block.max()) + 1
+        G = hierarchy.cell_graph(o.S[l], block, nb)
+        canon = hierarchy.greedy_coloring_in_order(G, np.arange(nb))
+        assert o.block_colors[l].max() <= canon.max()
     # coarse lattice levels of a near-uniform mesh reach 2^d colours
     assert o.cell_colors[o.L - 1].max() + 1 <= 2 ** dim
+    # a 3D mesh of 2^k + 1 vertices per axis has a level 1 coupled 4 steps far:
+    # colour blocks of 4 steps there
+    if dim == 3:
+        assert o.block_steps[1] == 4, o.block_steps
 
 
 def _literal_gs(A, b, x, order):
@@ -125,7 +153,7 @@ def test_gauss_seidel_orders(dim):
         b = rng.normal(size=n)
         x0 = rng.normal(size=n)
         order = list(_sweep_order(o, l))
-        S = ColoredGS(A, dim, o.cells[l], o.cell_colors[l])
+        S = o.gs(l)
         assert np.allclose(S.forward(b, x0), _literal_gs(Ad, b, x0, order), rtol=1e-12, atol=1e-12)
         assert np.allclose(S.backward(b, x0), _literal_gs(Ad, b, x0, order[::-1]),
                            rtol=1e-12, atol=1e-12)
@@ -141,6 +169,28 @@ def test_gauss_seidel_orders(dim):
         y = np.linalg.solve(np.tril(Ap), b[p])
         z = np.empty(n); z[p] = y
         assert np.allclose(S.forward(b, np.zeros(n)), z, rtol=1e-12, atol=1e-12)
+
+
+def test_gauss_seidel_order_with_color_blocks():
+    """On a level swept by colour blocks the coloured sweep still equals the
+    literal Algorithm 1 loop, in the order colours, blocks, cells, vertices,
+    components (the blocks of a colour updated together, the cells of a block
+    one after the other)."""
+    m = small3d(9, seed=2)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="auto"))
+    assert o.block_steps[1] == 4
+    rng = np.random.default_rng(6)
+    A = o.A[1]
+    Ad = A.toarray()
+    n = A.shape[0]
+    b, x0 = rng.normal(size=n), rng.normal(size=n)
+    order = list(_sweep_order(o, 1))
+    S = o.gs(1)
+    assert np.allclose(S.forward(b, x0), _literal_gs(Ad, b, x0, order), rtol=1e-12, atol=1e-12)
+    assert np.allclose(S.backward(b, x0), _literal_gs(Ad, b, x0, order[::-1]), rtol=1e-12, atol=1e-12)
+    # and it is a different order from the cells' own colouring
+    o2 = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    assert not np.allclose(o2.gs(1).forward(b, x0), S.forward(b, x0))
 
 
 def _closed_form_B(o, l, order_fn):

@@ -236,6 +236,10 @@ def small2d(n: int = 9, seed=0, E: float = 1.0, nu: float = 0.3, fix: str = "bou
         fixed[bnd] = 1
     elif fix == "x0":
         fixed[np.isclose(coords[:, 0], 0.0)] = 1
+    elif fix == "symmetry":
+        # rollers: u_x = 0 on x = 0, u_y = 0 on y = 0 (the corner is fully fixed)
+        fixed[coords[:, 0] == 0.0, 0] = 1
+        fixed[coords[:, 1] == 0.0, 1] = 1
     elif fix == "none":
         pass
     else:
@@ -253,6 +257,16 @@ def small3d(n: int = 5, seed=1, E: float = 1.0, nu: float = 0.3, fix: str = "x0"
         fixed[bnd] = 1
     elif fix == "x0":
         fixed[coords[:, 0] == 0.0] = 1
+    elif fix == "symmetry":
+        # rollers on the three coordinate planes: u_a = 0 on x_a = 0 (edges fix
+        # two components, the corner all three)
+        for a in range(3):
+            fixed[coords[:, a] == 0.0, a] = 1
+    elif fix == "roller_x1":
+        # clamped at x = 1, rollers u_y = 0 on y = 0 and u_z = 0 on z = 0
+        fixed[coords[:, 0] == 1.0] = 1
+        fixed[coords[:, 1] == 0.0, 1] = 1
+        fixed[coords[:, 2] == 0.0, 2] = 1
     elif fix == "none":
         pass
     else:
