@@ -26,8 +26,8 @@
  *  - Threads: one call in flight per handle. Different handles may be used
  *    from different threads.
  *  - Layouts: user-facing vectors are FP64, vertex-major [n_vertices][dim]
- *    (DOF = vertex*dim + component). Entries of a right-hand side at fixed DOFs
- *    are ignored; solutions are 0 there. Level vectors of the debug entry
+ *    (DOF = vertex*dim + component). Entries of a right-hand side or initial
+ *    guess at fixed DOFs are ignored; solutions are 0 there. Level vectors of the debug entry
  *    points are [n_level_vertices][dim] in the level's canonical order (fine
  *    level: free vertices in ascending mesh index; coarse levels: vertices in
  *    lexicographic (z, y, x) lattice-key order).
@@ -68,8 +68,14 @@ typedef struct {
   const int32_t* elems;        /* [n_elements][dim+1], 0-based, positively oriented      */
   const double* E;             /* [n_elements] Young's modulus, > 0                       */
   const double* nu;            /* [n_elements] Poisson ratio, in (-1, 0.5)                */
-  const uint8_t* fixed;        /* [n_vertices][dim], 1 = homogeneous Dirichlet DOF. A
-                                  vertex must have all or none of its DOFs fixed.         */
+  const uint8_t* fixed;        /* [n_vertices][dim], 1 = homogeneous Dirichlet DOF.
+                                  Fully fixed vertices are eliminated; a vertex with
+                                  some components fixed keeps its block with an
+                                  identity row and column for each fixed component and
+                                  zero prolongation rows for it (a coarse component
+                                  whose interpolating fine vertices all have it fixed
+                                  is constrained in turn): exactly eliminating those
+                                  DOFs (rollers, symmetry planes).                        */
 } vasmg_mesh;
 
 typedef struct {
@@ -120,7 +126,15 @@ typedef struct {
                                   back before vasmg_setup returns and no device memory
                                   is kept (a server's setup workers); EDEVICE without a
                                   device                                                  */
-  int32_t reserved[2];
+  int32_t color_blocks;        /* 0 = off (default): every Gauss-Seidel cell is its own
+                                  colour block; 1 = on: on 3D lattice levels whose
+                                  couplings reach 3 or 4 lattice steps, cells are grouped
+                                  into colour blocks of 4 steps (up to 8 cells, swept one
+                                  after the other inside a block), so that 8 colours
+                                  suffice instead of 27. Ignored (off) with block_rhs.
+                                  Changes the sweep order, hence results (the oracle
+                                  takes the same order).                                 */
+  int32_t reserved[1];
 } vasmg_options;
 
 typedef struct {
@@ -283,9 +297,16 @@ vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices
  *   cell   [n_vertices] int32 Gauss-Seidel cell of each vertex (cells numbered in
  *          canonical order of their lattice keys; fine level: the vertex itself;
  *          coarsest level: 0)
- *   color  [n_vertices] int32 colour of the vertex's cell (coarsest level: 0).
- *          A sweep visits colours ascending, then cells, then the vertices of a
- *          cell in canonical order, then components (Algorithm 1 in that order).
+ *   color  [n_vertices] int32 colour of the vertex's colour block (coarsest
+ *          level: 0). A sweep visits colours ascending, then the colour blocks
+ *          of a colour, then the cells of a block, then the vertices of a cell
+ *          in canonical order, then components (Algorithm 1 in that order).
+ *   block  [n_vertices] int32 colour block of each vertex (blocks numbered in
+ *          canonical order of their lattice keys; the cell where every cell is
+ *          its own block; coarsest level: 0)
+ *   fixed  [n_vertices] uint8 constrained components of each vertex (bit a =
+ *          component a; their rows and columns of vals are those of the
+ *          identity)
  *   rowptr [n_vertices+1] int64, cols [n_blocks] int32, vals [n_blocks][dim][dim] FP64
  *   p_rowptr [n_vertices+1] int64, p_cols [p_nnz] int32, p_vals [p_nnz] FP64
  *     (scalar prolongation P_level from this level's vertices to the next's).
@@ -293,7 +314,8 @@ vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices
  * download of the level values (EDEVICE if that failed). */
 vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* cell,
                                 int32_t* color, int64_t* rowptr, int32_t* cols, double* vals,
-                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals);
+                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals,
+                                int32_t* block, uint8_t* fixed);
 
 /* Root box [m, M]^dim of the region tree (Section 3.1.1 Step 1) and its depth. */
 vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_depth);

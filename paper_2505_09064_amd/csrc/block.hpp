@@ -407,7 +407,8 @@ template <typename T, int D, int K, int VF>
 __global__ __launch_bounds__(kBlock) void k_prolong_mc(int nf, const int* __restrict__ ptr,
                                                        const int* __restrict__ idx,
                                                        const T* __restrict__ w,
-                                                       const T* __restrict__ e, T* x) {
+                                                       const T* __restrict__ e, T* x,
+                                                       const uint8_t* __restrict__ fixed) {
   const int k = threadIdx.x % K;
   const int i = xcd_block() * (kBlock / K) + threadIdx.x / K;
   if (i >= nf) return;
@@ -423,8 +424,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_mc(int nf, const int* __rest
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += wp * ev[a];
   }
+  const int fx = fixed ? fixed[i] : 0;   // constrained components: zero prolongation rows
 #pragma unroll
-  for (int a = 0; a < D; ++a) xi[a] += acc[a];
+  for (int a = 0; a < D; ++a) xi[a] += ((fx >> a) & 1) ? T(0) : acc[a];
   BlockVecIO<T, D, VF>::store(x + o, xi);
 }
 
@@ -612,15 +614,19 @@ template <int D, int K>
 __global__ __launch_bounds__(kBlock) void k_gather_user_mc(int n, const int* __restrict__ map,
                                                            const double* __restrict__ src,
                                                            int64_t nv, int c0, int nc,
-                                                           double* __restrict__ dst) {
+                                                           double* __restrict__ dst,
+                                                           const uint8_t* __restrict__ fixed) {
   constexpr int DP = Pad<D>::value;
   const int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x;
   if (e >= static_cast<int64_t>(n) * K) return;
   const int i = static_cast<int>(e / K), k = static_cast<int>(e % K);
   const int64_t v = map[i];
+  const int fx = fixed ? fixed[i] : 0;   // constrained components read as 0
 #pragma unroll
   for (int a = 0; a < DP; ++a)
-    dst[e * DP + a] = (a < D && k < nc) ? src[(static_cast<int64_t>(c0 + k) * nv + v) * D + a] : 0.0;
+    dst[e * DP + a] = (a < D && k < nc && !((fx >> a) & 1))
+                          ? src[(static_cast<int64_t>(c0 + k) * nv + v) * D + a]
+                          : 0.0;
 }
 
 template <int D, int K>

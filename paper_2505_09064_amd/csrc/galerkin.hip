@@ -431,32 +431,37 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
 // ---------------------------------------------------------------------------
 constexpr int kLayoutStage = 1024;   // device columns of one row staged in LDS
 
-// Off-cell blocks below / above the row's cell. One wavefront per device row.
-__global__ __launch_bounds__(kThreads) void k_layout_count(int n, Csr A, const int* __restrict__ perm,
-                                                           const int* __restrict__ inv,
-                                                           const int* __restrict__ lo_,
-                                                           const int* __restrict__ hi_,
-                                                           int* __restrict__ cntL,
-                                                           int* __restrict__ cntU) {
+// Part of an off-cell block in device column j of a row with cell [lo, hi)
+// and colour block [blo, bhi); -1 inside the cell.
+__device__ __forceinline__ int layout_part(int j, int lo, int hi, int blo, int bhi) {
+  if (j >= lo && j < hi) return -1;
+  if (j < blo) return kPartL;
+  if (j < lo) return kPartE;
+  if (j < bhi) return kPartF;
+  return kPartU;
+}
+
+// Off-cell blocks of each part. One wavefront per device row.
+__global__ __launch_bounds__(kThreads) void k_layout_count(int n, Csr A, LayoutArgs a) {
   const int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  const int c = perm[i];
-  const int lo = lo_[i], hi = hi_[i];
-  int cl = 0, cu = 0;
+  const int c = a.perm[i];
+  const int lo = a.lo[i], hi = a.hi[i];
+  const int blo = a.blo ? a.blo[i] : lo, bhi = a.bhi ? a.bhi[i] : hi;
+  int cnt[kParts] = {0, 0, 0, 0};
   for (int64_t p = A.ptr[c] + lane; p < A.ptr[c + 1]; p += 64) {
-    const int j = inv[A.col[p]];
-    cl += j < lo;
-    cu += j >= hi;
+    const int q = layout_part(a.inv[A.col[p]], lo, hi, blo, bhi);
+#pragma unroll
+    for (int k = 0; k < kParts; ++k) cnt[k] += q == k;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    cl += __shfl_xor(cl, o, 64);
-    cu += __shfl_xor(cu, o, 64);
-  }
-  if (lane == 0) {
-    cntL[i] = cl;
-    cntU[i] = cu;
-  }
+#pragma unroll
+  for (int k = 0; k < kParts; ++k)
+    for (int o = 32; o > 0; o >>= 1) cnt[k] += __shfl_xor(cnt[k], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < kParts; ++k)
+      if (a.part[k].cnt) a.part[k].cnt[i] = cnt[k];
 }
 
 // One wavefront per device row: the row's device columns are staged in LDS
@@ -478,58 +483,60 @@ __global__ __launch_bounds__(kThreads) void k_layout_fill(Csr A, LayoutArgs a) {
   __syncthreads();
   if (!valid) return;
   const int lo = a.lo[i], hi = a.hi[i];
+  const int blo = a.blo ? a.blo[i] : lo, bhi = a.bhi ? a.bhi[i] : hi;
   auto col_of = [&](int e) { return staged ? sj[w][e] : a.inv[A.col[rb + e]]; };
   for (int e = lane; e < len; e += 64) {
     const int j = col_of(e);
     const double* blk = A.val + (rb + e) * DD;
-    if (j < lo || j >= hi) {
-      const bool low = j < lo;
+    const int pq = layout_part(j, lo, hi, blo, bhi);
+    if (pq >= 0) {
       int rank = 0;
       for (int f = 0; f < len; ++f) {
         const int jf = col_of(f);
-        rank += jf < j && (low || jf >= hi);
+        rank += jf < j && layout_part(jf, lo, hi, blo, bhi) == pq;
       }
-      const int64_t q = (low ? a.Lptr[i] : a.Uptr[i]) + rank;
-      const int64_t stride = low ? a.nL : a.nU;
-      (low ? a.Lcol : a.Ucol)[q] = j;
-      float* v32 = low ? a.L32 : a.U32;
-      double* v64 = low ? a.L64 : a.U64;
+      const LayoutPart& P = a.part[pq];
+      const int64_t q = P.ptr[i] + rank;
+      P.col[q] = j;
 #pragma unroll
       for (int t = 0; t < DD; ++t) {
-        if (v64) v64[t * stride + q] = blk[t];
-        if (v32) v32[t * stride + q] = static_cast<float>(blk[t]);
+        if (P.v64) P.v64[t * P.n + q] = blk[t];
+        if (P.v32) P.v32[t * P.n + q] = static_cast<float>(blk[t]);
       }
     } else if (a.cell_of_row) {
       const int64_t base = static_cast<int64_t>(a.cell_of_row[i]) * NU * NU;
       const int ki = i - lo, kj = j - lo;
+      const int fx = (j == i && a.fixed) ? a.fixed[i] : 0;
 #pragma unroll
       for (int r = 0; r < D; ++r)
 #pragma unroll
         for (int s = 0; s < D; ++s) {
           const int64_t m = base + (kj * D + s) * NU + (ki * D + r);
-          if (a.M64) a.M64[m] = blk[r * D + s];
-          if (a.M32) a.M32[m] = static_cast<float>(blk[r * D + s]);
+          const double v = (r == s && ((fx >> r) & 1)) ? 1.0 : blk[r * D + s];
+          if (a.M64) a.M64[m] = v;
+          if (a.M32) a.M32[m] = static_cast<float>(v);
         }
     } else {
+      const int fx = (j == i && a.fixed) ? a.fixed[i] : 0;
 #pragma unroll
       for (int t = 0; t < DD; ++t) {
-        if (a.M64) a.M64[static_cast<int64_t>(i) * DD + t] = blk[t];
-        if (a.M32) a.M32[static_cast<int64_t>(i) * DD + t] = static_cast<float>(blk[t]);
+        const double v = (t / D == t % D && ((fx >> (t / D)) & 1)) ? 1.0 : blk[t];
+        if (a.M64) a.M64[static_cast<int64_t>(i) * DD + t] = v;
+        if (a.M32) a.M32[static_cast<int64_t>(i) * DD + t] = static_cast<float>(v);
       }
     }
   }
   // padding of the rows' parts: column i, zero blocks
-  for (int part = 0; part < 2; ++part) {
-    const int64_t b = (part ? a.Uptr[i] : a.Lptr[i]) + (part ? a.cntU[i] : a.cntL[i]);
-    const int64_t e = part ? a.Uptr[i + 1] : a.Lptr[i + 1];
-    const int64_t stride = part ? a.nU : a.nL;
+  for (int pq = 0; pq < kParts; ++pq) {
+    const LayoutPart& P = a.part[pq];
+    if (!P.cnt) continue;
+    const int64_t b = P.ptr[i] + P.cnt[i];
+    const int64_t e = P.ptr[i + 1];
     for (int64_t q = b + lane; q < e; q += 64) {
-      (part ? a.Ucol : a.Lcol)[q] = i;
-      float* v32 = part ? a.U32 : a.L32;
-      double* v64 = part ? a.U64 : a.L64;
+      P.col[q] = i;
       for (int t = 0; t < DD; ++t) {
-        if (v64) v64[t * stride + q] = 0.0;
-        if (v32) v32[t * stride + q] = 0.0f;
+        if (P.v64) P.v64[t * P.n + q] = 0.0;
+        if (P.v32) P.v32[t * P.n + q] = 0.0f;
       }
     }
   }
@@ -554,6 +561,27 @@ struct MeshDev {
 };
 
 constexpr int kAsmStage = 512;   // element corners of one row staged in LDS
+
+// Zeroes the rows and columns of constrained components (fixed[row] bit a =
+// component a of that vertex). One thread per stored block.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_zero_constrained(int64_t n, const int64_t* __restrict__ ptr,
+                                                              const int32_t* __restrict__ col,
+                                                              double* __restrict__ val,
+                                                              const uint8_t* __restrict__ fixed) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kWaves) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const uint8_t fr = fixed[i];
+  for (int64_t p = ptr[i] + (threadIdx.x & 63); p < ptr[i + 1]; p += 64) {
+    const uint8_t fc = fixed[col[p]];
+    if (!fr && !fc) continue;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (((fr >> a) & 1) || ((fc >> b) & 1)) val[p * D * D + a * D + b] = 0.0;
+  }
+}
 
 // Free index of corner c of row i's element list (c = element slot * (d+1) + corner).
 __device__ __forceinline__ int asm_corner(const MeshDev& M, int64_t kb, int c) {
@@ -761,6 +789,7 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
   for (int64_t v = 0; v < m.nv; ++v)
     if (vfree[v] >= 0) f2m[vfree[v]] = static_cast<int32_t>(v);
   std::vector<void*> owned;
+  std::vector<uint8_t> fx;   // constrained components per fine row (stays until the copies end)
   gal::DevCsr A0;
   auto release_temps = [&] {
     for (void* p : owned) (void)hipFreeAsync(p, st);
@@ -811,6 +840,24 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
         hipLaunchKernelGGL(gal::k_asm_values<3>, dim3(grid), dim3(gal::kThreads), 0, st, n, M, A0.ptr,
                            A0.col, A0.val);
       gal::check(hipGetLastError(), "assembly values launch");
+      // vertices with some components fixed: zero rows and columns there
+      fx.assign(nfree, 0);
+      bool any = false;
+      for (int64_t r = 0; r < nfree; ++r) {
+        for (int a = 0; a < d; ++a)
+          if (m.fixed[static_cast<int64_t>(f2m[r]) * d + a]) fx[r] |= static_cast<uint8_t>(1u << a);
+        any = any || fx[r] != 0;
+      }
+      if (any) {
+        const uint8_t* dfx = gal::upload_temp(fx, st, owned);
+        if (d == 2)
+          hipLaunchKernelGGL(gal::k_zero_constrained<2>, dim3(grid), dim3(gal::kThreads), 0, st,
+                             static_cast<int64_t>(n), A0.ptr, A0.col, A0.val, dfx);
+        else
+          hipLaunchKernelGGL(gal::k_zero_constrained<3>, dim3(grid), dim3(gal::kThreads), 0, st,
+                             static_cast<int64_t>(n), A0.ptr, A0.col, A0.val, dfx);
+        gal::check(hipGetLastError(), "constrained rows launch");
+      }
     }
     A.col.resize(nnz);
     gal::check(hipMemcpyAsync(A.col.data(), A0.col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st),
@@ -851,13 +898,13 @@ bool galerkin_device_operator(const GalerkinDevice* G, int l, DevOperator* out) 
 
 void* galerkin_device_stream(const GalerkinDevice* G) { return G ? static_cast<void*>(G->st) : nullptr; }
 
-void layout_count(const DevOperator& A, const LayoutArgs& a, int* cntL, int* cntU, void* stream) {
+void layout_count(const DevOperator& A, const LayoutArgs& a, void* stream) {
   if (A.n != a.n) throw Error{VASMG_EINVAL, "internal: layout operator size"};
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int grid = (a.n + gal::kWaves - 1) / gal::kWaves;
   if (a.n > 0)
     hipLaunchKernelGGL(gal::k_layout_count, dim3(grid), dim3(gal::kThreads), 0, st, a.n,
-                       gal::Csr{A.ptr, A.col, A.val}, a.perm, a.inv, a.lo, a.hi, cntL, cntU);
+                       gal::Csr{A.ptr, A.col, A.val}, a);
   gal::check(hipGetLastError(), "layout count launch");
   gal::check(hipStreamSynchronize(st), "layout count");
 }

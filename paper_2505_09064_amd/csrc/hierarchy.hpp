@@ -42,14 +42,28 @@ struct Level {
   std::vector<Key> keys;       // coarse levels: lattice keys in canonical order
   BlockCSR A;                  // operator, canonical vertex order
   int max_region_depth = 0;    // coarse levels: deepest region of the level
-  // Gauss-Seidel order (levels below the coarsest): vertex -> cell, cell -> colour
+  // Gauss-Seidel order (levels below the coarsest): vertex -> cell, vertex ->
+  // colour block (whole cells), block -> colour. A sweep visits colours, the
+  // blocks of a colour, the cells of a block and the vertices of a cell in
+  // canonical order. block_steps: side of the blocks in lattice steps (2: a
+  // block is one cell; 4: up to 2^d cells; fine level: 1).
   std::vector<int32_t> cell;
-  std::vector<int32_t> cell_color;
   int64_t ncells = 0;
-  std::vector<int32_t> color;  // colour of each vertex's cell
+  std::vector<int32_t> block;
+  std::vector<int32_t> block_color;
+  int64_t nblocks = 0;
+  int block_steps = 1;
+  std::vector<int32_t> color;  // colour of each vertex's block
   int32_t ncolors = 0;
   ScalarCSR P;                 // prolongation to the next level (empty on the coarsest)
+  // Constrained components (homogeneous Dirichlet on some components of a
+  // vertex, or coarse components whose interpolating fine vertices all have
+  // them fixed): bit a of fixed[i] set = component a of vertex i. Empty when the
+  // level has none. A stores zero rows and columns there; the solve operator
+  // has an identity row and column (layouts, export, coarsest factor).
+  std::vector<uint8_t> fixed;
 };
+
 
 struct Hierarchy {
   int d = 0;
@@ -92,6 +106,7 @@ struct SetupParams {
   int capacity;                // leaf capacity (> 0)
   bool tree_free_only;         // tree over free vertices only
   int64_t coarsest_max_dofs;   // 0 = root level
+  bool color_blocks = false;   // colour blocks of 4 lattice steps where the reach allows (3D)
   GalerkinFn galerkin = nullptr;   // null: the host product (OpenMP)
   AssembleFn assemble = nullptr;   // null: the host assembly (OpenMP)
   SettleFn settle = nullptr;
@@ -142,31 +157,43 @@ void* galerkin_device_stream(const GalerkinDevice* g);
 
 // Device layout of one level from its canonical operator A (device pointers;
 // the level's device rows i = 0..n-1 map to canonical rows perm[i], canonical
-// columns to device columns by inv; [lo[i], hi[i]) is row i's cell).
-//   count: cntL[i] / cntU[i] = off-cell blocks of row i to columns below lo[i] /
-//          at or above hi[i];
-//   fill:  L and U parts (rows at Lptr / Uptr, padded entries: column i, zero
-//          blocks), columns ascending, values plane-major with strides nL / nU in
-//          the requested precisions; in-cell blocks into the dense cell matrices
-//          (cell_of_row non-null: column-major NU x NU per cell, NU = 2^d d) or the
-//          diagonal blocks (cell_of_row null). M32 / M64 are zeroed first.
+// columns to device columns by inv; [lo[i], hi[i]) is row i's cell and
+// [blo[i], bhi[i]) its colour block, the cell when blo / bhi are null).
+// Off-cell blocks fall into four parts by device column j:
+//   L: j < blo (earlier colours), E: blo <= j < lo (earlier cells of the block),
+//   F: hi <= j < bhi (later cells of the block), U: j >= bhi (later colours).
+//   count: cnt of each part per row (E / F only where their cnt is non-null);
+//   fill:  each part's rows at its ptr (padded entries: column i, zero blocks),
+//          columns ascending, values plane-major with stride n in the requested
+//          precisions; in-cell blocks into the dense cell matrices (cell_of_row
+//          non-null: column-major NU x NU per cell, NU = 2^d d) or the diagonal
+//          blocks (cell_of_row null). M32 / M64 are zeroed first. The diagonal
+//          entry of a constrained component (fixed non-null) is set to 1 (its
+//          row and column are zero in A).
 // Both are enqueued on `stream` (a hipStream_t; null = the null stream) and
 // return after it has finished them.
+enum { kPartL = 0, kPartE = 1, kPartF = 2, kPartU = 3, kParts = 4 };
+struct LayoutPart {
+  const int* ptr = nullptr;
+  int* cnt = nullptr;
+  int64_t n = 0;        // stored entries (plane stride)
+  int* col = nullptr;
+  float* v32 = nullptr;
+  double* v64 = nullptr;
+};
 struct LayoutArgs {
   int d = 0;   // 2 or 3
   int n = 0;
   const int *perm = nullptr, *inv = nullptr, *lo = nullptr, *hi = nullptr;
+  const int *blo = nullptr, *bhi = nullptr;
   const int* cell_of_row = nullptr;
-  const int *Lptr = nullptr, *Uptr = nullptr, *cntL = nullptr, *cntU = nullptr;
-  int64_t nL = 0, nU = 0;
-  int *Lcol = nullptr, *Ucol = nullptr;
-  float *L32 = nullptr, *U32 = nullptr;
-  double *L64 = nullptr, *U64 = nullptr;
+  const uint8_t* fixed = nullptr;   // per device row: constrained components (unit diagonal)
+  LayoutPart part[kParts];
   float* M32 = nullptr;
   double* M64 = nullptr;
   int64_t m_len = 0;   // elements of M32 / M64
 };
-void layout_count(const DevOperator& A, const LayoutArgs& a, int* cntL, int* cntU, void* stream);
+void layout_count(const DevOperator& A, const LayoutArgs& a, void* stream);
 void layout_fill(const DevOperator& A, const LayoutArgs& a, void* stream);
 
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
@@ -174,7 +201,8 @@ void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& ou
 
 // Damped vertex-block Jacobi smoother data: inverse diagonal blocks [n][d][d]
 // (canonical order) and the largest eigenvalue of D^{-1} A by power iteration.
-void block_diag_inverse(const BlockCSR& A, std::vector<double>& out);
+void block_diag_inverse(const BlockCSR& A, const std::vector<uint8_t>& fixed,
+                        std::vector<double>& out);
 double jacobi_lambda_max(const BlockCSR& A, const std::vector<double>& dinv, int iters);
 
 }  // namespace vasmg

@@ -474,11 +474,14 @@ __device__ __forceinline__ T own_reciprocal(const T* Mrow, int t, bool own) {
 // Per-cell block of NV * GR threads: lane group g (GR lanes, inside one
 // wavefront) sums the off-cell part of the cell's g-th row; the sums meet in
 // LDS; wavefront 0 then runs the sequential sweep over the cell's unknowns.
+// On colour-block levels (E, F non-null) the lower sums take E with L and the
+// upper sums F with U.
 template <typename T, int D, int GR>
 __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& L,
                                                   const Part<T>& U, const T* __restrict__ x,
                                                   bool want_lo, bool want_up, T (*sh_lo)[D],
-                                                  T (*sh_up)[D], int tc) {
+                                                  T (*sh_up)[D], int tc, const Part<T>* E = nullptr,
+                                                  const Part<T>* F = nullptr) {
   const int g = tc / GR, gl = tc % GR;
   T lo[D], up[D];
 #pragma unroll
@@ -486,7 +489,9 @@ __device__ __forceinline__ void cell_offcell_sums(int v0, int m, const Part<T>& 
   if (g < m) {
     const int i = v0 + g;
     if (want_lo) part_quad_product<T, D, GR>(L, i, gl, x, lo);
+    if (want_lo && E) part_quad_product<T, D, GR>(*E, i, gl, x, lo);
     if (want_up) part_quad_product<T, D, GR>(U, i, gl, x, up);
+    if (want_up && F) part_quad_product<T, D, GR>(*F, i, gl, x, up);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -585,15 +590,234 @@ __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_gs_cell(
   if (own) x[xi] = xc;
 }
 
+// ---------------------------------------------------------------------------
+// Colour-block levels (3D): cells are grouped into colour blocks of up to
+// NB = 2^D cells (a colour is given to a block; the cells of a block are swept
+// one after the other, in canonical order). A block's device rows are
+// contiguous, its cells in canonical order. Besides L and U (blocks to earlier
+// / later colours) a row has E and F: blocks to the earlier / later cells of
+// its own colour block.
+// One workgroup sweeps one colour block, wavefront w its cell w (GR = 64 / NV
+// lanes per row):
+//   phase A, all wavefronts at once: the products whose operand is final or
+//     old for the whole sweep of this colour, from x in HBM before any cell of
+//     the block is written: L (earlier colours: final) and, from a nonzero
+//     guess, F and U (forward: later cells and colours still old) or E and U
+//     (backward: earlier cells old, later colours new). Meanwhile the part the
+//     cells need at their turn (forward: E, backward: F) is staged in LDS for
+//     the whole block (it is contiguous in every plane), as is the block's x;
+//   phase B, cell by cell in sweep order: the turn part's products with the
+//     block's iterate in LDS, where the cells swept before hold their new
+//     values, then the sequential sweep inside the cell (as k_gs_cell); the new
+//     values go to LDS and HBM; a workgroup barrier closes each step.
+// The forward sweeps save s = b - L x - E x (final values) for the residual.
+// ---------------------------------------------------------------------------
+template <int D>
+struct BlockShape {
+  static constexpr int NB = 1 << D;           // cells per colour block
+  static constexpr int GR = 64 / (1 << D);    // lanes per row: one wavefront per cell
+  static constexpr int threads = NB * 64;
+};
+
+// Entries of the turn part staged in LDS per colour block (a multiple of kQuad;
+// entries beyond it are read from HBM at the turn).
+template <typename T>
+struct BlockStage {
+  static constexpr int cap = sizeof(T) == 4 ? 1408 : 704;
+};
+
+// acc += products of the turn part's positions [kb, ke) (relative to the
+// block's first entry; multiples of kQuad on cell levels) with the block's LDS
+// iterate xs (device rows from r0); entries below `staged` come from the LDS
+// stage (tcol, tval planes of stride CAP), the rest from the part in HBM.
+template <typename T, int D, int G, int CAP>
+__device__ __forceinline__ void block_turn_product(int kb, int ke, int lane, const Part<T>& P,
+                                                   int base, int staged, const int* tcol,
+                                                   const T* tval, const T* xs, int r0, T* acc) {
+  constexpr int DP = Pad<D>::value;
+  if constexpr (sizeof(T) == 4) {
+    for (int q = kb / kQuad + lane; q < ke / kQuad; q += G) {
+      const int e = q * kQuad;
+      int4 j;
+      T v[D * D][kQuad];
+      if (e < staged) {
+        j = *reinterpret_cast<const int4*>(tcol + e);
+#pragma unroll
+        for (int pl = 0; pl < D * D; ++pl) Quad<T>::load(tval + pl * CAP + e, v[pl]);
+      } else {
+        j = reinterpret_cast<const int4*>(P.col + base)[q];
+#pragma unroll
+        for (int pl = 0; pl < D * D; ++pl)
+          Quad<T>::load(P.val + static_cast<int64_t>(pl) * P.nnz + base + e, v[pl]);
+      }
+      const int jj[kQuad] = {(j.x - r0) * DP, (j.y - r0) * DP, (j.z - r0) * DP, (j.w - r0) * DP};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const T* vv = v[a * D + b];
+          acc[a] += vv[0] * xs[jj[0] + b] + vv[1] * xs[jj[1] + b] + vv[2] * xs[jj[2] + b] +
+                    vv[3] * xs[jj[3] + b];
+        }
+      }
+    }
+  } else {
+    for (int e = kb + lane; e < ke; e += G) {
+      const bool st = e < staged;
+      const int j = ((st ? tcol[e] : P.col[base + e]) - r0) * DP;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const int pl = a * D + b;
+          const T v = st ? tval[pl * CAP + e] : P.val[static_cast<int64_t>(pl) * P.nnz + base + e];
+          acc[a] += v * xs[j + b];
+        }
+      }
+    }
+  }
+}
+
+// Two workgroups per compute unit (4 waves per SIMD: at most 128 VGPRs).
+template <typename T, int D, int MODE>
+__global__ __launch_bounds__(BlockShape<D>::threads, 4) void k_gs_block(
+    int blk0, const int* __restrict__ block_ptr, const int* __restrict__ cell_ptr, Part<T> L,
+    Part<T> U, Part<T> E, Part<T> F, const T* __restrict__ cellM, const T* __restrict__ b, T* x,
+    T* __restrict__ s_save) {
+  constexpr int DP = Pad<D>::value, DD = D * D;
+  constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
+  constexpr int NB = BlockShape<D>::NB, GR = BlockShape<D>::GR;
+  constexpr int CAP = BlockStage<T>::cap;
+  __shared__ __align__(16) T xs[NB * NV * DP];
+  __shared__ __align__(16) int tcol[CAP];
+  __shared__ __align__(16) T tval[DD * CAP];
+  const Part<T>& TP = MODE == 2 ? F : E;   // the part taken at each cell's turn
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bk = blk0 + xcd_block();
+  const int cb = block_ptr[bk], nc = block_ptr[bk + 1] - cb;
+  const int r0 = cell_ptr[cb], nrow = cell_ptr[cb + nc] - r0;
+  // stage the block's turn part (contiguous in each plane, 16-byte aligned)
+  const int tbase = TP.ptr[r0];
+  const int staged = min(TP.ptr[r0 + nrow] - tbase, CAP);
+  {
+    constexpr int VW = 16 / sizeof(T);   // elements per 16-byte copy
+    for (int e = threadIdx.x * 4; e < staged; e += blockDim.x * 4)
+      *reinterpret_cast<int4*>(tcol + e) = *reinterpret_cast<const int4*>(TP.col + tbase + e);
+    for (int pl = 0; pl < DD; ++pl) {
+      const T* src = TP.val + static_cast<int64_t>(pl) * TP.nnz + tbase;
+      for (int e = threadIdx.x * VW; e < staged; e += blockDim.x * VW)
+        *reinterpret_cast<int4*>(tval + pl * CAP + e) = *reinterpret_cast<const int4*>(src + e);
+    }
+    for (int e = threadIdx.x; e < nrow * DP; e += blockDim.x)
+      xs[e] = MODE != 0 ? x[static_cast<int64_t>(r0) * DP + e] : T(0);
+  }
+  // this wavefront's cell: the owned unknown t = lane (vertex t / D, component t % D)
+  const bool has = w < nc;
+  const int c = cb + (has ? w : 0);
+  const int v0 = cell_ptr[c], m = has ? cell_ptr[c + 1] - v0 : 0, n = m * D;
+  const int t = lane;
+  const bool own = t < n;
+  const int k = own ? t / D : 0, a = own ? t % D : 0;
+  const int64_t xi = static_cast<int64_t>(v0 + k) * DP + a;
+  T Mrow[NU];
+  const T* Mc = cellM + static_cast<int64_t>(c) * NU * NU;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) Mrow[u] = (own && u < n) ? Mc[u * NU + t] : T(0);
+  const T bt = own ? b[xi] : T(0);
+  T xc = (own && MODE != 0) ? x[xi] : T(0);
+  // phase A (the turn part's row bounds are loaded now: at the turn only LDS is read)
+  const int g = lane / GR, gl = lane % GR;
+  const int tkb = g < m ? TP.ptr[v0 + g] - tbase : 0, tke = g < m ? TP.ptr[v0 + g + 1] - tbase : 0;
+  T pa[D], pu[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) { pa[q] = T(0); pu[q] = T(0); }
+  if (g < m) {
+    const int i = v0 + g;
+    part_quad_product<T, D, GR>(L, i, gl, x, pa);
+    if (MODE == 1) {
+      part_quad_product<T, D, GR>(F, i, gl, x, pu);
+      part_quad_product<T, D, GR>(U, i, gl, x, pu);
+    }
+    if (MODE == 2) {
+      part_quad_product<T, D, GR>(E, i, gl, x, pa);
+      part_quad_product<T, D, GR>(U, i, gl, x, pa);
+    }
+  }
+  T my_pa = T(0), my_pu = T(0);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {   // every lane takes part in each shuffle
+    const T s1 = __shfl(group_sum<T, GR>(pa[q]), k * GR, 64);
+    const T s2 = MODE == 1 ? __shfl(group_sum<T, GR>(pu[q]), k * GR, 64) : T(0);
+    if (q == a) { my_pa = s1; my_pu = s2; }
+  }
+  const T rdg = own_reciprocal<T, NU>(Mrow, t, own);
+  __syncthreads();   // stage and block iterate in LDS
+  // phase B: the cells in sweep order
+  for (int step = 0; step < nc; ++step) {
+    const int kk = MODE == 2 ? nc - 1 - step : step;
+    if (w == kk) {
+      T pt[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) pt[q] = T(0);
+      if (g < m)
+        block_turn_product<T, D, GR, CAP>(tkb, tke, gl, TP, tbase, staged, tcol, tval, xs, r0, pt);
+      T my_pt = T(0);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const T s1 = __shfl(group_sum<T, GR>(pt[q]), k * GR, 64);
+        if (q == a) my_pt = s1;
+      }
+      T acc;
+      if (MODE != 2) {
+        const T s_t = own ? bt - my_pa - my_pt : T(0);
+        if (s_save && own) s_save[xi] = s_t;
+        acc = s_t - my_pu;
+      } else {
+        acc = own ? bt - my_pa - my_pt : T(0);
+      }
+      if (MODE != 0) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (u < n) {
+            const T xu = bcast(xc, u);
+            if (u != t) acc -= Mrow[u] * xu;
+          }
+        }
+      }
+#pragma unroll
+      for (int uu = 0; uu < NU; ++uu) {
+        const int u = MODE == 2 ? NU - 1 - uu : uu;
+        if (u < n) {
+          T delta = T(0);
+          if (t == u) {
+            const T xn = acc * rdg;
+            delta = xn - xc;
+            xc = xn;
+          }
+          delta = bcast(delta, u);
+          if (t != u) acc -= Mrow[u] * delta;
+        }
+      }
+      if (own) {
+        xs[(v0 + k - r0) * DP + a] = xc;
+        x[xi] = xc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // out_t = base_t - (off-cell part)_t - (M x)_t on cell levels.
 //   KIND 0: residual after a forward sweep: base = saved s, upper range only
+//           (U, and F on colour-block levels: s holds b - L x - E x)
 //   KIND 1: full residual: base = b, both ranges
 //   KIND 2: SpMV: base = 0, both ranges, result negated (y = A x)
-template <typename T, int D, int GR, int KIND>
+//   BLK: a colour-block level, E (with L) and F (with U) taken as well.
+template <typename T, int D, int GR, int KIND, bool BLK>
 __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_cell_apply(
-    int ncell, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, const T* __restrict__ cellM,
-    const T* __restrict__ base, const T* __restrict__ x, T* __restrict__ out,
-    const int* __restrict__ done) {
+    int ncell, const int* __restrict__ cell_ptr, Part<T> L, Part<T> U, Part<T> E, Part<T> F,
+    const T* __restrict__ cellM, const T* __restrict__ base, const T* __restrict__ x,
+    T* __restrict__ out, const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
   constexpr int NV = CellShape<D>::NV, NU = CellShape<D>::NU;
@@ -620,7 +844,8 @@ __global__ __launch_bounds__((CellPack<D, GR>::threads)) void k_cell_apply(
       if (KIND != 2) bt = base[xi];
     }
   }
-  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, KIND != 0, true, sh_lo[slot], sh_up[slot], t);
+  cell_offcell_sums<T, D, GR>(v0, m, L, U, x, KIND != 0, true, sh_lo[slot], sh_up[slot], t,
+                              BLK ? &E : nullptr, BLK ? &F : nullptr);
   if (threadIdx.x >= 64) return;
   const T off = own ? (KIND != 0 ? sh_lo[slot][k][a] : T(0)) + sh_up[slot][k][a] : T(0);
   T mx = T(0);
@@ -703,11 +928,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int* __restri
   if (lane == 0) VecIO<T, D>::store(bc + static_cast<int64_t>(I) * DP, acc);
 }
 
+// fixed (optional): constrained components of the fine rows, whose
+// prolongation rows are zero.
 template <typename T, int D, int GT>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __restrict__ ptr,
                                                         const int* __restrict__ idx,
                                                         const T* __restrict__ w,
                                                         const T* __restrict__ e, T* x,
+                                                        const uint8_t* __restrict__ fixed,
                                                         const int* __restrict__ done) {
   if (done && *done) return;
   constexpr int DP = Pad<D>::value;
@@ -721,8 +949,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, const int* __res
   for (int a = 0; a < D; ++a) acc[a] = T(0);
   transfer_row<T, D, GT>(ptr[i], ptr[i + 1], lane, idx, w, e, acc);
   if (lane == 0) {
+    const int fx = fixed ? fixed[i] : 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) xi[a] += acc[a];
+    for (int a = 0; a < D; ++a) xi[a] += ((fx >> a) & 1) ? T(0) : acc[a];
     VecIO<T, D>::store(x + static_cast<int64_t>(i) * DP, xi);
   }
 }
@@ -823,6 +1052,7 @@ struct BottomLevel {
   const T* p_w = nullptr;
   const int *pt_ptr = nullptr, *pt_idx = nullptr;
   const T* pt_w = nullptr;
+  const uint8_t* fixed = nullptr;   // constrained components (zero prolongation rows), or null
 };
 
 template <typename T>
@@ -980,7 +1210,7 @@ __device__ __forceinline__ void bottom_sweep(const BottomLevel<T>& lv, const Bot
 template <typename T, int D, bool ADD, typename TD>
 __device__ __forceinline__ void bottom_transfer(int nrows, const int* ptr, const int* idx,
                                                 const T* w, const T* src, int sstride, TD* dst,
-                                                int dstride) {
+                                                int dstride, const uint8_t* fixed = nullptr) {
   for (int i = threadIdx.x; i < nrows; i += blockDim.x) {
     T acc[D];
 #pragma unroll
@@ -991,10 +1221,11 @@ __device__ __forceinline__ void bottom_transfer(int nrows, const int* ptr, const
 #pragma unroll
       for (int q = 0; q < D; ++q) acc[q] += wp * e[q];
     }
+    const int fx = (ADD && fixed) ? fixed[i] : 0;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
       if (ADD)
-        dst[i * dstride + q] += acc[q];
+        dst[i * dstride + q] += ((fx >> q) & 1) ? T(0) : acc[q];
       else
         dst[i * dstride + q] = static_cast<TD>(acc[q]);
     }
@@ -1083,9 +1314,10 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a,
     const BottomLevel<T>& lv = a.lev[k];
     const BottomVecs<T> v = vecs(k);
     if (k + 1 < a.nlev)
-      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, vecs(k + 1).x, DP, v.x, DP);
+      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, vecs(k + 1).x, DP, v.x, DP,
+                                     lv.fixed);
     else
-      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, cx, D, v.x, DP);
+      bottom_transfer<T, D, true, T>(lv.n, lv.p_ptr, lv.p_idx, lv.p_w, cx, D, v.x, DP, lv.fixed);
     __syncthreads();
     for (int it = 0; it < a.npost; ++it) bottom_sweep<T, D, 2>(lv, v);
   }
@@ -1270,17 +1502,21 @@ __global__ __launch_bounds__(kBlock) void k_sub_norm(int64_t n, const double* __
 }
 
 // user layout [nv][D] <-> device numbering (padded) through a vertex map
+// fixed (optional): constrained components of the rows, read as 0.
 template <typename TS, typename TD, int D>
 __global__ __launch_bounds__(kBlock) void k_gather_user(int n, const int* __restrict__ map,
                                                         const TS* __restrict__ src,
-                                                        TD* __restrict__ dst) {
+                                                        TD* __restrict__ dst,
+                                                        const uint8_t* __restrict__ fixed) {
   constexpr int DP = Pad<D>::value;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int64_t v = map[i];
+  const int fx = fixed ? fixed[i] : 0;
 #pragma unroll
   for (int a = 0; a < DP; ++a)
-    dst[static_cast<int64_t>(i) * DP + a] = a < D ? static_cast<TD>(src[v * D + a]) : TD(0);
+    dst[static_cast<int64_t>(i) * DP + a] =
+        (a < D && !((fx >> a) & 1)) ? static_cast<TD>(src[v * D + a]) : TD(0);
 }
 
 template <typename TS, typename TD, int D>

@@ -81,16 +81,8 @@ void validate(const MeshView& m) {
   const int d = m.d;
   for (int64_t i = 0; i < m.nv * d; ++i)
     if (!std::isfinite(m.coords[i])) fail(1, "non-finite vertex coordinate");
-  for (int64_t v = 0; v < m.nv; ++v) {
-    int nf = 0;
-    for (int a = 0; a < d; ++a) {
-      uint8_t f = m.fixed[v * d + a];
-      if (f > 1) fail(1, "fixed flags must be 0 or 1");
-      nf += f;
-    }
-    if (nf != 0 && nf != d)
-      fail(1, "vertex " + std::to_string(v) + " has only some components fixed (unsupported)");
-  }
+  for (int64_t v = 0; v < m.nv * d; ++v)
+    if (m.fixed[v] > 1) fail(1, "fixed flags must be 0 or 1");
   for (int64_t e = 0; e < m.ne; ++e) {
     if (!(m.E[e] > 0.0) || !std::isfinite(m.E[e])) fail(1, "E must be finite and > 0");
     if (!(m.nu[e] > -1.0 && m.nu[e] < 0.5)) fail(1, "nu must lie in (-1, 0.5)");
@@ -511,43 +503,77 @@ int32_t greedy_color_in_order(const std::vector<int64_t>& ptr, const std::vector
   return ncol;
 }
 
-// Fine level: every vertex is a cell, coloured in canonical order. Coarse
-// lattice levels: cells of side 2 * (finest region side of the level), in
-// canonical order of their cell keys; the colouring with the fewest colours
-// among the canonical, (cell key mod 2)-class and (cell key mod 3)-class
-// visiting orders is kept (ties keep the earlier order).
-void build_gs_order(Level& lv, bool lattice, int d) {
+// Lattice blocks of side `side` (key units): vertex -> block in canonical order
+// of the block keys; returns the sorted block keys.
+std::vector<Key> lattice_blocks(const Level& lv, uint64_t side, std::vector<int32_t>& of) {
   const int64_t n = lv.n;
-  std::vector<Key> ckeys;
+  std::vector<Key> ck(n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) ck[i][a] = lv.keys[i][a] / side;
+  std::vector<Key> keys = ck;
+  __gnu_parallel::sort(keys.begin(), keys.end(), key_less);
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  of.resize(n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    of[i] = static_cast<int32_t>(std::lower_bound(keys.begin(), keys.end(), ck[i], key_less) -
+                                 keys.begin());
+  return keys;
+}
+
+// Fine level: every vertex is a cell and a colour block, coloured in canonical
+// order. Coarse lattice levels: cells of side 2 * h (h = the finest region side
+// of the level), in canonical order of their cell keys; in 3D with colour
+// blocks on, where the couplings reach 3 or 4 steps of h, the cells are grouped
+// into blocks of side 4 h (blocks two apart along an axis are then at least 5
+// steps apart, so only neighbouring blocks couple and 2^d colours suffice),
+// else every cell is its own block. Blocks are coloured greedily; the colouring
+// with the fewest colours among the canonical, (block key mod 2)-class and
+// (block key mod 3)-class visiting orders is kept (ties keep the earlier order).
+void build_gs_order(Level& lv, bool lattice, int d, bool color_blocks) {
+  const int64_t n = lv.n;
+  std::vector<Key> bkeys;
   if (!lattice) {
     lv.cell.resize(n);
     std::iota(lv.cell.begin(), lv.cell.end(), 0);
     lv.ncells = n;
+    lv.block = lv.cell;
+    lv.nblocks = n;
+    lv.block_steps = 1;
   } else {
-    const uint64_t cs = 2 * side_of(lv.max_region_depth);
-    std::vector<Key> ck(n);
-    for (int64_t i = 0; i < n; ++i)
-      for (int a = 0; a < 3; ++a) ck[i][a] = lv.keys[i][a] / cs;
-    ckeys = ck;
-    __gnu_parallel::sort(ckeys.begin(), ckeys.end(), key_less);
-    ckeys.erase(std::unique(ckeys.begin(), ckeys.end()), ckeys.end());
-    lv.ncells = static_cast<int64_t>(ckeys.size());
-    lv.cell.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-      lv.cell[i] = static_cast<int32_t>(
-          std::lower_bound(ckeys.begin(), ckeys.end(), ck[i], key_less) - ckeys.begin());
+    const uint64_t h = side_of(lv.max_region_depth);
+    bkeys = lattice_blocks(lv, 2 * h, lv.cell);
+    lv.ncells = static_cast<int64_t>(bkeys.size());
+    lv.block_steps = 2;
+    if (color_blocks && d == 3) {
+      uint64_t reach = 0;
+#pragma omp parallel for schedule(static) reduction(max : reach)
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = lv.A.rowptr[i]; p < lv.A.rowptr[i + 1]; ++p) {
+          const Key& a = lv.keys[i];
+          const Key& b = lv.keys[lv.A.col[p]];
+          for (int q = 0; q < 3; ++q) reach = std::max(reach, a[q] > b[q] ? a[q] - b[q] : b[q] - a[q]);
+        }
+      if (reach > 2 * h && reach <= 4 * h) lv.block_steps = 4;
+    }
+    if (lv.block_steps == 4) {
+      bkeys = lattice_blocks(lv, 4 * h, lv.block);
+    } else {
+      lv.block = lv.cell;
+    }
+    lv.nblocks = static_cast<int64_t>(bkeys.size());
   }
-  // cell adjacency from the structural block pattern
-  const int64_t nc = lv.ncells;
+  // block adjacency from the structural block pattern
+  const int64_t nc = lv.nblocks;
   std::vector<int64_t> vptr(nc + 1, 0);
-  for (int64_t i = 0; i < n; ++i) vptr[lv.cell[i] + 1]++;
+  for (int64_t i = 0; i < n; ++i) vptr[lv.block[i] + 1]++;
   for (int64_t c = 0; c < nc; ++c) vptr[c + 1] += vptr[c];
   std::vector<int32_t> members(n);
   {
     std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
-    for (int64_t i = 0; i < n; ++i) members[fill[lv.cell[i]]++] = static_cast<int32_t>(i);
+    for (int64_t i = 0; i < n; ++i) members[fill[lv.block[i]]++] = static_cast<int32_t>(i);
   }
-  // each cell's neighbour list is independent: built in parallel, then packed
+  // each block's neighbour list is independent: built in parallel, then packed
   std::vector<int64_t> gptr(nc + 1, 0);
   std::vector<int32_t> gadj;
   {
@@ -558,7 +584,7 @@ void build_gs_order(Level& lv, bool lattice, int d) {
       for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) {
         const int32_t v = members[q];
         for (int64_t p = lv.A.rowptr[v]; p < lv.A.rowptr[v + 1]; ++p)
-          tmp.push_back(lv.cell[lv.A.col[p]]);
+          tmp.push_back(lv.block[lv.A.col[p]]);
       }
       std::sort(tmp.begin(), tmp.end());
       tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
@@ -583,7 +609,7 @@ void build_gs_order(Level& lv, bool lattice, int d) {
       for (int64_t c = 0; c < nc; ++c) {
         int64_t w = 1;
         for (int a = 0; a < d; ++a) {
-          cls[c] += static_cast<int64_t>(ckeys[c][a] % q) * w;
+          cls[c] += static_cast<int64_t>(bkeys[c][a] % q) * w;
           w *= q;
         }
       }
@@ -596,16 +622,33 @@ void build_gs_order(Level& lv, bool lattice, int d) {
   for (int o = 1; o < n_orders; ++o)
     if (ncol[o] < ncol[best_o]) best_o = o;
   const int32_t best = ncol[best_o];
-  lv.cell_color.swap(cand[best_o]);
+  lv.block_color.swap(cand[best_o]);
   lv.ncolors = best;
   lv.color.resize(n);
-  for (int64_t i = 0; i < n; ++i) lv.color[i] = lv.cell_color[lv.cell[i]];
+  for (int64_t i = 0; i < n; ++i) lv.color[i] = lv.block_color[lv.block[i]];
+}
+
+// Sets the rows and columns of the constrained components of A to zero.
+void zero_constrained(BlockCSR& A, const std::vector<uint8_t>& fixed) {
+  if (fixed.empty()) return;
+  const int d = A.d, dd = d * d;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+      const uint8_t fr = fixed[i], fc = fixed[A.col[p]];
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b)
+          if (((fr >> a) & 1) || ((fc >> b) & 1)) A.val[p * dd + a * d + b] = 0.0;
+    }
 }
 
 // --------------------------------------------------------------------------
 // dense Cholesky (lower), FP64
 // --------------------------------------------------------------------------
-void dense_cholesky(const BlockCSR& A, std::vector<double>& L, int64_t& n) {
+// Lower Cholesky factor of the coarsest operator, with an identity row and
+// column at its constrained components.
+void dense_cholesky(const BlockCSR& A, const std::vector<uint8_t>& fixed, std::vector<double>& L,
+                    int64_t& n) {
   const int d = A.d, dd = d * d;
   n = A.n * d;
   if (n > 20000) fail(1, "coarsest level too large for a dense factorisation");
@@ -617,6 +660,10 @@ void dense_cholesky(const BlockCSR& A, std::vector<double>& L, int64_t& n) {
       for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) M[(i * d + a) * n + j * d + b] = A.val[p * dd + a * d + b];
     }
+  if (!fixed.empty())
+    for (int64_t i = 0; i < A.n; ++i)
+      for (int a = 0; a < d; ++a)
+        if ((fixed[i] >> a) & 1) M[(i * d + a) * n + i * d + a] = 1.0;
   for (int64_t i = 0; i < n; ++i) maxdiag = std::max(maxdiag, M[i * n + i]);
   for (int64_t j = 0; j < n; ++j) {
     double s = M[j * n + j];
@@ -654,14 +701,22 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     t0 = t1;
   };
 
-  // free vertices (fine canonical order = ascending mesh index)
+  // free vertices: those with at least one unconstrained component (fine
+  // canonical order = ascending mesh index); fully fixed vertices are eliminated
   std::vector<int32_t> vfree(m.nv, -1);
   int64_t nfree = 0;
-  for (int64_t v = 0; v < m.nv; ++v)
-    if (!m.fixed[v * d]) {
-      vfree[v] = static_cast<int32_t>(nfree++);
-      H.free_vertices.push_back(static_cast<int32_t>(v));
-    }
+  std::vector<uint8_t> fixed0;
+  bool partial = false;
+  for (int64_t v = 0; v < m.nv; ++v) {
+    uint8_t bits = 0;
+    for (int a = 0; a < d; ++a)
+      if (m.fixed[v * d + a]) bits |= static_cast<uint8_t>(1u << a);
+    if (bits == (1u << d) - 1) continue;
+    vfree[v] = static_cast<int32_t>(nfree++);
+    H.free_vertices.push_back(static_cast<int32_t>(v));
+    fixed0.push_back(bits);
+    partial = partial || bits != 0;
+  }
   if (nfree == 0) fail(1, "every vertex is fixed: nothing to solve");
   int64_t bad = m.ne;   // first inverted or degenerate element, if any
 #pragma omp parallel for schedule(static) reduction(min : bad)
@@ -681,10 +736,13 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   {
     Level& L0 = H.levels.back();
     L0.n = nfree;
-    if (prm.assemble)
-      prm.assemble(prm.galerkin_ctx, m, vfree, nfree, L0.A);
-    else
+    if (partial) L0.fixed = fixed0;
+    if (prm.assemble) {
+      prm.assemble(prm.galerkin_ctx, m, vfree, nfree, L0.A);   // constrained rows zeroed there
+    } else {
       assemble_fine(m, vfree, nfree, L0.A);
+      zero_constrained(L0.A, L0.fixed);
+    }
   }
   mark("validate+assemble");
 
@@ -833,6 +891,20 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     R.swap(Rn);
   }
 
+  // constrained components of the coarse levels: a coarse component is
+  // constrained when every fine vertex interpolating from it has it fixed
+  // (its column of P with the fixed rows zeroed is empty)
+  for (size_t l = 0; l + 1 < H.levels.size(); ++l) {
+    const Level& f = H.levels[l];
+    if (f.fixed.empty()) break;
+    Level& c = H.levels[l + 1];
+    std::vector<uint8_t> cm(c.n, static_cast<uint8_t>((1u << d) - 1));
+    for (int64_t i = 0; i < f.n; ++i)
+      for (int64_t p = f.P.rowptr[i]; p < f.P.rowptr[i + 1]; ++p) cm[f.P.col[p]] &= f.fixed[i];
+    bool any = false;
+    for (uint8_t b : cm) any = any || b != 0;
+    if (any) c.fixed.swap(cm);
+  }
   mark("coarse regions+P");
   // ---- Galerkin operators, with optional truncation of the hierarchy
   size_t nlev = H.levels.size();
@@ -854,11 +926,12 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
   coarsest.P = ScalarCSR();
   coarsest.color.assign(coarsest.n, 0);
   coarsest.ncolors = 0;
-  for (size_t l = 0; l + 1 < H.levels.size(); ++l) build_gs_order(H.levels[l], l > 0, d);
+  for (size_t l = 0; l + 1 < H.levels.size(); ++l)
+    build_gs_order(H.levels[l], l > 0, d, prm.color_blocks);
   mark("cells+colours");
   if (prm.settle && coarsest.A.val.size() != coarsest.A.col.size() * static_cast<size_t>(d * d))
     prm.settle(prm.galerkin_ctx);   // a fine level that is also the coarsest: its values now
-  dense_cholesky(coarsest.A, H.chol, H.n_coarse_dofs);
+  dense_cholesky(coarsest.A, coarsest.fixed, H.chol, H.n_coarse_dofs);
   mark("coarsest factor");
 }
 
@@ -876,7 +949,8 @@ namespace vasmg {
 
 // Inverse of every vertex's d x d diagonal block (Gauss-Jordan with partial
 // pivoting, FP64), [n][d][d] in canonical order.
-void block_diag_inverse(const BlockCSR& A, std::vector<double>& out) {
+void block_diag_inverse(const BlockCSR& A, const std::vector<uint8_t>& fixed,
+                        std::vector<double>& out) {
   const int d = A.d, dd = d * d;
   const int64_t n = A.n;
   out.assign(static_cast<size_t>(n) * dd, 0.0);
@@ -887,6 +961,9 @@ void block_diag_inverse(const BlockCSR& A, std::vector<double>& out) {
     for (int64_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p)
       if (A.col[p] == i)
         for (int e = 0; e < dd; ++e) a[e] = A.val[p * dd + e];
+    if (!fixed.empty())   // identity rows of the constrained components
+      for (int r = 0; r < d; ++r)
+        if ((fixed[i] >> r) & 1) a[r * d + r] = 1.0;
     for (int r = 0; r < d; ++r)
       for (int c = 0; c < d; ++c) inv[r * d + c] = (r == c) ? 1.0 : 0.0;
     for (int c = 0; c < d; ++c) {

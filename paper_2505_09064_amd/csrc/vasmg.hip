@@ -72,10 +72,22 @@ struct DevLevel {
   bool cells = false;              // coarse lattice level: Gauss-Seidel over cells
   int ncells = 0;
   int* cell_ptr = nullptr;         // cell levels: first device row of each cell
+  // colour-block levels (cells grouped into blocks of several cells, a colour
+  // per block): color_ptr then counts blocks, block_ptr gives each block's
+  // first cell, and the off-cell blocks inside a row's colour block form the
+  // parts E (earlier cells) and F (later cells)
+  bool blocks = false;
+  int nblocks = 0;
+  int* block_ptr = nullptr;
+  int *Eptr = nullptr, *Ecol = nullptr, *Fptr = nullptr, *Fcol = nullptr;
+  float *Eval32 = nullptr, *Fval32 = nullptr;
+  double *Eval64 = nullptr, *Fval64 = nullptr;
+  int64_t nnz_e = 0, nnz_f = 0, Estride = 0, Fstride = 0;
   int* color_ptr_dev = nullptr;    // device copy of color_ptr (fused bottom levels only)
   float* cellM32 = nullptr;        // cell levels: dense in-cell blocks (column-major)
   double* cellM64 = nullptr;
   int* perm = nullptr;             // device row -> canonical index
+  uint8_t* fixed = nullptr;        // constrained components per device row (null: none)
   // off-diagonal blocks to earlier colours (L) and to later colours (U)
   int *Lptr = nullptr, *Lcol = nullptr, *Uptr = nullptr, *Ucol = nullptr;
   float *Lval32 = nullptr, *Uval32 = nullptr;
@@ -316,7 +328,24 @@ void upload_transfers(vasmg_ctx& C, int l, bool need32, bool need64, const std::
 
 void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
                          const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
-                         const std::vector<int>& cell_ptr);
+                         const std::vector<int>& cell_ptr, const std::vector<int>& blk_lo,
+                         const std::vector<int>& blk_hi);
+
+// Device numbering of level l: canonical rows sorted by colour, colour block,
+// cell (ties keep the canonical order); the identity on the coarsest level.
+std::vector<int> device_order(const vasmg_ctx& C, int l) {
+  const Level& hl = C.H.levels[l];
+  std::vector<int> perm(static_cast<size_t>(hl.n));
+  std::iota(perm.begin(), perm.end(), 0);
+  if (l != C.L)
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
+      if (hl.block[a] != hl.block[b]) return hl.block[a] < hl.block[b];
+      return hl.cell[a] < hl.cell[b];
+    });
+  return perm;
+}
+
 void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv_next) {
   const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
@@ -325,45 +354,64 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
   dl.d = d;
   const bool coarsest = (l == C.L);
   dl.cells = !coarsest && l > 0;
-  // device order: colour, then cell, then canonical index (identity on the coarsest)
-  std::vector<int> perm(n), inv(n);
-  std::iota(perm.begin(), perm.end(), 0);
+  // device order: colour, colour block, cell, canonical index (identity on the coarsest)
+  const std::vector<int> perm = device_order(C, l);
+  std::vector<int> inv(n);
   if (coarsest) {
     dl.ncolors = 1;
     dl.color_ptr = {0, n};
   } else {
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
-      return hl.cell[a] < hl.cell[b];
-    });
     dl.ncolors = hl.ncolors;
   }
   for (int i = 0; i < n; ++i) inv[perm[i]] = i;
   dl.perm = C.upload(perm);
+  if (!hl.fixed.empty()) {
+    std::vector<uint8_t> fx(n);
+    for (int i = 0; i < n; ++i) fx[i] = hl.fixed[perm[i]];
+    dl.fixed = C.upload(fx);
+  }
   if (coarsest && l > 0) return;   // a coarse coarsest level only needs its factor and vectors
 
-  // cell of each device row (single rows on point levels)
-  std::vector<int> cell_lo(n), cell_hi(n), cell_ptr;
+  // cell (and colour block) of each device row (single rows on point levels)
+  std::vector<int> cell_lo(n), cell_hi(n), cell_ptr, blk_lo, blk_hi, block_ptr;
   if (dl.cells) {
+    dl.blocks = hl.block_steps > 2;
     std::vector<int> ccp(dl.ncolors + 1, 0);
     for (int i = 0; i < n; ++i) {
-      if (i == 0 || hl.cell[perm[i]] != hl.cell[perm[i - 1]]) {
-        cell_ptr.push_back(i);
+      const bool new_cell = i == 0 || hl.cell[perm[i]] != hl.cell[perm[i - 1]];
+      const bool new_block = i == 0 || hl.block[perm[i]] != hl.block[perm[i - 1]];
+      if (new_cell) cell_ptr.push_back(i);
+      if (new_block) {
+        block_ptr.push_back(static_cast<int>(cell_ptr.size()) - 1);
         ccp[hl.color[perm[i]] + 1]++;
       }
     }
     cell_ptr.push_back(n);
+    block_ptr.push_back(static_cast<int>(cell_ptr.size()) - 1);
     for (size_t c = 0; c + 1 < cell_ptr.size(); ++c)
       if (cell_ptr[c + 1] - cell_ptr[c] > (1 << d))
         throw vasmg::Error{VASMG_EINVAL, "internal: Gauss-Seidel cell larger than 2^d vertices"};
+    for (size_t k = 0; k + 1 < block_ptr.size(); ++k)
+      if (block_ptr[k + 1] - block_ptr[k] > (dl.blocks ? (1 << d) : 1))
+        throw vasmg::Error{VASMG_EINVAL, "internal: colour block with too many cells"};
     for (int c = 0; c < dl.ncolors; ++c) ccp[c + 1] += ccp[c];
-    dl.color_ptr = ccp;
+    dl.color_ptr = ccp;   // cells per colour, or colour blocks per colour
     dl.ncells = static_cast<int>(cell_ptr.size()) - 1;
+    dl.nblocks = static_cast<int>(block_ptr.size()) - 1;
     for (int c = 0; c < dl.ncells; ++c)
       for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) {
         cell_lo[i] = cell_ptr[c];
         cell_hi[i] = cell_ptr[c + 1];
       }
+    if (dl.blocks) {
+      blk_lo.resize(n);
+      blk_hi.resize(n);
+      for (int k = 0; k < dl.nblocks; ++k)
+        for (int i = cell_ptr[block_ptr[k]]; i < cell_ptr[block_ptr[k + 1]]; ++i) {
+          blk_lo[i] = cell_ptr[block_ptr[k]];
+          blk_hi[i] = cell_ptr[block_ptr[k + 1]];
+        }
+    }
   } else {
     if (!coarsest) {
       dl.color_ptr.assign(dl.ncolors + 1, 0);
@@ -375,12 +423,13 @@ void upload_level(vasmg_ctx& C, int l, bool need32, bool need64, const std::vect
       cell_hi[i] = i + 1;
     }
   }
-  upload_level_device(C, l, need32, need64, inv, cell_lo, cell_hi, cell_ptr);
+  upload_level_device(C, l, need32, need64, inv, cell_lo, cell_hi, cell_ptr, blk_lo, blk_hi);
+  if (dl.blocks) dl.block_ptr = C.upload(block_ptr);
   if (!coarsest) upload_transfers(C, l, need32, need64, perm, inv_next);
   if (!coarsest && C.opt.smoother == VASMG_SMOOTHER_JACOBI) {
     if (C.gdev) galerkin_device_join(C.gdev);   // the host values of the level
     std::vector<double> dinv;
-    block_diag_inverse(hl.A, dinv);
+    block_diag_inverse(hl.A, hl.fixed, dinv);
     const double lam = jacobi_lambda_max(hl.A, dinv, 30);
     if (!(lam > 0.0) || !std::isfinite(lam))
       throw vasmg::Error{VASMG_EDEGENERATE, "Jacobi smoother: no positive eigenvalue estimate"};
@@ -456,7 +505,8 @@ struct TempDev {
 // Only the renumbering, the cell ranges and the row pointers travel besides.
 void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const std::vector<int>& inv,
                          const std::vector<int>& cell_lo, const std::vector<int>& cell_hi,
-                         const std::vector<int>& cell_ptr) {
+                         const std::vector<int>& cell_ptr, const std::vector<int>& blk_lo,
+                         const std::vector<int>& blk_hi) {
   const Level& hl = C.H.levels[l];
   DevLevel& dl = C.lev[l];
   const int d = C.d, dd = d * d, n = dl.n, NU = (1 << d) * d;
@@ -484,24 +534,41 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
       for (int i = cell_ptr[c]; i < cell_ptr[c + 1]; ++i) cor[i] = c;
     a.cell_of_row = tmp.up(cor);
   }
-  std::vector<int> cntL(n, 0), cntU(n, 0);
-  int* d_cntL = tmp.up(cntL);
-  int* d_cntU = tmp.up(cntU);
-  layout_count(A, a, d_cntL, d_cntU, st);
-  HIP_CHECK(hipMemcpyAsync(cntL.data(), d_cntL, n * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(cntU.data(), d_cntU, n * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (dl.blocks) {
+    a.blo = tmp.up(blk_lo);
+    a.bhi = tmp.up(blk_hi);
+  }
+  a.fixed = dl.fixed;
+  // parts: L (earlier colours), E / F (earlier / later cells of the row's colour
+  // block, colour-block levels only), U (later colours)
+  const int nparts = dl.blocks ? kParts : 2;
+  const int pidx[kParts] = {kPartL, kPartU, kPartE, kPartF};
+  std::vector<int> cnt[kParts];
+  int* d_cnt[kParts] = {nullptr, nullptr, nullptr, nullptr};
+  for (int q = 0; q < nparts; ++q) {
+    cnt[pidx[q]].assign(n, 0);
+    d_cnt[pidx[q]] = tmp.up(cnt[pidx[q]]);
+    a.part[pidx[q]].cnt = d_cnt[pidx[q]];
+  }
+  layout_count(A, a, st);
+  for (int q = 0; q < nparts; ++q)
+    HIP_CHECK(hipMemcpyAsync(cnt[pidx[q]].data(), d_cnt[pidx[q]], n * sizeof(int),
+                             hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   for (int i = 0; i < n; ++i) {
-    dl.nnz_lo += cntL[i];
-    dl.nnz_up += cntU[i];
+    dl.nnz_lo += cnt[kPartL][i];
+    dl.nnz_up += cnt[kPartU][i];
+    if (dl.blocks) {
+      dl.nnz_e += cnt[kPartE][i];
+      dl.nnz_f += cnt[kPartF][i];
+    }
   }
-  dl.nnz = dl.nnz_lo + dl.nnz_up;
+  dl.nnz = dl.nnz_lo + dl.nnz_up + dl.nnz_e + dl.nnz_f;
   set_lanes(dl);
-  // the L (earlier colours) and U (later colours) parts, each plane-major over its
-  // own blocks; on cell levels every row is padded to whole quads of 4 blocks
-  // (zero blocks pointing at the row itself), so a lane reads 4 consecutive
-  // blocks with one 16-byte load per plane
-  const std::vector<int> Lptr = padded_ptr(cntL, dl.cells), Uptr = padded_ptr(cntU, dl.cells);
+  // every part plane-major over its own blocks; on cell levels every row is
+  // padded to whole quads of 4 blocks (zero blocks pointing at the row itself),
+  // so a lane reads 4 consecutive blocks with one 16-byte load per plane
+  const std::vector<int> Lptr = padded_ptr(cnt[kPartL], dl.cells), Uptr = padded_ptr(cnt[kPartU], dl.cells);
   const int64_t nL = Lptr[n], nU = Uptr[n];
   dl.Lstride = nL;
   dl.Ustride = nU;
@@ -509,32 +576,46 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
   dl.Uptr = C.upload(Uptr);
   dl.Lcol = C.dalloc<int>(nL);
   dl.Ucol = C.dalloc<int>(nU);
+  int64_t nE = 0, nF = 0;
+  if (dl.blocks) {
+    const std::vector<int> Eptr = padded_ptr(cnt[kPartE], true), Fptr = padded_ptr(cnt[kPartF], true);
+    nE = Eptr[n];
+    nF = Fptr[n];
+    dl.Estride = nE;
+    dl.Fstride = nF;
+    dl.Eptr = C.upload(Eptr);
+    dl.Fptr = C.upload(Fptr);
+    dl.Ecol = C.dalloc<int>(nE);
+    dl.Fcol = C.dalloc<int>(nF);
+  }
   if (dl.cells) dl.cell_ptr = C.upload(cell_ptr);
   const int64_t m_len = dl.cells ? static_cast<int64_t>(dl.ncells) * NU * NU : static_cast<int64_t>(n) * dd;
   if (need64) {
     dl.Lval64 = C.dalloc<double>(nL * dd);
     dl.Uval64 = C.dalloc<double>(nU * dd);
+    if (dl.blocks) {
+      dl.Eval64 = C.dalloc<double>(nE * dd);
+      dl.Fval64 = C.dalloc<double>(nF * dd);
+    }
     (dl.cells ? dl.cellM64 : dl.diag64) = C.dalloc<double>(m_len);
     dl.has64 = true;
   }
   if (need32) {
     dl.Lval32 = C.dalloc<float>(nL * dd);
     dl.Uval32 = C.dalloc<float>(nU * dd);
+    if (dl.blocks) {
+      dl.Eval32 = C.dalloc<float>(nE * dd);
+      dl.Fval32 = C.dalloc<float>(nF * dd);
+    }
     (dl.cells ? dl.cellM32 : dl.diag32) = C.dalloc<float>(m_len);
     dl.has32 = true;
   }
-  a.Lptr = dl.Lptr;
-  a.Uptr = dl.Uptr;
-  a.cntL = d_cntL;
-  a.cntU = d_cntU;
-  a.nL = nL;
-  a.nU = nU;
-  a.Lcol = dl.Lcol;
-  a.Ucol = dl.Ucol;
-  a.L32 = dl.Lval32;
-  a.U32 = dl.Uval32;
-  a.L64 = dl.Lval64;
-  a.U64 = dl.Uval64;
+  a.part[kPartL] = {dl.Lptr, d_cnt[kPartL], nL, dl.Lcol, dl.Lval32, dl.Lval64};
+  a.part[kPartU] = {dl.Uptr, d_cnt[kPartU], nU, dl.Ucol, dl.Uval32, dl.Uval64};
+  if (dl.blocks) {
+    a.part[kPartE] = {dl.Eptr, d_cnt[kPartE], nE, dl.Ecol, dl.Eval32, dl.Eval64};
+    a.part[kPartF] = {dl.Fptr, d_cnt[kPartF], nF, dl.Fcol, dl.Fval32, dl.Fval64};
+  }
   a.M32 = dl.cells ? dl.cellM32 : dl.diag32;
   a.M64 = dl.cells ? dl.cellM64 : dl.diag64;
   a.m_len = m_len;
@@ -543,16 +624,9 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
 
 // inverse permutation of level l's device numbering (canonical -> device)
 std::vector<int> device_inverse(const vasmg_ctx& C, int l) {
-  const Level& hl = C.H.levels[l];
-  const int n = static_cast<int>(hl.n);
-  std::vector<int> perm(n), inv(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  if (l != C.L)
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
-      return hl.cell[a] < hl.cell[b];
-    });
-  for (int i = 0; i < n; ++i) inv[perm[i]] = i;
+  const std::vector<int> perm = device_order(C, l);
+  std::vector<int> inv(perm.size());
+  for (size_t i = 0; i < perm.size(); ++i) inv[perm[i]] = static_cast<int>(i);
   return inv;
 }
 
@@ -668,6 +742,8 @@ template <>
 struct LevelMats<float> {
   static dev::Part<float> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval32, l.Lstride}; }
   static dev::Part<float> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval32, l.Ustride}; }
+  static dev::Part<float> E(const DevLevel& l) { return {l.Eptr, l.Ecol, l.Eval32, l.Estride}; }
+  static dev::Part<float> F(const DevLevel& l) { return {l.Fptr, l.Fcol, l.Fval32, l.Fstride}; }
   static const float* diag(const DevLevel& l) { return l.diag32; }
   static const float* pw(const DevLevel& l) { return l.p_w32; }
   static const float* ptw(const DevLevel& l) { return l.pt_w32; }
@@ -679,6 +755,8 @@ template <>
 struct LevelMats<double> {
   static dev::Part<double> L(const DevLevel& l) { return {l.Lptr, l.Lcol, l.Lval64, l.Lstride}; }
   static dev::Part<double> U(const DevLevel& l) { return {l.Uptr, l.Ucol, l.Uval64, l.Ustride}; }
+  static dev::Part<double> E(const DevLevel& l) { return {l.Eptr, l.Ecol, l.Eval64, l.Estride}; }
+  static dev::Part<double> F(const DevLevel& l) { return {l.Fptr, l.Fcol, l.Fval64, l.Fstride}; }
   static const double* diag(const DevLevel& l) { return l.diag64; }
   static const double* pw(const DevLevel& l) { return l.p_w64; }
   static const double* ptw(const DevLevel& l) { return l.pt_w64; }
@@ -712,6 +790,7 @@ dev::BottomLevel<T>* upload_bottom(vasmg_ctx& C) {
     b.pt_ptr = lv.pt_ptr;
     b.pt_idx = lv.pt_idx;
     b.pt_w = LevelMats<T>::ptw(lv);
+    b.fixed = lv.fixed;
     v.push_back(b);
   }
   return C.upload(v);
@@ -728,7 +807,7 @@ void select_bottom(vasmg_ctx& C) {
   const int tb = C.lev[C.L - 1].has64 ? 8 : 4;
   const int maxlev = C.opt.cycle == VASMG_CYCLE_W ? 1 : dev::kBottomLevels;
   auto fits = [&](const DevLevel& lv) {
-    if (!lv.cells) return false;
+    if (!lv.cells || lv.blocks) return false;
     for (int c = 0; c < lv.ncolors; ++c)
       if (lv.color_ptr[c + 1] - lv.color_ptr[c] > kBottomCellsPerColour) return false;
     return true;
@@ -808,9 +887,39 @@ void launch_gs_color(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
     default: { constexpr int GR = 64; __VA_ARGS__; } break;   \
   }
 
+// One colour of a colour-block level: one workgroup per block (k_gs_block).
+// The V-cycle kernels do not read the stop flag (see enqueue_iter_B).
+template <typename T, int D>
+void launch_gs_blocks(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s_save,
+                      hipStream_t st) {
+  if constexpr (D == 3) {
+    const int k0 = lv.color_ptr[c], nk = lv.color_ptr[c + 1] - k0;
+    if (nk <= 0) return;
+    const T* M = LevelMats<T>::cellM(lv);
+    const dev::Part<T> Lp = LevelMats<T>::L(lv), Up = LevelMats<T>::U(lv);
+    const dev::Part<T> Ep = LevelMats<T>::E(lv), Fp = LevelMats<T>::F(lv);
+    const dim3 grid(nk), blk(dev::BlockShape<D>::threads);
+    if (mode == 0)
+      hipLaunchKernelGGL((dev::k_gs_block<T, D, 0>), grid, blk, 0, st, k0, lv.block_ptr,
+                         lv.cell_ptr, Lp, Up, Ep, Fp, M, b, x, s_save);
+    else if (mode == 1)
+      hipLaunchKernelGGL((dev::k_gs_block<T, D, 1>), grid, blk, 0, st, k0, lv.block_ptr,
+                         lv.cell_ptr, Lp, Up, Ep, Fp, M, b, x, s_save);
+    else
+      hipLaunchKernelGGL((dev::k_gs_block<T, D, 2>), grid, blk, 0, st, k0, lv.block_ptr,
+                         lv.cell_ptr, Lp, Up, Ep, Fp, M, b, x, static_cast<T*>(nullptr));
+  } else {
+    throw vasmg::Error{VASMG_EINVAL, "internal: colour blocks are built in 3D only"};
+  }
+}
+
 template <typename T, int D>
 void launch_gs_cells(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s_save,
                      const int* done, hipStream_t st) {
+  if (lv.blocks) {
+    launch_gs_blocks<T, D>(lv, c, mode, b, x, s_save, st);
+    return;
+  }
   const int c0 = lv.color_ptr[c], nc = lv.color_ptr[c + 1] - c0;
   if (nc <= 0) return;
   const T* M = LevelMats<T>::cellM(lv);
@@ -833,12 +942,18 @@ void launch_gs_cells(const DevLevel& lv, int c, int mode, const T* b, T* x, T* s
 template <typename T, int D, int KIND>
 void launch_cell_apply(const DevLevel& lv, const T* base, const T* x, T* out, const int* done,
                        hipStream_t st) {
+  const dev::Part<T> Ep = LevelMats<T>::E(lv), Fp = LevelMats<T>::F(lv);
   DISPATCH_GR(lv.G, {
     using Pack = dev::CellPack<D, GR>;
-    hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND>),
-                       dim3((lv.ncells + Pack::CPW - 1) / Pack::CPW), dim3(Pack::threads), 0, st,
-                       lv.ncells, lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
-                       LevelMats<T>::cellM(lv), base, x, out, done);
+    const dim3 grid((lv.ncells + Pack::CPW - 1) / Pack::CPW), blk(Pack::threads);
+    if (lv.blocks)
+      hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND, true>), grid, blk, 0, st, lv.ncells,
+                         lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv), Ep, Fp,
+                         LevelMats<T>::cellM(lv), base, x, out, done);
+    else
+      hipLaunchKernelGGL((dev::k_cell_apply<T, D, GR, KIND, false>), grid, blk, 0, st, lv.ncells,
+                         lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv), Ep, Fp,
+                         LevelMats<T>::cellM(lv), base, x, out, done);
   });
 }
 
@@ -917,7 +1032,7 @@ template <typename T, int D>
 void launch_prolong(const DevLevel& lv, const T* e, T* x, const int* done, hipStream_t st) {
   hipLaunchKernelGGL((dev::k_prolong_add<T, D, kProlongLanes>),
                      dim3(grid_for(lv.n, dev::kBlock / kProlongLanes)), dim3(dev::kBlock), 0, st,
-                     lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv), e, x, done);
+                     lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv), e, x, lv.fixed, done);
 }
 
 template <typename T>
@@ -996,14 +1111,15 @@ LevelBytes level_bytes(const vasmg_ctx& C, int l, int tb) {
   const int NU = (1 << D) * D;
   const double own = lv.cells ? lv.ncells * (NU * NU * static_cast<double>(tb) + 4.0)
                               : n * dd * static_cast<double>(tb);
-  const double rows = n * 12.0;                      // rowptr, lower end, upper begin
+  const double rows = n * (lv.blocks ? 20.0 : 12.0);  // row pointers of the parts
   const int launches_per_sweep = lv.ncolors;
   (void)launches_per_sweep;
   LevelBytes b{};
-  b.gs_fwd0 = lv.nnz_lo * blk + rows + own + 4 * vec;        // b, x(w), s(w), x gathers
-  b.gs_fwd = (lv.nnz_lo + lv.nnz_up) * blk + rows + own + 5 * vec;
-  b.residual = lv.nnz_up * blk + rows + own + 4 * vec;       // s, x, gathers, r(w)
-  b.gs_bwd = (lv.nnz_lo + lv.nnz_up) * blk + rows + own + 4 * vec;
+  const double all = static_cast<double>(lv.nnz_lo + lv.nnz_up + lv.nnz_e + lv.nnz_f);
+  b.gs_fwd0 = (lv.nnz_lo + lv.nnz_e) * blk + rows + own + 4 * vec;   // b, x(w), s(w), x gathers
+  b.gs_fwd = all * blk + rows + own + 5 * vec;
+  b.residual = (lv.nnz_up + lv.nnz_f) * blk + rows + own + 4 * vec;  // s, x, gathers, r(w)
+  b.gs_bwd = all * blk + rows + own + 4 * vec;
   const double nn = lv.nnext;
   b.restrict_ = lv.p_nnz * (4.0 + tb) + (nn + 1) * 4 + vec + nn * DP * tb;
   b.prolong = lv.p_nnz * (4.0 + tb) + (n + 1) * 4 + nn * DP * tb + 2 * vec;
@@ -1378,7 +1494,8 @@ int solve_one(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x
   const int gflat = kFlatGrid;
   HIP_CHECK(hipEventRecord(C.ev[0], st));
   hipLaunchKernelGGL((dev::k_gather_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
-                     dim3(dev::kBlock), 0, st, n0, C.user_map, d_rhs, C.F);
+                     dim3(dev::kBlock), 0, st, n0, C.user_map, d_rhs, C.F,
+                     static_cast<const uint8_t*>(C.lev[0].fixed));
   // ||F||, then r = F - A x0 (or F), p = 0
   hipLaunchKernelGGL((dev::k_dot<double>), dim3(gflat), dim3(dev::kBlock), 0, st, n0p, C.F, C.F,
                      C.partial, static_cast<const int*>(nullptr));
@@ -1388,7 +1505,8 @@ int solve_one(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x
   HIP_CHECK(hipMemcpyAsync(&C.sc->rtol, C.h_rtol, sizeof(double), hipMemcpyHostToDevice, st));
   if (d_x0) {
     hipLaunchKernelGGL((dev::k_gather_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
-                       dim3(dev::kBlock), 0, st, n0, C.user_map, d_x0, C.X);
+                       dim3(dev::kBlock), 0, st, n0, C.user_map, d_x0, C.X,
+                       static_cast<const uint8_t*>(C.lev[0].fixed));
     launch_spmv<double, D>(C.lev[0], C.X, C.Q, nullptr, 0, nullptr, st);
     hipLaunchKernelGGL(dev::k_sub_norm, dim3(gflat), dim3(dev::kBlock), 0, st, n0p, C.F, C.Q, C.R,
                        C.partial);
@@ -1674,11 +1792,11 @@ void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
     if (l == 0)
       hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K, dev::Pad<D>::value>), pgrid, dim3(dev::kBlock),
                          0, st, lv.n, lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
-                         static_cast<const T*>(C.kx[l + 1]), x);
+                         static_cast<const T*>(C.kx[l + 1]), x, static_cast<const uint8_t*>(lv.fixed));
     else
       hipLaunchKernelGGL((dev::k_prolong_mc<T, D, K, D>), pgrid, dim3(dev::kBlock), 0, st, lv.n,
                          lv.p_ptr, lv.p_idx, LevelMats<T>::pw(lv),
-                         static_cast<const T*>(C.kx[l + 1]), x);
+                         static_cast<const T*>(C.kx[l + 1]), x, static_cast<const uint8_t*>(lv.fixed));
     for (int k = 0; k < C.opt.n_post; ++k)
       launch_gs_sweep_mc<T, D, K>(lv, true, false, b, x, nullptr, st);
   }
@@ -1748,14 +1866,14 @@ int solve_block(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d
   const dim3 gk(grid_for(static_cast<int64_t>(n0) * K, dev::kBlock));
   HIP_CHECK(hipEventRecord(C.ev[0], st));
   hipLaunchKernelGGL((dev::k_gather_user_mc<D, K>), gk, dim3(dev::kBlock), 0, st, n0, C.user_map,
-                     d_rhs, nv, c0, nc, C.kF);
+                     d_rhs, nv, c0, nc, C.kF, static_cast<const uint8_t*>(C.lev[0].fixed));
   hipLaunchKernelGGL((dev::k_dot_mc<K, DP, double>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.kF,
                      C.kF, C.kpartial);
   hipLaunchKernelGGL((dev::k_finalize_mc<dev::FIN_NORMF, K>), dim3(K), dim3(dev::kBlock), 0, st,
                      C.kpartial, gflat, C.ksc);
   if (d_x0) {
     hipLaunchKernelGGL((dev::k_gather_user_mc<D, K>), gk, dim3(dev::kBlock), 0, st, n0, C.user_map,
-                       d_x0, nv, c0, nc, C.kX);
+                       d_x0, nv, c0, nc, C.kX, static_cast<const uint8_t*>(C.lev[0].fixed));
     hipLaunchKernelGGL((dev::k_zero_cols_mc<K, DP>), dim3(gflat), dim3(dev::kBlock), 0, st, n, C.ksc,
                        C.kX);
     launch_spmv_mc<D, K>(C, C.kX, C.kQ, nullptr, st);
@@ -1950,11 +2068,15 @@ unsigned char* scratch_address(int dev) {
   return static_cast<unsigned char*>(g_scratch_ptr[dev]);
 }
 
+// masked: the level's constrained components read as 0 (the restriction's
+// zero prolongation rows)
 template <typename T, int D>
-void debug_gather(vasmg_ctx& C, int l, const double* src, T* dst, hipStream_t st) {
+void debug_gather(vasmg_ctx& C, int l, const double* src, T* dst, hipStream_t st,
+                  bool masked = false) {
   const int n = static_cast<int>(C.H.levels[l].n);
   hipLaunchKernelGGL((dev::k_gather_user<double, T, D>), dim3(grid_for(n, dev::kBlock)),
-                     dim3(dev::kBlock), 0, st, n, C.lev[l].perm, src, dst);
+                     dim3(dev::kBlock), 0, st, n, C.lev[l].perm, src, dst,
+                     masked ? static_cast<const uint8_t*>(C.lev[l].fixed) : nullptr);
 }
 template <typename T, int D>
 void debug_scatter(vasmg_ctx& C, int l, const T* src, double* dst, hipStream_t st) {
@@ -2053,7 +2175,11 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       throw vasmg::Error{VASMG_EINVAL, "setup_device must be 0 or 1"};
     MeshView mv{mesh->dim, mesh->n_vertices, mesh->coords, mesh->n_elements, mesh->elems,
                 mesh->E, mesh->nu, mesh->fixed};
+    if (o.color_blocks != 0 && o.color_blocks != 1)
+      throw vasmg::Error{VASMG_EINVAL, "color_blocks must be 0 (off) or 1 (on)"};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
+    // the block right-hand-side kernels sweep one cell per workgroup: no colour blocks
+    prm.color_blocks = o.color_blocks == 1 && o.block_rhs == 0;
     std::unique_ptr<GalerkinDevice, void (*)(GalerkinDevice*)> gdev(nullptr, galerkin_device_destroy);
     if (o.setup_device == 1) {
       if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device for setup_device = 1"};
@@ -2269,7 +2395,8 @@ vasmg_status vasmg_level_info(vasmg_handle h, int32_t level, int64_t* n_vertices
 
 vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, int32_t* cell,
                                 int32_t* color, int64_t* rowptr, int32_t* cols, double* vals,
-                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals) {
+                                int64_t* p_rowptr, int32_t* p_cols, double* p_vals,
+                                int32_t* block, uint8_t* fixed) {
   if (!h || level < 0 || level >= static_cast<int32_t>(h->H.levels.size())) {
     g_last_error = "null handle or level out of range";
     return VASMG_EINVAL;
@@ -2292,9 +2419,23 @@ vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, in
   if (cell) {
     for (int64_t i = 0; i < lv.n; ++i) cell[i] = lv.cell.empty() ? 0 : lv.cell[i];
   }
+  if (block) {
+    for (int64_t i = 0; i < lv.n; ++i) block[i] = lv.block.empty() ? 0 : lv.block[i];
+  }
   if (rowptr) std::copy(lv.A.rowptr.begin(), lv.A.rowptr.end(), rowptr);
   if (cols) std::copy(lv.A.col.begin(), lv.A.col.end(), cols);
-  if (vals) std::copy(lv.A.val.begin(), lv.A.val.end(), vals);
+  if (vals) {
+    std::copy(lv.A.val.begin(), lv.A.val.end(), vals);
+    if (!lv.fixed.empty())   // identity rows of the constrained components
+      for (int64_t i = 0; i < lv.n; ++i)
+        for (int64_t p = lv.A.rowptr[i]; p < lv.A.rowptr[i + 1]; ++p)
+          if (lv.A.col[p] == i)
+            for (int a = 0; a < d; ++a)
+              if ((lv.fixed[i] >> a) & 1) vals[p * d * d + a * d + a] = 1.0;
+  }
+  if (fixed) {
+    for (int64_t i = 0; i < lv.n; ++i) fixed[i] = lv.fixed.empty() ? 0 : lv.fixed[i];
+  }
   if (p_rowptr) {
     if (lv.P.rowptr.empty())
       std::fill(p_rowptr, p_rowptr + lv.n + 1, 0);
@@ -2406,7 +2547,7 @@ vasmg_status vasmg_restrict_device(vasmg_handle h, int32_t level, int32_t precis
       constexpr int D = decltype(dtag)::value;
       T* r = static_cast<T*>(lv.r);
       T* bc = static_cast<T*>(nx.b);
-      debug_gather<T, D>(*h, level, d_r, r, st);
+      debug_gather<T, D>(*h, level, d_r, r, st, true);
       launch_restrict<T, D>(lv, r, bc, nullptr, st);
       debug_scatter<T, D>(*h, level + 1, bc, d_bc, st);
     };

@@ -56,7 +56,8 @@ class Options(C.Structure):
                 ("preconditioner", C.c_int32), ("profile", C.c_int32),
                 ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
                 ("block_rhs", C.c_int32), ("cycle", C.c_int32), ("smoother", C.c_int32),
-                ("setup_device", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("setup_device", C.c_int32), ("color_blocks", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class PhaseStat(C.Structure):
@@ -126,7 +127,7 @@ def lib():
             "vasmg_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]),
             "vasmg_level_info": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
                                        C.POINTER(i64)]),
-            "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "vasmg_tree_info": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
             "vasmg_spmv_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_gs_sweep_device": (i32, [vp, i32, i32, i32, vp, vp, vp]),
@@ -346,11 +347,13 @@ class Solver:
         prow = np.empty(n + 1, dtype=np.int64)
         pcol = np.empty(pn, dtype=np.int32)
         pval = np.empty(pn, dtype=np.float64)
+        block = np.empty(n, dtype=np.int32)
+        fixed = np.empty(n, dtype=np.uint8)
         _check(lib().vasmg_export_level(self._h, level, _ptr(keys), _ptr(cell), _ptr(color),
                                         _ptr(rowptr), _ptr(cols), _ptr(vals), _ptr(prow),
-                                        _ptr(pcol), _ptr(pval)))
+                                        _ptr(pcol), _ptr(pval), _ptr(block), _ptr(fixed)))
         return dict(keys=keys, cell=cell, color=color, rowptr=rowptr, cols=cols, vals=vals,
-                    p_rowptr=prow, p_cols=pcol, p_vals=pval, **info)
+                    p_rowptr=prow, p_cols=pcol, p_vals=pval, block=block, fixed=fixed, **info)
 
     def tree_info(self):
         m, M, dep = C.c_double(), C.c_double(), C.c_int32()

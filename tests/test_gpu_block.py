@@ -11,7 +11,7 @@ initial guesses are covered.
 import numpy as np
 import pytest
 
-from oracle import Oracle
+from oracle import Oracle, OracleOptions
 from workloads import fourier_body_force, load_function_tet, load_function_tri, small2d, small3d
 
 torch = pytest.importorskip("torch")
@@ -51,7 +51,8 @@ def _setup(dim, precision, K):
     key = (dim, precision, K)
     if key not in _cache:
         m = small3d(9, seed=5) if dim == 3 else small2d(33, seed=3)
-        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+        # block right-hand-side handles sweep without colour blocks
+        o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="off"))
         s = V.Solver.from_mesh(m, precision=precision, block_rhs=K)
         _cache[key] = (m, o, s)
     return _cache[key]
@@ -156,4 +157,25 @@ def test_full_size_block_workload_properties():
         x1 = d_x1.cpu().numpy()
         assert abs(i1["iterations"] - infos[c]["iterations"]) <= 1
         assert np.linalg.norm(X[c] - x1) / np.linalg.norm(x1) < 1e-5
+    s.free()
+
+
+@pytest.mark.parametrize("K", [4, 16])
+def test_block_rollers_match_oracle_per_column(K):
+    """Block right-hand sides on a mesh with partially constrained vertices
+    (rollers on the three symmetry planes): every column against its own
+    oracle solve (FP64 within 1e-8, +-1 iteration), zero at the fixed DOFs
+    even where the load cases put nonzero entries there."""
+    m = small3d(9, seed=5, fix="symmetry")
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="off"))
+    s = V.Solver.from_mesh(m, precision=V.FP64, block_rhs=K)
+    F = np.stack(_loads(m, 6))
+    X, infos = s.solve(F, 1e-8)
+    fixed = m.fixed.astype(bool)
+    for c in range(6):
+        xo, io = o.solve(F[c], 1e-8)
+        assert infos[c]["converged"] == 1
+        assert abs(infos[c]["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(X[c] - xo) / np.linalg.norm(xo) <= 1e-8
+        assert np.all(X[c][fixed] == 0)
     s.free()

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle, OracleOptions
-from oracle.hierarchy import block_prolongation
+from oracle.hierarchy import masked_prolongation
 from oracle.smoother import ColoredGS
 from workloads import cfg1, manufactured_mesh, small2d, small3d
 
@@ -60,7 +60,16 @@ MESHES = {
     "small3d_n9": lambda: small3d(9, seed=5),
     "graded2d_n33_nu049": lambda: small2d(33, seed=None, graded=True, nu=0.49),
     "mixed3d_n8": lambda: _mixed3d(),
+    # rollers (partially constrained vertices) on symmetry planes
+    "symmetry2d_n17": lambda: small2d(17, seed=2, fix="symmetry"),
+    "symmetry3d_n9": lambda: small3d(9, seed=5, fix="symmetry"),
+    # Gauss-Seidel by colour blocks (option color_blocks = 1)
+    "blocks3d_n9": lambda: small3d(9, seed=5),
+    "blocks_symmetry3d_n9": lambda: small3d(9, seed=5, fix="symmetry"),
 }
+# handle and oracle options of the meshes above
+MESH_OPTS = {"blocks3d_n9": ({"color_blocks": 1}, {"color_blocks": "auto"}),
+             "blocks_symmetry3d_n9": ({"color_blocks": 1}, {"color_blocks": "auto"})}
 
 
 def _mixed3d():
@@ -78,9 +87,10 @@ def _pair(name, precision=V.FP64, **kw):
     key = (name, precision, tuple(sorted(kw.items())))
     if key not in _cache:
         m = MESHES[name]()
-        oo = OracleOptions(**{k: v for k, v in kw.items() if k in ("coarsest_max_dofs",)})
+        hkw, okw = MESH_OPTS.get(name, ({}, {}))
+        oo = OracleOptions(**okw, **{k: v for k, v in kw.items() if k in ("coarsest_max_dofs",)})
         o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, oo)
-        s = V.Solver.from_mesh(m, precision=precision, **kw)
+        s = V.Solver.from_mesh(m, precision=precision, **hkw, **kw)
         _cache[key] = (m, o, s)
     return _cache[key]
 
@@ -102,9 +112,8 @@ def test_kernel_parity_per_level(name, prec):
         s.spmv_device(l, prec, _dev(x), y)
         assert _rel(_host(y).ravel(), A @ x.ravel()) < tol, (l, "spmv")
         # GS forward and backward sweeps from a nonzero guess
-        S = ColoredGS(A, d, o.cells[l], o.cell_colors[l])
-        S32 = (ColoredGS(A, d, o.cells[l], o.cell_colors[l], np.float32)
-               if prec == V.FP32_PRECOND else None)
+        S = o.gs(l)
+        S32 = o.gs(l, np.float32) if prec == V.FP32_PRECOND else None
         for bw in (0, 1):
             xg = _dev(x)
             s.gs_sweep_device(l, prec, bw, _dev(b), xg)
@@ -122,7 +131,7 @@ def test_kernel_parity_per_level(name, prec):
                 assert err <= bar, (l, "gs", bw, err, bar)
                 assert _rel(got, ref) < 1e-4, (l, "gs", bw)
         # restriction and prolongation
-        Pb = block_prolongation(o.P[l], d)
+        Pb = masked_prolongation(o.P[l], d, o.cmask[l])     # zero rows at fixed components
         nc = Pb.shape[1] // d
         bc = torch.zeros((nc, d), dtype=torch.float64, device="cuda")
         s.restrict_device(l, prec, _dev(x), bc)
@@ -166,7 +175,7 @@ def test_solve_parity_fp64(name):
     assert abs(info["iterations"] - io["iterations"]) <= 1
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
     assert info["rel_res_true"] < 1e-6
-    assert np.all(x[m.fixed.any(axis=1)] == 0)
+    assert np.all(x[m.fixed.astype(bool)] == 0)
 
 
 @pytest.mark.parametrize("name", list(MESHES))
@@ -277,6 +286,24 @@ def test_truncated_and_single_level_hierarchies():
         s.free()
 
 
+def _golden_sketch():
+    """sketch() of tests/golden/make_oracle_golden.py (the script that wrote the
+    stored values)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_oracle_golden",
+                                                  os.path.join(GOLD, "make_oracle_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.sketch
+
+
+def _sketch_error(g, x):
+    """Estimate of |x - x_oracle|_2 from the stored sketch of the oracle's
+    solution (projections on seeded random-sign vectors)."""
+    sk = _golden_sketch()(x)
+    return float(np.linalg.norm(sk - np.array(g["sketch_x"])) / np.sqrt(g["sketch_rows"]))
+
+
 def test_full_size_3d_workload_against_oracle_golden():
     """The 65^3 benchmark workload (811,200 DOFs) in the benchmark's launch
     configuration (autotuned lanes): sampled solution values and iteration
@@ -295,15 +322,21 @@ def test_full_size_3d_workload_against_oracle_golden():
     xs = x[np.array(g["sample_vertices"])]
     assert np.abs(xs - np.array(g["sample_x"])).max() <= 1e-8 * g["x_norminf"]
     assert abs(np.linalg.norm(x) - g["x_norm2"]) <= 1e-8 * g["x_norm2"]
+    # the whole vector: its 2-norm distance from the oracle's, through the sketch
+    e2 = _sketch_error(g, x) / g["x_norm2"]
+    print("cfg2 fp64 whole-vector relative error (sketch)", e2)
+    assert e2 <= 1e-8
     s.free()
     s = V.Solver.from_mesh(m, precision=V.FP32_PRECOND, autotune=1)
     x32, info = s.solve(m.rhs[0], 1e-6)
+    e32 = _sketch_error(g, x32) / g["x_norm2"]
     print("cfg2 mixed gpu", info["iterations"], "oracle fp32-mode", g["fp32"]["iterations"],
-          info["t_solve_ms"], "ms")
+          info["t_solve_ms"], "ms", "whole-vector error vs the FP64 oracle (sketch)", e32)
     assert info["converged"] == 1 and info["rel_res_true"] < 1e-6
     assert abs(info["iterations"] - g["fp32"]["iterations"]) <= 1
     xs = x32[np.array(g["sample_vertices"])]
     assert np.abs(xs - np.array(g["sample_x"])).max() <= 1e-5 * g["x_norminf"]
+    assert e32 <= 1e-5
     s.free()
 
 
@@ -326,6 +359,10 @@ def test_full_size_graded_2d_against_oracle_golden():
     assert abs(info["iterations"] - g["fp64"]["iterations"]) <= 1
     assert np.abs(x[idx] - np.array(g["sample_x"])).max() <= 1e-8 * g["x_norminf"]
     assert abs(np.linalg.norm(x) - g["x_norm2"]) <= 1e-8 * g["x_norm2"]
+    if "sketch_x" in g:
+        e2 = _sketch_error(g, x) / g["x_norm2"]
+        print("cfg3 fp64 whole-vector relative error (sketch)", e2)
+        assert e2 <= 1e-8
     s.free()
     s = V.Solver.from_mesh(m, precision=V.FP32_PRECOND)
     x32, info = s.solve(m.rhs[0], 1e-6)
@@ -410,10 +447,10 @@ def test_jacobi_smoother_parity(name, cycle):
 
 def _expected_bottom(s, tb, cycle):
     """First level of the fused bottom (levels lo..L-1 and the coarsest solve in
-    one workgroup) under the selection rule: Gauss-Seidel cell levels from L-1
-    upwards, at most 16 cells per colour, their LDS arrays within 56 KiB, at
-    most 4 levels (1 for the W-cycle), never level 0, coarsest solve by the
-    inverse (at most 256 DOFs)."""
+    one workgroup) under the selection rule: Gauss-Seidel cell levels without
+    colour blocks from L-1 upwards, at most 16 cells per colour, their LDS arrays
+    within 56 KiB, at most 4 levels (1 for the W-cycle), never level 0, coarsest
+    solve by the inverse (at most 256 DOFs)."""
     nl, _, dim = s.hierarchy_info()
     L = nl - 1
     if L < 2 or s.level_info(L)["n_vertices"] * dim > 256:
@@ -428,6 +465,8 @@ def _expected_bottom(s, tb, cycle):
         for c, col in set(zip(e["cell"].tolist(), e["color"].tolist())):
             per[col] = per.get(col, 0) + 1
         ncells = len(set(e["cell"].tolist()))
+        if len(set(e["block"].tolist())) < ncells:     # a colour-block level
+            break
         size = 4 * n * dp * tb + 4 * ((ncol + 1) + (ncells + 1) + 2 * (n + 1))
         if max(per.values()) > 16 or used + size > 56 * 1024:
             break
@@ -445,7 +484,8 @@ def test_fused_bottom_selection(name, prec, cycle):
     above cover each depth in 2D and 3D, FP64 and FP32), and the preconditioner
     with it still matches the oracle."""
     m = MESHES[name]()
-    s = V.Solver.from_mesh(m, precision=prec, cycle=cycle)
+    hkw, okw = MESH_OPTS.get(name, ({}, {}))
+    s = V.Solver.from_mesh(m, precision=prec, cycle=cycle, **hkw)
     lo = _expected_bottom(s, 8 if prec == V.FP64 else 4, cycle)
     assert lo is not None
     phases = s.profile_iteration(1)
@@ -453,7 +493,7 @@ def test_fused_bottom_selection(name, prec, cycle):
     assert [p["level"] for p in bottom] == [lo]
     assert max(p["level"] for p in phases) == lo
     cname = {V.CYCLE_V: "V", V.CYCLE_W: "W"}[cycle]
-    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(cycle=cname))
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(cycle=cname, **okw))
     n = o.A[0].shape[0] // m.dim
     r = np.random.default_rng(4).normal(size=(n, m.dim))
     z = torch.zeros_like(_dev(r))
@@ -522,22 +562,25 @@ def test_binding_refuses_unsafe_device_tensors():
 
 FULL_PATH = {
     "cube33_3d": lambda: small3d(33, seed=1, fix="x0"),
+    "cube33_3d_color_blocks": lambda: small3d(33, seed=1, fix="x0"),
     "graded129_2d_nu049": lambda: small2d(129, seed=None, graded=True, nu=0.49),
 }
 
 
 def _launch_shapes(s):
-    """Per smoothed level: colours, longest block row, and the most cells (or
-    rows, on the fine level) one colour launch takes."""
+    """Per smoothed level: colours, longest block row, whether cells are grouped
+    into colour blocks, and the most workgroup units (colour blocks, cells, or
+    rows on the fine level) one colour launch takes."""
     nl, _, _ = s.hierarchy_info()
     out = []
     for l in range(nl - 1):
         e = s.export_level(l)
-        unit = np.arange(e["n_vertices"]) if l == 0 else e["cell"]
+        unit = np.arange(e["n_vertices"]) if l == 0 else e["block"]
         per = {}
         for _, col in set(zip(unit.tolist(), e["color"].tolist())):
             per[col] = per.get(col, 0) + 1
         out.append(dict(level=l, colors=int(e["n_colors"]), max_row=int(np.diff(e["rowptr"]).max()),
+                        blocks=bool(l > 0 and np.unique(e["block"]).size < np.unique(e["cell"]).size),
                         per_colour=sorted(per.values())))
     return out
 
@@ -546,23 +589,30 @@ def _launch_shapes(s):
 def test_full_vector_parity_on_full_size_paths(name):
     """Whole solution vectors against the oracle on meshes whose hierarchies take
     the launch paths of the full-size workloads, in the benchmark's launch
-    configuration (autotuned lanes): 3D, a level 1 of 27 colours whose rows reach
-    400 blocks (several quad steps per lane) and whose colour launches hold more
-    cells than the chip has XCDs, unevenly divided over them; 2D graded nu = 0.49,
-    more than a thousand cells per colour packed four to a wavefront; the fused
-    bottom where the selection rule puts it. FP64 within 1e-8 of max |x| element
-    by element and +-1 iteration; the FP32 V-cycle within +-1 iteration of the
-    oracle's FP32 mode, its error against the FP64 oracle reported."""
+    configuration (autotuned lanes): 3D, a level 1 whose rows reach 400 blocks
+    (several quad steps per lane), swept in 27 colours (default) or by colour
+    blocks in 8 colours (option color_blocks), its colour launches holding more
+    workgroups than the chip has XCDs, unevenly divided over them; 2D graded
+    nu = 0.49, more than a thousand cells per colour packed four to a wavefront;
+    the fused bottom where the selection rule puts it. FP64 within 1e-8 of max |x|
+    element by element and +-1 iteration; the FP32 V-cycle within +-1 iteration
+    of the oracle's FP32 mode, its error against the FP64 oracle reported."""
     m = FULL_PATH[name]()
-    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    on = name.endswith("color_blocks")
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed,
+               OracleOptions(color_blocks="auto" if on else "off"))
     xo, io = o.solve(m.rhs[0], 1e-6)
     _, io32 = o.solve(m.rhs[0], 1e-6, precision="fp32")
     for prec in (V.FP64, V.FP32_PRECOND):
-        s = V.Solver.from_mesh(m, precision=prec, autotune=1)
+        s = V.Solver.from_mesh(m, precision=prec, autotune=1, color_blocks=1 if on else 0)
         shapes = _launch_shapes(s)
         if m.dim == 3:
             l1 = shapes[1]
-            assert l1["colors"] == 27 and l1["max_row"] > 256, l1
+            assert l1["max_row"] > 256, l1
+            if on:
+                assert l1["blocks"] and l1["colors"] == 8, l1
+            else:
+                assert not l1["blocks"] and l1["colors"] == 27, l1
             assert max(l1["per_colour"]) > 64
             assert any(c % 8 for c in l1["per_colour"])
         else:

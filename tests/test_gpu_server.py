@@ -23,9 +23,10 @@ def _requests():
     out = []
     for i in range(8):
         if i % 2 == 0:
-            m = small2d(9 + 4 * i, seed=i, nu=0.3 + 0.02 * i)
+            m = small2d(9 + 4 * i, seed=i, nu=0.3 + 0.02 * i,
+                        fix="symmetry" if i == 4 else "boundary")
         else:
-            m = small3d(5 + i // 2, seed=i, fix="x0")
+            m = small3d(5 + i // 2, seed=i, fix="symmetry" if i == 5 else "x0")
         rng = np.random.default_rng(i)
         m.E = np.where(rng.random(m.elems.shape[0]) < 0.5, 1.0, 100.0)
         out.append(m)

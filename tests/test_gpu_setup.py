@@ -56,6 +56,8 @@ CASES = {
                   OracleOptions(tree_vertices="free")),
     "truncated": (lambda: small2d(21, seed=7), {"coarsest_max_dofs": 300},
                   OracleOptions(coarsest_max_dofs=300)),
+    "symmetry3d": (lambda: small3d(9, seed=5, fix="symmetry"), {}, OracleOptions()),
+    "clamp_rollers3d": (lambda: small3d(7, seed=3, fix="roller_x1"), {}, OracleOptions()),
 }
 
 
@@ -70,7 +72,8 @@ def test_device_galerkin_matches_oracle_and_host(name):
     Ld, Lh = _levels(sd), _levels(sh)
     assert len(Ld) == len(Lh) == o.L + 1
     for l, (ed, eh) in enumerate(zip(Ld, Lh)):
-        for key in ("rowptr", "cols", "cell", "color", "keys", "p_rowptr", "p_cols", "p_vals"):
+        for key in ("rowptr", "cols", "cell", "block", "color", "fixed", "keys", "p_rowptr",
+                    "p_cols", "p_vals"):
             if ed.get(key) is not None:
                 assert np.array_equal(ed[key], eh[key]), (l, key)
         Ad = _bsr(ed, d)
@@ -86,7 +89,7 @@ def test_device_galerkin_matches_oracle_and_host(name):
     sh.free()
 
 
-@pytest.mark.parametrize("name", ["small3d", "small2d_x0", "graded"])
+@pytest.mark.parametrize("name", ["small3d", "small2d_x0", "graded", "symmetry3d"])
 @pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
 def test_device_layout_kernels_per_level(name, prec):
     """The level layouts built on the device (colour-ordered rows, sorted and
@@ -115,7 +118,7 @@ def test_device_layout_kernels_per_level(name, prec):
         assert _rel(_host(yd).ravel(), A @ x.ravel()) < tol, (l, "spmv")
         if l == 0:
             assert np.array_equal(_host(yd), _host(yh)), "fine SpMV not bitwise equal"
-        S = ColoredGS(A, d, o.cells[l], o.cell_colors[l])
+        S = o.gs(l)
         for bw in (0, 1):
             xd, xh = _dev(x), _dev(x)
             sd.gs_sweep_device(l, prec, bw, _dev(b), xd)

@@ -48,6 +48,7 @@ def _compare(mesh, oopts=None, **kw):
         assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs"
         if l < o.L:
             assert np.array_equal(e["cell"], o.cells[l])
+            assert np.array_equal(e["block"], o.blocks[l])
             assert np.array_equal(e["color"], o.colors[l])
             assert e["n_colors"] == o.colors[l].max() + 1
             P = sp.csr_matrix((e["p_vals"], e["p_cols"], e["p_rowptr"]), shape=o.P[l].shape)
@@ -55,11 +56,18 @@ def _compare(mesh, oopts=None, **kw):
             assert diff.nnz == 0 or abs(diff).max() == 0.0, "P not bit-identical"
         if l >= 1:
             assert np.array_equal(e["keys"], o.levels.level_keys(l))
+        # constrained components (bit a = component a) against the oracle's mask
+        bits = np.zeros(n, dtype=np.uint8)
+        for a in range(d):
+            bits |= (o.cmask[l].reshape(n, d)[:, a].astype(np.uint8) << a)
+        assert np.array_equal(e["fixed"], bits), l
     s.free()
 
 
 @pytest.mark.parametrize("name", ["cfg1", "small3d", "small2d_x0", "graded", "cap9", "free_tree",
-                                  "truncated", "mixed_material"])
+                                  "truncated", "mixed_material", "symmetry2d", "symmetry3d",
+                                  "clamp_rollers3d", "symmetry3d_color_blocks", "symmetry3d_free_tree",
+                                  "small3d_color_blocks"])
 def test_host_setup_matches_oracle(name):
     if name == "cfg1":
         _compare(cfg1())
@@ -81,6 +89,20 @@ def test_host_setup_matches_oracle(name):
         m.E = np.where(rng.random(m.elems.shape[0]) < 0.5, 1.0, 100.0)
         m.nu = rng.uniform(0.25, 0.45, m.elems.shape[0])
         _compare(m)
+    elif name == "symmetry2d":
+        _compare(small2d(17, seed=2, fix="symmetry"))
+    elif name == "symmetry3d":
+        _compare(small3d(9, seed=5, fix="symmetry"))
+    elif name == "clamp_rollers3d":
+        _compare(small3d(7, seed=3, fix="roller_x1"))
+    elif name == "small3d_color_blocks":
+        _compare(small3d(9, seed=5), OracleOptions(color_blocks="auto"), color_blocks=1)
+    elif name == "symmetry3d_color_blocks":
+        _compare(small3d(9, seed=5, fix="symmetry"), OracleOptions(color_blocks="auto"),
+                 color_blocks=1)
+    elif name == "symmetry3d_free_tree":
+        _compare(small3d(9, seed=5, fix="symmetry"), OracleOptions(tree_vertices="free"),
+                 tree_vertices=V.TREE_FREE)
 
 
 def _expect(status, mesh_fn, **kw):
@@ -92,8 +114,8 @@ def _expect(status, mesh_fn, **kw):
 
 
 def test_setup_rejects_invalid_input():
-    def partial():
-        m = small2d(5); m.fixed[7, 0] = 1; m.fixed[7, 1] = 0; return m
+    def bad_flag():
+        m = small2d(5); m.fixed[7, 0] = 2; return m
 
     def inverted():
         m = small2d(5); m.elems[3, [1, 2]] = m.elems[3, [2, 1]]; return m
@@ -119,7 +141,7 @@ def test_setup_rejects_invalid_input():
         m.fixed = np.concatenate([m.fixed, np.ones((6, 2), np.uint8)])
         return m
 
-    for fn in (partial, inverted, bad_nu, bad_E, bad_index, nan_coord, all_fixed, duplicates):
+    for fn in (bad_flag, inverted, bad_nu, bad_E, bad_index, nan_coord, all_fixed, duplicates):
         _expect(V.EINVAL, fn)
     _expect(V.EDEGENERATE, lambda: small2d(6, fix="none"))
     _expect(V.EINVAL, lambda: small2d(5), leaf_capacity=-1)
