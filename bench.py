@@ -482,6 +482,16 @@ def main():
                                             iterations=rc[-1][1]["iterations"],
                                             rel_res_true=rc[-1][1]["rel_res_true"])
         c27.free()
+        # Gauss-Seidel by colour blocks on level 1 (8 colours of up to 8 cells
+        # swept in sequence inside a block, instead of 27 colours of cells)
+        cbk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, color_blocks=1,
+                                 autotune=0 if args.no_autotune else 1)
+        time_solves(cbk, d_rhs, d_x, 1)
+        rk = time_solves(cbk, d_rhs, d_x, max(3, args.steps // 4))
+        variants["mixed_color_blocks"] = dict(ms_per_solve=float(np.mean([r[0] for r in rk])),
+                                              iterations=rk[-1][1]["iterations"],
+                                              rel_res_true=rk[-1][1]["rel_res_true"])
+        cbk.free()
         # block right-hand sides: 16 smooth random load cases solved as 16 PCG
         # recurrences that share every matrix read
         from workloads import load_fourier_tet
