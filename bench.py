@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
 # (FETCH_SIZE, WRITE_SIZE) of `bench.py --counters`, calibrated by a 256 MiB copy
 # (profiles/k_gs_cell_bwd_level1_65cubed_mixed.md). Valid only for the kernel
 # source it was measured on: reported as null once kernels.hpp has changed.
-TRAFFIC_RECORD = {"kernels_sha256": "43900f3a66a7dc60bc51e502d09ea84853036bc9ae422924f24385a67c8b8461",
-                  "bytes_per_launch": 48511440}
+TRAFFIC_RECORD = {"kernels_sha256": "79cbcb57094d2792d54c70b9af206c644b2b447c0c898e276d1a2df2dccb2069",
+                  "bytes_per_launch": 49692850}
 
 
 def traffic_per_launch():
