@@ -446,6 +446,7 @@ def main():
     dev_setup = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, setup_device=1,
                                    autotune=0 if args.no_autotune else 1)
     t_setup_dev = time.perf_counter() - t0
+    dev_phases = {n: round(ms, 2) for n, ms in dev_setup.setup_phases()}
     dev_info = dev_setup.solve_device(d_rhs, d_x, 1e-6)
     dev_setup.free()
     log(f"setup (mixed, device Galerkin + layout) {t_setup_dev:.2f}s, "
@@ -598,6 +599,7 @@ def main():
         "rel_res_true": info["rel_res_true"],
         "setup_s": t_setup,
         "setup_device_s": t_setup_dev,
+        "setup_device_phases_ms": dev_phases,
         "setup_device_iterations": dev_info["iterations"],
         "timed_region_s": t_total,
         "iteration_ms_profiled": it_ms,

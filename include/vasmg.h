@@ -114,9 +114,14 @@ typedef struct {
                                   (4/3) / lambda_max(D^-1 A), estimated per level by 30
                                   power iterations at setup)                            */
   int32_t setup_device;        /* 0 = hierarchy built on the host (default); 1 = the
-                                  Galerkin coarse operators A_{l+1} = P_l^T A_l P_l
-                                  (Section 3, equation (Ac)) are formed on the current
-                                  HIP device: same columns, values equal to rounding
+                                  fine assembly, the region tree, lattice keys and
+                                  prolongations (Section 3.1, 3.2: the host's
+                                  decisions, keys and weights bit for bit; trees deeper
+                                  than 21 levels in 3D or 32 in 2D are built on the
+                                  host) and the Galerkin coarse operators
+                                  A_{l+1} = P_l^T A_l P_l (Section 3, equation (Ac))
+                                  are formed on the current HIP device, the latter
+                                  with the same columns, values equal to rounding
                                   (another order of the FP64 sums), deterministic; the
                                   level layouts are then built from the resident
                                   operators, and the host copies of the FP64 level
@@ -319,6 +324,20 @@ vasmg_status vasmg_export_level(vasmg_handle h, int32_t level, int64_t* keys, in
 
 /* Root box [m, M]^dim of the region tree (Section 3.1.1 Step 1) and its depth. */
 vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_depth);
+
+/* Wall-clock milliseconds of the setup phases, in the order they ran (names
+ * such as "validate+assemble", "tree", "P0", "coarse regions+P" for the host
+ * tree and prolongations, "tree+P (device)" when setup_device = 1 built them
+ * on the device, "galerkin", "cells+colours", "coarsest factor", then
+ * "upload" or "upload+autotune" unless host_only). Writes up to
+ * max_out entries (name NUL-terminated, truncated to 31 characters) and the
+ * number of phases to *n_out. */
+typedef struct {
+  char name[32];
+  double ms;
+} vasmg_setup_phase;
+vasmg_status vasmg_setup_phases(vasmg_handle h, vasmg_setup_phase* out, int32_t max_out,
+                                int32_t* n_out);
 
 /* ---------------------------------------------------------------------------
  * Single-step device entry points (FP64 in/out, device pointers, canonical

@@ -8,6 +8,8 @@
   * csrc/server.hip (serving engine: host threads and streams over the C ABI);
   * csrc/galerkin.hip (device setup: fine assembly, Galerkin coarse operators,
     level layouts; no floating-point contraction);
+  * csrc/tree.hip (device setup: region tree, lattice keys, prolongations; no
+    floating-point contraction);
   * linked into paper_2505_09064_amd/libvasmg.so.
 
 Run: python -m paper_2505_09064_amd.build   (or __graft_entry__.build()).
@@ -49,15 +51,17 @@ def build(verbose: bool = True) -> str:
     hip_o = os.path.join(BUILD, "vasmg.o")
     server_o = os.path.join(BUILD, "server.o")
     galerkin_o = os.path.join(BUILD, "galerkin.o")
+    tree_o = os.path.join(BUILD, "tree.o")
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o])
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "server.hip"), "-o", server_o])
     # the device setup follows the host arithmetic operation by operation: no
     # floating-point contraction there
     _run([HIPCC, *HIP_FLAGS, "-ffp-contract=off", "-c", os.path.join(CSRC, "galerkin.hip"),
           "-o", galerkin_o])
+    _run([HIPCC, *HIP_FLAGS, "-ffp-contract=off", "-c", os.path.join(CSRC, "tree.hip"), "-o", tree_o])
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "vasmg.hip"), "-o", hip_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, hip_o, server_o, galerkin_o, setup_o,
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, hip_o, server_o, galerkin_o, tree_o, setup_o,
           "-lgomp", "-lpthread"])
     os.replace(tmp, LIB)
     return LIB

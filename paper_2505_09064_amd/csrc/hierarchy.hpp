@@ -102,6 +102,22 @@ using AssembleFn = void (*)(void* ctx, const MeshView& m, const std::vector<int3
 // Brings every level's values to the host (values produced elsewhere).
 using SettleFn = void (*)(void* ctx);
 
+// Region tree, level lattice keys and prolongations (Section 3.1.1 Steps 1-4,
+// Section 3.1.2, Section 3.2) built elsewhere with the host build's decisions,
+// keys and weights: P[l] prolongs level l + 1 to level l, keys[l] and
+// max_region_depth[l] describe level l >= 1 (keys[0] is empty).
+struct Transfers {
+  double m = 0.0, M = 0.0;   // root box
+  int max_depth = 0;
+  std::vector<ScalarCSR> P;
+  std::vector<std::vector<Key>> keys;
+  std::vector<int> max_region_depth;
+};
+// Returns false (out untouched) where it cannot build them: the host does.
+using TransfersFn = bool (*)(void* ctx, const MeshView& m, const std::vector<int32_t>& tree_vtx,
+                             const std::vector<int32_t>& free_vertices,
+                             const std::vector<int32_t>& pos_in_tree, int capacity, Transfers& out);
+
 struct SetupParams {
   int capacity;                // leaf capacity (> 0)
   bool tree_free_only;         // tree over free vertices only
@@ -110,7 +126,8 @@ struct SetupParams {
   GalerkinFn galerkin = nullptr;   // null: the host product (OpenMP)
   AssembleFn assemble = nullptr;   // null: the host assembly (OpenMP)
   SettleFn settle = nullptr;
-  void* galerkin_ctx = nullptr;    // context of the three callbacks
+  TransfersFn transfers = nullptr;   // null: the host tree and prolongations
+  void* galerkin_ctx = nullptr;    // context of the callbacks
 };
 
 // Vertex -> element lists (elements ascending per vertex).
@@ -134,6 +151,11 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
                      int64_t nfree, BlockCSR& A);
 // SettleFn: joins every download.
 void galerkin_device_settle(void* ctx);
+// TransfersFn on the device (tree.hip), on the context's stream: false for trees
+// deeper than packed 64-bit lattice keys allow (21 levels in 3D, 32 in 2D).
+bool transfers_device(void* ctx, const MeshView& m, const std::vector<int32_t>& tree_vtx,
+                      const std::vector<int32_t>& free_vertices, const std::vector<int32_t>& pos_in_tree,
+                      int capacity, Transfers& out);
 // Starts the background downloads of the products' values into the host
 // hierarchy (levels other than the coarsest, whose values arrive at once);
 // free_after: each level's device copy is released once its values are home.

@@ -752,143 +752,161 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     if (!prm.tree_free_only || vfree[v] >= 0) tree_vtx.push_back(static_cast<int32_t>(v));
   std::vector<int32_t> pos_in_tree(m.nv, -1);
   for (size_t i = 0; i < tree_vtx.size(); ++i) pos_in_tree[tree_vtx[i]] = static_cast<int32_t>(i);
-  TreeResult T;
-  build_tree(m.coords, tree_vtx, d, prm.capacity, T);
-  mark("tree");
-  H.box_m = T.m;
-  H.box_M = T.M;
-  H.max_depth = T.max_depth;
-  const double S = T.M - T.m;
-  auto keycoord = [&](uint64_t K) { return T.m + S * (static_cast<double>(K) * kKeyScale); };
+  Transfers X;
+  if (prm.transfers &&
+      prm.transfers(prm.galerkin_ctx, m, tree_vtx, H.free_vertices, pos_in_tree, prm.capacity, X)) {
+    H.box_m = X.m;
+    H.box_M = X.M;
+    H.max_depth = X.max_depth;
+    H.levels[0].P = std::move(X.P[0]);
+    for (size_t l = 1; l < X.keys.size(); ++l) {
+      if (H.levels.size() == H.levels.capacity()) fail(1, "internal error: too many levels");
+      H.levels.emplace_back();
+      Level& lv = H.levels.back();
+      lv.keys = std::move(X.keys[l]);
+      lv.n = static_cast<int64_t>(lv.keys.size());
+      lv.max_region_depth = X.max_region_depth[l];
+      if (l < X.P.size()) lv.P = std::move(X.P[l]);
+    }
+    mark("tree+P (device)");
+  } else {
+    TreeResult T;
+    build_tree(m.coords, tree_vtx, d, prm.capacity, T);
+    mark("tree");
+    H.box_m = T.m;
+    H.box_M = T.M;
+    H.max_depth = T.max_depth;
+    const double S = T.M - T.m;
+    auto keycoord = [&](uint64_t K) { return T.m + S * (static_cast<double>(K) * kKeyScale); };
 
-  // ---- Step 3: non-empty leaves = level-1 regions
-  std::vector<Region> R;
-  R.reserve(tree_vtx.size());
-  for (size_t i = 0; i < tree_vtx.size(); ++i) R.push_back({T.leaf_depth[i], T.leaf_lo[i]});
-  __gnu_parallel::sort(R.begin(), R.end(), region_less);
-  R.erase(std::unique(R.begin(), R.end(), region_eq), R.end());
+    // ---- Step 3: non-empty leaves = level-1 regions
+    std::vector<Region> R;
+    R.reserve(tree_vtx.size());
+    for (size_t i = 0; i < tree_vtx.size(); ++i) R.push_back({T.leaf_depth[i], T.leaf_lo[i]});
+    __gnu_parallel::sort(R.begin(), R.end(), region_less);
+    R.erase(std::unique(R.begin(), R.end(), region_eq), R.end());
 
-  // ---- Step 4 + Section 3.2: P_0 by multilinear interpolation in the leaf
-  std::vector<Key> cur_keys;
-  {
-    // 2^d slots per row, filled in parallel; zero weights are dropped after
-    std::vector<Triplet> tr(static_cast<size_t>(nfree) << d, Triplet{0, Key{0, 0, 0}, 0.0});
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < nfree; ++i) {
-      const int32_t v = H.free_vertices[i];
-      const int32_t t = pos_in_tree[v];
-      const int dep = T.leaf_depth[t];
-      const Key lo = T.leaf_lo[t];
-      const uint64_t s = side_of(dep);
-      double tup[3], tdn[3];
-      for (int a = 0; a < d; ++a) {
-        const double lc = keycoord(lo[a]);
-        const double hc = keycoord(lo[a] + s);
-        const double x = m.coords[int64_t(v) * d + a];
-        tup[a] = (x - lc) / (hc - lc);
-        tdn[a] = (hc - x) / (hc - lc);
-      }
-      for (int b = 0; b < (1 << d); ++b) {
-        double w = 1.0;
-        Key k = lo;
+    // ---- Step 4 + Section 3.2: P_0 by multilinear interpolation in the leaf
+    std::vector<Key> cur_keys;
+    {
+      // 2^d slots per row, filled in parallel; zero weights are dropped after
+      std::vector<Triplet> tr(static_cast<size_t>(nfree) << d, Triplet{0, Key{0, 0, 0}, 0.0});
+  #pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < nfree; ++i) {
+        const int32_t v = H.free_vertices[i];
+        const int32_t t = pos_in_tree[v];
+        const int dep = T.leaf_depth[t];
+        const Key lo = T.leaf_lo[t];
+        const uint64_t s = side_of(dep);
+        double tup[3], tdn[3];
         for (int a = 0; a < d; ++a) {
-          const bool up = (b >> a) & 1;
-          w = w * (up ? tup[a] : tdn[a]);
-          if (up) k[a] += s;
+          const double lc = keycoord(lo[a]);
+          const double hc = keycoord(lo[a] + s);
+          const double x = m.coords[int64_t(v) * d + a];
+          tup[a] = (x - lc) / (hc - lc);
+          tdn[a] = (hc - x) / (hc - lc);
         }
-        tr[(i << d) + b] = {i, k, w};
+        for (int b = 0; b < (1 << d); ++b) {
+          double w = 1.0;
+          Key k = lo;
+          for (int a = 0; a < d; ++a) {
+            const bool up = (b >> a) & 1;
+            w = w * (up ? tup[a] : tdn[a]);
+            if (up) k[a] += s;
+          }
+          tr[(i << d) + b] = {i, k, w};
+        }
       }
+      tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
+               tr.end());
+      cur_keys = triplets_to_csr(tr, nfree, H.levels[0].P);
     }
-    tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
-             tr.end());
-    cur_keys = triplets_to_csr(tr, nfree, H.levels[0].P);
-  }
-  mark("P0");
+    mark("P0");
 
-  // ---- Section 3.1.2: merge the deepest regions until only the root is left
-  while (true) {
-    if (H.levels.size() == H.levels.capacity()) fail(1, "internal error: too many levels");
-    H.levels.emplace_back();
-    Level& lv = H.levels.back();
-    lv.n = static_cast<int64_t>(cur_keys.size());
-    lv.keys = cur_keys;
-    int Dstar = 0;
-    for (const auto& r : R) Dstar = std::max(Dstar, r.depth);
-    lv.max_region_depth = Dstar;
-    if (R.size() == 1 && R[0].depth == 1) break;
-    const uint64_t ps = side_of(Dstar - 1);
-    std::vector<Region> Rn;
-    std::vector<std::pair<Key, Key>> corner_parent;   // corner of a merged region -> parent lo
-    for (const auto& r : R) {
-      if (r.depth != Dstar) {
-        Rn.push_back(r);
-        continue;
-      }
-      Region p{Dstar - 1, r.lo};
-      for (int a = 0; a < d; ++a) p.lo[a] = (r.lo[a] / ps) * ps;
-      Rn.push_back(p);
-      const uint64_t s = side_of(Dstar);
-      for (int b = 0; b < (1 << d); ++b) {
-        Key k = r.lo;
-        for (int a = 0; a < d; ++a)
-          if ((b >> a) & 1) k[a] += s;
-        corner_parent.emplace_back(k, p.lo);
-      }
-    }
-    __gnu_parallel::sort(Rn.begin(), Rn.end(), region_less);
-    Rn.erase(std::unique(Rn.begin(), Rn.end(), region_eq), Rn.end());
-    // a total order (corner, then parent): deterministic for any thread count; a
-    // corner shared by two merged parents lies on their common face, where both
-    // give the same interpolation corners and weights
-    __gnu_parallel::sort(corner_parent.begin(), corner_parent.end(),
-                         [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
-                           if (a.first != b.first) return key_less(a.first, b.first);
-                           return key_less(a.second, b.second);
-                         });
-    const std::vector<Key> next_all = region_corners(Rn, d);
-    // 2^d slots per row, filled in parallel; zero weights are dropped after
-    const int64_t ncur = static_cast<int64_t>(cur_keys.size());
-    std::vector<Triplet> tr(static_cast<size_t>(ncur) << d, Triplet{0, Key{0, 0, 0}, 0.0});
-    int not_corner = 0;
-#pragma omp parallel for schedule(static) reduction(|| : not_corner)
-    for (int64_t i = 0; i < ncur; ++i) {
-      const Key& kv = cur_keys[i];
-      if (std::binary_search(next_all.begin(), next_all.end(), kv, key_less)) {
-        tr[i << d] = {i, kv, 1.0};
-        continue;
-      }
-      auto it = std::lower_bound(corner_parent.begin(), corner_parent.end(), kv,
-                                 [](const std::pair<Key, Key>& a, const Key& k) {
-                                   return key_less(a.first, k);
-                                 });
-      if (it == corner_parent.end() || it->first != kv) {
-        not_corner = 1;
-        continue;
-      }
-      const Key plo = it->second;
-      double up[3];
-      for (int a = 0; a < d; ++a) {
-        const uint64_t rel = kv[a] - plo[a];
-        up[a] = rel == ps ? 1.0 : (rel == 0 ? 0.0 : 0.5);
-      }
-      for (int b = 0; b < (1 << d); ++b) {
-        double w = 1.0;
-        Key k = plo;
-        for (int a = 0; a < d; ++a) {
-          const bool hi = (b >> a) & 1;
-          w = w * (hi ? up[a] : 1.0 - up[a]);
-          if (hi) k[a] += ps;
+    // ---- Section 3.1.2: merge the deepest regions until only the root is left
+    while (true) {
+      if (H.levels.size() == H.levels.capacity()) fail(1, "internal error: too many levels");
+      H.levels.emplace_back();
+      Level& lv = H.levels.back();
+      lv.n = static_cast<int64_t>(cur_keys.size());
+      lv.keys = cur_keys;
+      int Dstar = 0;
+      for (const auto& r : R) Dstar = std::max(Dstar, r.depth);
+      lv.max_region_depth = Dstar;
+      if (R.size() == 1 && R[0].depth == 1) break;
+      const uint64_t ps = side_of(Dstar - 1);
+      std::vector<Region> Rn;
+      std::vector<std::pair<Key, Key>> corner_parent;   // corner of a merged region -> parent lo
+      for (const auto& r : R) {
+        if (r.depth != Dstar) {
+          Rn.push_back(r);
+          continue;
         }
-        tr[(i << d) + b] = {i, k, w};
+        Region p{Dstar - 1, r.lo};
+        for (int a = 0; a < d; ++a) p.lo[a] = (r.lo[a] / ps) * ps;
+        Rn.push_back(p);
+        const uint64_t s = side_of(Dstar);
+        for (int b = 0; b < (1 << d); ++b) {
+          Key k = r.lo;
+          for (int a = 0; a < d; ++a)
+            if ((b >> a) & 1) k[a] += s;
+          corner_parent.emplace_back(k, p.lo);
+        }
       }
+      __gnu_parallel::sort(Rn.begin(), Rn.end(), region_less);
+      Rn.erase(std::unique(Rn.begin(), Rn.end(), region_eq), Rn.end());
+      // a total order (corner, then parent): deterministic for any thread count; a
+      // corner shared by two merged parents lies on their common face, where both
+      // give the same interpolation corners and weights
+      __gnu_parallel::sort(corner_parent.begin(), corner_parent.end(),
+                           [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
+                             if (a.first != b.first) return key_less(a.first, b.first);
+                             return key_less(a.second, b.second);
+                           });
+      const std::vector<Key> next_all = region_corners(Rn, d);
+      // 2^d slots per row, filled in parallel; zero weights are dropped after
+      const int64_t ncur = static_cast<int64_t>(cur_keys.size());
+      std::vector<Triplet> tr(static_cast<size_t>(ncur) << d, Triplet{0, Key{0, 0, 0}, 0.0});
+      int not_corner = 0;
+  #pragma omp parallel for schedule(static) reduction(|| : not_corner)
+      for (int64_t i = 0; i < ncur; ++i) {
+        const Key& kv = cur_keys[i];
+        if (std::binary_search(next_all.begin(), next_all.end(), kv, key_less)) {
+          tr[i << d] = {i, kv, 1.0};
+          continue;
+        }
+        auto it = std::lower_bound(corner_parent.begin(), corner_parent.end(), kv,
+                                   [](const std::pair<Key, Key>& a, const Key& k) {
+                                     return key_less(a.first, k);
+                                   });
+        if (it == corner_parent.end() || it->first != kv) {
+          not_corner = 1;
+          continue;
+        }
+        const Key plo = it->second;
+        double up[3];
+        for (int a = 0; a < d; ++a) {
+          const uint64_t rel = kv[a] - plo[a];
+          up[a] = rel == ps ? 1.0 : (rel == 0 ? 0.0 : 0.5);
+        }
+        for (int b = 0; b < (1 << d); ++b) {
+          double w = 1.0;
+          Key k = plo;
+          for (int a = 0; a < d; ++a) {
+            const bool hi = (b >> a) & 1;
+            w = w * (hi ? up[a] : 1.0 - up[a]);
+            if (hi) k[a] += ps;
+          }
+          tr[(i << d) + b] = {i, k, w};
+        }
+      }
+      if (not_corner) fail(1, "internal error: interpolated vertex is not a corner of a merged region");
+      tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
+               tr.end());
+      cur_keys = triplets_to_csr(tr, static_cast<int64_t>(cur_keys.size()), lv.P);
+      R.swap(Rn);
     }
-    if (not_corner) fail(1, "internal error: interpolated vertex is not a corner of a merged region");
-    tr.erase(std::remove_if(tr.begin(), tr.end(), [](const Triplet& t) { return t.w == 0.0; }),
-             tr.end());
-    Level& prev = H.levels[H.levels.size() - 2];
-    (void)prev;
-    cur_keys = triplets_to_csr(tr, static_cast<int64_t>(cur_keys.size()), lv.P);
-    R.swap(Rn);
+    mark("coarse regions+P");
   }
 
   // constrained components of the coarse levels: a coarse component is
@@ -905,7 +923,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     for (uint8_t b : cm) any = any || b != 0;
     if (any) c.fixed.swap(cm);
   }
-  mark("coarse regions+P");
+  if (!H.levels[0].fixed.empty()) mark("coarse constraints");
   // ---- Galerkin operators, with optional truncation of the hierarchy
   size_t nlev = H.levels.size();
   for (size_t l = 0; l + 1 < nlev; ++l) {

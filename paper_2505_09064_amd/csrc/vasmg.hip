@@ -2187,6 +2187,7 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       prm.galerkin = galerkin_device;
       prm.assemble = assemble_device;
       prm.settle = galerkin_device_settle;
+      prm.transfers = transfers_device;
       prm.galerkin_ctx = gdev.get();
     }
     build_hierarchy(mv, prm, C->H);
@@ -2222,9 +2223,10 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
         galerkin_device_start_downloads(gdev.get(), true);
         C->gdev_bg = gdev.release();
       }
-      if (o.verbose)
-        std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", "upload+autotune",
-                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      C->H.phase_ms.emplace_back(o.autotune ? "upload+autotune" : "upload", ms);
+      if (o.verbose) std::fprintf(stderr, "[vasmg] setup %-18s %9.1f ms\n", C->H.phase_ms.back().first.c_str(), ms);
     }
     *out = C.release();
     return VASMG_OK;
@@ -2455,6 +2457,22 @@ vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_
   if (m) *m = h->H.box_m;
   if (M) *M = h->H.box_M;
   if (max_depth) *max_depth = h->H.max_depth;
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_setup_phases(vasmg_handle h, vasmg_setup_phase* out, int32_t max_out,
+                                int32_t* n_out) {
+  if (!h || max_out < 0 || (max_out > 0 && !out)) {
+    g_last_error = "null handle or output";
+    return VASMG_EINVAL;
+  }
+  const auto& ph = h->H.phase_ms;
+  for (int32_t i = 0; i < max_out && i < static_cast<int32_t>(ph.size()); ++i) {
+    std::memset(out[i].name, 0, sizeof(out[i].name));
+    std::strncpy(out[i].name, ph[i].first.c_str(), sizeof(out[i].name) - 1);
+    out[i].ms = ph[i].second;
+  }
+  if (n_out) *n_out = static_cast<int32_t>(ph.size());
   return VASMG_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
     "vasmg_upload", "vasmg_device_bytes", "vasmg_server_default_config", "vasmg_server_create",
     "vasmg_server_submit", "vasmg_server_wait", "vasmg_server_stats", "vasmg_server_destroy",
-    "vasmg_set_galerkin_window", "vasmg_solve_noalloc",
+    "vasmg_set_galerkin_window", "vasmg_solve_noalloc", "vasmg_setup_phases",
 ]
 
 
@@ -63,6 +63,10 @@ class Options(C.Structure):
 class PhaseStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("level", C.c_int32), ("launches", C.c_int32),
                 ("ms", C.c_double), ("bytes", C.c_double)]
+
+
+class SetupPhase(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("ms", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -129,6 +133,7 @@ def lib():
                                        C.POINTER(i64)]),
             "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "vasmg_tree_info": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
+            "vasmg_setup_phases": (i32, [vp, vp, i32, C.POINTER(i32)]),
             "vasmg_spmv_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_gs_sweep_device": (i32, [vp, i32, i32, i32, vp, vp, vp]),
             "vasmg_restrict_device": (i32, [vp, i32, i32, vp, vp, vp]),
@@ -359,6 +364,14 @@ class Solver:
         m, M, dep = C.c_double(), C.c_double(), C.c_int32()
         _check(lib().vasmg_tree_info(self._h, C.byref(m), C.byref(M), C.byref(dep)))
         return m.value, M.value, dep.value
+
+    def setup_phases(self):
+        """[(name, ms)] of the setup phases, in the order they ran."""
+        n = C.c_int32()
+        _check(lib().vasmg_setup_phases(self._h, None, 0, C.byref(n)))
+        buf = (SetupPhase * max(n.value, 1))()
+        _check(lib().vasmg_setup_phases(self._h, buf, n.value, C.byref(n)))
+        return [(buf[i].name.decode(), buf[i].ms) for i in range(n.value)]
 
     # -- single-step device entry points -----------------------------------
     def _level_shape(self, level):

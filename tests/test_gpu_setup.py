@@ -85,6 +85,60 @@ def test_device_galerkin_matches_oracle_and_host(name):
         assert (S != (o.S[l] > 0)).nnz == 0, "structural pattern differs from the oracle"
     # the device assembly follows the host's arithmetic: the same fine values bit for bit
     assert np.array_equal(Ld[0]["vals"], Lh[0]["vals"])
+    # the tree, keys and prolongations came from the device build
+    assert "tree+P (device)" in [n for n, _ in sd.setup_phases()]
+    assert "tree" in [n for n, _ in sh.setup_phases()]
+    assert sd.tree_info() == sh.tree_info()
+    sd.free()
+    sh.free()
+
+
+def _compare_transfers(sd, sh):
+    """Device- and host-built trees, keys and prolongations: identical."""
+    assert sd.tree_info() == sh.tree_info()
+    Ld, Lh = _levels(sd), _levels(sh)
+    assert len(Ld) == len(Lh)
+    for l, (ed, eh) in enumerate(zip(Ld, Lh)):
+        for key in ("keys", "p_rowptr", "p_cols", "p_vals", "cell", "color", "rowptr", "cols"):
+            if eh.get(key) is not None:
+                assert np.array_equal(ed[key], eh[key]), (l, key)
+
+
+@pytest.mark.parametrize("name", ["cube33_3d", "graded129_2d", "cube33_3d_free_tree"])
+def test_device_tree_matches_host_at_size(name):
+    """The device tree build (level-synchronous rounds, packed lattice keys)
+    at sizes with many rounds, large sorts and deep graded trees: the same root
+    box, depth, level keys and prolongations (structure and weights bit for bit)
+    as the host build, whose own output is pinned to the oracle's."""
+    kw = {"tree_vertices": V.TREE_FREE} if name.endswith("free_tree") else {}
+    m = small2d(129, seed=None, graded=True, nu=0.49) if name.startswith("graded") else \
+        small3d(33, seed=1, fix="x0")
+    sd = V.Solver.from_mesh(m, setup_device=1, host_only=1, **kw)
+    sh = V.Solver.from_mesh(m, host_only=1, **kw)
+    assert "tree+P (device)" in [n for n, _ in sd.setup_phases()]
+    _compare_transfers(sd, sh)
+    sd.free()
+    sh.free()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_device_tree_falls_back_to_host_when_too_deep(dim):
+    """A leaf's capacity of fixed vertices within 2^-44 (2D) / 2^-30 (3D) of
+    the box of another vertex need a tree deeper than packed keys allow (32 / 21
+    levels): the device build declines, the host builds it, and the result
+    equals a host setup's."""
+    m = small2d(7, seed=2) if dim == 2 else small3d(5, seed=2)
+    eps = 2.0 ** -44 if dim == 2 else 2.0 ** -30
+    cap = 4 if dim == 2 else 8
+    extra = m.coords[12:13] + eps * np.arange(1, cap + 1)[:, None]
+    m.coords = np.concatenate([m.coords, extra])
+    m.fixed = np.concatenate([m.fixed, np.ones((cap, dim), np.uint8)])
+    sd = V.Solver.from_mesh(m, setup_device=1, host_only=1)
+    sh = V.Solver.from_mesh(m, host_only=1)
+    names = [n for n, _ in sd.setup_phases()]
+    assert "tree" in names and "tree+P (device)" not in names
+    assert sd.tree_info()[2] > (32 if dim == 2 else 21)
+    _compare_transfers(sd, sh)
     sd.free()
     sh.free()
 
