@@ -252,6 +252,9 @@ def bench_cfg4(args, V, torch):
     print(json.dumps(line), flush=True)
 
 
+PACK_MAX_DOFS = 20000      # serving: requests this small are packed in the packed phase
+
+
 def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
     """The serving stream: requests i = 0..N-1 (2D or 3D jittered meshes, DOFs
     log-uniform in [1e3, 1e6], 1:100 materials), each a new mesh, so latency
@@ -260,7 +263,10 @@ def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
     time (one slot, one setup worker); then all N arrive as a Poisson stream at
     0.7x that rate into a server with 4 slots and 4 setup workers. Latency =
     done - arrival. The first 8 results must be bitwise identical alone and in
-    the mix. Returns a dict of the figures."""
+    the mix. With saturated: all N submitted at once, first unpacked, then with
+    requests of at most PACK_MAX_DOFS packed (vasmg_pack: one solve per pack);
+    the packed results are compared with the unpacked ones. Returns a dict of
+    the figures."""
     from workloads import request_mesh
     N = max(8, N)
     t0 = time.perf_counter()
@@ -314,6 +320,38 @@ def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
         srv2.close()
         lat2 = np.array([g[1]["t_done_ms"] - g[1]["t_submit_ms"] for g in got2])
         log(f"saturated: {N / t_sat:.2f} requests/s")
+        # the same, small requests packed (one upload and one solve per pack)
+        srv3 = V.Server(slots=4, setup_workers=4, pack_max_dofs=PACK_MAX_DOFS, pack_max_parts=16,
+                        **opts)
+        t1 = time.perf_counter()
+        ids3 = [srv3.submit(m, m.rhs[0], 1e-6) for m in meshes]
+        got3 = [srv3.wait(r) for r in ids3]
+        t_pack = time.perf_counter() - t1
+        srv3.close()
+        lat3 = np.array([g[1]["t_done_ms"] - g[1]["t_submit_ms"] for g in got3])
+        small = [i for i in range(N) if dofs[i] <= PACK_MAX_DOFS]
+        packed = [i for i in small if got3[i][1]["pack_size"] > 1]
+        # device time of a small request's solve: alone, and its share of its pack
+        solo_ms = [got2[i][1]["info"]["t_solve_ms"] for i in small]
+        share_ms = [got3[i][1]["info"]["t_solve_ms"] / got3[i][1]["pack_size"] for i in small]
+        diff = max((np.linalg.norm(got3[i][0] - got2[i][0]) / max(np.linalg.norm(got2[i][0]), 1e-300)
+                    for i in range(N) if got3[i][0] is not None and got2[i][0] is not None),
+                   default=0.0)
+        pack_stats = {
+            "packed_saturated_requests_per_s": N / t_pack,
+            "packed_saturated_p50_ms": float(np.percentile(lat3, 50)),
+            "packed_saturated_p99_ms": float(np.percentile(lat3, 99)),
+            "pack_max_dofs": PACK_MAX_DOFS, "small_requests": len(small),
+            "small_requests_packed": len(packed),
+            "mean_pack_size": float(np.mean([got3[i][1]["pack_size"] for i in packed])) if packed else 1.0,
+            "small_request_solve_ms_alone": float(np.mean(solo_ms)) if small else None,
+            "small_request_solve_ms_packed_share": float(np.mean(share_ms)) if small else None,
+            "packed_all_ok": all(g[1]["status"] == V.OK for g in got3),
+            "packed_vs_unpacked_max_rel_diff": float(diff),
+        }
+        log(f"packed saturated: {N / t_pack:.2f} requests/s, {len(packed)}/{len(small)} small "
+            f"requests packed, solve {pack_stats['small_request_solve_ms_alone']:.2f} ms alone -> "
+            f"{pack_stats['small_request_solve_ms_packed_share']:.2f} ms share")
     res = [g[1] for g in got]
     ok = [r["status"] == V.OK for r in res] + [g[1]["status"] == V.OK for g in (got2 or [])]
     lat = np.array([r["t_done_ms"] - r["t_submit_ms"] for r in res])
@@ -344,6 +382,7 @@ def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
         out.update({"saturated_requests_per_s": N / t_sat,
                     "saturated_p50_ms": float(np.percentile(lat2, 50)),
                     "saturated_p99_ms": float(np.percentile(lat2, 99))})
+        out.update(pack_stats)
     return out
 
 

@@ -152,6 +152,9 @@ typedef struct {
   double t_precond_ms;         /* profile=1: accumulated V-cycle time                     */
   double t_vector_ms;          /* profile=1: accumulated PCG vector-kernel time           */
   double bytes_model;          /* algorithmic HBM bytes of the solve (byte model)         */
+  int32_t status;              /* this solve's (column's, part's) status: VASMG_OK,
+                                  VASMG_ENOTCONV or VASMG_EBREAKDOWN                     */
+  int32_t reserved;
 } vasmg_solve_info;
 
 /* Fill *out with the defaults for dimension dim (2 or 3). */
@@ -209,6 +212,49 @@ vasmg_status vasmg_upload(vasmg_handle h, void* stream);
  * bound of what vasmg_upload will allocate (admission control). */
 vasmg_status vasmg_device_bytes(vasmg_handle h, int64_t* bytes);
 
+/* ---------------------------------------------------------------------------
+ * Packed solves: several small independent problems (one load case each) run
+ * as one. The packed handle's hierarchy is the block-diagonal union of the
+ * parts' (level l holds every part's level l; a part with fewer levels repeats
+ * its coarsest level below its depth, joined by identity prolongations, so its
+ * V-cycle still ends in its exact coarse solve); its coarsest factor is the
+ * parts' factors on the diagonal. One SpMV and one V-cycle per iteration serve
+ * every part, so a part pays the launches once for the whole pack; each part
+ * keeps its own PCG recurrence (Section 2.2, Algorithm 2: its own dot products,
+ * alpha, beta and stopping test ||r|| / ||F|| < rtol) and stops when it
+ * converges, as it would alone (results equal to rounding: the dot products
+ * sum in another order). Only vasmg_solve_packed(_device),
+ * vasmg_apply_precond_device (the union's V-cycle), the introspection calls and
+ * vasmg_free apply to a packed handle (EINVAL from the other solve calls).
+ * ------------------------------------------------------------------------- */
+
+/* Packs the hierarchies of n_parts handles (host-only or uploaded; each set up
+ * with the V-ASMG Gauss-Seidel V-cycle, block_rhs = 0, color_blocks = 0, and the
+ * same dim, precision and n_pre / n_post; EINVAL otherwise, or when their
+ * coarsest levels hold more than 4096 DOFs together) into a new host-only
+ * handle; upload it with vasmg_upload. The parts stay owned by the caller and
+ * unchanged; max_iters is the largest of theirs. Packed vectors are the parts'
+ * user vectors one after the other: part i's [n_vertices_i][dim] block starts
+ * at vertex vertex_offsets[i] (vasmg_packed_info). */
+vasmg_status vasmg_pack(const vasmg_handle* parts, int32_t n_parts, vasmg_handle* out);
+
+/* Number of parts (0: not a packed handle) and, if vertex_offsets is non-NULL,
+ * the n_parts + 1 vertex offsets of the parts in packed vectors. */
+vasmg_status vasmg_packed_info(vasmg_handle h, int32_t* n_parts, int64_t* vertex_offsets);
+
+/* Solves every part from x0 = 0 with rtol. d_rhs, d_x: packed vectors (device,
+ * [sum n_vertices_i][dim], FP64); info: [n_parts] host array, one report per
+ * part (iterations, converged, rel_res, rel_res_true; t_solve_ms is the whole
+ * packed solve's device time). Returns EBREAKDOWN if some part broke down, else
+ * ENOTCONV if some part did not reach rtol within max_iters, else OK; the other
+ * parts' results are valid either way. */
+vasmg_status vasmg_solve_packed_device(vasmg_handle h, const double* d_rhs, double* d_x, double rtol,
+                                       void* stream, vasmg_solve_info* info);
+
+/* vasmg_solve_packed_device with host vectors (staged through device buffers). */
+vasmg_status vasmg_solve_packed(vasmg_handle h, const double* rhs, double* x, double rtol,
+                                vasmg_solve_info* info);
+
 /* Release every host and device resource of h. NULL-safe. */
 void vasmg_free(vasmg_handle h);
 
@@ -239,6 +285,21 @@ typedef struct {
                                   0 = 80% of the device's free memory at creation       */
   vasmg_options options;       /* solver options of every request (leaf_capacity 0 =
                                   each request's dimension default)                      */
+  int32_t pack_max_dofs;       /* 0 (default) = every request solved on its own; > 0 =
+                                  a request of at most this many DOFs admitted while
+                                  other such requests (same dimension and rtol) wait
+                                  set up is packed with them (vasmg_pack, up to
+                                  pack_max_parts, their coarsest levels within 256
+                                  DOFs together): one upload and one solve for the
+                                  pack, each request with its own PCG recurrence.
+                                  Packed results equal the request's alone result to
+                                  rounding, not bit for bit. Needs the V-ASMG
+                                  Gauss-Seidel V-cycle without colour blocks.           */
+  int32_t pack_max_parts;      /* largest pack, 2..256 (default 16)                       */
+  int32_t pack_wait_ms;        /* batching window, 0..10000 (default 0): a slot holding a
+                                  packable request waits up to this long for more while
+                                  setups are still running                               */
+  int32_t reserved;
 } vasmg_server_config;
 
 typedef struct {
@@ -246,6 +307,9 @@ typedef struct {
   int32_t status;              /* of the request's setup, upload or solve; ENOMEM if its
                                   device bytes exceed the whole budget                  */
   int32_t slot;                /* device slot that ran it (-1: none)                      */
+  int32_t pack_size;           /* requests solved together with it in one packed solve,
+                                  itself included (1: alone, 0: never admitted)          */
+  int32_t reserved;
   int64_t device_bytes;        /* device bytes it held while resident                     */
   double t_submit_ms, t_setup_start_ms, t_setup_end_ms, t_admit_ms, t_done_ms;
                                /* server clock (ms since vasmg_server_create)             */

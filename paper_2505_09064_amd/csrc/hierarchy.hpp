@@ -221,6 +221,13 @@ void layout_fill(const DevOperator& A, const LayoutArgs& a, void* stream);
 // Builds the whole hierarchy on the host. Throws vasmg::Error.
 void build_hierarchy(const MeshView& mesh, const SetupParams& prm, Hierarchy& out);
 
+// Block-diagonal union of finished hierarchies of the same dimension (no colour
+// blocks): level l holds level l of every part, a shallower part padded with
+// copies of its coarsest level (identity prolongations, point Gauss-Seidel);
+// the coarsest factor is the parts' factors on the diagonal; the union's mesh
+// vertices are the parts' one after the other. Throws vasmg::Error.
+void pack_hierarchies(const std::vector<const Hierarchy*>& parts, Hierarchy& out);
+
 // Damped vertex-block Jacobi smoother data: inverse diagonal blocks [n][d][d]
 // (canonical order) and the largest eigenvalue of D^{-1} A by power iteration.
 void block_diag_inverse(const BlockCSR& A, const std::vector<uint8_t>& fixed,

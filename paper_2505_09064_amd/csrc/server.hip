@@ -36,6 +36,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Packed coarsest levels stay within the size the coarse solve applies as one
+// explicit inverse.
+constexpr int64_t kPackCoarseMax = 256;
+
 struct Request {
   int64_t id = 0;
   int32_t dim = 0;
@@ -46,6 +50,7 @@ struct Request {
   double rtol = 1e-6;
   vasmg_handle h = nullptr;
   int64_t bytes = 0;
+  int64_t dofs = 0, coarse_dofs = 0;   // fine and coarsest-level DOFs of the hierarchy
   bool done = false;
   vasmg_request_result res{};
 };
@@ -80,10 +85,10 @@ struct vasmg_server {
     std::snprintf(r->res.message, sizeof(r->res.message), "%s: %s", what, why ? why : "");
   }
 
-  // caller holds mu
-  void finish(const ReqPtr& r, int status) {
+  // caller holds mu; t_done < 0: now
+  void finish(const ReqPtr& r, int status, double t_done = -1.0) {
     r->res.status = status;
-    r->res.t_done_ms = now_ms();
+    r->res.t_done_ms = t_done < 0.0 ? now_ms() : t_done;
     r->done = true;
     ++completed;
     cv.notify_all();
@@ -119,6 +124,15 @@ struct vasmg_server {
       if (st != VASMG_OK) note(r, "setup", vasmg_last_error());
       int64_t bytes = 0;
       if (st == VASMG_OK) st = vasmg_device_bytes(h, &bytes);
+      if (st == VASMG_OK) {
+        int32_t nl = 0, dim = 0;
+        int64_t nd = 0, nvc = 0, nb = 0, pn = 0;
+        int32_t nc = 0;
+        st = vasmg_hierarchy_info(h, &nl, &nd, &dim);
+        if (st == VASMG_OK) st = vasmg_level_info(h, nl - 1, &nvc, &nb, &nc, &pn);
+        r->dofs = nd;
+        r->coarse_dofs = nvc * dim;
+      }
       r->res.t_setup_end_ms = now_ms();
       // the mesh copies are no longer needed
       std::vector<double>().swap(r->coords);
@@ -142,12 +156,156 @@ struct vasmg_server {
     }
   }
 
+  bool packable(const Request& q) const {
+    const vasmg_options& o = cfg.options;
+    return cfg.pack_max_dofs > 0 && cfg.pack_max_parts > 1 && q.dofs <= cfg.pack_max_dofs &&
+           o.preconditioner == VASMG_PRECOND_VASMG && o.cycle == VASMG_CYCLE_V &&
+           o.smoother == VASMG_SMOOTHER_GS && o.color_blocks == 0;
+  }
+
+  // One request alone on the slot: upload, solve, result back. Returns its status;
+  // r->bytes ends as the device bytes it held.
+  int run_single(hipStream_t st, bool have_stream, const ReqPtr& r) {
+    int status = have_stream ? vasmg_upload(r->h, st) : VASMG_EDEVICE;
+    if (status != VASMG_OK) note(r, "upload", have_stream ? vasmg_last_error() : "no stream");
+    double *d_rhs = nullptr, *d_x = nullptr;
+    const size_t vbytes = sizeof(double) * static_cast<size_t>(r->nv) * r->dim;
+    if (status == VASMG_OK) {
+      int64_t actual = 0;
+      vasmg_device_bytes(r->h, &actual);
+      actual += 2 * static_cast<int64_t>(vbytes);
+      std::lock_guard<std::mutex> g(mu);
+      in_use += actual - r->bytes;       // the estimate is an upper bound
+      r->bytes = actual;
+      r->res.device_bytes = actual;
+      peak = std::max(peak, in_use);
+    }
+    if (status == VASMG_OK) {
+      hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_rhs), vbytes, st);
+      if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_x), vbytes, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(d_rhs, r->rhs.data(), vbytes, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) {
+        status = VASMG_ENOMEM;
+        note(r, "vectors", hipGetErrorString(e));
+      }
+    }
+    if (status == VASMG_OK) {
+      status = vasmg_solve_device(r->h, d_rhs, nullptr, d_x, 1, r->rtol, st, &r->res.info);
+      if (status != VASMG_OK) note(r, "solve", vasmg_last_error());
+      r->x.resize(static_cast<size_t>(r->nv) * r->dim);
+      hipError_t e = hipMemcpyAsync(r->x.data(), d_x, vbytes, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        status = VASMG_EDEVICE;
+        note(r, "result copy", hipGetErrorString(e));
+      }
+    }
+    if (d_rhs) (void)hipFreeAsync(d_rhs, st);
+    if (d_x) (void)hipFreeAsync(d_x, st);
+    vasmg_free(r->h);                    // stream-ordered frees on st
+    r->h = nullptr;
+    if (have_stream) (void)hipStreamSynchronize(st);   // memory back before it is counted free
+    return status;
+  }
+
+  // Small requests packed into one handle (vasmg_pack): one upload, one solve
+  // with a PCG recurrence per request, results split back. statuses[i] per request.
+  void run_pack(hipStream_t st, bool have_stream, const std::vector<ReqPtr>& batch,
+                std::vector<int>& statuses, int64_t& held) {
+    const int n = static_cast<int>(batch.size());
+    statuses.assign(n, VASMG_OK);
+    std::vector<vasmg_handle> hs;
+    int64_t nv = 0;
+    for (const ReqPtr& r : batch) {
+      hs.push_back(r->h);
+      nv += r->nv;
+    }
+    const int dim = batch[0]->dim;
+    vasmg_handle ph = nullptr;
+    int status = have_stream ? vasmg_pack(hs.data(), n, &ph) : VASMG_EDEVICE;
+    const char* what = "pack";
+    if (status == VASMG_OK) {
+      status = vasmg_upload(ph, st);
+      what = "upload";
+    }
+    std::string why = status == VASMG_OK ? "" : (have_stream ? vasmg_last_error() : "no stream");
+    for (const ReqPtr& r : batch) {   // the host hierarchies are in the packed handle now
+      vasmg_free(r->h);
+      r->h = nullptr;
+    }
+    double *d_rhs = nullptr, *d_x = nullptr;
+    const size_t vbytes = sizeof(double) * static_cast<size_t>(nv) * dim;
+    if (status == VASMG_OK) {
+      int64_t actual = 0;
+      vasmg_device_bytes(ph, &actual);
+      actual += 2 * static_cast<int64_t>(vbytes);
+      std::lock_guard<std::mutex> g(mu);
+      in_use += actual - held;
+      held = actual;
+      peak = std::max(peak, in_use);
+    }
+    std::vector<double> stage;
+    if (status == VASMG_OK) {
+      stage.resize(static_cast<size_t>(nv) * dim);
+      size_t o = 0;
+      for (const ReqPtr& r : batch) {
+        std::copy(r->rhs.begin(), r->rhs.end(), stage.begin() + o);
+        o += r->rhs.size();
+      }
+      hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_rhs), vbytes, st);
+      if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_x), vbytes, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(d_rhs, stage.data(), vbytes, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) {
+        status = VASMG_ENOMEM;
+        what = "vectors";
+        why = hipGetErrorString(e);
+      }
+    }
+    std::vector<vasmg_solve_info> infos(n);
+    if (status == VASMG_OK) {
+      const int s = vasmg_solve_packed_device(ph, d_rhs, d_x, batch[0]->rtol, st, infos.data());
+      hipError_t e = hipMemcpyAsync(stage.data(), d_x, vbytes, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        status = VASMG_EDEVICE;
+        what = "result copy";
+        why = hipGetErrorString(e);
+      } else if (s != VASMG_OK && s != VASMG_ENOTCONV && s != VASMG_EBREAKDOWN) {
+        status = s;
+        what = "solve";
+        why = vasmg_last_error();
+      }
+    }
+    size_t o = 0;
+    for (int i = 0; i < n; ++i) {
+      const ReqPtr& r = batch[i];
+      if (status != VASMG_OK) {
+        statuses[i] = status;
+        note(r, what, why.c_str());
+        continue;
+      }
+      r->res.info = infos[i];
+      r->x.assign(stage.begin() + o, stage.begin() + o + r->rhs.size());
+      o += r->rhs.size();
+      statuses[i] = infos[i].status;
+      if (statuses[i] != VASMG_OK)
+        note(r, "solve", statuses[i] == VASMG_ENOTCONV ? "PCG did not reach rtol within max_iters"
+                                                      : "PCG breakdown");
+      r->res.device_bytes = held;
+    }
+    if (d_rhs) (void)hipFreeAsync(d_rhs, st);
+    if (d_x) (void)hipFreeAsync(d_x, st);
+    vasmg_free(ph);
+    if (have_stream) (void)hipStreamSynchronize(st);
+  }
+
   void slot_loop(int slot) {
     (void)hipSetDevice(device);
     hipStream_t st = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
     for (;;) {
-      ReqPtr r;
+      std::vector<ReqPtr> batch;
+      int64_t held = 0;
       {
         std::unique_lock<std::mutex> g(mu);
         cv.wait(g, [&] {
@@ -155,58 +313,62 @@ struct vasmg_server {
           return stop && admit_q.empty() && setup_q.empty() && setups_active == 0;
         });
         if (admit_q.empty()) break;        // stopping and nothing left to run
-        r = admit_q.front();
+        const ReqPtr r0 = admit_q.front();
         admit_q.pop_front();
-        in_use += r->bytes;
-        peak = std::max(peak, in_use);
-        ++running;
-      }
-      r->res.t_admit_ms = now_ms();
-      r->res.slot = slot;
-      int status = have_stream ? vasmg_upload(r->h, st) : VASMG_EDEVICE;
-      if (status != VASMG_OK) note(r, "upload", have_stream ? vasmg_last_error() : "no stream");
-      double *d_rhs = nullptr, *d_x = nullptr;
-      const size_t vbytes = sizeof(double) * static_cast<size_t>(r->nv) * r->dim;
-      if (status == VASMG_OK) {
-        int64_t actual = 0;
-        vasmg_device_bytes(r->h, &actual);
-        actual += 2 * static_cast<int64_t>(vbytes);
-        std::lock_guard<std::mutex> g(mu);
-        in_use += actual - r->bytes;       // the estimate is an upper bound
-        r->bytes = actual;
-        r->res.device_bytes = actual;
-        peak = std::max(peak, in_use);
-      }
-      if (status == VASMG_OK) {
-        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_rhs), vbytes, st);
-        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&d_x), vbytes, st);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(d_rhs, r->rhs.data(), vbytes, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) {
-          status = VASMG_ENOMEM;
-          note(r, "vectors", hipGetErrorString(e));
+        batch.push_back(r0);
+        held = r0->bytes;
+        if (packable(*r0)) {
+          // small requests set up and waiting behind it join it: same dimension
+          // and tolerance, their coarsest levels together within kPackCoarseMax
+          int64_t coarse = r0->coarse_dofs;
+          auto gather = [&] {
+            for (auto it = admit_q.begin();
+                 it != admit_q.end() && static_cast<int>(batch.size()) < cfg.pack_max_parts;) {
+              const ReqPtr& q = *it;
+              if (packable(*q) && q->dim == r0->dim && q->rtol == r0->rtol &&
+                  coarse + q->coarse_dofs <= kPackCoarseMax && in_use + held + q->bytes <= budget) {
+                coarse += q->coarse_dofs;
+                held += q->bytes;
+                batch.push_back(q);
+                it = admit_q.erase(it);
+              } else {
+                ++it;
+              }
+            }
+          };
+          gather();
+          // batching window: while setups are still running, wait up to
+          // pack_wait_ms for more small requests (each finished setup wakes us)
+          const auto deadline = Clock::now() + std::chrono::milliseconds(cfg.pack_wait_ms);
+          while (cfg.pack_wait_ms > 0 && static_cast<int>(batch.size()) < cfg.pack_max_parts &&
+                 (setups_active > 0 || !setup_q.empty())) {
+            const bool timed_out = cv.wait_until(g, deadline) == std::cv_status::timeout;
+            gather();
+            if (timed_out) break;
+          }
         }
+        in_use += held;
+        peak = std::max(peak, in_use);
+        running += static_cast<int>(batch.size());
       }
-      if (status == VASMG_OK) {
-        status = vasmg_solve_device(r->h, d_rhs, nullptr, d_x, 1, r->rtol, st, &r->res.info);
-        if (status != VASMG_OK) note(r, "solve", vasmg_last_error());
-        r->x.resize(static_cast<size_t>(r->nv) * r->dim);
-        hipError_t e = hipMemcpyAsync(r->x.data(), d_x, vbytes, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-          status = VASMG_EDEVICE;
-          note(r, "result copy", hipGetErrorString(e));
-        }
+      const double t_admit = now_ms();
+      for (const ReqPtr& r : batch) {
+        r->res.t_admit_ms = t_admit;
+        r->res.slot = slot;
+        r->res.pack_size = static_cast<int32_t>(batch.size());
       }
-      if (d_rhs) (void)hipFreeAsync(d_rhs, st);
-      if (d_x) (void)hipFreeAsync(d_x, st);
-      vasmg_free(r->h);                    // stream-ordered frees on st
-      r->h = nullptr;
-      if (have_stream) (void)hipStreamSynchronize(st);   // memory back before it is counted free
+      std::vector<int> statuses;
+      if (batch.size() == 1) {
+        statuses.push_back(run_single(st, have_stream, batch[0]));
+        held = batch[0]->bytes;
+      } else {
+        run_pack(st, have_stream, batch, statuses, held);
+      }
       std::lock_guard<std::mutex> g(mu);
-      in_use -= r->bytes;
-      --running;
-      finish(r, status);
+      in_use -= held;
+      running -= static_cast<int>(batch.size());
+      const double t_done = now_ms();   // a pack's requests complete together
+      for (size_t i = 0; i < batch.size(); ++i) finish(batch[i], statuses[i], t_done);
     }
     if (have_stream) (void)hipStreamDestroy(st);
   }
@@ -220,6 +382,9 @@ vasmg_status vasmg_server_default_config(vasmg_server_config* cfg) {
   cfg->slots = 4;
   cfg->setup_workers = 4;
   cfg->hbm_budget_bytes = 0;
+  cfg->pack_max_dofs = 0;
+  cfg->pack_max_parts = 16;
+  cfg->pack_wait_ms = 0;
   const vasmg_status st = vasmg_default_options(3, &cfg->options);
   cfg->options.leaf_capacity = 0;          // each request: its dimension's default
   return st;
@@ -229,7 +394,8 @@ vasmg_status vasmg_server_create(const vasmg_server_config* cfg, vasmg_server_ha
   if (!cfg || !out) return VASMG_EINVAL;
   *out = nullptr;
   if (cfg->slots < 1 || cfg->slots > 64 || cfg->setup_workers < 1 || cfg->setup_workers > 64 ||
-      cfg->hbm_budget_bytes < 0)
+      cfg->hbm_budget_bytes < 0 || cfg->pack_max_dofs < 0 || cfg->pack_max_parts < 0 ||
+      cfg->pack_max_parts > 256 || cfg->pack_wait_ms < 0 || cfg->pack_wait_ms > 10000)
     return VASMG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return VASMG_EDEVICE;

@@ -683,7 +683,160 @@ void dense_cholesky(const BlockCSR& A, const std::vector<uint8_t>& fixed, std::v
   L.swap(M);
 }
 
+// Point Gauss-Seidel order of a level used as a smoothing level although its
+// own hierarchy ends there (a packed part shallower than the others): single
+// vertices (a single cell when it has at most 2^d vertices and lies below the
+// fine level), greedy first-fit colours in canonical order.
+void padded_gs_order(const Level& src, int d, bool fine, Level& out_part) {
+  const int64_t n = src.n;
+  out_part.cell.resize(n);
+  out_part.block.resize(n);
+  if (!fine && n <= (int64_t(1) << d)) {
+    std::fill(out_part.cell.begin(), out_part.cell.end(), 0);
+    out_part.ncells = 1;
+    out_part.block_color.assign(1, 0);
+    out_part.color.assign(n, 0);
+    out_part.ncolors = 1;
+  } else {
+    std::iota(out_part.cell.begin(), out_part.cell.end(), 0);
+    out_part.ncells = n;
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<int64_t> ptr(src.A.rowptr.begin(), src.A.rowptr.end());
+    out_part.ncolors = greedy_color_in_order(ptr, src.A.col, order, out_part.block_color);
+    out_part.color = out_part.block_color;
+  }
+  out_part.block = out_part.cell;
+  out_part.nblocks = out_part.ncells;
+}
+
 }  // namespace
+
+// --------------------------------------------------------------------------
+// Packing: the block-diagonal union of several hierarchies (independent
+// problems solved together). Level l of the union holds level l of every part;
+// a part with fewer levels contributes copies of its coarsest level below its
+// own depth, joined by identity prolongations and swept as a smoothing level:
+// the coarse solve under it is exact, so its V-cycle still returns the coarse
+// solution (to rounding). Cells, colour blocks and vertices keep their order
+// inside each part (a part's cells before the next part's within a colour);
+// the union's "mesh" is the parts' meshes one after the other.
+// --------------------------------------------------------------------------
+void pack_hierarchies(const std::vector<const Hierarchy*>& parts, Hierarchy& U) {
+  if (parts.empty()) fail(1, "nothing to pack");
+  const int d = parts[0]->d;
+  int Lmax = 0;
+  for (const Hierarchy* p : parts) {
+    if (p->d != d) fail(1, "packed problems must have the same dimension");
+    for (const Level& lv : p->levels)
+      if (lv.block_steps > 2) fail(1, "packed problems must not use colour blocks");
+    Lmax = std::max(Lmax, static_cast<int>(p->levels.size()) - 1);
+  }
+  const int np = static_cast<int>(parts.size());
+  U = Hierarchy();
+  U.d = d;
+  U.capacity = parts[0]->capacity;
+  int64_t vo = 0;
+  for (const Hierarchy* p : parts) {
+    for (int32_t v : p->free_vertices) U.free_vertices.push_back(static_cast<int32_t>(v + vo));
+    vo += p->n_mesh_vertices;
+    U.max_depth = std::max(U.max_depth, p->max_depth);
+  }
+  if (vo > INT32_MAX) fail(1, "packed problems exceed 2^31 vertices");
+  U.n_mesh_vertices = vo;
+  auto src_of = [&](int i, int l) {
+    return std::min(l, static_cast<int>(parts[i]->levels.size()) - 1);
+  };
+  U.levels.resize(Lmax + 1);
+  for (int l = 0; l <= Lmax; ++l) {
+    Level& u = U.levels[l];
+    u.A.d = d;
+    u.A.rowptr.assign(1, 0);
+    bool any_fixed = false;
+    for (int i = 0; i < np; ++i) any_fixed = any_fixed || !parts[i]->levels[src_of(i, l)].fixed.empty();
+    int64_t off = 0, cell_off = 0;
+    const bool coarsest = l == Lmax;
+    for (int i = 0; i < np; ++i) {
+      const int si = src_of(i, l);
+      const Level& s = parts[i]->levels[si];
+      const bool padded = si < l || (si == static_cast<int>(parts[i]->levels.size()) - 1 && !coarsest);
+      // operator: block diagonal
+      const int64_t base = u.A.col.size();
+      for (int64_t r = 0; r < s.n; ++r) u.A.rowptr.push_back(base + s.A.rowptr[r + 1]);
+      for (int32_t c : s.A.col) u.A.col.push_back(static_cast<int32_t>(c + off));
+      u.A.val.insert(u.A.val.end(), s.A.val.begin(), s.A.val.end());
+      if (any_fixed) {
+        if (s.fixed.empty())
+          u.fixed.insert(u.fixed.end(), s.n, 0);
+        else
+          u.fixed.insert(u.fixed.end(), s.fixed.begin(), s.fixed.end());
+      }
+      if (!coarsest) {
+        // prolongation to the next level: the part's own, or the identity
+        const int sn = src_of(i, l + 1);
+        int64_t noff = 0;
+        for (int j = 0; j < i; ++j) noff += parts[j]->levels[src_of(j, l + 1)].n;
+        ScalarCSR& P = u.P;
+        if (P.rowptr.empty()) P.rowptr.assign(1, 0);
+        if (sn > si) {
+          const int64_t pb = P.col.size();
+          for (int64_t r = 0; r < s.n; ++r) P.rowptr.push_back(pb + s.P.rowptr[r + 1]);
+          for (int32_t c : s.P.col) P.col.push_back(static_cast<int32_t>(c + noff));
+          P.val.insert(P.val.end(), s.P.val.begin(), s.P.val.end());
+        } else {
+          for (int64_t r = 0; r < s.n; ++r) {
+            P.col.push_back(static_cast<int32_t>(r + noff));
+            P.val.push_back(1.0);
+            P.rowptr.push_back(static_cast<int64_t>(P.col.size()));
+          }
+        }
+        // Gauss-Seidel order: the part's own, or point order on a padded level
+        Level pad;
+        const Level* g = &s;
+        if (padded) {
+          padded_gs_order(s, d, l == 0, pad);
+          g = &pad;
+        }
+        for (int64_t r = 0; r < s.n; ++r) {
+          u.cell.push_back(static_cast<int32_t>(g->cell[r] + cell_off));
+          u.color.push_back(g->color[r]);
+        }
+        for (int64_t c = 0; c < g->ncells; ++c) u.block_color.push_back(g->block_color[c]);
+        cell_off += g->ncells;
+        u.ncolors = std::max(u.ncolors, g->ncolors);
+      }
+      off += s.n;
+    }
+    u.n = off;
+    u.A.n = off;
+    if (!coarsest) {
+      u.P.nrows = off;
+      int64_t nn = 0;
+      for (int i = 0; i < np; ++i) nn += parts[i]->levels[src_of(i, l + 1)].n;
+      u.P.ncols = nn;
+      u.ncells = cell_off;
+      u.block = u.cell;
+      u.nblocks = cell_off;
+      u.block_steps = l == 0 ? 1 : 2;
+    } else {
+      u.color.assign(off, 0);
+      u.ncolors = 0;
+    }
+  }
+  // coarsest factor: the parts' own factors on the diagonal
+  int64_t nc = 0;
+  for (const Hierarchy* p : parts) nc += p->n_coarse_dofs;
+  if (nc > 4096) fail(1, "packed coarsest levels exceed 4096 DOFs");
+  U.n_coarse_dofs = nc;
+  U.chol.assign(static_cast<size_t>(nc * nc), 0.0);
+  int64_t o = 0;
+  for (const Hierarchy* p : parts) {
+    const int64_t m = p->n_coarse_dofs;
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t j = 0; j <= i; ++j) U.chol[(o + i) * nc + o + j] = p->chol[i * m + j];
+    o += m;
+  }
+}
 
 // --------------------------------------------------------------------------
 void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {

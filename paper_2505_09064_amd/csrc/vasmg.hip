@@ -27,6 +27,7 @@
 #include "hierarchy.hpp"
 #include "kernels.hpp"
 #include "block.hpp"
+#include "packed.hpp"
 
 using namespace vasmg;
 using dev::Scalars;
@@ -202,6 +203,15 @@ struct vasmg_ctx {
   hipGraphExec_t kgA = nullptr, kgB = nullptr;
   GalerkinDevice* gdev = nullptr;     // setup_device = 1, during the upload only
   GalerkinDevice* gdev_bg = nullptr;  // owned: value downloads still running after setup
+  // packed problems (vasmg_pack): nseg segments of the fine level, each with its
+  // own PCG scalars (0: one problem)
+  int nseg = 0;
+  std::vector<int64_t> seg_vertex_off;   // [nseg + 1] mesh-vertex offsets of the parts
+  std::vector<int64_t> seg_free_off;     // [nseg + 1] fine canonical vertex offsets
+  int *seg_ptr = nullptr, *seg_rows = nullptr, *seg_of_row = nullptr;
+  Scalars* ssc = nullptr;                // [nseg]
+  int* seg_running = nullptr;            // segments still iterating
+  hipGraphExec_t sgA = nullptr, sgB = nullptr;
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -261,6 +271,8 @@ struct vasmg_ctx {
     if (gB) (void)hipGraphExecDestroy(gB);
     if (kgA) (void)hipGraphExecDestroy(kgA);
     if (kgB) (void)hipGraphExecDestroy(kgB);
+    if (sgA) (void)hipGraphExecDestroy(sgA);
+    if (sgB) (void)hipGraphExecDestroy(sgB);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -722,6 +734,27 @@ void upload_all(vasmg_ctx& C) {
   C.h_rtol = reinterpret_cast<double*>(static_cast<char*>(C.pinned) + 256);
   for (auto& e : C.ev) HIP_CHECK(hipEventCreate(&e));
   HIP_CHECK(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking));
+  if (C.nseg > 0) {
+    // segment of each fine device row, and each segment's rows (ascending)
+    const std::vector<int> perm0 = device_order(C, 0);
+    std::vector<int> of(C.n0), cnt(C.nseg + 1, 0);
+    for (int i = 0; i < C.n0; ++i) {
+      const int64_t v = perm0[i];
+      of[i] = static_cast<int>(std::upper_bound(C.seg_free_off.begin(), C.seg_free_off.end(), v) -
+                               C.seg_free_off.begin()) - 1;
+      cnt[of[i] + 1]++;
+    }
+    for (int k = 0; k < C.nseg; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int> rows(C.n0), fill(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < C.n0; ++i) rows[fill[of[i]]++] = i;
+    C.seg_of_row = C.upload(of);
+    C.seg_ptr = C.upload(cnt);
+    C.seg_rows = C.upload(rows);
+    C.ssc = C.dalloc<Scalars>(C.nseg);
+    C.clear(C.ssc, sizeof(Scalars) * C.nseg);
+    C.seg_running = C.dalloc<int>(1);
+    C.clear(C.seg_running, sizeof(int));
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -1483,6 +1516,125 @@ void ensure_graphs(vasmg_ctx& C) {
 }
 
 // -------------------------------------------------------------------------
+// Packed problems: the shared SpMV and V-cycle, per-segment scalars
+// -------------------------------------------------------------------------
+// q = A p; alpha_s; x, r updates; ||r||_s and the stopping test; running count
+template <int D>
+void enqueue_packed_A(vasmg_ctx& C, hipStream_t st) {
+  launch_spmv<double, D>(C.lev[0], C.P, C.Q, nullptr, 0, nullptr, st);
+  hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_ALPHA, false, double>), dim3(C.nseg), dim3(dev::kBlock), 0,
+                     st, C.seg_ptr, C.seg_rows, C.DP, C.P, C.Q, C.ssc);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_seg_update_xr<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.DP, C.seg_of_row, C.ssc, C.P, C.Q, C.X, C.R, static_cast<float*>(C.lev[0].b));
+  else
+    hipLaunchKernelGGL((dev::k_seg_update_xr<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.DP, C.seg_of_row, C.ssc, C.P, C.Q, C.X, C.R, static_cast<double*>(nullptr));
+  hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_RES, false, double>), dim3(C.nseg), dim3(dev::kBlock), 0,
+                     st, C.seg_ptr, C.seg_rows, C.DP, C.R, C.R, C.ssc);
+  hipLaunchKernelGGL(dev::k_seg_running, dim3(1), dim3(dev::kBlock), 0, st, C.nseg, C.ssc,
+                     C.seg_running);
+}
+
+// z = B r (the whole packed V-cycle); rho_s, beta_s; p = z + beta_s p
+template <int D>
+void enqueue_packed_B(vasmg_ctx& C, hipStream_t st) {
+  enqueue_precond<D>(C, nullptr, st);
+  if (C.vc32) {
+    const float* z = static_cast<const float*>(C.lev[0].x);
+    hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_BETA, false, float>), dim3(C.nseg), dim3(dev::kBlock), 0,
+                       st, C.seg_ptr, C.seg_rows, C.DP, C.R, z, C.ssc);
+    hipLaunchKernelGGL((dev::k_seg_update_p<float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.DP, C.seg_of_row, C.ssc, z, C.P);
+  } else {
+    const double* z = static_cast<const double*>(C.lev[0].x);
+    hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_BETA, false, double>), dim3(C.nseg), dim3(dev::kBlock),
+                       0, st, C.seg_ptr, C.seg_rows, C.DP, C.R, z, C.ssc);
+    hipLaunchKernelGGL((dev::k_seg_update_p<double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, C.n0p,
+                       C.DP, C.seg_of_row, C.ssc, z, C.P);
+  }
+}
+
+template <int D>
+void ensure_packed_graphs(vasmg_ctx& C) {
+  if (!C.sgA) C.sgA = capture(C, &enqueue_packed_A<D>);
+  if (!C.sgB) C.sgB = capture(C, &enqueue_packed_B<D>);
+}
+
+// All segments from x0 = 0: d_rhs / d_x the parts' user vectors one after the
+// other ([sum n_vertices][D], device); info[nseg].
+template <int D>
+int solve_packed(vasmg_ctx& C, const double* d_rhs, double* d_x, double rtol, hipStream_t st,
+                 vasmg_solve_info* info) {
+  ensure_packed_graphs<D>(C);
+  const int n0 = C.n0;
+  const int64_t n0p = C.n0p;
+  const int nseg = C.nseg;
+  HIP_CHECK(hipEventRecord(C.ev[0], st));
+  hipLaunchKernelGGL((dev::k_gather_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n0, C.user_map, d_rhs, C.F,
+                     static_cast<const uint8_t*>(C.lev[0].fixed));
+  hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_NORMF, false, double>), dim3(nseg), dim3(dev::kBlock), 0, st,
+                     C.seg_ptr, C.seg_rows, C.DP, C.F, C.F, C.ssc);
+  hipLaunchKernelGGL(dev::k_seg_start, dim3(grid_for(nseg, dev::kBlock)), dim3(dev::kBlock), 0, st, nseg,
+                     C.ssc, rtol);
+  launch_fill<double>(C.X, n0p, 0.0, st);
+  launch_fill<double>(C.P, n0p, 0.0, st);
+  hipLaunchKernelGGL((dev::k_convert<double, double>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, n0p, C.F,
+                     C.R);
+  if (C.vc32)
+    hipLaunchKernelGGL((dev::k_convert<double, float>), dim3(kFlatGrid), dim3(dev::kBlock), 0, st, n0p,
+                       C.R, static_cast<float*>(C.lev[0].b));
+  hipLaunchKernelGGL(dev::k_seg_running, dim3(1), dim3(dev::kBlock), 0, st, nseg, C.ssc, C.seg_running);
+  int running = 0;
+  HIP_CHECK(hipMemcpyAsync(&running, C.seg_running, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (running > 0) {
+    // Algorithm 2 initialisation for every segment: z = B r, p = z, rho = r^T z
+    HIP_CHECK(hipGraphLaunch(C.sgB, st));
+    for (int k = 0; k < C.opt.max_iters; ++k) {
+      HIP_CHECK(hipGraphLaunch(C.sgA, st));
+      HIP_CHECK(hipMemcpyAsync(&running, C.seg_running, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      if (running == 0) break;
+      HIP_CHECK(hipGraphLaunch(C.sgB, st));
+    }
+  }
+  // true residuals, scatter
+  launch_spmv<double, D>(C.lev[0], C.X, C.Q, nullptr, 0, nullptr, st);
+  hipLaunchKernelGGL((dev::k_seg_dot<dev::FIN_TRUE, true, double>), dim3(nseg), dim3(dev::kBlock), 0, st,
+                     C.seg_ptr, C.seg_rows, C.DP, C.F, C.Q, C.ssc);
+  launch_fill<double>(d_x, C.H.n_mesh_vertices * D, 0.0, st);
+  hipLaunchKernelGGL((dev::k_scatter_user<double, double, D>), dim3(grid_for(n0, dev::kBlock)),
+                     dim3(dev::kBlock), 0, st, n0, C.user_map, C.X, d_x);
+  std::vector<Scalars> hs(nseg);
+  HIP_CHECK(hipMemcpyAsync(hs.data(), C.ssc, sizeof(Scalars) * nseg, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipEventRecord(C.ev[1], st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipGetLastError());
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, C.ev[0], C.ev[1]));
+  int worst = VASMG_OK;
+  for (int k = 0; k < nseg; ++k) {
+    const Scalars& s = hs[k];
+    vasmg_solve_info& o = info[k];
+    std::memset(&o, 0, sizeof(o));
+    const bool conv = s.status != 5 && (s.normF == 0.0 || s.res / s.normF < rtol);
+    o.iterations = s.iters;
+    o.converged = conv ? 1 : 0;
+    o.rel_res = s.normF > 0 ? s.res / s.normF : 0.0;
+    o.rel_res_true = s.normF > 0 ? s.res_true / s.normF : 0.0;
+    o.t_solve_ms = ms;
+    o.status = s.status == 5 ? VASMG_EBREAKDOWN : (conv ? VASMG_OK : VASMG_ENOTCONV);
+    if (o.status == VASMG_EBREAKDOWN)
+      worst = VASMG_EBREAKDOWN;
+    else if (o.status == VASMG_ENOTCONV && worst == VASMG_OK)
+      worst = VASMG_ENOTCONV;
+  }
+  return worst;
+}
+
+// -------------------------------------------------------------------------
 // one right-hand side: d_rhs/d_x user layout [nv][D] (device), d_x0 may be NULL
 // -------------------------------------------------------------------------
 template <int D>
@@ -1593,6 +1745,8 @@ int solve_one(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d_x
     HIP_CHECK(hipEventElapsedTime(&ms, C.ev[0], C.ev[1]));
     info->iterations = s.iters;
     info->converged = status == VASMG_OK ? 1 : 0;
+    info->status = status;
+    info->reserved = 0;
     info->rel_res = normF > 0 ? s.res / normF : 0.0;
     info->rel_res_true = normF > 0 ? s.res_true / normF : 0.0;
     info->t_solve_ms = ms;
@@ -1945,6 +2099,8 @@ int solve_block(vasmg_ctx& C, const double* d_rhs, const double* d_x0, double* d
       f.rel_res_true = normF[k] > 0 ? sk.res_true / normF[k] : 0.0;
       f.t_solve_ms = ms;
       f.t_spmv_ms = f.t_precond_ms = f.t_vector_ms = f.bytes_model = 0.0;
+      f.status = status;
+      f.reserved = 0;
     }
   }
   return worst;
@@ -1970,6 +2126,10 @@ void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
   // at the first solve: a solve then instantiates and allocates nothing.
   auto graphs = [&](auto dtag) {
     constexpr int D = decltype(dtag)::value;
+    if (C.nseg > 0) {
+      ensure_packed_graphs<D>(C);
+      return;
+    }
     ensure_graphs<D>(C);
     if (C.K > 0) DISPATCH_K(C.K, { ensure_block_graphs<D, KK>(C); });
   };
@@ -2020,6 +2180,7 @@ int64_t estimate_device_bytes(const vasmg_ctx& C) {
   b += 6 * n0p * 8 + H.levels[0].n * 4 + H.n_coarse_dofs * H.n_coarse_dofs * 16;   // factor + inverse
   b += (std::max<int64_t>(kFlatGrid, H.levels[0].n / 4 + 1)) * 8 * (1 + K);
   b += 5 * n0p * 8 * K;
+  if (C.nseg > 0) b += H.levels[0].n * 12 + static_cast<int64_t>(C.nseg + 1) * (4 + sizeof(Scalars));
   return b + b / 20 + (1 << 20);
 }
 
@@ -2254,6 +2415,7 @@ vasmg_status vasmg_solve_device(vasmg_handle h, const double* d_rhs, const doubl
     check_handle(h);
     if (!d_rhs || !d_x || n_rhs < 1) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/n_rhs"};
     if (!(rtol > 0.0)) throw vasmg::Error{VASMG_EINVAL, "rtol must be > 0"};
+    if (h->nseg > 0) throw vasmg::Error{VASMG_EINVAL, "packed handle: use vasmg_solve_packed(_device)"};
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t stride = h->H.n_mesh_vertices * h->d;
     int worst = VASMG_OK;
@@ -2321,6 +2483,7 @@ vasmg_status vasmg_solve_noalloc(vasmg_handle h, const double* rhs, const double
   try {
     check_handle(h);
     if (!rhs || !x || n_rhs < 1) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/n_rhs"};
+    if (h->nseg > 0) throw vasmg::Error{VASMG_EINVAL, "packed handle: use vasmg_solve_packed(_device)"};
     const size_t vec = sizeof(double) * static_cast<size_t>(h->H.n_mesh_vertices) * h->d *
                        static_cast<size_t>(n_rhs);
     const size_t slot = (vec + 255) / 256 * 256;
@@ -2342,6 +2505,114 @@ vasmg_status vasmg_solve_noalloc(vasmg_handle h, const double* rhs, const double
     g_last_error = msg;
     return s;
   } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_pack(const vasmg_handle* parts, int32_t n_parts, vasmg_handle* out) {
+  try {
+    if (!out) throw vasmg::Error{VASMG_EINVAL, "null output"};
+    *out = nullptr;
+    if (!parts || n_parts < 1) throw vasmg::Error{VASMG_EINVAL, "no parts to pack"};
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<const Hierarchy*> hs;
+    const vasmg_options& o0 = parts[0] ? parts[0]->opt : vasmg_options{};
+    int32_t max_iters = 0;
+    for (int i = 0; i < n_parts; ++i) {
+      vasmg_handle p = parts[i];
+      if (!p) throw vasmg::Error{VASMG_EINVAL, "null part handle"};
+      if (p->nseg > 0) throw vasmg::Error{VASMG_EINVAL, "a part is itself packed"};
+      const vasmg_options& o = p->opt;
+      if (o.preconditioner != VASMG_PRECOND_VASMG || o.cycle != VASMG_CYCLE_V ||
+          o.smoother != VASMG_SMOOTHER_GS || o.block_rhs != 0 || o.color_blocks != 0)
+        throw vasmg::Error{VASMG_EINVAL,
+                           "packing needs the V-ASMG Gauss-Seidel V-cycle without block_rhs or colour blocks"};
+      if (o.precision != o0.precision || o.n_pre != o0.n_pre || o.n_post != o0.n_post ||
+          p->d != parts[0]->d)
+        throw vasmg::Error{VASMG_EINVAL, "packed parts differ in dimension, precision or sweeps"};
+      p->settle_host_values();
+      hs.push_back(&p->H);
+      max_iters = std::max(max_iters, o.max_iters);
+    }
+    auto C = std::make_unique<vasmg_ctx>();
+    pack_hierarchies(hs, C->H);
+    C->opt = o0;
+    C->opt.host_only = 1;
+    C->opt.max_iters = max_iters;
+    C->d = parts[0]->d;
+    C->DP = C->d == 3 ? 4 : 2;
+    C->L = static_cast<int>(C->H.levels.size()) - 1;
+    C->vc32 = o0.precision == VASMG_FP32_PRECOND;
+    C->host_only = true;
+    C->nseg = n_parts;
+    C->seg_vertex_off.assign(1, 0);
+    C->seg_free_off.assign(1, 0);
+    for (int i = 0; i < n_parts; ++i) {
+      C->seg_vertex_off.push_back(C->seg_vertex_off.back() + parts[i]->H.n_mesh_vertices);
+      C->seg_free_off.push_back(C->seg_free_off.back() + parts[i]->H.levels[0].n);
+    }
+    C->H.phase_ms.emplace_back(
+        "pack", std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    *out = C.release();
+    return VASMG_OK;
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return VASMG_ENOMEM;
+  }
+}
+
+vasmg_status vasmg_packed_info(vasmg_handle h, int32_t* n_parts, int64_t* vertex_offsets) {
+  if (!h) {
+    g_last_error = "null handle";
+    return VASMG_EINVAL;
+  }
+  if (n_parts) *n_parts = h->nseg;
+  if (vertex_offsets && h->nseg > 0)
+    std::copy(h->seg_vertex_off.begin(), h->seg_vertex_off.end(), vertex_offsets);
+  return VASMG_OK;
+}
+
+vasmg_status vasmg_solve_packed_device(vasmg_handle h, const double* d_rhs, double* d_x, double rtol,
+                                       void* stream, vasmg_solve_info* info) {
+  try {
+    check_handle(h);
+    if (h->nseg == 0) throw vasmg::Error{VASMG_EINVAL, "not a packed handle (vasmg_pack)"};
+    if (!d_rhs || !d_x || !info) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/info"};
+    if (!(rtol > 0.0)) throw vasmg::Error{VASMG_EINVAL, "rtol must be > 0"};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int worst = h->d == 2 ? solve_packed<2>(*h, d_rhs, d_x, rtol, st, info)
+                                : solve_packed<3>(*h, d_rhs, d_x, rtol, st, info);
+    if (worst == VASMG_ENOTCONV) g_last_error = "PCG did not reach rtol within max_iters (some part)";
+    if (worst == VASMG_EBREAKDOWN) g_last_error = "PCG breakdown in some part";
+    return static_cast<vasmg_status>(worst);
+  } catch (const vasmg::Error& e) {
+    return fail_with(e);
+  }
+}
+
+vasmg_status vasmg_solve_packed(vasmg_handle h, const double* rhs, double* x, double rtol,
+                                vasmg_solve_info* info) {
+  double *drhs = nullptr, *dx = nullptr;
+  try {
+    check_handle(h);
+    if (h->nseg == 0) throw vasmg::Error{VASMG_EINVAL, "not a packed handle (vasmg_pack)"};
+    if (!rhs || !x || !info) throw vasmg::Error{VASMG_EINVAL, "bad rhs/x/info"};
+    const size_t bytes = sizeof(double) * h->H.n_mesh_vertices * h->d;
+    HIP_CHECK(hipMalloc(&drhs, bytes));
+    HIP_CHECK(hipMalloc(&dx, bytes));
+    HIP_CHECK(hipMemcpy(drhs, rhs, bytes, hipMemcpyHostToDevice));
+    const vasmg_status s = vasmg_solve_packed_device(h, drhs, dx, rtol, nullptr, info);
+    const std::string msg = g_last_error;
+    HIP_CHECK(hipMemcpy(x, dx, bytes, hipMemcpyDeviceToHost));
+    (void)hipFree(drhs);
+    (void)hipFree(dx);
+    g_last_error = msg;
+    return s;
+  } catch (const vasmg::Error& e) {
+    if (drhs) (void)hipFree(drhs);
+    if (dx) (void)hipFree(dx);
     return fail_with(e);
   }
 }

@@ -33,7 +33,8 @@ EXPORTED = [
     "vasmg_prolong_device", "vasmg_apply_precond_device", "vasmg_profile_iteration",
     "vasmg_upload", "vasmg_device_bytes", "vasmg_server_default_config", "vasmg_server_create",
     "vasmg_server_submit", "vasmg_server_wait", "vasmg_server_stats", "vasmg_server_destroy",
-    "vasmg_set_galerkin_window", "vasmg_solve_noalloc", "vasmg_setup_phases",
+    "vasmg_set_galerkin_window", "vasmg_solve_noalloc", "vasmg_setup_phases", "vasmg_pack",
+    "vasmg_packed_info", "vasmg_solve_packed_device", "vasmg_solve_packed",
 ]
 
 
@@ -73,7 +74,8 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_res", C.c_double),
                 ("rel_res_true", C.c_double), ("t_solve_ms", C.c_double),
                 ("t_spmv_ms", C.c_double), ("t_precond_ms", C.c_double),
-                ("t_vector_ms", C.c_double), ("bytes_model", C.c_double)]
+                ("t_vector_ms", C.c_double), ("bytes_model", C.c_double),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,12 +83,14 @@ class SolveInfo(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("setup_workers", C.c_int32),
-                ("hbm_budget_bytes", C.c_int64), ("options", Options)]
+                ("hbm_budget_bytes", C.c_int64), ("options", Options),
+                ("pack_max_dofs", C.c_int32), ("pack_max_parts", C.c_int32),
+                ("pack_wait_ms", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RequestResult(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("slot", C.c_int32),
-                ("device_bytes", C.c_int64), ("t_submit_ms", C.c_double),
+                ("pack_size", C.c_int32), ("reserved", C.c_int32), ("device_bytes", C.c_int64), ("t_submit_ms", C.c_double),
                 ("t_setup_start_ms", C.c_double), ("t_setup_end_ms", C.c_double),
                 ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("info", SolveInfo),
                 ("message", C.c_char * 128)]
@@ -134,6 +138,10 @@ def lib():
             "vasmg_export_level": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "vasmg_tree_info": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32)]),
             "vasmg_setup_phases": (i32, [vp, vp, i32, C.POINTER(i32)]),
+            "vasmg_pack": (i32, [vp, i32, C.POINTER(vp)]),
+            "vasmg_packed_info": (i32, [vp, C.POINTER(i32), vp]),
+            "vasmg_solve_packed_device": (i32, [vp, vp, vp, dbl, vp, vp]),
+            "vasmg_solve_packed": (i32, [vp, vp, vp, dbl, vp]),
             "vasmg_spmv_device": (i32, [vp, i32, i32, vp, vp, vp]),
             "vasmg_gs_sweep_device": (i32, [vp, i32, i32, i32, vp, vp, vp]),
             "vasmg_restrict_device": (i32, [vp, i32, i32, vp, vp, vp]),
@@ -423,15 +431,75 @@ class Solver:
                                                 _stream_ptr(stream)))
 
 
+class PackedSolver(Solver):
+    """Owns a packed handle (vasmg_pack): several small problems solved as one,
+    each with its own PCG recurrence. `parts` are Solver objects (host-only or
+    uploaded); they stay valid and owned by the caller."""
+
+    def __init__(self, parts, upload: bool = True):
+        if not parts:
+            raise ValueError("nothing to pack")
+        arr = (C.c_void_p * len(parts))(*[p.handle.value for p in parts])
+        h = C.c_void_p()
+        _check(lib().vasmg_pack(arr, len(parts), C.byref(h)))
+        self._h = h
+        self._arrays = None
+        self.dim = parts[0].dim
+        self.options = parts[0].options
+        n = C.c_int32()
+        offs = np.zeros(len(parts) + 1, dtype=np.int64)
+        _check(lib().vasmg_packed_info(h, C.byref(n), _ptr(offs)))
+        self.n_parts = n.value
+        self.offsets = offs
+        self.n_vertices = int(offs[-1])
+        self.device = None
+        if upload:
+            _check(lib().vasmg_upload(h, None))
+            import torch
+            self.device = torch.cuda.current_device()
+
+    def solve_packed(self, rhs_list, rtol: float = 1e-6, check: bool = True):
+        """Host arrays [n_vertices_i, dim], one per part -> ([x_i], [info_i])."""
+        if len(rhs_list) != self.n_parts:
+            raise ValueError(f"expected {self.n_parts} right-hand sides")
+        R = np.concatenate([np.ascontiguousarray(r, dtype=np.float64).reshape(-1, self.dim)
+                            for r in rhs_list])
+        if R.shape[0] != self.n_vertices:
+            raise ValueError("right-hand sides do not match the parts' vertex counts")
+        X = np.zeros_like(R)
+        infos = (SolveInfo * self.n_parts)()
+        st = lib().vasmg_solve_packed(self._h, _ptr(R), _ptr(X), rtol, infos)
+        if check and st not in (OK, ENOTCONV):
+            _check(st)
+        out = [i.as_dict() for i in infos]      # "status": each part's own
+        o = self.offsets
+        return [X[o[i]:o[i + 1]].copy() for i in range(self.n_parts)], out
+
+    def solve_packed_device(self, d_rhs, d_x, rtol: float = 1e-6, stream=None, check: bool = True):
+        """Packed torch FP64 device tensors [sum n_vertices_i, dim] -> [info_i]."""
+        shape = (self.n_vertices, self.dim)
+        _check_tensor(d_rhs, shape, "d_rhs", self.device)
+        _check_tensor(d_x, shape, "d_x", self.device)
+        infos = (SolveInfo * self.n_parts)()
+        st = lib().vasmg_solve_packed_device(self._h, _ptr(d_rhs), _ptr(d_x), rtol,
+                                             _stream_ptr(stream), infos)
+        if check and st not in (OK, ENOTCONV):
+            _check(st)
+        return [i.as_dict() for i in infos]      # "status": each part's own
+
+
 class Server:
     """Continuous-batching solve server (vasmg_server_*): requests are set up on
     host threads, admitted to device slots by HBM footprint, solved on the
     slots' own streams, and collected with wait()."""
 
-    def __init__(self, slots: int = 4, setup_workers: int = 4, hbm_budget_bytes: int = 0, **opts):
+    def __init__(self, slots: int = 4, setup_workers: int = 4, hbm_budget_bytes: int = 0,
+                 pack_max_dofs: int = 0, pack_max_parts: int = 16, pack_wait_ms: int = 0, **opts):
         cfg = ServerConfig()
         _check(lib().vasmg_server_default_config(C.byref(cfg)))
         cfg.slots, cfg.setup_workers, cfg.hbm_budget_bytes = slots, setup_workers, hbm_budget_bytes
+        cfg.pack_max_dofs, cfg.pack_max_parts = pack_max_dofs, pack_max_parts
+        cfg.pack_wait_ms = pack_wait_ms
         for k, v in opts.items():
             setattr(cfg.options, k, v)
         h = C.c_void_p()

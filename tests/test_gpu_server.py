@@ -134,6 +134,13 @@ def test_budget_bounds_resident_bytes():
                 assert a["t_done_ms"] <= b["t_admit_ms"] or b["t_done_ms"] <= a["t_admit_ms"]
 
 
+def test_server_config_validation():
+    for kw in (dict(pack_max_dofs=-1), dict(pack_max_parts=300), dict(pack_wait_ms=-5)):
+        with pytest.raises(V.VasmgError) as ei:
+            V.Server(slots=1, setup_workers=1, **kw)
+        assert ei.value.status == V.EINVAL, kw
+
+
 def test_failing_requests_fail_alone():
     ok1, big, ok2 = small2d(9, seed=1), small3d(12, seed=2), small2d(11, seed=3)
     bad = small2d(9, seed=4)
@@ -162,3 +169,39 @@ def test_uploaded_bytes_within_estimate():
     assert np.array_equal(x, xa)
     assert V.lib().vasmg_upload(s._h, None) == V.EINVAL      # already on the device
     s.free()
+
+
+@pytest.mark.parametrize("precision", [V.FP64, V.FP32_PRECOND])
+def test_packed_serving(precision):
+    """Packing on (pack_max_dofs, a batching window long enough for every setup
+    to finish, one slot): the 2D and the 3D requests are each solved as one
+    pack, and every result still matches the oracle's solve of its own request
+    and the request solved alone (FP64: 1e-10 relative, +-1 iteration; the dot
+    products sum in another order)."""
+    reqs = _requests()
+    srv = V.Server(slots=1, setup_workers=4, precision=precision, pack_max_dofs=100000,
+                   pack_max_parts=8, pack_wait_ms=5000)
+    ids = [srv.submit(m, m.rhs[0], 1e-6) for m in reqs]
+    got = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["peak_bytes"] <= st["budget_bytes"]
+    sizes = [res["pack_size"] for _, res in got]
+    assert max(sizes) > 1, sizes
+    for i, (m, (x, res)) in enumerate(zip(reqs, got)):
+        assert res["status"] == V.OK and res["info"]["status"] == V.OK, res
+        _check_against_oracle(i, m, x, res["info"], precision)
+        xa, ia = _alone(m, precision=precision)
+        assert abs(res["info"]["iterations"] - ia["iterations"]) <= 1
+        if precision == V.FP64:
+            assert np.linalg.norm(x - xa) / np.linalg.norm(xa) <= 1e-10
+        t = [res[k] for k in ("t_submit_ms", "t_setup_start_ms", "t_setup_end_ms", "t_admit_ms",
+                              "t_done_ms")]
+        assert all(a <= b for a, b in zip(t, t[1:])), t
+    # requests packed together share their admission and completion times
+    by_admit = {}
+    for _, res in got:
+        by_admit.setdefault(res["t_admit_ms"], []).append(res)
+    for group in by_admit.values():
+        assert all(r["pack_size"] == len(group) for r in group)
+        assert len({r["t_done_ms"] for r in group}) == 1
