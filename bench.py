@@ -136,7 +136,8 @@ def bench_block16(args, V, torch):
     mesh = cfg2()
     d_F = torch.from_numpy(np.stack(load_fourier_tet(mesh.coords, mesh.elems, 16))).to("cuda")
     d_X = torch.zeros_like(d_F)
-    blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16)
+    blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16,
+                             autotune=0 if args.no_autotune else 1)
     time_solves(blk, d_F, d_X, max(1, args.warmup))
     rb = time_solves(blk, d_F, d_X, max(1, min(args.steps, 5)))
     ms = float(np.mean([r[0] for r in rb]))
@@ -210,7 +211,8 @@ def bench_cfg4(args, V, torch):
     d_F = torch.from_numpy(np.stack(mesh.rhs)).to("cuda")
     d_X = torch.zeros_like(d_F)
     t0 = time.perf_counter()
-    blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16, verbose=1)
+    blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16, verbose=1,
+                             autotune=0 if args.no_autotune else 1)
     t_setup = time.perf_counter() - t0
     log(f"setup (block) {t_setup:.1f}s")
     time_solves(blk, d_F, d_X, args.warmup if args.warmup > 0 else 1)
@@ -253,6 +255,72 @@ def bench_cfg4(args, V, torch):
 
 
 PACK_MAX_DOFS = 20000      # serving: requests this small are packed in the packed phase
+
+
+def pack_leg(V, meshes, reps: int = 3):
+    """Small requests (at most PACK_MAX_DOFS DOFs) of the serving stream solved
+    one after another on one stream, each alone, against the same requests
+    packed (vasmg_pack: up to 16 per pack, same dimension, coarsest levels
+    within 256 DOFs together), FP32 V-cycle, rtol 1e-6. Setups, uploads and
+    packing happen before the timed region; the solves run with their inputs
+    resident in HBM. Median of `reps` passes over all of them."""
+    import torch
+    small = [m for m in meshes if m.n_dofs <= PACK_MAX_DOFS]
+    if len(small) < 2:
+        return None
+    alone, rhs = [], []
+    for m in small:
+        alone.append(V.Solver.from_mesh(m, precision=V.FP32_PRECOND, autotune=0))
+        rhs.append(torch.from_numpy(np.ascontiguousarray(m.rhs[0])).to("cuda"))
+    xs = [torch.zeros_like(r) for r in rhs]
+    # packs: by dimension, in order, closed at 16 parts or 256 coarsest DOFs
+    packs, cur, coarse = [], [], 0
+    hosts = [V.Solver.from_mesh(m, precision=V.FP32_PRECOND, host_only=1) for m in small]
+    order = sorted(range(len(small)), key=lambda i: small[i].dim)
+    for i in order:
+        h = hosts[i]
+        nl = h.hierarchy_info()[0]
+        c = h.level_info(nl - 1)["n_vertices"] * small[i].dim
+        if cur and (small[cur[0]].dim != small[i].dim or len(cur) == 16 or coarse + c > 256):
+            packs.append(cur)
+            cur, coarse = [], 0
+        cur.append(i)
+        coarse += c
+    packs.append(cur)
+    pks = [V.PackedSolver([hosts[i] for i in p]) for p in packs]
+    prhs = [torch.cat([rhs[i] for i in p]) for p in packs]
+    px = [torch.zeros_like(r) for r in prhs]
+    t_alone, t_packed, it_alone, it_packed = [], [], None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it_alone = [s.solve_device(r, x, 1e-6)["iterations"] for s, r, x in zip(alone, rhs, xs)]
+        torch.cuda.synchronize()
+        t_alone.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        infos = [pk.solve_packed_device(r, x, 1e-6) for pk, r, x in zip(pks, prhs, px)]
+        torch.cuda.synchronize()
+        t_packed.append(time.perf_counter() - t0)
+        it_packed = {i: inf["iterations"] for p, inf_p in zip(packs, infos) for i, inf in zip(p, inf_p)}
+    diff, dit = 0.0, 0
+    for p, x in zip(packs, px):
+        parts = torch.split(x, [small[i].n_vertices for i in p])
+        for i, xp in zip(p, parts):
+            a = xs[i].cpu().numpy()
+            diff = max(diff, float(np.linalg.norm(xp.cpu().numpy() - a) / max(np.linalg.norm(a), 1e-300)))
+            dit = max(dit, abs(it_packed[i] - it_alone[i]))
+    for o in alone + pks + hosts:
+        o.free()
+    ta, tp = float(np.median(t_alone)), float(np.median(t_packed))
+    n = len(small)
+    return {
+        "small_requests": n, "max_dofs": PACK_MAX_DOFS,
+        "dofs_mean": float(np.mean([m.n_dofs for m in small])), "packs": len(packs),
+        "mean_parts_per_pack": n / len(packs),
+        "ms_per_request_alone": 1e3 * ta / n, "ms_per_request_packed": 1e3 * tp / n,
+        "speedup": ta / tp, "mean_iterations_alone": float(np.mean(it_alone)),
+        "max_iteration_difference": dit, "max_rel_diff_packed_vs_alone": diff,
+    }
 
 
 def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
@@ -383,6 +451,12 @@ def serve_leg(V, N: int, host_setup: bool = False, saturated: bool = True):
                     "saturated_p50_ms": float(np.percentile(lat2, 50)),
                     "saturated_p99_ms": float(np.percentile(lat2, 99))})
         out.update(pack_stats)
+    pk = pack_leg(V, meshes)
+    if pk is not None:
+        out["packed_small_solves"] = pk
+        log(f"packed small solves: {pk['small_requests']} requests in {pk['packs']} packs, "
+            f"{pk['ms_per_request_alone']:.2f} ms alone -> {pk['ms_per_request_packed']:.2f} ms "
+            f"per request ({pk['speedup']:.1f}x), max rel diff {pk['max_rel_diff_packed_vs_alone']:.1e}")
     return out
 
 
@@ -509,8 +583,14 @@ def main():
         fp64 = V.Solver.from_mesh(mesh, precision=V.FP64, autotune=0 if args.no_autotune else 1)
         time_solves(fp64, d_rhs, d_x, 1)
         r64 = time_solves(fp64, d_rhs, d_x, max(3, args.steps // 4))
-        variants["fp64_vasmg"] = dict(ms_per_solve=float(np.mean([r[0] for r in r64])),
-                                      iterations=r64[-1][1]["iterations"])
+        ms64 = float(np.mean([r[0] for r in r64]))
+        ph64 = fp64.profile_iteration(3)
+        b64 = sum(p["bytes"] for p in ph64) / 3          # byte model, one FP64 iteration
+        spmv_b = sum(p["bytes"] for p in ph64 if p["name"] == "spmv_f64") / 3
+        vec_b = sum(p["bytes"] for p in ph64 if p["name"] == "pcg_vectors") / 3
+        variants["fp64_vasmg"] = dict(ms_per_solve=ms64, iterations=r64[-1][1]["iterations"],
+                                      iteration_bytes=b64,
+                                      solve_GBps=b64 * r64[-1][1]["iterations"] / (ms64 * 1e-3) / 1e9)
         fp64.free()
         # leaf capacity 27: the 3D analogue of the capacity under which the method
         # reduces to geometric multigrid on uniform grids (the paper's Theorem 2)
@@ -540,7 +620,8 @@ def main():
         log(f"16 load cases: {time.perf_counter() - t0:.1f}s")
         d_F16 = torch.from_numpy(F16).to("cuda")
         d_X16 = torch.zeros_like(d_F16)
-        blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16)
+        blk = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, block_rhs=16,
+                                 autotune=0 if args.no_autotune else 1)
         time_solves(blk, d_F16, d_X16, 1)
         rb = time_solves(blk, d_F16, d_X16, max(3, args.steps // 4))
         ib = rb[-1][1]
@@ -553,8 +634,15 @@ def main():
         blk.free()
         jac = V.Solver.from_mesh(mesh, precision=V.FP64, preconditioner=V.PRECOND_JACOBI)
         rj = time_solves(jac, d_rhs, d_x, 2)
-        variants["fp64_jacobi_pcg"] = dict(ms_per_solve=float(np.mean([r[0] for r in rj])),
-                                           iterations=rj[-1][1]["iterations"])
+        msj = float(np.mean([r[0] for r in rj]))
+        # byte model of one Jacobi-PCG iteration: the FP64 SpMV and PCG vector
+        # phases (same fine matrix as above) plus z = D^-1 r (inverse diagonal
+        # blocks once, r in, z out; padded vectors)
+        n0 = mesh.n_dofs // 3
+        bj = spmv_b + vec_b + n0 * 9 * 8 + 2 * n0 * 4 * 8
+        variants["fp64_jacobi_pcg"] = dict(ms_per_solve=msj, iterations=rj[-1][1]["iterations"],
+                                           iteration_bytes=bj,
+                                           solve_GBps=bj * rj[-1][1]["iterations"] / (msj * 1e-3) / 1e9)
         jac.free()
         # the small 2D manufactured-solution workload on the GPU (latency-bound)
         from workloads import cfg1

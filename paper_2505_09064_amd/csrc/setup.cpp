@@ -79,17 +79,34 @@ void validate(const MeshView& m) {
   if (m.nv >= (int64_t(1) << 31) / 3) fail(1, "too many vertices for int32 indexing");
   if (!m.coords || !m.elems || !m.E || !m.nu || !m.fixed) fail(1, "null mesh array");
   const int d = m.d;
-  for (int64_t i = 0; i < m.nv * d; ++i)
-    if (!std::isfinite(m.coords[i])) fail(1, "non-finite vertex coordinate");
-  for (int64_t v = 0; v < m.nv * d; ++v)
-    if (m.fixed[v] > 1) fail(1, "fixed flags must be 0 or 1");
-  for (int64_t e = 0; e < m.ne; ++e) {
+  const int64_t nvd = m.nv * d;
+  int bad_coord = 0, bad_flag = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad_coord, bad_flag)
+  for (int64_t i = 0; i < nvd; ++i) {
+    bad_coord |= std::isfinite(m.coords[i]) ? 0 : 1;
+    bad_flag |= m.fixed[i] > 1 ? 1 : 0;
+  }
+  if (bad_coord) fail(1, "non-finite vertex coordinate");
+  if (bad_flag) fail(1, "fixed flags must be 0 or 1");
+  // the first invalid element (found in parallel), then its first failing check
+  auto element_ok = [&](int64_t e) {
+    if (!(m.E[e] > 0.0) || !std::isfinite(m.E[e])) return false;
+    if (!(m.nu[e] > -1.0 && m.nu[e] < 0.5)) return false;
+    for (int a = 0; a <= d; ++a) {
+      const int32_t v = m.elems[e * (d + 1) + a];
+      if (v < 0 || v >= m.nv) return false;
+    }
+    return true;
+  };
+  int64_t first = m.ne;
+#pragma omp parallel for schedule(static) reduction(min : first)
+  for (int64_t e = 0; e < m.ne; ++e)
+    if (!element_ok(e)) first = std::min(first, e);
+  if (first < m.ne) {
+    const int64_t e = first;
     if (!(m.E[e] > 0.0) || !std::isfinite(m.E[e])) fail(1, "E must be finite and > 0");
     if (!(m.nu[e] > -1.0 && m.nu[e] < 0.5)) fail(1, "nu must lie in (-1, 0.5)");
-    for (int a = 0; a <= d; ++a) {
-      int32_t v = m.elems[e * (d + 1) + a];
-      if (v < 0 || v >= m.nv) fail(1, "element vertex index out of range");
-    }
+    fail(1, "element vertex index out of range");
   }
 }
 
@@ -563,31 +580,47 @@ void build_gs_order(Level& lv, bool lattice, int d, bool color_blocks) {
     }
     lv.nblocks = static_cast<int64_t>(bkeys.size());
   }
-  // block adjacency from the structural block pattern
+  // block adjacency from the structural block pattern (on the fine level, where
+  // every vertex is its own block, the pattern itself)
   const int64_t nc = lv.nblocks;
-  std::vector<int64_t> vptr(nc + 1, 0);
-  for (int64_t i = 0; i < n; ++i) vptr[lv.block[i] + 1]++;
-  for (int64_t c = 0; c < nc; ++c) vptr[c + 1] += vptr[c];
-  std::vector<int32_t> members(n);
-  {
-    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
-    for (int64_t i = 0; i < n; ++i) members[fill[lv.block[i]]++] = static_cast<int32_t>(i);
-  }
-  // each block's neighbour list is independent: built in parallel, then packed
-  std::vector<int64_t> gptr(nc + 1, 0);
+  std::vector<int64_t> gptr;
   std::vector<int32_t> gadj;
-  {
+  const std::vector<int64_t>* adj_ptr = &gptr;
+  const std::vector<int32_t>* adj = &gadj;
+  if (!lattice) {
+    adj_ptr = &lv.A.rowptr;
+    adj = &lv.A.col;
+  } else {
+    std::vector<int64_t> vptr(nc + 1, 0);
+    for (int64_t i = 0; i < n; ++i) vptr[lv.block[i] + 1]++;
+    for (int64_t c = 0; c < nc; ++c) vptr[c + 1] += vptr[c];
+    std::vector<int32_t> members(n);
+    {
+      std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+      for (int64_t i = 0; i < n; ++i) members[fill[lv.block[i]]++] = static_cast<int32_t>(i);
+    }
+    // each block's neighbour list is independent: the distinct neighbour blocks
+    // found with a per-thread marker (no sort of the raw entries), then sorted
+    gptr.assign(nc + 1, 0);
     std::vector<std::vector<int32_t>> nb(nc);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t c = 0; c < nc; ++c) {
-      auto& tmp = nb[c];
-      for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) {
-        const int32_t v = members[q];
-        for (int64_t p = lv.A.rowptr[v]; p < lv.A.rowptr[v + 1]; ++p)
-          tmp.push_back(lv.block[lv.A.col[p]]);
+#pragma omp parallel
+    {
+      std::vector<int64_t> mark(nc, -1);
+#pragma omp for schedule(dynamic, 256)
+      for (int64_t c = 0; c < nc; ++c) {
+        auto& tmp = nb[c];
+        for (int64_t q = vptr[c]; q < vptr[c + 1]; ++q) {
+          const int32_t v = members[q];
+          for (int64_t p = lv.A.rowptr[v]; p < lv.A.rowptr[v + 1]; ++p) {
+            const int32_t b = lv.block[lv.A.col[p]];
+            if (mark[b] != c) {
+              mark[b] = c;
+              tmp.push_back(b);
+            }
+          }
+        }
+        std::sort(tmp.begin(), tmp.end());
       }
-      std::sort(tmp.begin(), tmp.end());
-      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
     }
     for (int64_t c = 0; c < nc; ++c) gptr[c + 1] = gptr[c] + static_cast<int64_t>(nb[c].size());
     gadj.resize(gptr[nc]);
@@ -616,7 +649,7 @@ void build_gs_order(Level& lv, bool lattice, int d, bool color_blocks) {
       std::stable_sort(order.begin(), order.end(),
                        [&](int64_t a, int64_t b) { return cls[a] < cls[b]; });
     }
-    ncol[o] = greedy_color_in_order(gptr, gadj, order, cand[o]);
+    ncol[o] = greedy_color_in_order(*adj_ptr, *adj, order, cand[o]);
   }
   int best_o = 0;
   for (int o = 1; o < n_orders; ++o)

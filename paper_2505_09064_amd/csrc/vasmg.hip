@@ -212,6 +212,7 @@ struct vasmg_ctx {
   Scalars* ssc = nullptr;                // [nseg]
   int* seg_running = nullptr;            // segments still iterating
   hipGraphExec_t sgA = nullptr, sgB = nullptr;
+  mutable std::vector<std::vector<int>> order_cache;   // device numbering per level (setup)
 
   template <class T>
   T* dalloc(int64_t count) {
@@ -343,18 +344,33 @@ void upload_level_device(vasmg_ctx& C, int l, bool need32, bool need64, const st
                          const std::vector<int>& cell_ptr, const std::vector<int>& blk_lo,
                          const std::vector<int>& blk_hi);
 
+// Stable counting sort of perm by key[perm[i]] in [0, range).
+void counting_sort_by(std::vector<int>& perm, const std::vector<int32_t>& key, int64_t range) {
+  std::vector<int64_t> cnt(static_cast<size_t>(range) + 1, 0);
+  for (int i : perm) cnt[key[i] + 1]++;
+  for (int64_t k = 0; k < range; ++k) cnt[k + 1] += cnt[k];
+  std::vector<int> out(perm.size());
+  for (int i : perm) out[cnt[key[i]]++] = i;
+  perm.swap(out);
+}
+
 // Device numbering of level l: canonical rows sorted by colour, colour block,
 // cell (ties keep the canonical order); the identity on the coarsest level.
+// Three stable counting sorts (cell, then block, then colour), computed once
+// per level and kept.
 std::vector<int> device_order(const vasmg_ctx& C, int l) {
+  if (static_cast<int>(C.order_cache.size()) > l && !C.order_cache[l].empty())
+    return C.order_cache[l];
   const Level& hl = C.H.levels[l];
   std::vector<int> perm(static_cast<size_t>(hl.n));
   std::iota(perm.begin(), perm.end(), 0);
-  if (l != C.L)
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-      if (hl.color[a] != hl.color[b]) return hl.color[a] < hl.color[b];
-      if (hl.block[a] != hl.block[b]) return hl.block[a] < hl.block[b];
-      return hl.cell[a] < hl.cell[b];
-    });
+  if (l != C.L && hl.n > 0) {
+    counting_sort_by(perm, hl.cell, hl.ncells);
+    if (hl.block != hl.cell) counting_sort_by(perm, hl.block, hl.nblocks);
+    counting_sort_by(perm, hl.color, std::max<int32_t>(hl.ncolors, 1));
+  }
+  if (static_cast<int>(C.order_cache.size()) <= l) C.order_cache.resize(l + 1);
+  C.order_cache[l] = perm;
   return perm;
 }
 
@@ -755,6 +771,7 @@ void upload_all(vasmg_ctx& C) {
     C.seg_running = C.dalloc<int>(1);
     C.clear(C.seg_running, sizeof(int));
   }
+  std::vector<std::vector<int>>().swap(C.order_cache);   // numbering no longer needed
 }
 
 // -------------------------------------------------------------------------
@@ -1890,6 +1907,24 @@ void launch_gs_sweep_mc(const DevLevel& lv, bool backward, bool zero_guess, cons
   }
 }
 
+// r = b - A x of a level from the forward sweep's saved lower sums s
+template <typename T, int D, int K>
+void launch_residual_mc(const DevLevel& lv, const T* s, const T* x, T* r, hipStream_t st) {
+  if (lv.cells) {
+    DISPATCH_CELL_GL(lv.mcGL, {
+      hipLaunchKernelGGL((dev::k_cell_residual_mc<T, D, K, GL>), dim3(lv.ncells), dim3((1 << D) * GL), 0,
+                         st, lv.cell_ptr, LevelMats<T>::L(lv), LevelMats<T>::U(lv),
+                         LevelMats<T>::cellM(lv), s, x, r);
+    });
+  } else {
+    DISPATCH_POINT_GL(lv.mcGL, {
+      hipLaunchKernelGGL((dev::k_residual_upper_mc<T, D, K, GL>), dim3(grid_for(lv.n, dev::kBlock / GL)),
+                         dim3(dev::kBlock), 0, st, lv.n, LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x,
+                         r);
+    });
+  }
+}
+
 template <typename T, int D, int K>
 void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
   const int L = C.L;
@@ -1900,19 +1935,7 @@ void enqueue_vcycle_mc(vasmg_ctx& C, hipStream_t st) {
     T* s = static_cast<T*>(C.ks[l]);
     T* r = static_cast<T*>(C.kr[l]);
     for (int k = 0; k < C.opt.n_pre; ++k) launch_gs_sweep_mc<T, D, K>(lv, false, k == 0, b, x, s, st);
-    if (lv.cells) {
-      DISPATCH_CELL_GL(lv.mcGL, {
-        hipLaunchKernelGGL((dev::k_cell_residual_mc<T, D, K, GL>), dim3(lv.ncells),
-                           dim3((1 << D) * GL), 0, st, lv.cell_ptr, LevelMats<T>::L(lv),
-                           LevelMats<T>::U(lv), LevelMats<T>::cellM(lv), s, x, r);
-      });
-    } else {
-      DISPATCH_POINT_GL(lv.mcGL, {
-        hipLaunchKernelGGL((dev::k_residual_upper_mc<T, D, K, GL>),
-                           dim3(grid_for(lv.n, dev::kBlock / GL)), dim3(dev::kBlock), 0, st, lv.n,
-                           LevelMats<T>::U(lv), LevelMats<T>::diag(lv), s, x, r);
-      });
-    }
+    launch_residual_mc<T, D, K>(lv, s, x, r, st);
     const dim3 rgrid(grid_for(lv.nnext, dev::kBlock / K));
     if (l == 0)
       hipLaunchKernelGGL((dev::k_restrict_mc<T, D, K, dev::Pad<D>::value>), rgrid, dim3(dev::kBlock),
@@ -2110,6 +2133,66 @@ bool device_available();
 
 // Device upload of a host-built hierarchy (+ block vectors, autotuning).
 // alloc_stream != NULL: allocations are stream-ordered on it.
+// Block right-hand sides: lanes per block row of each level (narrow or wide
+// groups) by timing the level's own block kernels (forward zero-guess sweep,
+// residual, backward sweep; on the fine level also the block SpMV, which shares
+// the setting); the fastest median of three wins.
+template <typename T, int D, int K>
+double time_level_mc(vasmg_ctx& C, int l, hipStream_t st) {
+  DevLevel& lv = C.lev[l];
+  T* b = static_cast<T*>(C.kb[l]);
+  T* x = static_cast<T*>(C.kx[l]);
+  T* s = static_cast<T*>(C.ks[l]);
+  T* r = static_cast<T*>(C.kr[l]);
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  std::vector<float> t;
+  for (int rep = 0; rep < 4; ++rep) {
+    HIP_CHECK(hipEventRecord(e0, st));
+    launch_gs_sweep_mc<T, D, K>(lv, false, true, b, x, s, st);
+    launch_residual_mc<T, D, K>(lv, s, x, r, st);
+    launch_gs_sweep_mc<T, D, K>(lv, true, false, b, x, s, st);
+    if (l == 0) launch_spmv_mc<D, K>(C, C.kP, C.kQ, nullptr, st);
+    HIP_CHECK(hipEventRecord(e1, st));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+template <int D, int K>
+void autotune_block(vasmg_ctx& C) {
+  hipStream_t st = C.cap_stream;
+  for (int l = 0; l < C.L; ++l) {
+    DevLevel& lv = C.lev[l];
+    const bool fine64 = l == 0 && !C.vc32;
+    int best_gl = lv.mcGL;
+    double best = 1e30;
+    const int opts[2] = {lv.cells ? dev::kCellLanesNarrow : dev::kPointLanesNarrow,
+                         lv.cells ? dev::kCellLanesWide : dev::kPointLanesWide};
+    for (int gl : opts) {
+      lv.mcGL = gl;
+      const double ms = (C.vc32 && !fine64) ? time_level_mc<float, D, K>(C, l, st)
+                                            : time_level_mc<double, D, K>(C, l, st);
+      if (ms < best) {
+        best = ms;
+        best_gl = gl;
+      }
+    }
+    lv.mcGL = best_gl;
+    if (C.opt.verbose)
+      std::fprintf(stderr, "[vasmg] autotune block level %d: %d lanes per row (%.3f ms)\n", l, best_gl,
+                   best);
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
   if (!device_available()) throw vasmg::Error{VASMG_EDEVICE, "no HIP device available"};
   HIP_CHECK(hipGetDevice(&C.device));
@@ -2121,6 +2204,13 @@ void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
       autotune<2>(C);
     else
       autotune<3>(C);
+    if (C.K > 0) {
+      if (C.d == 2) {
+        DISPATCH_K(C.K, { autotune_block<2, KK>(C); });
+      } else {
+        DISPATCH_K(C.K, { autotune_block<3, KK>(C); });
+      }
+    }
   }
   // The PCG graphs are captured here, after the lanes per row are final, and not
   // at the first solve: a solve then instantiates and allocates nothing.

@@ -96,6 +96,25 @@ def test_block_mixed_matches_single_column_solves(dim):
     single.free()
 
 
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+def test_block_autotuned_lanes_match_oracle_per_column(prec):
+    """With autotune = 1 the block kernels' lanes per row are timed per level
+    (narrow or wide groups); every column still meets its own oracle solve's bars
+    (FP64 1e-8, FP32 V-cycle 1e-5; +-1 iteration)."""
+    m = small3d(9, seed=5)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="off"))
+    s = V.Solver.from_mesh(m, precision=prec, block_rhs=16, autotune=1)
+    F = np.stack(_loads(m, 16))
+    X, infos = s.solve(F, 1e-6)
+    for c in (0, 7, 15):
+        xo, io = o.solve(F[c], 1e-6)
+        err = np.linalg.norm(X[c] - xo) / np.linalg.norm(xo)
+        assert infos[c]["converged"] == 1 and infos[c]["rel_res_true"] < 1e-6
+        assert abs(infos[c]["iterations"] - io["iterations"]) <= 1
+        assert err < (1e-8 if prec == V.FP64 else 1e-5), (c, err)
+    s.free()
+
+
 def test_block_zero_column_and_initial_guess():
     m, o, s = _setup(3, V.FP64, 4)
     F = np.stack(_loads(m, 4))
