@@ -392,7 +392,8 @@ vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_
 /* Wall-clock milliseconds of the setup phases, in the order they ran (names
  * such as "validate+assemble", "tree", "P0", "coarse regions+P" for the host
  * tree and prolongations, "tree+P (device)" when setup_device = 1 built them
- * on the device, "galerkin", "cells+colours", "coarsest factor", then
+ * on the device, "galerkin" — "galerkin (+ordering)" when the device products
+ * run beside the host's cells and colours —, "cells+colours", "coarsest factor", then
  * "upload" or "upload+autotune" unless host_only). Writes up to
  * max_out entries (name NUL-terminated, truncated to 31 characters) and the
  * number of phases to *n_out. */

@@ -254,6 +254,8 @@ struct GalerkinDevice {
   int window = gal::kMaxWindowCols;
   const BlockCSR* cached = nullptr;   // host operator of the last resident level
   std::vector<gal::DevCsr> lev;       // resident canonical operators, by level
+  std::vector<gal::DevCsr> adopted;   // prolongations built on the device, by level
+  std::vector<int64_t> adopted_cols;
   struct Pending {
     int level;
     BlockCSR* host;
@@ -270,6 +272,7 @@ struct GalerkinDevice {
   ~GalerkinDevice() {
     join();   // downloads not started by now are not needed
     for (auto& L : lev) L.release(st);
+    for (auto& P : adopted) P.release(st);
     if (st) (void)hipStreamSynchronize(st);
     if (st) (void)hipStreamDestroy(st);
     if (dl) (void)hipStreamDestroy(dl);
@@ -373,17 +376,37 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     throw Error{VASMG_EINVAL, "internal: device Galerkin products out of level order"};
   }
   const DevCsr& dA = G.lev.back();
-  // P and its transpose (rows = coarse vertices), built on the host: <= 2^d
+  const size_t l = G.lev.size() - 1;
+  DevCsr dP, dPT, AP, C;
+  if (l < G.adopted.size() && G.adopted[l].ptr && G.adopted[l].nrows == P.nrows &&
+      G.adopted[l].nnz == static_cast<int64_t>(P.col.size()) && G.adopted_cols[l] == P.ncols) {
+    // P already on the device (device tree build): its transpose built there too
+    dP = G.adopted[l];
+    G.adopted[l] = DevCsr();
+    dPT.nrows = P.ncols;
+    dPT.nnz = dP.nnz;
+    try {
+      dPT.ptr = dmalloc<int64_t>(P.ncols + 1, st, "rowptr");
+      dPT.col = dmalloc<int32_t>(dP.nnz, st, "columns");
+      dPT.val = dmalloc<double>(dP.nnz, st, "values");
+      transpose_device(st, dP.nrows, P.ncols, dP.nnz, dP.ptr, dP.col, dP.val, dPT.ptr, dPT.col, dPT.val);
+    } catch (...) {
+      dP.release(st);
+      dPT.release(st);
+      throw;
+    }
+  }
+  // else P and its transpose (rows = coarse vertices), built on the host: <= 2^d
   // entries per P row
   ScalarCSR PT;
-  PT.nrows = P.ncols;
-  PT.ncols = P.nrows;
-  PT.rowptr.assign(P.ncols + 1, 0);
-  for (int32_t c : P.col) PT.rowptr[c + 1]++;
-  for (int64_t r = 0; r < P.ncols; ++r) PT.rowptr[r + 1] += PT.rowptr[r];
-  PT.col.resize(P.col.size());
-  PT.val.resize(P.col.size());
-  {
+  if (!dP.ptr) {
+    PT.nrows = P.ncols;
+    PT.ncols = P.nrows;
+    PT.rowptr.assign(P.ncols + 1, 0);
+    for (int32_t c : P.col) PT.rowptr[c + 1]++;
+    for (int64_t r = 0; r < P.ncols; ++r) PT.rowptr[r + 1] += PT.rowptr[r];
+    PT.col.resize(P.col.size());
+    PT.val.resize(P.col.size());
     std::vector<int64_t> fill(PT.rowptr.begin(), PT.rowptr.end() - 1);
     for (int64_t r = 0; r < P.nrows; ++r)
       for (int64_t p = P.rowptr[r]; p < P.rowptr[r + 1]; ++p) {
@@ -392,10 +415,11 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
         PT.val[q] = P.val[p];
       }
   }
-  DevCsr dP, dPT, AP, C;
   try {
-    upload(dP, P.nrows, P.rowptr, P.col, P.val, st);
-    upload(dPT, PT.nrows, PT.rowptr, PT.col, PT.val, st);
+    if (!dP.ptr) {
+      upload(dP, P.nrows, P.rowptr, P.col, P.val, st);
+      upload(dPT, PT.nrows, PT.rowptr, PT.col, PT.val, st);
+    }
     product<D, true>(G, dA, dP, P.ncols, AP);
     product<D, false>(G, dPT, AP, P.ncols, C);
     Ac.n = P.ncols;
@@ -765,6 +789,23 @@ GalerkinDevice* galerkin_device_create(int window_cols) {
 
 void galerkin_device_destroy(GalerkinDevice* G) { delete G; }
 
+void galerkin_device_adopt_prolongation(GalerkinDevice* G, int level, int64_t nrows, int64_t ncols,
+                                        int64_t nnz, int64_t* ptr, int32_t* col, double* val) {
+  if (level < 0) return;
+  if (static_cast<size_t>(level) >= G->adopted.size()) {
+    G->adopted.resize(level + 1);
+    G->adopted_cols.resize(level + 1, 0);
+  }
+  G->adopted[level].release(G->st);
+  gal::DevCsr& D = G->adopted[level];
+  D.nrows = nrows;
+  D.nnz = nnz;
+  D.ptr = ptr;
+  D.col = col;
+  D.val = val;
+  G->adopted_cols[level] = ncols;
+}
+
 void galerkin_device(void* ctx, const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac, bool coarsest) {
   auto& G = *static_cast<GalerkinDevice*>(ctx);
   if (A.d == 2)
@@ -782,9 +823,6 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
   hipStream_t st = G.st;
   const int d = m.d, nvpe = d + 1, dd = d * d;
   const int n = static_cast<int>(nfree);
-  std::vector<int64_t> vptr, velem64;
-  vertex_elements(m, vptr, velem64);
-  std::vector<int32_t> velem(velem64.begin(), velem64.end());
   std::vector<int32_t> f2m(nfree);
   for (int64_t v = 0; v < m.nv; ++v)
     if (vfree[v] >= 0) f2m[vfree[v]] = static_cast<int32_t>(v);
@@ -805,8 +843,15 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
     M.nu = gal::upload_temp(m.nu, static_cast<size_t>(m.ne), st, owned);
     M.vfree = gal::upload_temp(vfree, st, owned);
     M.fine2mesh = gal::upload_temp(f2m, st, owned);
-    M.vptr = gal::upload_temp(vptr, st, owned);
-    M.velem = gal::upload_temp(velem, st, owned);
+    {   // vertex -> element lists, built on the device
+      int64_t* vp = gal::dmalloc<int64_t>(m.nv + 1, st, "vertex elements");
+      owned.push_back(vp);
+      int32_t* ve = gal::dmalloc<int32_t>(m.ne * nvpe, st, "vertex elements");
+      owned.push_back(ve);
+      vertex_elements_device(st, M.elems, m.ne, nvpe, m.nv, vp, ve);
+      M.vptr = vp;
+      M.velem = ve;
+    }
     const int grid = (n + gal::kWaves - 1) / gal::kWaves;
     int64_t* cnt = gal::dmalloc<int64_t>(n, st, "row counts");
     owned.push_back(cnt);

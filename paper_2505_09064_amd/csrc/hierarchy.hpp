@@ -151,6 +151,22 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
                      int64_t nfree, BlockCSR& A);
 // SettleFn: joins every download.
 void galerkin_device_settle(void* ctx);
+// Takes ownership of level l's prolongation on the device (stream-ordered
+// allocations on the context's stream; int64 row pointers, int32 columns, FP64
+// weights): the product from level l then uses it (and its transpose, built on
+// the device) instead of uploading the host copy.
+void galerkin_device_adopt_prolongation(GalerkinDevice* g, int level, int64_t nrows, int64_t ncols,
+                                        int64_t nnz, int64_t* ptr, int32_t* col, double* val);
+// Transpose of a scalar CSR matrix on the device (tree.hip): the entries of each
+// column in row order, as a sequential transpose gives them. Device pointers,
+// enqueued on stream.
+void transpose_device(void* stream, int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* ptr,
+                      const int32_t* col, const double* val, int64_t* tptr, int32_t* tcol, double* tval);
+// Vertex -> element lists of a mesh on the device (tree.hip), as the host's
+// vertex_elements (elements ascending per vertex): elems [ne][nvpe], vptr
+// [nv + 1], velem [ne * nvpe], device pointers; enqueued on stream.
+void vertex_elements_device(void* stream, const int32_t* elems, int64_t ne, int nvpe, int64_t nv,
+                            int64_t* vptr, int32_t* velem);
 // TransfersFn on the device (tree.hip), on the context's stream: false for trees
 // deeper than packed 64-bit lattice keys allow (21 levels in 3D, 32 in 2D).
 bool transfers_device(void* ctx, const MeshView& m, const std::vector<int32_t>& tree_vtx,

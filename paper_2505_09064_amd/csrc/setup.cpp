@@ -31,7 +31,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 #include "hierarchy.hpp"
@@ -1110,28 +1112,54 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     if (any) c.fixed.swap(cm);
   }
   if (!H.levels[0].fixed.empty()) mark("coarse constraints");
-  // ---- Galerkin operators, with optional truncation of the hierarchy
+  // ---- Galerkin operators, with optional truncation of the hierarchy. With the
+  // products on the device, each level's Gauss-Seidel order (which needs only its
+  // own structure) is built on a host thread of its own while the product from
+  // that level runs.
   size_t nlev = H.levels.size();
+  std::vector<std::thread> order_threads;
+  struct JoinAll {   // joined on every exit, exceptions from the products included
+    std::vector<std::thread>& t;
+    ~JoinAll() {
+      for (auto& x : t)
+        if (x.joinable()) x.join();
+    }
+  } join_guard{order_threads};
+  std::vector<std::exception_ptr> order_err(nlev);
+  const int nth = omp_get_max_threads();
   for (size_t l = 0; l + 1 < nlev; ++l) {
     if (prm.coarsest_max_dofs > 0 && H.levels[l].n * d <= prm.coarsest_max_dofs) {
       nlev = l + 1;
       break;
     }
     if (prm.galerkin) {
+      order_threads.emplace_back([&, l] {
+        try {
+          omp_set_num_threads(nth);
+          build_gs_order(H.levels[l], l > 0, d, prm.color_blocks);
+        } catch (...) {
+          order_err[l] = std::current_exception();
+        }
+      });
       const bool coarsest =
           l + 2 == nlev || (prm.coarsest_max_dofs > 0 && H.levels[l + 1].n * d <= prm.coarsest_max_dofs);
       prm.galerkin(prm.galerkin_ctx, H.levels[l].A, H.levels[l].P, H.levels[l + 1].A, coarsest);
     } else
       galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
   }
+  if (!order_threads.empty()) mark("galerkin (+ordering)");
+  for (auto& t : order_threads) t.join();
+  for (const auto& e : order_err)
+    if (e) std::rethrow_exception(e);
+  if (order_threads.empty()) mark("galerkin");
   H.levels.resize(nlev);
-  mark("galerkin");
   Level& coarsest = H.levels.back();
   coarsest.P = ScalarCSR();
   coarsest.color.assign(coarsest.n, 0);
   coarsest.ncolors = 0;
-  for (size_t l = 0; l + 1 < H.levels.size(); ++l)
-    build_gs_order(H.levels[l], l > 0, d, prm.color_blocks);
+  if (order_threads.empty())
+    for (size_t l = 0; l + 1 < H.levels.size(); ++l)
+      build_gs_order(H.levels[l], l > 0, d, prm.color_blocks);
   mark("cells+colours");
   if (prm.settle && coarsest.A.val.size() != coarsest.A.col.size() * static_cast<size_t>(d * d))
     prm.settle(prm.galerkin_ctx);   // a fine level that is also the coarsest: its values now

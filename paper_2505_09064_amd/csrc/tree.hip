@@ -529,7 +529,7 @@ void download(std::vector<T>& h, const T* d, int64_t n, hipStream_t st) {
 }
 
 template <int D>
-bool build(hipStream_t st, const MeshView& mesh, const std::vector<int32_t>& tree_vtx,
+bool build(GalerkinDevice* g, hipStream_t st, const MeshView& mesh, const std::vector<int32_t>& tree_vtx,
            const std::vector<int32_t>& free_vertices, const std::vector<int32_t>& pos_in_tree,
            int cap, Transfers& out) {
   const int64_t N = static_cast<int64_t>(tree_vtx.size());
@@ -695,6 +695,25 @@ bool build(hipStream_t st, const MeshView& mesh, const std::vector<int32_t>& tre
       download(H.val, P.val, P.nnz, st);
     }
   }
+  // device copies of the prolongations for the Galerkin products (owned by the
+  // context from here on)
+  for (int l = 0; l + 1 < L; ++l) {
+    const DevP& P = levels[l].P;
+    int64_t* ptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    check(hipMallocAsync(reinterpret_cast<void**>(&ptr), (P.nrows + 1) * sizeof(int64_t), st), "allocation");
+    check(hipMallocAsync(reinterpret_cast<void**>(&col), std::max<int64_t>(P.nnz, 1) * sizeof(int32_t), st),
+          "allocation");
+    check(hipMallocAsync(reinterpret_cast<void**>(&val), std::max<int64_t>(P.nnz, 1) * sizeof(double), st),
+          "allocation");
+    check(hipMemcpyAsync(ptr, P.ptr, (P.nrows + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
+    if (P.nnz > 0) {
+      check(hipMemcpyAsync(col, P.col, P.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "copy");
+      check(hipMemcpyAsync(val, P.val, P.nnz * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    }
+    galerkin_device_adopt_prolongation(g, l, P.nrows, P.ncols, P.nnz, ptr, col, val);
+  }
   check(hipStreamSynchronize(st), "download");
   const int sh = kKeyBits - B;
   for (int l = 1; l < L; ++l) {
@@ -709,15 +728,113 @@ bool build(hipStream_t st, const MeshView& mesh, const std::vector<int32_t>& tre
   return true;
 }
 
+// ---- vertex -> element lists (the host's vertex_elements, elements ascending)
+__global__ void k_ve_count(int64_t nslots, const int32_t* __restrict__ elems,
+                           unsigned long long* __restrict__ cnt) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (q < nslots) atomicAdd(&cnt[elems[q]], 1ull);
+}
+
+__global__ void k_ve_fill(int64_t nslots, int nvpe, const int32_t* __restrict__ elems,
+                          const int64_t* __restrict__ vptr, int* __restrict__ fill,
+                          int32_t* __restrict__ velem) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (q >= nslots) return;
+  const int32_t v = elems[q];
+  velem[vptr[v] + atomicAdd(&fill[v], 1)] = static_cast<int32_t>(q / nvpe);
+}
+
+// each vertex's list in ascending element order (the slots were claimed in any order)
+__global__ void k_ve_sort(int64_t nv, const int64_t* __restrict__ vptr, int32_t* __restrict__ velem) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (v >= nv) return;
+  const int64_t b = vptr[v], e = vptr[v + 1];
+  for (int64_t i = b + 1; i < e; ++i) {
+    const int32_t t = velem[i];
+    int64_t j = i;
+    while (j > b && velem[j - 1] > t) {
+      velem[j] = velem[j - 1];
+      --j;
+    }
+    velem[j] = t;
+  }
+}
+
+// ---- transpose of a scalar CSR matrix
+__global__ void k_row_of(int64_t nrows, const int64_t* __restrict__ ptr, int32_t* __restrict__ row) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (r >= nrows) return;
+  for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) row[p] = static_cast<int32_t>(r);
+}
+
+__global__ void k_count_cols(int64_t nnz, const int32_t* __restrict__ col, unsigned long long* __restrict__ cnt) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (p < nnz) atomicAdd(&cnt[col[p]], 1ull);
+}
+
+__global__ void k_gather_transposed(int64_t nnz, const int32_t* __restrict__ order,
+                                    const int32_t* __restrict__ row, const double* __restrict__ val,
+                                    int32_t* __restrict__ tcol, double* __restrict__ tval) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (q >= nnz) return;
+  const int32_t p = order[q];
+  tcol[q] = row[p];
+  tval[q] = val[p];
+}
+
 }  // namespace tree
+
+void transpose_device(void* stream, int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* ptr,
+                      const int32_t* col, const double* val, int64_t* tptr, int32_t* tcol, double* tval) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  tree::Arena A(st);
+  tree::check(hipMemsetAsync(tptr, 0, sizeof(int64_t), st), "clear");
+  if (nnz > 0) {
+    int32_t* row = A.get<int32_t>(nnz);
+    tree::k_row_of<<<tree::grid_for(nrows), tree::kThreads, 0, st>>>(nrows, ptr, row);
+    int32_t* idx = A.get<int32_t>(nnz);
+    tree::k_iota<<<tree::grid_for(nnz), tree::kThreads, 0, st>>>(nnz, idx);
+    // entries by column, stably (row order kept inside a column); columns >= 0
+    uint32_t* ks = A.get<uint32_t>(nnz);
+    int32_t* order = A.get<int32_t>(nnz);
+    int bits = 1;
+    while ((int64_t(1) << bits) < ncols) ++bits;
+    tree::sort_pairs(A, reinterpret_cast<const uint32_t*>(col), ks, idx, order, nnz, bits);
+    tree::k_gather_transposed<<<tree::grid_for(nnz), tree::kThreads, 0, st>>>(nnz, order, row, val, tcol, tval);
+  }
+  if (ncols > 0) {
+    auto* cnt = A.get<unsigned long long>(ncols);
+    tree::check(hipMemsetAsync(cnt, 0, ncols * sizeof(unsigned long long), st), "clear");
+    if (nnz > 0) tree::k_count_cols<<<tree::grid_for(nnz), tree::kThreads, 0, st>>>(nnz, col, cnt);
+    tree::inclusive_sum(A, reinterpret_cast<const int64_t*>(cnt), tptr + 1, ncols);
+  }
+  tree::check(hipGetLastError(), "launch");
+}
+
+void vertex_elements_device(void* stream, const int32_t* elems, int64_t ne, int nvpe, int64_t nv,
+                            int64_t* vptr, int32_t* velem) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  tree::Arena A(st);
+  const int64_t ns = ne * nvpe;
+  auto* cnt = A.get<unsigned long long>(nv);
+  int* fill = A.get<int>(nv);
+  tree::check(hipMemsetAsync(cnt, 0, nv * sizeof(unsigned long long), st), "clear");
+  tree::check(hipMemsetAsync(fill, 0, nv * sizeof(int), st), "clear");
+  tree::check(hipMemsetAsync(vptr, 0, sizeof(int64_t), st), "clear");
+  tree::k_ve_count<<<tree::grid_for(ns), tree::kThreads, 0, st>>>(ns, elems, cnt);
+  tree::inclusive_sum(A, reinterpret_cast<const int64_t*>(cnt), vptr + 1, nv);
+  tree::k_ve_fill<<<tree::grid_for(ns), tree::kThreads, 0, st>>>(ns, nvpe, elems, vptr, fill, velem);
+  tree::k_ve_sort<<<tree::grid_for(nv), tree::kThreads, 0, st>>>(nv, vptr, velem);
+  tree::check(hipGetLastError(), "launch");
+}
 
 bool transfers_device(void* ctx, const MeshView& m, const std::vector<int32_t>& tree_vtx,
                       const std::vector<int32_t>& free_vertices, const std::vector<int32_t>& pos_in_tree,
                       int capacity, Transfers& out) {
   auto* g = static_cast<GalerkinDevice*>(ctx);
   hipStream_t st = static_cast<hipStream_t>(galerkin_device_stream(g));
-  if (m.d == 3) return tree::build<3>(st, m, tree_vtx, free_vertices, pos_in_tree, capacity, out);
-  return tree::build<2>(st, m, tree_vtx, free_vertices, pos_in_tree, capacity, out);
+  if (m.d == 3) return tree::build<3>(g, st, m, tree_vtx, free_vertices, pos_in_tree, capacity, out);
+  return tree::build<2>(g, st, m, tree_vtx, free_vertices, pos_in_tree, capacity, out);
 }
 
 }  // namespace vasmg
