@@ -559,9 +559,16 @@ def main():
     dev_setup = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, setup_device=1,
                                    autotune=0 if args.no_autotune else 1)
     t_setup_dev = time.perf_counter() - t0
-    dev_phases = {n: round(ms, 2) for n, ms in dev_setup.setup_phases()}
     dev_info = dev_setup.solve_device(d_rhs, d_x, 1e-6)
     dev_setup.free()
+    # a second device setup (the kernels loaded by now, autotune off): the cost a
+    # serving process pays per request of this size
+    t0 = time.perf_counter()
+    dev2 = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, setup_device=1, autotune=0)
+    t_setup_dev2 = time.perf_counter() - t0
+    dev_phases = {n: round(ms, 2) for n, ms in dev2.setup_phases()}
+    dev2.free()
+    log(f"setup (mixed, device, second, autotune off) {t_setup_dev2:.3f}s: {dev_phases}")
     log(f"setup (mixed, device Galerkin + layout) {t_setup_dev:.2f}s, "
         f"{dev_info['iterations']} its")
     for i in range(args.warmup):
@@ -726,7 +733,8 @@ def main():
         "rel_res_true": info["rel_res_true"],
         "setup_s": t_setup,
         "setup_device_s": t_setup_dev,
-        "setup_device_phases_ms": dev_phases,
+        "setup_device_warm_s": t_setup_dev2,
+        "setup_device_warm_phases_ms": dev_phases,
         "setup_device_iterations": dev_info["iterations"],
         "timed_region_s": t_total,
         "iteration_ms_profiled": it_ms,
