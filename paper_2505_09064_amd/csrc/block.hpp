@@ -26,13 +26,23 @@ namespace dev {
 constexpr int kPointLanesNarrow = 16, kPointLanesWide = 64;
 constexpr int kCellLanesNarrow = 32, kCellLanesWide = 64;
 
-// D components at stride VS: aligned vector loads at the padded stride, else
-// component loads.
+// Three consecutive FP32 values at 4-byte alignment: one 12-byte load.
+struct alignas(4) Float3 {
+  float a, b, c;
+};
+
+// D components at stride VS: aligned vector loads at the padded stride, one
+// 12-byte load for packed 3D FP32 components, else component loads.
 template <typename T, int D, int VS>
 struct BlockVecIO {
   static __device__ __forceinline__ void load(const T* p, T* v) {
     if constexpr (VS == Pad<D>::value) {
       VecIO<T, D>::load(p, v);
+    } else if constexpr (sizeof(T) == 4 && D == 3) {
+      const Float3 f = *reinterpret_cast<const Float3*>(p);
+      v[0] = f.a;
+      v[1] = f.b;
+      v[2] = f.c;
     } else {
 #pragma unroll
       for (int a = 0; a < D; ++a) v[a] = p[a];
