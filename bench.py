@@ -155,6 +155,32 @@ def bench_block16(args, V, torch):
         "max_rel_res_true": float(max(i["rel_res_true"] for i in ib))}), flush=True)
 
 
+def bench_setup(args, V, torch):
+    """Device setup of the 65^3 workload (setup_device = 1, FP32 V-cycle, autotune
+    off), three times in one process: the first loads the kernels, the later
+    ones are what a serving process pays per request of this size."""
+    from workloads import cfg2
+    mesh = cfg2()
+    times, phases = [], []
+    for rep in range(3):
+        t0 = time.perf_counter()
+        s = V.Solver.from_mesh(mesh, precision=V.FP32_PRECOND, setup_device=1, autotune=0)
+        times.append(time.perf_counter() - t0)
+        phases.append({n: round(ms, 2) for n, ms in s.setup_phases()})
+        s.free()
+        log(f"setup {rep}: {1e3 * times[-1]:.1f} ms {phases[-1]}")
+    warm = float(np.median(times[1:]))
+    print(json.dumps({
+        "metric": "V-ASMG device setup time (fine assembly, tree, prolongations, Galerkin "
+                  "products, colouring, layouts)", "value": warm, "unit": "s",
+        "n_gpus": 1, "steps": 2, "warmup": 1, "ms_per_step": 1e3 * warm, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (setup)", "data": "synthetic",
+        "config": {"workload": "3D P1 elasticity, 65^3 jittered Kuhn mesh (seed 1), clamped x=0, "
+                               "811,200 DOFs, setup_device=1, autotune off",
+                   "n_dofs": mesh.n_dofs},
+        "first_setup_s": times[0], "setup_s": times, "phases_ms": phases}), flush=True)
+
+
 def bench_cfg3(args, V, torch):
     """The 2D nearly incompressible graded workload: 1025^2 vertices with the map
     x -> x^2, y -> y^2, nu = 0.49, E in {1, 100} on a random 8x8 checkerboard
@@ -488,13 +514,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--workload", choices=["cfg2", "cfg3", "block16", "cfg4", "serve"],
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "block16", "cfg4", "serve", "setup"],
                     default="cfg2",
                     help="cfg2: the headline 65^3 workload (default); cfg3: the graded 2D "
                          "nu=0.49 workload, mixed vs FP64; cfg4: 129^3 with 16 load "
                          "cases, block solve against column-by-column solves; block16: the 65^3 mesh with "
                          "16 load cases, block solve only; serve: the request stream through the "
-                         "continuous-batching server")
+                         "continuous-batching server; setup: three device setups of the 65^3 workload")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving leg reported among the headline's variants")
@@ -525,6 +551,9 @@ def main():
         return
     if args.workload == "cfg3":
         bench_cfg3(args, V, torch)
+        return
+    if args.workload == "setup":
+        bench_setup(args, V, torch)
         return
     if args.workload == "serve":
         bench_serve(args, V)
