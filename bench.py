@@ -47,6 +47,14 @@ def traffic_per_launch():
     return None
 
 
+def device_info(torch):
+    """The GPU the benchmark ran on, as the runtime reports it (the roofline's
+    peak assumes an MI355X: 256 compute units, 8 TB/s HBM3E)."""
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count, "memory_gib": round(p.total_memory / 2**30, 1)}
+
+
 def host_cpu():
     """Core count and CPU model of the machine the benchmark runs on."""
     model = None
@@ -774,6 +782,7 @@ def main():
                      "kernel": f"{dom['name']} on level {dom['level']}",
                      "launch_us": dom_launch_ms * 1e3, "launch_bytes": dom_launch_bytes},
         "cpu_baseline": cpu,
+        "device": device_info(torch),
         "variants": variants,
     }
     print(json.dumps(line), flush=True)
