@@ -215,3 +215,19 @@ def test_binding_refuses_tensors_it_cannot_pass_safely():
         _check_tensor(np.zeros((4, 3)), (4, 3), "d_x")
     with pytest.raises(ValueError, match="torch tensor"):
         _check_tensor(None, (4, 3), "d_x")
+
+
+def test_setup_phases_of_a_host_setup():
+    """vasmg_setup_phases reports the host setup's phases in the order they ran
+    (the host tree and prolongations, then the products and the ordering), with
+    non-negative wall-clock times; a partially constrained mesh adds the coarse
+    constraint phase."""
+    s = V.Solver.from_mesh(small3d(7, seed=2), host_only=1)
+    ph = s.setup_phases()
+    assert [n for n, _ in ph] == ["validate+assemble", "tree", "P0", "coarse regions+P", "galerkin",
+                                  "cells+colours", "coarsest factor"]
+    assert all(ms >= 0.0 for _, ms in ph)
+    s.free()
+    s = V.Solver.from_mesh(small3d(7, seed=3, fix="roller_x1"), host_only=1)
+    assert "coarse constraints" in [n for n, _ in s.setup_phases()]
+    s.free()
