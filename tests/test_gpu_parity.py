@@ -634,3 +634,28 @@ def test_full_vector_parity_on_full_size_paths(name):
             assert abs(info["iterations"] - io32["iterations"]) <= 1
             assert err_inf <= 1e-5
         s.free()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small3d_rollers"])
+@pytest.mark.parametrize("prec", [V.FP64, V.FP32_PRECOND])
+def test_accuracy_against_direct_solve(name, prec):
+    """The solution against a sparse direct solve of the same system (the
+    accuracy metric ||x - x_ref|| / ||x_ref||, x_ref from SciPy's spsolve on the
+    oracle's operator): within kappa(A) * rtol for rtol 1e-6 and 1e-10 (the
+    stopping rule bounds the relative residual; kappa from the dense spectrum),
+    and tightening the tolerance tightens the error."""
+    m = cfg1() if name == "cfg1" else small3d(7, seed=3, fix="roller_x1")
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    F = m.rhs[0]
+    xr = o.direct_solve(F)
+    ev = np.linalg.eigvalsh(o.A[0].toarray())
+    kappa = ev[-1] / ev[0]
+    errs = []
+    with V.Solver.from_mesh(m, precision=prec) as s:
+        for rtol in (1e-6, 1e-10):
+            x, info = s.solve(F, rtol)
+            assert info["converged"] == 1 and info["rel_res_true"] < rtol
+            err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+            assert err <= kappa * rtol, (rtol, err, kappa)
+            errs.append(err)
+    assert errs[1] < errs[0]
