@@ -299,6 +299,15 @@ typedef struct {
   int32_t pack_wait_ms;        /* batching window, 0..10000 (default 0): a slot holding a
                                   packable request waits up to this long for more while
                                   setups are still running                               */
+  int32_t host_setup_max_dofs_2d; /* with options.setup_device = 1: a request of at most
+                                  this many DOFs (n_vertices * dim, fixed ones included)
+                                  is set up on the host all the same, where the device
+                                  setup's fixed costs (launches, host round trips of the
+                                  tree's rounds, allocations) exceed the host's work;
+                                  >= 0, default 131072 (2D) and 16384 (3D). Both setups
+                                  build the same hierarchy (the Galerkin products to
+                                  rounding)                                              */
+  int32_t host_setup_max_dofs_3d;
   int32_t reserved;
 } vasmg_server_config;
 
@@ -309,7 +318,7 @@ typedef struct {
   int32_t slot;                /* device slot that ran it (-1: none)                      */
   int32_t pack_size;           /* requests solved together with it in one packed solve,
                                   itself included (1: alone, 0: never admitted)          */
-  int32_t reserved;
+  int32_t setup_device;        /* 1: its hierarchy was built by the device setup          */
   int64_t device_bytes;        /* device bytes it held while resident                     */
   double t_submit_ms, t_setup_start_ms, t_setup_end_ms, t_admit_ms, t_done_ms;
                                /* server clock (ms since vasmg_server_create)             */

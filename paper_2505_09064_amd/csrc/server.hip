@@ -119,6 +119,10 @@ struct vasmg_server {
       vasmg_options o = cfg.options;
       o.host_only = 1;
       o.block_rhs = 0;
+      const int64_t mesh_dofs = static_cast<int64_t>(r->nv) * r->dim;
+      if (mesh_dofs <= (r->dim == 2 ? cfg.host_setup_max_dofs_2d : cfg.host_setup_max_dofs_3d))
+        o.setup_device = 0;
+      r->res.setup_device = o.setup_device ? 1 : 0;
       vasmg_handle h = nullptr;
       int st = vasmg_setup(&m, &o, &h);
       if (st != VASMG_OK) note(r, "setup", vasmg_last_error());
@@ -385,6 +389,8 @@ vasmg_status vasmg_server_default_config(vasmg_server_config* cfg) {
   cfg->pack_max_dofs = 0;
   cfg->pack_max_parts = 16;
   cfg->pack_wait_ms = 0;
+  cfg->host_setup_max_dofs_2d = 131072;
+  cfg->host_setup_max_dofs_3d = 16384;
   const vasmg_status st = vasmg_default_options(3, &cfg->options);
   cfg->options.leaf_capacity = 0;          // each request: its dimension's default
   return st;
@@ -395,7 +401,8 @@ vasmg_status vasmg_server_create(const vasmg_server_config* cfg, vasmg_server_ha
   *out = nullptr;
   if (cfg->slots < 1 || cfg->slots > 64 || cfg->setup_workers < 1 || cfg->setup_workers > 64 ||
       cfg->hbm_budget_bytes < 0 || cfg->pack_max_dofs < 0 || cfg->pack_max_parts < 0 ||
-      cfg->pack_max_parts > 256 || cfg->pack_wait_ms < 0 || cfg->pack_wait_ms > 10000)
+      cfg->pack_max_parts > 256 || cfg->pack_wait_ms < 0 || cfg->pack_wait_ms > 10000 ||
+      cfg->host_setup_max_dofs_2d < 0 || cfg->host_setup_max_dofs_3d < 0)
     return VASMG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return VASMG_EDEVICE;

@@ -85,12 +85,13 @@ class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_int32), ("setup_workers", C.c_int32),
                 ("hbm_budget_bytes", C.c_int64), ("options", Options),
                 ("pack_max_dofs", C.c_int32), ("pack_max_parts", C.c_int32),
-                ("pack_wait_ms", C.c_int32), ("reserved", C.c_int32)]
+                ("pack_wait_ms", C.c_int32), ("host_setup_max_dofs_2d", C.c_int32),
+                ("host_setup_max_dofs_3d", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RequestResult(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("slot", C.c_int32),
-                ("pack_size", C.c_int32), ("reserved", C.c_int32), ("device_bytes", C.c_int64), ("t_submit_ms", C.c_double),
+                ("pack_size", C.c_int32), ("setup_device", C.c_int32), ("device_bytes", C.c_int64), ("t_submit_ms", C.c_double),
                 ("t_setup_start_ms", C.c_double), ("t_setup_end_ms", C.c_double),
                 ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("info", SolveInfo),
                 ("message", C.c_char * 128)]
@@ -494,12 +495,17 @@ class Server:
     slots' own streams, and collected with wait()."""
 
     def __init__(self, slots: int = 4, setup_workers: int = 4, hbm_budget_bytes: int = 0,
-                 pack_max_dofs: int = 0, pack_max_parts: int = 16, pack_wait_ms: int = 0, **opts):
+                 pack_max_dofs: int = 0, pack_max_parts: int = 16, pack_wait_ms: int = 0,
+                 host_setup_max_dofs=None, **opts):
+        """host_setup_max_dofs: (2D, 3D) DOF limits up to which a request is set
+        up on the host even with setup_device = 1; None: the library's defaults."""
         cfg = ServerConfig()
         _check(lib().vasmg_server_default_config(C.byref(cfg)))
         cfg.slots, cfg.setup_workers, cfg.hbm_budget_bytes = slots, setup_workers, hbm_budget_bytes
         cfg.pack_max_dofs, cfg.pack_max_parts = pack_max_dofs, pack_max_parts
         cfg.pack_wait_ms = pack_wait_ms
+        if host_setup_max_dofs is not None:
+            cfg.host_setup_max_dofs_2d, cfg.host_setup_max_dofs_3d = host_setup_max_dofs
         for k, v in opts.items():
             setattr(cfg.options, k, v)
         h = C.c_void_p()

@@ -92,20 +92,42 @@ def test_device_setup_workers():
     setup_device = 1, transient device memory ordered on each worker's stream)
     while other requests solve and capture graphs: every result equals the same
     request solved alone from a device setup, bit for bit, and takes the
-    iterations of a host setup."""
+    iterations of a host setup. The size limits of the host setup are off here,
+    so every request takes the device setup."""
     reqs = _requests()
-    srv = V.Server(slots=3, setup_workers=3, setup_device=1)
+    srv = V.Server(slots=3, setup_workers=3, setup_device=1, host_setup_max_dofs=(0, 0))
     ids = [srv.submit(m, m.rhs[0], 1e-6) for m in reqs]
     got = [srv.wait(i) for i in ids]
     srv.close()
     for i, (m, (x, res)) in enumerate(zip(reqs, got)):
         assert res["status"] == V.OK, res
+        assert res["setup_device"] == 1
         _check_against_oracle(i, m, x, res["info"], V.FP64)
         xa, ia = _alone(m, setup_device=1)
         assert np.array_equal(x, xa), np.abs(x - xa).max()
         _, ih = _alone(m)
         assert res["info"]["iterations"] == ih["iterations"]
         assert res["info"]["rel_res_true"] < 1e-6
+
+
+def test_small_requests_set_up_on_the_host():
+    """With setup_device = 1, requests at or below the dimension's DOF limit are
+    set up on the host (their results equal the host-setup solve alone, bit for
+    bit) and larger ones on the device (equal to the device-setup solve alone)."""
+    reqs = [small2d(9, seed=1), small3d(5, seed=2), small2d(13, seed=3), small3d(7, seed=4)]
+    lim2, lim3 = 2 * 9 * 9, 3 * 6 * 6 * 6          # 9x9 and 5^3 vertices at or below
+    srv = V.Server(slots=2, setup_workers=2, setup_device=1, host_setup_max_dofs=(lim2, lim3))
+    ids = [srv.submit(m, m.rhs[0], 1e-6) for m in reqs]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    for i, (m, (x, res)) in enumerate(zip(reqs, got)):
+        assert res["status"] == V.OK, res
+        lim = lim2 if m.dim == 2 else lim3
+        on_device = int(m.coords.size > lim)
+        assert res["setup_device"] == on_device, (i, m.coords.size, res["setup_device"])
+        xa, _ = _alone(m, setup_device=on_device)
+        assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
+    assert [r["setup_device"] for _, r in got] == [0, 0, 1, 1]
 
 
 def test_budget_bounds_resident_bytes():
@@ -135,7 +157,8 @@ def test_budget_bounds_resident_bytes():
 
 
 def test_server_config_validation():
-    for kw in (dict(pack_max_dofs=-1), dict(pack_max_parts=300), dict(pack_wait_ms=-5)):
+    for kw in (dict(pack_max_dofs=-1), dict(pack_max_parts=300), dict(pack_wait_ms=-5),
+               dict(host_setup_max_dofs=(-1, 0)), dict(host_setup_max_dofs=(0, -1))):
         with pytest.raises(V.VasmgError) as ei:
             V.Server(slots=1, setup_workers=1, **kw)
         assert ei.value.status == V.EINVAL, kw
