@@ -167,6 +167,19 @@ def test_default_options():
         V.default_options(4)
 
 
+def test_server_default_config():
+    """The documented server defaults (no device needed to read them): 4 slots, 4
+    setup workers, 80% of free memory, packing off, and the host-setup size limits
+    of 131,072 DOFs in 2D and 16,384 in 3D."""
+    cfg = V.ServerConfig()
+    V._check(V.lib().vasmg_server_default_config(V.C.byref(cfg)))
+    assert (cfg.slots, cfg.setup_workers, cfg.hbm_budget_bytes) == (4, 4, 0)
+    assert (cfg.pack_max_dofs, cfg.pack_max_parts, cfg.pack_wait_ms) == (0, 16, 0)
+    assert (cfg.host_setup_max_dofs_2d, cfg.host_setup_max_dofs_3d) == (131072, 16384)
+    assert cfg.options.leaf_capacity == 0 and cfg.options.n_pre == 1
+    assert V.lib().vasmg_server_default_config(None) == V.EINVAL
+
+
 def test_device_bytes_estimate_and_no_device_paths():
     import torch
     m = small3d(7, seed=2)
