@@ -704,7 +704,9 @@ void dense_cholesky(const BlockCSR& A, const std::vector<uint8_t>& fixed, std::v
     double s = M[j * n + j];
     for (int64_t k = 0; k < j; ++k) s -= M[j * n + k] * M[j * n + k];
     if (!(s > 1e-12 * maxdiag) || !std::isfinite(s))
-      fail(6, "coarsest operator is not positive definite (are any DOFs fixed?)");
+      fail(6, "coarsest operator is not positive definite: no DOFs fixed (rigid-body modes), or "
+                "fewer free DOFs than the coarser levels' vertices can take (e.g. a mesh with a "
+                "single free vertex)");
     const double ljj = std::sqrt(s);
     M[j * n + j] = ljj;
     for (int64_t i = j + 1; i < n; ++i) {

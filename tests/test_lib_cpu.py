@@ -144,6 +144,13 @@ def test_setup_rejects_invalid_input():
     for fn in (bad_flag, inverted, bad_nu, bad_E, bad_index, nan_coord, all_fixed, duplicates):
         _expect(V.EINVAL, fn)
     _expect(V.EDEGENERATE, lambda: small2d(6, fix="none"))
+    # one free vertex interpolated from 2^d coarse corners: a rank-d coarsest
+    # operator, refused by the oracle as well
+    for one_free in (lambda: small2d(3, seed=1, fix="boundary"), lambda: small3d(3, seed=1, fix="boundary")):
+        _expect(V.EDEGENERATE, one_free)
+        m = one_free()
+        with pytest.raises(np.linalg.LinAlgError):
+            Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
     _expect(V.EINVAL, lambda: small2d(5), leaf_capacity=-1)
     _expect(V.EINVAL, lambda: small2d(5), block_rhs=5)
 
