@@ -121,6 +121,40 @@ def test_device_tree_matches_host_at_size(name):
     sh.free()
 
 
+def _random_tree_mesh(i):
+    rng = np.random.default_rng(7000 + i)
+    dim = int(rng.integers(2, 4))
+    tie = rng.random() < 0.3          # no jitter, 2^k + 1 vertices: points on midlines
+    if dim == 2:
+        n = int(2 ** rng.integers(2, 7) + 1) if tie else int(rng.integers(4, 90))
+        m = small2d(n, seed=None if tie else int(rng.integers(0, 1000)),
+                    fix=str(rng.choice(["boundary", "x0", "symmetry"])))
+    else:
+        n = int(2 ** rng.integers(2, 5) + 1) if tie else int(rng.integers(3, 26))
+        m = small3d(n, seed=None if tie else int(rng.integers(0, 1000)),
+                    fix=str(rng.choice(["x0", "symmetry", "roller_x1"])))
+    if rng.random() < 0.5:            # clustered points: monotone per-axis maps
+        m.coords = m.coords ** rng.uniform(0.4, 3.0, size=dim)
+    cap = int(rng.choice([0, 0, 0, 1, 2, 3, 5, 9, 12, 27]))
+    tv = V.TREE_FREE if rng.random() < 0.3 else V.TREE_ALL
+    return m, cap, tv
+
+
+@pytest.mark.parametrize("i", range(30))
+def test_device_tree_matches_host_random(i):
+    """Seeded random meshes (clustered points, vertices exactly on midlines, leaf
+    capacities 1 to 27, all or free tree vertices): the device tree build gives the
+    host's root box, depth, keys, prolongations, cells, colours and operator
+    patterns bit for bit."""
+    m, cap, tv = _random_tree_mesh(i)
+    sh = V.Solver.from_mesh(m, host_only=1, leaf_capacity=cap, tree_vertices=tv)
+    sd = V.Solver.from_mesh(m, host_only=1, setup_device=1, leaf_capacity=cap, tree_vertices=tv)
+    assert "tree+P (device)" in [n for n, _ in sd.setup_phases()]
+    _compare_transfers(sd, sh)
+    sd.free()
+    sh.free()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_device_tree_falls_back_to_host_when_too_deep(dim):
     """A leaf's capacity of fixed vertices within 2^-44 (2D) / 2^-30 (3D) of
