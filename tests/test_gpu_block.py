@@ -198,3 +198,43 @@ def test_block_rollers_match_oracle_per_column(K):
         assert np.linalg.norm(X[c] - xo) / np.linalg.norm(xo) <= 1e-8
         assert np.all(X[c][fixed] == 0)
     s.free()
+
+
+@pytest.mark.parametrize("i", range(12))
+def test_block_random_configurations_match_oracle(i):
+    """Seeded random meshes (2D and 3D, full, roller and symmetry conditions, 1:100
+    materials), K = 4, 8 or 16 with 1 to 2K load cases (ragged last block, some
+    with a zero column), FP64 or FP32 V-cycle, host or device setup: every column
+    against its own oracle solve (FP64 1e-8 and +-1 iteration, FP32 1e-6); a zero
+    column takes 0 iterations and returns 0."""
+    rng = np.random.default_rng(11000 + i)
+    dim = int(rng.integers(2, 4))
+    if dim == 2:
+        m = small2d(int(rng.integers(5, 50)), seed=int(rng.integers(0, 1000)),
+                    fix=str(rng.choice(["boundary", "x0", "symmetry"])), nu=float(rng.uniform(0.25, 0.45)))
+    else:
+        m = small3d(int(rng.integers(3, 13)), seed=int(rng.integers(0, 1000)),
+                    fix=str(rng.choice(["x0", "symmetry", "roller_x1"])), nu=float(rng.uniform(0.25, 0.45)))
+    m.E = np.where(rng.random(m.elems.shape[0]) < 0.5, 1.0, 100.0)
+    K = int(rng.choice([4, 8, 16]))
+    nr = int(rng.integers(1, 2 * K + 1))
+    F = rng.normal(size=(nr,) + m.coords.shape) * (1 - m.fixed)
+    if nr > 2 and rng.random() < 0.3:
+        F[1] = 0.0
+    prec = V.FP64 if rng.random() < 0.5 else V.FP32_PRECOND
+    sdev = int(rng.random() < 0.5)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
+    with V.Solver.from_mesh(m, precision=prec, block_rhs=K, setup_device=sdev) as s:
+        X, infos = s.solve(F, 1e-8)
+    for c in range(nr):
+        if not np.any(F[c]):
+            assert infos[c]["iterations"] == 0 and not np.any(X[c]), c
+            continue
+        xo, io = o.solve(F[c], 1e-8)
+        err = np.linalg.norm(X[c] - xo) / np.linalg.norm(xo)
+        assert infos[c]["converged"] == 1 and infos[c]["rel_res_true"] < 1e-8, (c, infos[c])
+        if prec == V.FP64:
+            assert abs(infos[c]["iterations"] - io["iterations"]) <= 1, (c, infos[c]["iterations"], io)
+            assert err <= 1e-8, (c, err)
+        else:
+            assert err <= 1e-6, (c, err)
