@@ -403,7 +403,10 @@ vasmg_status vasmg_tree_info(vasmg_handle h, double* m, double* M, int32_t* max_
  * tree and prolongations, "tree+P (device)" when setup_device = 1 built them
  * on the device, "galerkin" — "galerkin (+ordering)" when the device products
  * run beside the host's cells and colours —, "cells+colours", "coarsest factor", then
- * "upload" or "upload+autotune" unless host_only). Writes up to
+ * unless host_only "upload: layouts" (the level layouts and transfers),
+ * "upload: autotune" (autotune = 1) and "upload: graphs" (capture and
+ * instantiation of the solve's graphs); host wall time until each part
+ * returned, so device work still queued counts in the next). Writes up to
  * max_out entries (name NUL-terminated, truncated to 31 characters) and the
  * number of phases to *n_out. */
 typedef struct {

@@ -256,6 +256,8 @@ struct GalerkinDevice {
   std::vector<gal::DevCsr> lev;       // resident canonical operators, by level
   std::vector<gal::DevCsr> adopted;   // prolongations built on the device, by level
   std::vector<int64_t> adopted_cols;
+  std::vector<gal::DevCsr> kept;      // each level's prolongation after its product,
+  std::vector<int64_t> kept_cols;     // for the device-numbered transfers of the upload
   struct Pending {
     int level;
     BlockCSR* host;
@@ -273,6 +275,7 @@ struct GalerkinDevice {
     join();   // downloads not started by now are not needed
     for (auto& L : lev) L.release(st);
     for (auto& P : adopted) P.release(st);
+    for (auto& P : kept) P.release(st);
     if (st) (void)hipStreamSynchronize(st);
     if (st) (void)hipStreamDestroy(st);
     if (dl) (void)hipStreamDestroy(dl);
@@ -442,7 +445,14 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     C.release(st);
     throw;
   }
-  dP.release(st);
+  // P stays for the upload's device-numbered transfers (canonical rows and columns)
+  if (G.kept.size() <= l) {
+    G.kept.resize(l + 1);
+    G.kept_cols.resize(l + 1, 0);
+  }
+  G.kept[l].release(st);
+  G.kept[l] = dP;
+  G.kept_cols[l] = P.ncols;
   dPT.release(st);
   AP.release(st);
   G.lev.push_back(C);
@@ -942,6 +952,25 @@ bool galerkin_device_operator(const GalerkinDevice* G, int l, DevOperator* out) 
 }
 
 void* galerkin_device_stream(const GalerkinDevice* G) { return G ? static_cast<void*>(G->st) : nullptr; }
+
+bool galerkin_device_prolongation(GalerkinDevice* G, int level, int64_t* nrows, int64_t* ncols,
+                                  int64_t* nnz, const int64_t** ptr, const int32_t** col,
+                                  const double** val) {
+  if (!G || level < 0 || static_cast<size_t>(level) >= G->kept.size() || !G->kept[level].ptr)
+    return false;
+  const gal::DevCsr& P = G->kept[level];
+  *nrows = P.nrows;
+  *ncols = G->kept_cols[level];
+  *nnz = P.nnz;
+  *ptr = P.ptr;
+  *col = P.col;
+  *val = P.val;
+  return true;
+}
+
+void galerkin_device_release_prolongation(GalerkinDevice* G, int level) {
+  if (G && level >= 0 && static_cast<size_t>(level) < G->kept.size()) G->kept[level].release(G->st);
+}
 
 void layout_count(const DevOperator& A, const LayoutArgs& a, void* stream) {
   if (A.n != a.n) throw Error{VASMG_EINVAL, "internal: layout operator size"};

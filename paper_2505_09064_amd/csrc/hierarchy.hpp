@@ -192,6 +192,24 @@ struct DevOperator {
 bool galerkin_device_operator(const GalerkinDevice* g, int l, DevOperator* out);
 // The context's stream (a hipStream_t).
 void* galerkin_device_stream(const GalerkinDevice* g);
+// Level l's canonical prolongation (int64 row pointers, int32 columns, FP64
+// weights), kept on the device after the level's Galerkin product for the
+// upload, on the context's stream; false when there is none. Released by
+// galerkin_device_release_prolongation or with the context.
+bool galerkin_device_prolongation(GalerkinDevice* g, int level, int64_t* nrows, int64_t* ncols,
+                                  int64_t* nnz, const int64_t** ptr, const int32_t** col,
+                                  const double** val);
+void galerkin_device_release_prolongation(GalerkinDevice* g, int level);
+// A level's transfers in device numbering from its canonical prolongation on
+// the device (tree.hip): row i of P is canonical row perm[i], its columns
+// renumbered by inv_next in their canonical order; P^T the stable transpose
+// (entries of a column in row order); 32-bit row pointers; weights copied
+// (pw64, tw64) and rounded to FP32 (pw32, tw32) where those are non-null. The
+// arrays the host's upload builds, bit for bit. Device pointers, on stream.
+void transfers_layout_device(void* stream, int64_t n, int64_t nn, int64_t nnz, const int64_t* ptr,
+                             const int32_t* col, const double* val, const int32_t* perm,
+                             const int32_t* inv_next, int32_t* pptr, int32_t* pidx, double* pw64,
+                             float* pw32, int32_t* tptr, int32_t* tidx, double* tw64, float* tw32);
 
 // Device layout of one level from its canonical operator A (device pointers;
 // the level's device rows i = 0..n-1 map to canonical rows perm[i], canonical

@@ -811,6 +811,71 @@ void transpose_device(void* stream, int64_t nrows, int64_t ncols, int64_t nnz, c
   tree::check(hipGetLastError(), "launch");
 }
 
+namespace tree {
+
+// Row lengths of P in device order: row i is canonical row perm[i].
+__global__ void k_perm_rowlen(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ perm,
+                              int64_t* __restrict__ len) {
+  const int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x;
+  if (i < n) len[i] = ptr[perm[i] + 1] - ptr[perm[i]];
+}
+
+// Row i's entries: canonical row perm[i] in its order, columns renumbered.
+__global__ void k_perm_fill(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const int32_t* __restrict__ perm,
+                            const int32_t* __restrict__ inv_next, const int64_t* __restrict__ pptr,
+                            int32_t* __restrict__ pidx, double* __restrict__ pw) {
+  const int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x;
+  if (i >= n) return;
+  const int64_t b = ptr[perm[i]], e = ptr[perm[i] + 1];
+  int64_t q = pptr[i];
+  for (int64_t p = b; p < e; ++p, ++q) {
+    pidx[q] = inv_next[col[p]];
+    pw[q] = val[p];
+  }
+}
+
+__global__ void k_narrow_ptr(int64_t n, const int64_t* __restrict__ p64, int32_t* __restrict__ p32) {
+  const int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x;
+  if (i < n) p32[i] = static_cast<int32_t>(p64[i]);
+}
+
+__global__ void k_round_f32(int64_t n, const double* __restrict__ v, float* __restrict__ w) {
+  const int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x;
+  if (i < n) w[i] = static_cast<float>(v[i]);
+}
+
+}  // namespace tree
+
+void transfers_layout_device(void* stream, int64_t n, int64_t nn, int64_t nnz, const int64_t* ptr,
+                             const int32_t* col, const double* val, const int32_t* perm,
+                             const int32_t* inv_next, int32_t* pptr, int32_t* pidx, double* pw64,
+                             float* pw32, int32_t* tptr, int32_t* tidx, double* tw64, float* tw32) {
+  if (nnz > INT32_MAX) throw Error{VASMG_EINVAL, "prolongation too large for 32-bit row pointers"};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  tree::Arena A(st);
+  int64_t* pptr64 = A.get<int64_t>(n + 1);
+  int64_t* tptr64 = A.get<int64_t>(nn + 1);
+  double* pw = pw64 ? pw64 : A.get<double>(nnz);
+  double* tw = tw64 ? tw64 : A.get<double>(nnz);
+  tree::check(hipMemsetAsync(pptr64, 0, sizeof(int64_t), st), "clear");
+  if (n > 0) {
+    int64_t* len = A.get<int64_t>(n);
+    tree::k_perm_rowlen<<<tree::grid_for(n), tree::kThreads, 0, st>>>(n, ptr, perm, len);
+    tree::inclusive_sum(A, len, pptr64 + 1, n);
+    tree::k_perm_fill<<<tree::grid_for(n), tree::kThreads, 0, st>>>(n, ptr, col, val, perm, inv_next, pptr64,
+                                                                  pidx, pw);
+  }
+  transpose_device(st, n, nn, nnz, pptr64, pidx, pw, tptr64, tidx, tw);
+  tree::k_narrow_ptr<<<tree::grid_for(n + 1), tree::kThreads, 0, st>>>(n + 1, pptr64, pptr);
+  tree::k_narrow_ptr<<<tree::grid_for(nn + 1), tree::kThreads, 0, st>>>(nn + 1, tptr64, tptr);
+  if (pw32 && nnz > 0) tree::k_round_f32<<<tree::grid_for(nnz), tree::kThreads, 0, st>>>(nnz, pw, pw32);
+  if (tw32 && nnz > 0) tree::k_round_f32<<<tree::grid_for(nnz), tree::kThreads, 0, st>>>(nnz, tw, tw32);
+  tree::check(hipGetLastError(), "launch");
+  // the arena's temporaries are released in stream order; the caller synchronises
+  // before it uses the results off this stream
+}
+
 void vertex_elements_device(void* stream, const int32_t* elems, int64_t ne, int nvpe, int64_t nv,
                             int64_t* vptr, int32_t* velem) {
   hipStream_t st = static_cast<hipStream_t>(stream);
