@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <future>
 #include <mutex>
 #include <new>
 #include <string>
@@ -251,6 +252,7 @@ struct GalerkinDevice {
   int device = 0;
   hipStream_t st = nullptr;   // products and layouts
   hipStream_t dl = nullptr;   // background value downloads
+  hipStream_t sd = nullptr;   // structure downloads (beside the next product)
   int window = gal::kMaxWindowCols;
   const BlockCSR* cached = nullptr;   // host operator of the last resident level
   std::vector<gal::DevCsr> lev;       // resident canonical operators, by level
@@ -263,6 +265,13 @@ struct GalerkinDevice {
     BlockCSR* host;
   };
   std::vector<Pending> pending;       // value downloads not started yet
+  // each product's structure (and the coarsest's values) on its way to the host,
+  // by level; the next product runs meanwhile
+  std::vector<std::shared_future<void>> structure;
+  void wait_structure(int level) {   // level < 0: all; rethrows a download's error
+    for (size_t k = 0; k < structure.size(); ++k)
+      if ((level < 0 || static_cast<int>(k) == level) && structure[k].valid()) structure[k].get();
+  }
   std::vector<std::thread> downloads;
   std::mutex mu;
   std::string dl_error;
@@ -272,6 +281,8 @@ struct GalerkinDevice {
     downloads.clear();
   }
   ~GalerkinDevice() {
+    for (auto& f : structure)   // the device copies they read stay until they end
+      if (f.valid()) f.wait();
     join();   // downloads not started by now are not needed
     for (auto& L : lev) L.release(st);
     for (auto& P : adopted) P.release(st);
@@ -279,6 +290,7 @@ struct GalerkinDevice {
     if (st) (void)hipStreamSynchronize(st);
     if (st) (void)hipStreamDestroy(st);
     if (dl) (void)hipStreamDestroy(dl);
+    if (sd) (void)hipStreamDestroy(sd);
   }
 };
 
@@ -427,17 +439,28 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     product<D, false>(G, dPT, AP, P.ncols, C);
     Ac.n = P.ncols;
     Ac.d = D;
-    Ac.rowptr.resize(C.nrows + 1);
-    Ac.col.resize(C.nnz);
-    check(hipMemcpyAsync(Ac.rowptr.data(), C.ptr, (C.nrows + 1) * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, st), "copy");
-    check(hipMemcpyAsync(Ac.col.data(), C.col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-    if (coarsest) {
-      Ac.val.resize(C.nnz * DD);
-      check(hipMemcpyAsync(Ac.val.data(), C.val, C.nnz * DD * sizeof(double), hipMemcpyDeviceToHost, st),
-            "copy");
-    }
-    check(hipStreamSynchronize(st), "download");
+    // the structure (and the coarsest's values) goes to the host on a thread of
+    // its own while the next product runs; whoever reads it first waits for it
+    // (galerkin_device_wait_structure). C stays resident until the download ends.
+    GalerkinDevice* Gp = &G;
+    const DevCsr Cs = C;
+    BlockCSR* host = &Ac;
+    if (G.structure.size() <= l + 1) G.structure.resize(l + 2);
+    G.structure[l + 1] = std::async(std::launch::async, [Gp, Cs, host, coarsest] {
+                           check(hipSetDevice(Gp->device), "device");
+                           host->rowptr.resize(Cs.nrows + 1);
+                           host->col.resize(Cs.nnz);
+                           check(hipMemcpyAsync(host->rowptr.data(), Cs.ptr, (Cs.nrows + 1) * sizeof(int64_t),
+                                                hipMemcpyDeviceToHost, Gp->sd), "copy");
+                           check(hipMemcpyAsync(host->col.data(), Cs.col, Cs.nnz * sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, Gp->sd), "copy");
+                           if (coarsest) {
+                             host->val.resize(Cs.nnz * DD);
+                             check(hipMemcpyAsync(host->val.data(), Cs.val, Cs.nnz * DD * sizeof(double),
+                                                  hipMemcpyDeviceToHost, Gp->sd), "copy");
+                           }
+                           check(hipStreamSynchronize(Gp->sd), "structure download");
+                         }).share();
   } catch (...) {
     dP.release(st);
     dPT.release(st);
@@ -790,6 +813,7 @@ GalerkinDevice* galerkin_device_create(int window_cols) {
   hipError_t e = hipGetDevice(&G->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&G->st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&G->dl, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&G->sd, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete G;
     gal::check(e, "stream");
@@ -931,7 +955,12 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
 
 void galerkin_device_settle(void* ctx) { galerkin_device_join(static_cast<GalerkinDevice*>(ctx)); }
 
+void galerkin_device_wait_structure(void* ctx, int level) {
+  static_cast<GalerkinDevice*>(ctx)->wait_structure(level);
+}
+
 void galerkin_device_start_downloads(GalerkinDevice* G, bool free_after) {
+  G->wait_structure(-1);   // value downloads may free the levels these read
   for (const auto& p : G->pending)
     G->downloads.emplace_back(gal::download_values, G, p.level, p.host, free_after);
   G->pending.clear();

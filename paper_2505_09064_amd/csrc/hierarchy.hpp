@@ -101,6 +101,9 @@ using AssembleFn = void (*)(void* ctx, const MeshView& m, const std::vector<int3
                             int64_t nfree, BlockCSR& A);
 // Brings every level's values to the host (values produced elsewhere).
 using SettleFn = void (*)(void* ctx);
+// Waits until level l's structure (l < 0: every level's) has reached the host
+// hierarchy; rethrows a failed download.
+using WaitFn = void (*)(void* ctx, int level);
 
 // Region tree, level lattice keys and prolongations (Section 3.1.1 Steps 1-4,
 // Section 3.1.2, Section 3.2) built elsewhere with the host build's decisions,
@@ -126,6 +129,7 @@ struct SetupParams {
   GalerkinFn galerkin = nullptr;   // null: the host product (OpenMP)
   AssembleFn assemble = nullptr;   // null: the host assembly (OpenMP)
   SettleFn settle = nullptr;
+  WaitFn wait_structure = nullptr;   // null: a product's structure is home on return
   TransfersFn transfers = nullptr;   // null: the host tree and prolongations
   void* galerkin_ctx = nullptr;    // context of the callbacks
 };
@@ -151,6 +155,8 @@ void assemble_device(void* ctx, const MeshView& m, const std::vector<int32_t>& v
                      int64_t nfree, BlockCSR& A);
 // SettleFn: joins every download.
 void galerkin_device_settle(void* ctx);
+// WaitFn: the products' structures reach the host on threads of their own.
+void galerkin_device_wait_structure(void* ctx, int level);
 // Takes ownership of level l's prolongation on the device (stream-ordered
 // allocations on the context's stream; int64 row pointers, int32 columns, FP64
 // weights): the product from level l then uses it (and its transpose, built on

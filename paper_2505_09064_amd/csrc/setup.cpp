@@ -1138,6 +1138,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
       order_threads.emplace_back([&, l] {
         try {
           omp_set_num_threads(nth);
+          if (l > 0 && prm.wait_structure) prm.wait_structure(prm.galerkin_ctx, static_cast<int>(l));
           build_gs_order(H.levels[l], l > 0, d, prm.color_blocks);
         } catch (...) {
           order_err[l] = std::current_exception();
@@ -1149,6 +1150,7 @@ void build_hierarchy(const MeshView& m, const SetupParams& prm, Hierarchy& H) {
     } else
       galerkin(H.levels[l].A, H.levels[l].P, H.levels[l + 1].A);
   }
+  if (prm.galerkin && prm.wait_structure) prm.wait_structure(prm.galerkin_ctx, -1);
   if (!order_threads.empty()) mark("galerkin (+ordering)");
   for (auto& t : order_threads) t.join();
   for (const auto& e : order_err)

@@ -2483,6 +2483,7 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
       prm.galerkin = galerkin_device;
       prm.assemble = assemble_device;
       prm.settle = galerkin_device_settle;
+      prm.wait_structure = galerkin_device_wait_structure;
       prm.transfers = transfers_device;
       prm.galerkin_ctx = gdev.get();
     }
