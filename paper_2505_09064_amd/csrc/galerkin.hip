@@ -267,10 +267,18 @@ struct GalerkinDevice {
   std::vector<Pending> pending;       // value downloads not started yet
   // each product's structure (and the coarsest's values) on its way to the host,
   // by level; the next product runs meanwhile
-  std::vector<std::shared_future<void>> structure;
-  void wait_structure(int level) {   // level < 0: all; rethrows a download's error
-    for (size_t k = 0; k < structure.size(); ++k)
-      if ((level < 0 || static_cast<int>(k) == level) && structure[k].valid()) structure[k].get();
+  std::vector<std::shared_future<void>> structure;   // guarded by smu
+  std::mutex smu;
+  // level < 0: all; rethrows a download's error. Any thread: it waits on copies
+  // of the futures taken under the lock (the products append to the list).
+  void wait_structure(int level) {
+    std::vector<std::shared_future<void>> w;
+    {
+      std::lock_guard<std::mutex> g(smu);
+      for (size_t k = 0; k < structure.size(); ++k)
+        if ((level < 0 || static_cast<int>(k) == level) && structure[k].valid()) w.push_back(structure[k]);
+    }
+    for (auto& f : w) f.get();
   }
   std::vector<std::thread> downloads;
   std::mutex mu;
@@ -445,6 +453,7 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     GalerkinDevice* Gp = &G;
     const DevCsr Cs = C;
     BlockCSR* host = &Ac;
+    std::lock_guard<std::mutex> guard(G.smu);
     if (G.structure.size() <= l + 1) G.structure.resize(l + 2);
     G.structure[l + 1] = std::async(std::launch::async, [Gp, Cs, host, coarsest] {
                            check(hipSetDevice(Gp->device), "device");
