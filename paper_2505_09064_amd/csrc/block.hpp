@@ -4,16 +4,18 @@
 // Vectors interleave the columns per vertex, v[(row*K + k)*VS + a] (column k,
 // component a, stride VS): the K columns of one neighbour are K*VS consecutive
 // values, so the lanes of a row that own the K columns gather them in one
-// contiguous load while reading the same matrix block (a broadcast). The fine
-// level keeps the padded stride (2 / 4: aligned vector loads, the layout of the
-// FP64 PCG vectors); the coarse levels, whose cell kernels are bound by these
-// gathers, store D components with no padding (3D: a quarter fewer bytes).
+// contiguous load while sharing one read of the matrix block (staged in LDS,
+// below). The fine level keeps the padded stride (2 / 4: aligned vector loads,
+// the layout of the FP64 PCG vectors); the coarse levels store D components with
+// no padding (3D: a quarter fewer gathered bytes).
 // A row is handled by GL lanes = K columns x (GL/K) block slots; the slots
 // stride the row's blocks and are combined with cross-lane shuffles.
 // Per-column scalars (alpha, beta, rho, residual, stop flag) follow Algorithm 2
 // for every column separately; a column that has converged stops updating its
 // vectors while the others go on.
 #pragma once
+
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -67,38 +69,111 @@ __device__ __forceinline__ T slot_sum(T v) {
   return v;
 }
 
-// acc += sum over blocks [kb, ke) of A_blk x_col(blk)[column k]; slot s of S
-// takes blocks kb + s, kb + s + S, ...
-template <typename T, int D, int K, int S, int VS>
-__device__ __forceinline__ void mc_row_product(int kb, int ke, int slot, int k,
-                                               const int* __restrict__ col,
-                                               const T* __restrict__ val, int64_t nnz,
-                                               const T* __restrict__ x, T* acc) {
-  constexpr int UN = sizeof(T) == 4 ? 4 : 2;
-  int p = kb + slot;
-  for (; p + (UN - 1) * S < ke; p += UN * S) {
-    int j[UN];
+// acc += sum over blocks [kb, ke) of A_blk x_col(blk)[column k]; lane (slot, k)
+// of the row group takes blocks kb + slot, kb + slot + S, ... in ascending order.
+// The blocks go in chunks of CH (kStage on the cell levels, 4 per slot on the
+// point levels): the row group's GL lanes copy a chunk's D*D planes and columns
+// into LDS with coalesced loads (each value read once), and then every lane
+// reads its blocks from there. Read directly, each matrix value would be loaded
+// by each of the K column lanes, which multiplies what the load path returns
+// per block by K. The next chunk's values are loaded while the current one is
+// used.
+constexpr int kStage = 16;
+
+template <typename T, int D, int CH>
+struct StageShape {
+  static constexpr int DD = D * D;
+  static constexpr int V = 16 / sizeof(T);               // values per 16-byte LDS read
+  static constexpr int BS = (DD + V - 1) / V * V;         // LDS stride of one block
+  static constexpr int NE = (DD + 1) * CH;                // planes and columns per chunk
+};
+
+template <typename T, int D, int CH = kStage>
+struct alignas(16) RowStage {
+  T val[CH * StageShape<T, D, CH>::BS];
+  int col[CH];
+};
+
+template <typename T, int D, int K, int S, int VS, int GL, int CH = kStage>
+__device__ __forceinline__ void mc_row_product_staged(int kb, int ke, int self, int lane, int slot,
+                                                      int k, const int* __restrict__ col,
+                                                      const T* __restrict__ val, int64_t nnz,
+                                                      const T* __restrict__ x, T* acc,
+                                                      RowStage<T, D, CH>& st) {
+  using SS = StageShape<T, D, CH>;
+  using IT = std::conditional_t<sizeof(T) == 4, int32_t, int64_t>;   // a column in a value's bits
+  constexpr int NR = (SS::NE + GL - 1) / GL;   // staged values per lane and chunk
+  constexpr int PB = CH / S;                   // blocks per lane and chunk
+  static_assert(CH % S == 0, "slots divide a chunk");
+  T pv[NR];
+  auto fetch = [&](int p0) {
 #pragma unroll
-    for (int u = 0; u < UN; ++u) j[u] = col[p + u * S];
-    T xv[UN][D];
+    for (int r = 0; r < NR; ++r) {
+      const int e = lane + r * GL;
+      const int q = e / CH, b = e % CH;
+      T v = T(0);
+      if (e < SS::NE && p0 + b < ke) {
+        if (q < SS::DD) v = val[q * nnz + p0 + b];
+        else v = __builtin_bit_cast(T, static_cast<IT>(col[p0 + b]));
+      }
+      pv[r] = v;
+    }
+  };
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
+  if (kb < ke) fetch(kb);
+  for (int p0 = kb; p0 < ke; p0 += CH) {
 #pragma unroll
-    for (int u = 0; u < UN; ++u)
-      BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(j[u]) * K + k) * VS, xv[u]);
+    for (int r = 0; r < NR; ++r) {
+      const int e = lane + r * GL;
+      const int q = e / CH, b = e % CH;
+      if (e < SS::NE) {
+        if (q < SS::DD) st.val[b * SS::BS + q] = pv[r];
+        else st.col[b] = p0 + b < ke ? static_cast<int>(__builtin_bit_cast(IT, pv[r])) : self;
+      }
+    }
+    sync();
+    if (p0 + CH < ke) fetch(p0 + CH);
+    int j[PB];
 #pragma unroll
-    for (int u = 0; u < UN; ++u) block_fma<T, D>(val, nnz, p + u * S, xv[u], acc);
-  }
-  for (; p < ke; p += S) {
-    const int jj = col[p];
-    T xj[D];
-    BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(jj) * K + k) * VS, xj);
-    block_fma<T, D>(val, nnz, p, xj, acc);
+    for (int i = 0; i < PB; ++i) j[i] = st.col[slot + i * S];
+    T xv[PB][D];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      if (p0 + slot + i * S < ke)
+        BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(j[i]) * K + k) * VS, xv[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const int b = slot + i * S;
+      if (p0 + b < ke) {
+        const T* m = st.val + b * SS::BS;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) acc[a] += m[a * D + c] * xv[i][c];
+        }
+      }
+    }
+    sync();   // the buffer is refilled with the next chunk
   }
 }
 
-template <typename T, int D, int K, int S, int VS>
-__device__ __forceinline__ void mc_part_product(const Part<T>& p, int i, int slot, int k,
-                                                const T* __restrict__ x, T* acc) {
-  mc_row_product<T, D, K, S, VS>(p.ptr[i], p.ptr[i + 1], slot, k, p.col, p.val, p.nnz, x, acc);
+// Point-level rows: staged in chunks of 4 blocks per slot (4 blocks in flight
+// per lane), one buffer per row group.
+template <typename T, int D, int K, int GL>
+using PointStage = RowStage<T, D, 4 * (GL / K)>;
+
+template <typename T, int D, int K, int GL>
+__device__ __forceinline__ void mc_part_staged(const Part<T>& p, int i, int lane, int slot, int k,
+                                               const T* __restrict__ x, T* acc,
+                                               PointStage<T, D, K, GL>& st) {
+  constexpr int S = GL / K;
+  mc_row_product_staged<T, D, K, S, Pad<D>::value, GL, 4 * S>(p.ptr[i], p.ptr[i + 1], i, lane, slot,
+                                                              k, p.col, p.val, p.nnz, x, acc, st);
 }
 
 // Per-column block sums: thread t contributes v to column col_of(t); on return
@@ -125,16 +200,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mc(int n, Part<double> L, Part<
                                                     double* __restrict__ y,
                                                     double* __restrict__ partial) {
   constexpr int DP = Pad<D>::value;
-  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
+  __shared__ PointStage<double, D, K, GL> stg[kBlock / GL];
   double dot = 0.0;
   if (i < n) {
     double acc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = 0.0;
-    mc_part_product<double, D, K, S, Pad<D>::value>(L, i, slot, k, x, acc);
-    mc_part_product<double, D, K, S, Pad<D>::value>(U, i, slot, k, x, acc);
+    mc_part_staged<double, D, K, GL>(L, i, lane, slot, k, x, acc, stg[threadIdx.x / GL]);
+    mc_part_staged<double, D, K, GL>(U, i, lane, slot, k, x, acc, stg[threadIdx.x / GL]);
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] = slot_sum<double, K, GL>(acc[a]);
     if (slot == 0) {
@@ -168,7 +243,6 @@ __global__ __launch_bounds__(kBlock) void k_gs_color_mc(
     int row0, int nrows, Part<T> L, Part<T> U, const T* __restrict__ diag,
     const T* __restrict__ b, T* x, T* __restrict__ s_save) {
   constexpr int DP = Pad<D>::value;
-  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int g = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
   if (g >= nrows) return;
@@ -176,8 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_color_mc(
   T lo[D], up[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
-  mc_part_product<T, D, K, S, Pad<D>::value>(L, i, slot, k, x, lo);
-  if (MODE != 0) mc_part_product<T, D, K, S, Pad<D>::value>(U, i, slot, k, x, up);
+  __shared__ PointStage<T, D, K, GL> stg[kBlock / GL];
+  mc_part_staged<T, D, K, GL>(L, i, lane, slot, k, x, lo, stg[threadIdx.x / GL]);
+  if (MODE != 0) mc_part_staged<T, D, K, GL>(U, i, lane, slot, k, x, up, stg[threadIdx.x / GL]);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     lo[a] = slot_sum<T, K, GL>(lo[a]);
@@ -221,14 +296,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_upper_mc(
     int n, Part<T> U, const T* __restrict__ diag, const T* __restrict__ s_save,
     const T* __restrict__ x, T* __restrict__ r) {
   constexpr int DP = Pad<D>::value;
-  constexpr int S = GL / K;
   const int lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
   const int i = xcd_block() * (kBlock / GL) + threadIdx.x / GL;
   if (i >= n) return;
   T acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = T(0);
-  mc_part_product<T, D, K, S, Pad<D>::value>(U, i, slot, k, x, acc);
+  __shared__ PointStage<T, D, K, GL> stg[kBlock / GL];
+  mc_part_staged<T, D, K, GL>(U, i, lane, slot, k, x, acc, stg[threadIdx.x / GL]);
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = slot_sum<T, K, GL>(acc[a]);
   if (slot != 0) return;
@@ -258,6 +333,7 @@ struct CellLds {
   T M[NU * NU];
   T lo[NV][K][D];
   T up[NV][K][D];
+  RowStage<T, D> stage[NV];   // one per row group
 };
 
 template <typename T, int D, int K, int GL>
@@ -270,8 +346,13 @@ __device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L,
 #pragma unroll
   for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
   if (g < m) {
-    if (want_lo) mc_part_product<T, D, K, S, D>(L, v0 + g, slot, k, x, lo);
-    if (want_up) mc_part_product<T, D, K, S, D>(U, v0 + g, slot, k, x, up);
+    const int i = v0 + g;
+    if (want_lo)
+      mc_row_product_staged<T, D, K, S, D, GL>(L.ptr[i], L.ptr[i + 1], i, lane, slot, k, L.col,
+                                               L.val, L.nnz, x, lo, sh.stage[g]);
+    if (want_up)
+      mc_row_product_staged<T, D, K, S, D, GL>(U.ptr[i], U.ptr[i + 1], i, lane, slot, k, U.col,
+                                               U.val, U.nnz, x, up, sh.stage[g]);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
