@@ -304,8 +304,28 @@ struct GalerkinDevice {
 
 namespace gal {
 
-void upload(DevCsr& D, int64_t nrows, const std::vector<int64_t>& ptr,
-            const std::vector<int32_t>& col, const std::vector<double>& val, hipStream_t st) {
+// Maps the pages of a freshly sized host array from several threads (one write
+// per page), so that the kernel's page faults and page clearing are spread
+// over cores instead of falling on the single thread that copies into it.
+void first_touch(void* p, size_t bytes) {
+  constexpr size_t kPage = 4096;
+  constexpr int kThreads = 8;
+  if (bytes < (size_t(16) << 20)) return;
+  char* b = static_cast<char*>(p);
+  std::vector<std::thread> th;
+  th.reserve(kThreads);
+  for (int t = 0; t < kThreads; ++t) {
+    const size_t lo = bytes * t / kThreads, hi = bytes * (t + 1) / kThreads;
+    th.emplace_back([b, lo, hi] {
+      for (size_t o = lo; o < hi; o += kPage) reinterpret_cast<volatile char*>(b)[o] = 0;
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
+template <class ColV>   // std::vector<int32_t> or ColVec
+void upload(DevCsr& D, int64_t nrows, const std::vector<int64_t>& ptr, const ColV& col,
+            const std::vector<double>& val, hipStream_t st) {
   D.nrows = nrows;
   D.nnz = static_cast<int64_t>(col.size());
   D.ptr = dmalloc<int64_t>(ptr.size(), st, "rowptr");
@@ -458,7 +478,8 @@ void galerkin_d(GalerkinDevice& G, const BlockCSR& A, const ScalarCSR& P, BlockC
     G.structure[l + 1] = std::async(std::launch::async, [Gp, Cs, host, coarsest] {
                            check(hipSetDevice(Gp->device), "device");
                            host->rowptr.resize(Cs.nrows + 1);
-                           host->col.resize(Cs.nnz);
+                           host->col.resize(Cs.nnz);   // not cleared: the copy fills it
+                           first_touch(host->col.data(), Cs.nnz * sizeof(int32_t));
                            check(hipMemcpyAsync(host->rowptr.data(), Cs.ptr, (Cs.nrows + 1) * sizeof(int64_t),
                                                 hipMemcpyDeviceToHost, Gp->sd), "copy");
                            check(hipMemcpyAsync(host->col.data(), Cs.col, Cs.nnz * sizeof(int32_t),

@@ -18,13 +18,36 @@ struct Error {
 
 using Key = std::array<uint64_t, 3>;   // lattice key per axis (unused axes 0)
 
+// Allocator whose resize() leaves new elements uninitialised (default-init):
+// the column arrays of the coarse levels are filled by a copy right after they
+// are sized, and zero-filling 10^8 entries first costs tens of milliseconds.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+using ColVec = std::vector<int32_t, NoInitAlloc<int32_t>>;
+
 // d x d block CSR, structural pattern including the diagonal block, columns
 // ascending within a row. val holds row-major d x d blocks.
 struct BlockCSR {
   int64_t n = 0;
   int d = 0;
   std::vector<int64_t> rowptr;
-  std::vector<int32_t> col;
+  ColVec col;
   std::vector<double> val;
   int64_t nnzb() const { return static_cast<int64_t>(col.size()); }
 };

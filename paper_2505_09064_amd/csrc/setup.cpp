@@ -499,7 +499,7 @@ void galerkin(const BlockCSR& A, const ScalarCSR& P, BlockCSR& Ac) {
 // --------------------------------------------------------------------------
 // First fit over the graph (ptr, adj) visiting the nodes in `order`; self
 // loops are ignored (a node is uncoloured when visited).
-int32_t greedy_color_in_order(const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
+int32_t greedy_color_in_order(const std::vector<int64_t>& ptr, const int32_t* adj,
                               const std::vector<int64_t>& order, std::vector<int32_t>& color) {
   const int64_t n = static_cast<int64_t>(ptr.size()) - 1;
   color.assign(n, -1);
@@ -588,10 +588,8 @@ void build_gs_order(Level& lv, bool lattice, int d, bool color_blocks) {
   std::vector<int64_t> gptr;
   std::vector<int32_t> gadj;
   const std::vector<int64_t>* adj_ptr = &gptr;
-  const std::vector<int32_t>* adj = &gadj;
   if (!lattice) {
     adj_ptr = &lv.A.rowptr;
-    adj = &lv.A.col;
   } else {
     std::vector<int64_t> vptr(nc + 1, 0);
     for (int64_t i = 0; i < n; ++i) vptr[lv.block[i] + 1]++;
@@ -651,7 +649,7 @@ void build_gs_order(Level& lv, bool lattice, int d, bool color_blocks) {
       std::stable_sort(order.begin(), order.end(),
                        [&](int64_t a, int64_t b) { return cls[a] < cls[b]; });
     }
-    ncol[o] = greedy_color_in_order(*adj_ptr, *adj, order, cand[o]);
+    ncol[o] = greedy_color_in_order(*adj_ptr, lattice ? gadj.data() : lv.A.col.data(), order, cand[o]);
   }
   int best_o = 0;
   for (int o = 1; o < n_orders; ++o)
@@ -740,7 +738,7 @@ void padded_gs_order(const Level& src, int d, bool fine, Level& out_part) {
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::vector<int64_t> ptr(src.A.rowptr.begin(), src.A.rowptr.end());
-    out_part.ncolors = greedy_color_in_order(ptr, src.A.col, order, out_part.block_color);
+    out_part.ncolors = greedy_color_in_order(ptr, src.A.col.data(), order, out_part.block_color);
     out_part.color = out_part.block_color;
   }
   out_part.block = out_part.cell;

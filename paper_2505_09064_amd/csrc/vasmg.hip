@@ -558,8 +558,8 @@ struct TempDev {
     if (n) HIP_CHECK(hipMemcpyAsync(q, src, n * sizeof(T), hipMemcpyHostToDevice, st));
     return static_cast<T*>(q);
   }
-  template <class T>
-  T* up(const std::vector<T>& v) { return up(v.data(), v.size()); }
+  template <class T, class A>
+  T* up(const std::vector<T, A>& v) { return up(v.data(), v.size()); }
 };
 
 // Device layout of level l: built by the layout kernels from the level's
