@@ -139,7 +139,12 @@ typedef struct {
                                   suffice instead of 27. Ignored (off) with block_rhs.
                                   Changes the sweep order, hence results (the oracle
                                   takes the same order).                                 */
-  int32_t reserved[1];
+  int32_t block_lanes;         /* block_rhs only: lanes per block row of the block
+                                  kernels. 0 (default) = per level from its row
+                                  lengths, or timed with autotune = 1; 1 = the narrow
+                                  groups on every level (16 per point row, 32 per cell
+                                  row); 2 = the wide groups (64). Results differ by
+                                  rounding only; EINVAL outside 0..2                    */
 } vasmg_options;
 
 typedef struct {

@@ -1860,6 +1860,11 @@ void upload_block(vasmg_ctx& C, int K) {
       lv.mcGL = avg >= 48.0 ? dev::kCellLanesWide : dev::kCellLanesNarrow;
     else
       lv.mcGL = avg >= 24.0 ? dev::kPointLanesWide : dev::kPointLanesNarrow;
+    if (C.opt.block_lanes != 0) {   // forced: narrow (1) or wide (2) groups everywhere
+      const bool wide = C.opt.block_lanes == 2;
+      lv.mcGL = lv.cells ? (wide ? dev::kCellLanesWide : dev::kCellLanesNarrow)
+                         : (wide ? dev::kPointLanesWide : dev::kPointLanesNarrow);
+    }
   }
   C.kpartial = C.dalloc<double>(static_cast<int64_t>(C.kn_partial) * K);
   C.ksc = C.dalloc<Scalars>(K);
@@ -2246,7 +2251,7 @@ void upload_device(vasmg_ctx& C, hipStream_t alloc_stream) {
       autotune<2>(C);
     else
       autotune<3>(C);
-    if (C.K > 0) {
+    if (C.K > 0 && C.opt.block_lanes == 0) {
       if (C.d == 2) {
         DISPATCH_K(C.K, { autotune_block<2, KK>(C); });
       } else {
@@ -2473,6 +2478,8 @@ vasmg_status vasmg_setup(const vasmg_mesh* mesh, const vasmg_options* opt, vasmg
                 mesh->E, mesh->nu, mesh->fixed};
     if (o.color_blocks != 0 && o.color_blocks != 1)
       throw vasmg::Error{VASMG_EINVAL, "color_blocks must be 0 (off) or 1 (on)"};
+    if (o.block_lanes < 0 || o.block_lanes > 2)
+      throw vasmg::Error{VASMG_EINVAL, "block_lanes must be 0, 1 (narrow) or 2 (wide)"};
     SetupParams prm{o.leaf_capacity, o.tree_vertices == VASMG_TREE_FREE, o.coarsest_max_dofs};
     // the block right-hand-side kernels sweep one cell per workgroup: no colour blocks
     prm.color_blocks = o.color_blocks == 1 && o.block_rhs == 0;

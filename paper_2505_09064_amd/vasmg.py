@@ -58,7 +58,7 @@ class Options(C.Structure):
                 ("host_only", C.c_int32), ("verbose", C.c_int32), ("autotune", C.c_int32),
                 ("block_rhs", C.c_int32), ("cycle", C.c_int32), ("smoother", C.c_int32),
                 ("setup_device", C.c_int32), ("color_blocks", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("block_lanes", C.c_int32)]
 
 
 class PhaseStat(C.Structure):

@@ -115,6 +115,32 @@ def test_block_autotuned_lanes_match_oracle_per_column(prec):
     s.free()
 
 
+@pytest.mark.parametrize("dim,K,lanes,prec", [
+    (3, 16, 1, V.FP32_PRECOND), (3, 16, 2, V.FP32_PRECOND), (3, 16, 2, V.FP64),
+    (3, 4, 1, V.FP64), (3, 4, 2, V.FP32_PRECOND), (3, 8, 2, V.FP64),
+    (2, 16, 1, V.FP64), (2, 16, 2, V.FP32_PRECOND), (2, 4, 2, V.FP64), (2, 8, 1, V.FP32_PRECOND),
+])
+def test_block_forced_lane_groups_match_oracle(dim, K, lanes, prec):
+    """block_lanes = 1 / 2 puts the narrow / wide lane groups on every level, so
+    each staging shape of the block kernels (row groups of 16, 32 or 64 lanes;
+    1 to 16 block slots per column; FP32 and FP64 chunks) runs on point and cell
+    levels, with a ragged last block of columns: every column against its own
+    oracle solve (FP64 1e-8, FP32 V-cycle 1e-5; +-1 iteration)."""
+    m = small3d(9, seed=5) if dim == 3 else small2d(33, seed=3)
+    o = Oracle(m.coords, m.elems, m.E, m.nu, m.fixed, OracleOptions(color_blocks="off"))
+    s = V.Solver.from_mesh(m, precision=prec, block_rhs=K, block_lanes=lanes)
+    n_rhs = K + 3
+    F = np.stack(_loads(m, n_rhs))
+    X, infos = s.solve(F, 1e-6)
+    for c in (0, K - 1, K, n_rhs - 1):
+        xo, io = o.solve(F[c], 1e-6)
+        err = np.linalg.norm(X[c] - xo) / np.linalg.norm(xo)
+        assert infos[c]["converged"] == 1 and infos[c]["rel_res_true"] < 1e-6
+        assert abs(infos[c]["iterations"] - io["iterations"]) <= 1
+        assert err < (1e-8 if prec == V.FP64 else 1e-5), (c, err)
+    s.free()
+
+
 def test_block_zero_column_and_initial_guess():
     m, o, s = _setup(3, V.FP64, 4)
     F = np.stack(_loads(m, 4))

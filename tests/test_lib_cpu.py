@@ -153,6 +153,8 @@ def test_setup_rejects_invalid_input():
             Oracle(m.coords, m.elems, m.E, m.nu, m.fixed)
     _expect(V.EINVAL, lambda: small2d(5), leaf_capacity=-1)
     _expect(V.EINVAL, lambda: small2d(5), block_rhs=5)
+    _expect(V.EINVAL, lambda: small2d(5), block_rhs=4, block_lanes=3)
+    _expect(V.EINVAL, lambda: small2d(5), block_lanes=-1)
 
 
 def test_host_only_handle_refuses_device_calls():
@@ -169,7 +171,7 @@ def test_default_options():
     o = V.default_options(2)
     assert (o.leaf_capacity, o.n_pre, o.n_post, o.max_iters) == (4, 1, 1, 10000)
     assert V.default_options(3).leaf_capacity == 8
-    assert o.block_rhs == 0
+    assert o.block_rhs == 0 and o.block_lanes == 0
     with pytest.raises(V.VasmgError):
         V.default_options(4)
 
