@@ -173,7 +173,6 @@ __global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr 
                                                       const int32_t* __restrict__ ccol,
                                                       double* __restrict__ cval) {
   constexpr int DD = D * D;
-  constexpr int U = 8;
   const int32_t i = blockIdx.x;
   if (i >= nrows) return;
   const int64_t cb = cptr[i], ce = cptr[i + 1];
@@ -199,17 +198,17 @@ __global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr 
           for (int e = 0; e < DD; ++e) acc[e] += w * Y.val[q * DD + e];
         }
       };
-      int64_t q = qb;
-      for (; q + U <= qe; q += U) {
-        int j[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = Y.col[q + u];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (j[u] == my) add(q + u);
+      // Y's rows hold distinct columns in ascending order: at most one entry
+      // matches, found by bisection
+      int64_t lo = qb, hi = qe;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (Y.col[mid] < my)
+          lo = mid + 1;
+        else
+          hi = mid;
       }
-      for (; q < qe; ++q)
-        if (Y.col[q] == my) add(q);
+      if (lo < qe && Y.col[lo] == my) add(lo);
     }
     if (s < ce) {
 #pragma unroll
