@@ -167,8 +167,10 @@ __global__ __launch_bounds__(kThreads) void k_symbolic(int32_t nrows, Csr X, Csr
 
 // Values of row i of X * Y at the columns the symbolic pass wrote. XB: X holds
 // d x d blocks and Y scalars (A P); else X scalars and Y blocks (P^T (AP)).
-template <int D, bool XB>
-__global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr Y,
+// NT threads per row: 64 for A P, whose rows hold a few dozen blocks (a larger
+// workgroup would leave most of its wavefronts idle and fewer rows resident).
+template <int D, bool XB, int NT>
+__global__ __launch_bounds__(NT) void k_numeric(int32_t nrows, Csr X, Csr Y,
                                                       const int64_t* __restrict__ cptr,
                                                       const int32_t* __restrict__ ccol,
                                                       double* __restrict__ cval) {
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_numeric(int32_t nrows, Csr X, Csr 
   if (i >= nrows) return;
   const int64_t cb = cptr[i], ce = cptr[i + 1];
   const int64_t xb = X.ptr[i], xe = X.ptr[i + 1];
-  for (int64_t s0 = cb; s0 < ce; s0 += kThreads) {
+  for (int64_t s0 = cb; s0 < ce; s0 += NT) {
     if (s0 + (threadIdx.x & ~63) >= ce) break;   // this wave owns no block of the row
     const int64_t s = s0 + threadIdx.x;
     const int my = s < ce ? ccol[s] : -1;
@@ -367,7 +369,8 @@ void product(GalerkinDevice& G, const DevCsr& X, const DevCsr& Y, int64_t ncols,
     hipLaunchKernelGGL(k_symbolic<true>, dim3(n32), dim3(kThreads), 0, st, n32, X.view(), Y.view(),
                        G.window, nullptr, C.ptr, C.col);
     check(hipGetLastError(), "symbolic fill launch");
-    hipLaunchKernelGGL((k_numeric<D, XB>), dim3(n32), dim3(kThreads), 0, st, n32, X.view(),
+    constexpr int NT = XB ? 64 : kThreads;
+    hipLaunchKernelGGL((k_numeric<D, XB, NT>), dim3(n32), dim3(NT), 0, st, n32, X.view(),
                        Y.view(), C.ptr, C.col, C.val);
     check(hipGetLastError(), "numeric launch");
   }
