@@ -94,7 +94,7 @@ struct alignas(16) RowStage {
   int col[CH];
 };
 
-template <typename T, int D, int K, int S, int VS, int GL, int CH = kStage>
+template <typename T, int D, int K, int S, int VS, int GL, int CH = kStage, int CPL = 1>
 __device__ __forceinline__ void mc_row_product_staged(int kb, int ke, int self, int lane, int slot,
                                                       int k, const int* __restrict__ col,
                                                       const T* __restrict__ val, int64_t nnz,
@@ -140,11 +140,16 @@ __device__ __forceinline__ void mc_row_product_staged(int kb, int ke, int self, 
     int j[PB];
 #pragma unroll
     for (int i = 0; i < PB; ++i) j[i] = st.col[slot + i * S];
-    T xv[PB][D];
+    // CPL columns per lane: k, k + K / CPL, ...; acc[h * D + a] is column h's
+    T xv[PB][CPL][D];
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
-      if (p0 + slot + i * S < ke)
-        BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(j[i]) * K + k) * VS, xv[i]);
+      if (p0 + slot + i * S < ke) {
+#pragma unroll
+        for (int h = 0; h < CPL; ++h)
+          BlockVecIO<T, D, VS>::load(x + (static_cast<int64_t>(j[i]) * K + k + h * (K / CPL)) * VS,
+                                     xv[i][h]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
@@ -154,7 +159,11 @@ __device__ __forceinline__ void mc_row_product_staged(int kb, int ke, int self, 
 #pragma unroll
         for (int a = 0; a < D; ++a) {
 #pragma unroll
-          for (int c = 0; c < D; ++c) acc[a] += m[a * D + c] * xv[i][c];
+          for (int c = 0; c < D; ++c) {
+            const T mv = m[a * D + c];
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) acc[h * D + a] += mv * xv[i][h][c];
+          }
         }
       }
     }
@@ -340,30 +349,37 @@ template <typename T, int D, int K, int GL>
 __device__ __forceinline__ void mc_cell_offcell(int v0, int m, const Part<T>& L, const Part<T>& U,
                                                 const T* __restrict__ x, bool want_lo,
                                                 bool want_up, CellLds<T, D, K>& sh) {
-  constexpr int S = GL / K;
-  const int g = threadIdx.x / GL, lane = threadIdx.x % GL, slot = lane / K, k = lane % K;
-  T lo[D], up[D];
+  // two columns per lane (k and k + K/2) from 8 columns up: a staged block is
+  // read from LDS once for both
+  constexpr int CPL = K >= 8 ? 2 : 1, KL = K / CPL;
+  constexpr int S = GL / KL;
+  static_assert(S <= kStage, "slots fit a chunk");
+  const int g = threadIdx.x / GL, lane = threadIdx.x % GL, slot = lane / KL, k = lane % KL;
+  T lo[CPL * D], up[CPL * D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) { lo[a] = T(0); up[a] = T(0); }
+  for (int a = 0; a < CPL * D; ++a) { lo[a] = T(0); up[a] = T(0); }
   if (g < m) {
     const int i = v0 + g;
     if (want_lo)
-      mc_row_product_staged<T, D, K, S, D, GL>(L.ptr[i], L.ptr[i + 1], i, lane, slot, k, L.col,
-                                               L.val, L.nnz, x, lo, sh.stage[g]);
+      mc_row_product_staged<T, D, K, S, D, GL, kStage, CPL>(L.ptr[i], L.ptr[i + 1], i, lane, slot, k,
+                                                            L.col, L.val, L.nnz, x, lo, sh.stage[g]);
     if (want_up)
-      mc_row_product_staged<T, D, K, S, D, GL>(U.ptr[i], U.ptr[i + 1], i, lane, slot, k, U.col,
-                                               U.val, U.nnz, x, up, sh.stage[g]);
+      mc_row_product_staged<T, D, K, S, D, GL, kStage, CPL>(U.ptr[i], U.ptr[i + 1], i, lane, slot, k,
+                                                            U.col, U.val, U.nnz, x, up, sh.stage[g]);
   }
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    if (want_lo) lo[a] = slot_sum<T, K, GL>(lo[a]);
-    if (want_up) up[a] = slot_sum<T, K, GL>(up[a]);
+  for (int a = 0; a < CPL * D; ++a) {
+    if (want_lo) lo[a] = slot_sum<T, KL, GL>(lo[a]);
+    if (want_up) up[a] = slot_sum<T, KL, GL>(up[a]);
   }
   if (slot == 0) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      sh.lo[g][k][a] = lo[a];
-      sh.up[g][k][a] = up[a];
+    for (int h = 0; h < CPL; ++h) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        sh.lo[g][k + h * KL][a] = lo[h * D + a];
+        sh.up[g][k + h * KL][a] = up[h * D + a];
+      }
     }
   }
 }
