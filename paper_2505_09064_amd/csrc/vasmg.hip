@@ -1850,14 +1850,20 @@ void upload_block(vasmg_ctx& C, int K) {
     C.clear(*v, sizeof(double) * n);
   }
   if (!C.vc32) C.kb[0] = C.kR;    // FP64 V-cycle: its fine right-hand side is r
-  C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanesNarrow));
-  // lanes per block row: the wide groups (8 / 4 block slots per column at K = 16)
-  // for long rows, so a row costs few rounds of dependent loads per lane
+  // one partial per workgroup of the block SpMV: sized for the wide lane groups
+  // (fewest rows per workgroup), whichever the heuristic, the tuner or the
+  // block_lanes option puts on the fine level
+  C.kn_partial = std::max(kFlatGrid, grid_for(C.n0, dev::kBlock / dev::kPointLanesWide));
+  // lanes per block row: on the cell levels the narrow groups (their rows go
+  // through LDS in chunks, which keeps a long row's loads in flight with few
+  // slots, and more cells fit on a compute unit: 65^3, K = 16, 56.8 ms per
+  // block solve against 58.3 with the wide groups on the long-row levels); on
+  // the point level the wide groups for long rows
   for (int l = 0; l < C.L; ++l) {
     DevLevel& lv = C.lev[l];
     const double avg = lv.n > 0 ? static_cast<double>(lv.nnz) / lv.n : 0.0;
     if (lv.cells)
-      lv.mcGL = avg >= 48.0 ? dev::kCellLanesWide : dev::kCellLanesNarrow;
+      lv.mcGL = dev::kCellLanesNarrow;
     else
       lv.mcGL = avg >= 24.0 ? dev::kPointLanesWide : dev::kPointLanesNarrow;
     if (C.opt.block_lanes != 0) {   // forced: narrow (1) or wide (2) groups everywhere

@@ -141,6 +141,27 @@ def test_block_forced_lane_groups_match_oracle(dim, K, lanes, prec):
     s.free()
 
 
+def test_block_wide_lanes_past_the_flat_reduction_grid():
+    """Wide lane groups on a fine level of more than 4 x 1024 free vertices
+    (4,624 here) launch more block-SpMV workgroups than the flat reduction grid
+    holds partial sums; the partial buffer is sized for them (regression: setup
+    refused with EINVAL). The wide-lane solve matches the narrow-lane solve of the
+    same handle options column by column (FP64, 1e-8, iterations +-1)."""
+    m = small3d(17, seed=5)
+    F = np.stack(_loads(m, 16))
+    out = {}
+    for lanes in (1, 2):
+        s = V.Solver.from_mesh(m, precision=V.FP64, block_rhs=16, block_lanes=lanes)
+        X, infos = s.solve(F, 1e-8)
+        assert all(i["converged"] == 1 for i in infos)
+        out[lanes] = (X, [i["iterations"] for i in infos])
+        s.free()
+    (Xn, itn), (Xw, itw) = out[1], out[2]
+    for c in range(16):
+        assert abs(itn[c] - itw[c]) <= 1
+        assert np.linalg.norm(Xw[c] - Xn[c]) <= 1e-8 * np.linalg.norm(Xn[c]), c
+
+
 def test_block_zero_column_and_initial_guess():
     m, o, s = _setup(3, V.FP64, 4)
     F = np.stack(_loads(m, 4))
